@@ -435,6 +435,8 @@ int or_apply_A(int N, const int *nel, const double *D, const double *g, const in
  *     x = x + alpha p;  r = r - alpha w     (add2s2, twice)
  *     rtr = glsc3(r,c,r)
  *   stop when sqrt(rtr)/sqrt(glsc3(b,c,b)) <= tol (tol <= 0: run maxit).
+ * Before the first iteration the initial residual is tested the same way;
+ * a residual of exactly zero also ends the loop (no division by zero).
  * res_hist (length maxit+1, may be NULL) receives the recursive relative
  * residual, entry 0 being the initial one.  Returns the iteration count, or
  * -5 on breakdown (pap <= 0), -6 on a non-finite value.
@@ -471,12 +473,16 @@ int or_cg(int N, const int *nel, const double *D, const double *g, const int64_t
     double rnorm0 = or_glsc3(nl, r, c, r);
     int status = 0, it = 0;
     if (res_hist) res_hist[0] = bb > 0 ? sqrt(rnorm0) / sqrt(bb) : 0.0;
-    if (bb > 0) {
+    /* Table 1 has no test before the first iteration; here a residual that
+       already meets tol (or is exactly zero) ends the solve with 0 iterations. */
+    int converged0 = rnorm0 == 0.0 || (tol > 0 && sqrt(rnorm0) / sqrt(bb) <= tol);
+    if (bb > 0 && !converged0) {
         double rtz1 = 1.0, rtz2;
         for (int64_t l = 0; l < nl; ++l) p[l] = 0.0;
         for (it = 1; it <= maxit; ++it) {
             rtz2 = rtz1;
             rtz1 = or_glsc3(nl, r, c, r);
+            if (rtz1 == 0.0) { --it; break; }   /* exact solution reached */
             double beta = it == 1 ? 0.0 : rtz1 / rtz2;
             for (int64_t l = 0; l < nl; ++l) p[l] = beta * p[l] + r[l];
             or_apply(&op, p, w);

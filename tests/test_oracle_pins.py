@@ -363,6 +363,12 @@ def test_cg_fixed_iterations_and_history():
     x, it, hist = P.cg(f, tol=0.0, maxit=17)
     assert it == 17 and len(hist) == 18 and hist[0] == 1.0
     assert hist[-1] < hist[0]
+    # an exact initial guess ends the solve before the first iteration
+    xe, _, _ = P.cg(f, tol=1e-14, maxit=500)
+    x2, it2, h2 = P.cg(f, x0=xe, tol=1e-10, maxit=5)
+    assert it2 == 0 and np.allclose(x2, xe, rtol=4e-16, atol=0)   # projection may move 1 ulp
+    x3, it3, _ = P.cg(np.zeros(P.nl), tol=1e-10, maxit=5)
+    assert it3 == 0 and not x3.any()
 
 
 def test_cg_power_of_two_scaling():
