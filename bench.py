@@ -1,0 +1,189 @@
+"""Benchmark of the spectral-element Poisson CG hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: 16^3 = 4096 unit-cube hexahedra, N = 9 (10^3 GLL points per element,
+4,096,000 local points), load vector f ~ U[0,1) (PCG64 seed 2), homogeneous
+Dirichlet box, solved to a relative residual of 1e-8.  One step = one whole
+mixed-precision solve (FP32 operator / FP64 reductions, scalars and
+refinement); its FP64 CG counterpart is timed the same way next to it.
+
+Prints ONE JSON line: the mixed solve's CG GDOF*iter/s (local points x CG
+iterations / solve time), the FP64 solve's, the roofline of the dominant
+kernel (fused add2s1 + operator, HIP events on the solver's stream), the
+ax+dssum bandwidth at each precision, and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+NEL, N, TOL, SEED = (16, 16, 16), 9, 1e-8, 2
+PEAK_HBM_GBS = 8000.0
+
+
+def ax_dssum_bytes_per_point(sv, sg, sigma):
+    """Algorithmic HBM bytes per local point of nek_ax (operator + segment
+    dssum): u read, w write, six g factors, then for the element-surface
+    fraction sigma: w read + write and the int32 permutation, plus ~1 B of
+    segment offsets."""
+    return 2 * sv + 6 * sg + sigma * (2 * sv + 4) + 1
+
+
+def cg_operator_bytes_per_point(sv, sg):
+    """Fused add2s1 + operator kernel: r, p read, p, w write, six g factors."""
+    return 4 * sv + 6 * sg
+
+
+def time_ax_dssum(ctx, torch, dtype, reps=20):
+    u = torch.rand(ctx.nl, dtype=dtype, device="cuda")
+    w = torch.empty_like(u)
+    for _ in range(3):
+        ctx.ax(u, w)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        ctx.ax(u, w)
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps / 1e3
+
+
+def cpu_baseline(f, budget_s=15.0):
+    """The FP64 oracle (serial C) on the same workload, fixed iteration count."""
+    import oracle
+    from paper_2405_11065_amd import synth
+    P = oracle.Problem(N, NEL, synth.box_vertices(NEL))
+    t0 = time.perf_counter()
+    P.cg(f, tol=0.0, maxit=2)
+    per_it = (time.perf_counter() - t0) / 2
+    k = max(2, int(budget_s / max(per_it, 1e-6)))
+    t0 = time.perf_counter()
+    _, it, _ = P.cg(f, tol=0.0, maxit=k)
+    dt = time.perf_counter() - t0
+    return {"value": P.nl * it / dt / 1e9, "unit": "GDOF*iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"serial FP64 oracle CG on the same 16^3 N=9 problem, {it} fixed iterations "
+                      f"({dt:.1f} s), setup excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2405_11065_amd import nek, synth
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    nek.load()
+    torch.cuda.set_device(0)
+
+    ctx = nek.Context(NEL, N, prec="fp32")
+    nl = ctx.nl
+    f_host = synth.uniform_load(nl, SEED)
+    f = torch.from_numpy(f_host).cuda()
+    x = ctx.new_vector()
+
+    def solve():
+        _, st, _ = ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+        return st
+
+    # ---- mixed precision (the timed steps)
+    for _ in range(args.warmup):
+        solve()
+    ctx.prof_read(0, reset=True)
+    ctx.prof_read(1, reset=True)
+    ctx.prof_enable(4)
+    iters = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(args.steps):
+        st = solve()
+        iters += st["iters"]
+        stats.append(st)
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    ctx.prof_enable(0)
+    ax_ms, ax_n = ctx.prof_read(0)
+    up_ms, up_n = ctx.prof_read(1)
+    value = nl * iters / t_mixed / 1e9
+    ms_per_step = t_mixed / args.steps * 1e3
+
+    # ---- FP64 CG on the same input, same protocol
+    ctx.set_prec("fp64")
+    solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it64 = 0
+    for _ in range(args.steps):
+        it64 += solve()["iters"]
+    torch.cuda.synchronize()
+    t_fp64 = time.perf_counter() - t0
+
+    # ---- ax + dssum bandwidth at each precision (nek_ax)
+    sigma = 1.0 - ((N - 1) / (N + 1)) ** 3
+    axd = {}
+    for name, prec, dt, sv, sg in (("fp64", "fp64", torch.float64, 8, 8), ("fp32", "fp32", torch.float32, 4, 4),
+                                   ("bf16g", "bf16g", torch.float32, 4, 2)):
+        ctx.set_prec(prec)
+        t = time_ax_dssum(ctx, torch, dt)
+        b = ax_dssum_bytes_per_point(sv, sg, sigma) * nl
+        axd[name] = {"us": round(t * 1e6, 2), "GBps": round(b / t / 1e9, 1),
+                     "frac_hbm": round(b / t / 1e9 / PEAK_HBM_GBS, 3)}
+
+    bpp = cg_operator_bytes_per_point(4, 4)
+    ax_avg_s = ax_ms / max(ax_n, 1) / 1e3
+    achieved = bpp * nl / ax_avg_s / 1e9 if ax_n else None
+    cpu = None if args.no_cpu else cpu_baseline(f_host)
+
+    out = {
+        "metric": "CG GDOF*iter/s, mixed FP32/FP64 CG to rel residual 1e-8 (FP64 beside it); ax+dssum HBM GB/s",
+        "value": round(value, 3),
+        "unit": "GDOF*iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "box 16x16x16 unit-cube hexahedra, N=9, f~U[0,1) seed 2, tol 1e-8 relative",
+                   "local_points": nl, "precision": "FP32 operator/dssum, FP64 glsc3/scalars/x/refinement"},
+        "mixed": {"iters_per_solve": iters / args.steps, "outer_per_solve": stats[-1]["outer_iters"],
+                  "true_rel_res": stats[-1]["rel_res"], "ms_per_solve": round(ms_per_step, 3)},
+        "fp64": {"value": round(nl * it64 / t_fp64 / 1e9, 3), "iters_per_solve": it64 / args.steps,
+                 "ms_per_solve": round(t_fp64 / args.steps * 1e3, 3)},
+        "speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
+        "ax_dssum": axd,
+        "roofline": {"bound": "hbm", "kernel": "k_ax<NP=10,EPW=3,f32,f32,CG> (add2s1 + ax_e)",
+                     "achieved": round(achieved, 1) if achieved else None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None, "traffic": None,
+                     "bytes_per_point": bpp, "avg_us": round(ax_avg_s * 1e6, 2), "sampled_launches": ax_n,
+                     "update_kernel_avg_us": round(up_ms / max(up_n, 1) * 1e3, 2)},
+        "cpu_baseline": cpu,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

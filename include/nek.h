@@ -1,0 +1,215 @@
+/*
+ * nek.h -- C ABI of libnek, an MI355X (gfx950) implementation of the
+ * conjugate-gradient solve of the spectral-element Poisson problem that the
+ * Nekbone mini-app runs (Chen, de Oliveira Castro, Bientinesi, Iakymchuk,
+ * "Enabling mixed-precision with the help of tools: A Nekbone case study").
+ *
+ * Problem.  A box of nel[0] x nel[1] x nel[2] trilinear hexahedra, polynomial
+ * order N on Gauss-Lobatto-Legendre (GLL) points, homogeneous Dirichlet
+ * conditions on the six outer faces.  The matrix-free operator is the one the
+ * paper's Fig. 2 call graph evaluates: local_grad3 (derivatives along r, s, t
+ * with the 1-D GLL matrix D), the six geometric factors g1..g6, local_grad3_t,
+ * followed by gather-scatter (dssum) and the Dirichlet mask.
+ *
+ * Vector layout.  Every vector is an element-local ("duplicated") vector of
+ * n_local = E (N+1)^3 entries, index l = e (N+1)^3 + i + (N+1)(j + (N+1) k),
+ * e = ex + nel0 (ey + nel1 ez).  Copies of a shared node hold equal values
+ * in a continuous vector.
+ *
+ * Pointers.  Vector arguments are DEVICE pointers owned by the caller; the
+ * library never frees them and keeps none after a call returns.  Scalars,
+ * statistics, histories and nek_get outputs are HOST pointers.
+ *
+ * Streams.  All work of a context is enqueued on the hipStream_t given to
+ * nek_setup (NULL = the default stream).  nek_ax, nek_ax_local and nek_dssum
+ * return without synchronising; nek_glsc3, nek_get and the solvers
+ * synchronise before they return.
+ *
+ * Errors.  Every call returns a nek_status; nothing throws across the ABI.
+ * Negative values are errors (the context stays usable unless the value is
+ * NEK_E_HIP); NEK_NOCONV is a warning (x holds the last iterate).
+ * nek_strerror gives a static message.  Calls on one context must not
+ * overlap (one host thread at a time per context).
+ */
+#ifndef NEK_H
+#define NEK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nek_ctx nek_ctx;
+
+typedef enum {
+    NEK_OK = 0,
+    NEK_NOCONV = 1,          /* warning: maxit reached before tol           */
+    NEK_E_ARG = -1,          /* bad argument (NULL, size, unsupported N)    */
+    NEK_E_HIP = -2,          /* a HIP runtime call failed                   */
+    NEK_E_OOM = -3,          /* device or host allocation failed            */
+    NEK_E_JACOBIAN = -4,     /* det J <= 0 somewhere: inverted element      */
+    NEK_E_BREAKDOWN = -5,    /* CG breakdown: p.Ap <= 0                     */
+    NEK_E_NONFINITE = -6,    /* a NaN or Inf reached a reduction            */
+    NEK_E_STAGNATION = -7    /* mixed refinement stopped reducing and the
+                                FP64 fallback was disabled                  */
+} nek_status;
+
+/* Operator precision of a context's solves. */
+typedef enum {
+    NEK_PREC_FP64 = 0,       /* FP64 vectors, FP64 g                                   */
+    NEK_PREC_FP32 = 1,       /* mixed: FP32 p/w/r and FP32 g inside FP64 refinement    */
+    NEK_PREC_BF16G = 2       /* mixed: as FP32, g1..g6 stored as BF16 (RNE from FP64)  */
+} nek_prec;
+
+/* Element type of the vectors passed to nek_ax / nek_ax_local / nek_dssum /
+ * nek_glsc3. */
+typedef enum { NEK_F64 = 0, NEK_F32 = 1 } nek_dtype;
+
+typedef struct {
+    int nel[3];              /* elements per direction, each >= 1             */
+    double lo[3], hi[3];     /* box corners, used when vtx == NULL            */
+    const double *vtx;       /* optional host array [(nel0+1)(nel1+1)(nel2+1)][3],
+                                vertex lattice, x-index fastest; NULL = uniform
+                                lattice on [lo, hi]                           */
+} nek_mesh;
+
+typedef struct {
+    int prec;                /* nek_prec of nek_cg_solve                                */
+    double inner_tol;        /* mixed: inner relative tolerance; 0 = 1e-4 (FP32 g) or
+                                1e-2 (BF16 g)                                           */
+    int inner_maxit;         /* mixed: inner iteration cap per refinement step; 0 = 4000 */
+    int max_outer;           /* mixed: refinement steps cap; 0 = 30                      */
+    int fp64_fallback;       /* mixed: 1 = when a refinement step fails to halve the
+                                true residual, finish with FP64 CG from the current x  */
+    int elts_per_wg;         /* reserved, must be 0                                      */
+} nek_opts;
+
+typedef struct {
+    int iters;               /* CG iterations (mixed: sum of inner iterations)   */
+    int outer_iters;         /* mixed: refinement steps (true-residual checks)   */
+    int fp64_iters;          /* mixed: iterations of the FP64 fallback, if used  */
+    int status;              /* nek_status of the solve                          */
+    double rel_res;          /* FP64: last recursive relative residual;
+                                mixed: last true FP64 relative residual          */
+    double t_solve_s;        /* wall time of the solve on the context's stream   */
+} nek_stats;
+
+/* nek_get selectors (host output sizes in parentheses). */
+typedef enum {
+    NEK_GET_GLL = 0,         /* double xi[N+1]                                   */
+    NEK_GET_W = 1,           /* double w[N+1] (GLL weights)                      */
+    NEK_GET_D = 2,           /* double D[(N+1)^2], row-major, D[i][j] = l_j'(x_i) */
+    NEK_GET_G = 3,           /* double g[E][6][(N+1)^3]: G_rr, G_ss, G_tt, G_rs,
+                                G_rt, G_st (FP64)                                 */
+    NEK_GET_B = 4,           /* double B[n_local] (diagonal mass)                */
+    NEK_GET_GID = 5,         /* int64 gid[n_local]                               */
+    NEK_GET_MULT = 6,        /* int32 mult[n_local]                              */
+    NEK_GET_MASK = 7,        /* int8 mask[n_local], 0 on the Dirichlet boundary  */
+    NEK_GET_PERM = 8,        /* int32 perm[n_perm]                               */
+    NEK_GET_SEGPTR = 9,      /* int32 seg_ptr[n_seg+1]                           */
+    NEK_GET_SEGFLAG = 10,    /* int8 seg_flag[n_seg], 1 = masked segment         */
+    NEK_GET_XYZ = 11         /* double X[E][3][(N+1)^3] node coordinates         */
+} nek_get_what;
+
+/* nek_size selectors. */
+typedef enum {
+    NEK_SIZE_NLOCAL = 0, NEK_SIZE_NGLOBAL = 1, NEK_SIZE_E = 2,
+    NEK_SIZE_NPERM = 3, NEK_SIZE_NSEG = 4, NEK_SIZE_N = 5
+} nek_size_what;
+
+/*
+ * nek_setup -- build a context for one box mesh of order N (1 <= N <= 15).
+ * On the host, in FP64: GLL nodes and weights, D, geometry (trilinear map,
+ * J = D X, G, B), global numbering and the sorted-segment gather-scatter maps
+ * (the initialisation that the paper's mixed build keeps in double, Sect. 5).
+ * These are uploaded once; the FP32 / BF16 copies of g that opts->prec needs
+ * are rounded on the device.
+ * opts may be NULL (FP64 defaults).  stream is a hipStream_t or NULL.
+ * Returns NEK_E_JACOBIAN for an inverted element, NEK_E_ARG for bad sizes.
+ */
+int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, nek_ctx **out);
+
+/* nek_free -- release everything the context allocated.  NULL is a no-op. */
+void nek_free(nek_ctx *ctx);
+
+/* nek_size -- *out = the size selected by what (nek_size_what). */
+int nek_size(const nek_ctx *ctx, int what, int64_t *out);
+
+/* nek_get -- copy a setup array (nek_get_what) to host memory (synchronous). */
+int nek_get(nek_ctx *ctx, int what, void *host_out);
+
+/*
+ * nek_set_prec -- switch the precision of later nek_cg_solve calls.  Builds
+ * the FP32 or BF16 copy of g on first use.
+ */
+int nek_set_prec(nek_ctx *ctx, int prec);
+
+/*
+ * nek_ax_local -- w = A_L u, the unassembled element operator ax_e of the
+ * paper's Fig. 2 for every element (local_grad3, g1..g6, local_grad3_t).
+ * dtype NEK_F64 uses FP64 g; NEK_F32 uses the context's FP32 or BF16 g.
+ * u and w are device vectors of n_local entries and must not overlap.
+ */
+int nek_ax_local(nek_ctx *ctx, const void *u, void *w, int dtype);
+
+/*
+ * nek_ax -- w = M o dssum(A_L u): the assembled, masked operator (the ax call
+ * of Table 1 with its gather-scatter).  Same arguments as nek_ax_local.
+ */
+int nek_ax(nek_ctx *ctx, const void *u, void *w, int dtype);
+
+/*
+ * nek_dssum -- in place: every local copy of a global node receives the sum
+ * of all copies, taken in ascending local index (gather-scatter, gslib's
+ * gs_op in the paper); with apply_mask != 0 the Dirichlet nodes are then
+ * zeroed.  FP64 sums are bit-identical to a serial ascending-order sum; FP32
+ * copies are summed in FP64 and rounded once.
+ */
+int nek_dssum(nek_ctx *ctx, void *w, int dtype, int apply_mask);
+
+/*
+ * nek_glsc3 -- *out = sum_l a_l c_l b_l with c_l = 1 / multiplicity (glsc3 of
+ * Table 1), accumulated in FP64 in a fixed order (deterministic).
+ */
+int nek_glsc3(nek_ctx *ctx, const void *a, const void *b, int dtype, double *out);
+
+/*
+ * nek_cg_solve -- solve A x = b, b = M o dssum(f), by unpreconditioned CG in
+ * the order of the paper's Table 1, in the context's precision:
+ *  - NEK_PREC_FP64: FP64 CG; stops when the recursive relative residual
+ *    sqrt(glsc3(r,r)/glsc3(b,b)) <= tol; tol <= 0 runs exactly maxit
+ *    iterations.
+ *  - NEK_PREC_FP32 / NEK_PREC_BF16G: iterative refinement.  The outer loop
+ *    forms r = b - A x in FP64 (FP64 g) and stops when the true relative
+ *    residual <= tol; each inner solve is CG with an FP32 operator and FP64
+ *    reductions, scalars and correction; x accumulates in FP64.
+ * f (load vector), x0 (optional, projected as M o dssum(c o x0)) and x are
+ * FP64 device vectors of n_local entries; x may alias x0.  maxit caps the
+ * total CG iterations.  stats and res_hist (host, length maxit+1: entry 0 is
+ * the initial residual, entry k the residual after iteration k) may be NULL.
+ * Returns NEK_OK, NEK_NOCONV, or an error; stats->status repeats it.
+ */
+int nek_cg_solve(nek_ctx *ctx, const double *f, const double *x0, double tol, int maxit,
+                 double *x, nek_stats *stats, double *res_hist);
+
+/*
+ * Sampled kernel timing with HIP events on the context's stream, for
+ * roofline reporting.  nek_prof_enable(ctx, k): every k-th CG iteration of
+ * later solves is bracketed by events (k = 0 turns sampling off).
+ * nek_prof_read(ctx, kernel, &ms, &count, reset) returns the summed duration
+ * and number of sampled launches of kernel 0 (the fused add2s1 + operator
+ * kernel) or kernel 1 (the fused gather-scatter + update kernel); it
+ * synchronises the stream.  reset != 0 clears that kernel's totals.
+ */
+int nek_prof_enable(nek_ctx *ctx, int every);
+int nek_prof_read(nek_ctx *ctx, int kernel, double *total_ms, int64_t *count, int reset);
+
+/* nek_strerror -- static description of a status code. */
+const char *nek_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEK_H */

@@ -1,0 +1,44 @@
+/*
+ * nek_host.h -- host-only setup routines of libnek, callable without a GPU.
+ *
+ * They compute the FP64 initialisation that nek_setup uploads to the device
+ * (the part the paper keeps in double precision, Sect. 5): the GLL rule, the
+ * differentiation matrix, trilinear geometry, global numbering and the
+ * sorted-segment gather-scatter maps.  All pointers are HOST pointers owned
+ * by the caller and sized as stated; nothing is retained.  Each returns
+ * NEK_OK (0) or a negative nek_status from nek.h.
+ */
+#ifndef NEK_HOST_H
+#define NEK_HOST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* GLL nodes xi[N+1] (ascending, -1 .. 1) and weights w[N+1]; 1 <= N <= 15. */
+int nek_host_gll(int N, double *xi, double *w);
+
+/* D[(N+1)^2], row-major, D[i][j] = derivative at xi_i of the Lagrange
+ * polynomial of node j (barycentric form, rows summing to zero). */
+int nek_host_deriv(int N, double *D);
+
+/* Geometry of the box nel[3] from the vertex lattice vtx (as in nek_mesh):
+ * g[E][6][(N+1)^3], B[E][(N+1)^3], X[E][3][(N+1)^3] (X may be NULL).
+ * Returns NEK_E_JACOBIAN (-4) for an inverted element. */
+int nek_host_geometry(int N, const int nel[3], const double *vtx, double *g, double *B, double *X);
+
+/* Per local node: gid (int64), multiplicity (int32), mask (int8); any may be
+ * NULL. */
+int nek_host_numbering(int N, const int nel[3], int64_t *gid, int32_t *mult, int8_t *mask);
+
+/* Segment sizes, then the maps: perm[n_perm], seg_ptr[n_seg+1], seg_flag[n_seg]. */
+int nek_host_segment_sizes(int N, const int nel[3], int64_t *n_perm, int64_t *n_seg);
+int nek_host_segments(int N, const int nel[3], int32_t *perm, int32_t *seg_ptr, int8_t *seg_flag);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEK_HOST_H */

@@ -1,0 +1,357 @@
+// Host-side FP64 initialisation for libnek: GLL rule, differentiation
+// matrix, trilinear geometry and the sorted-segment gather-scatter maps.
+// The paper's mixed build leaves all of this set-up in double precision and
+// lowers only the CG loop (Sect. 5).
+#include "nek_setup.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <thread>
+#include <vector>
+
+namespace nek {
+
+// Legendre P_N, P_N' at x by the three-term recurrence and
+// P'_{k+1} = P'_{k-1} + (2k+1) P_k.
+static void legendre_with_deriv(int N, double x, double &p, double &dp)
+{
+    double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
+    if (N == 0) { p = 1.0; dp = 0.0; return; }
+    for (int k = 1; k < N; ++k) {
+        double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+        double d2 = d0 + (2 * k + 1) * p1;
+        p0 = p1; p1 = p2;
+        d0 = d1; d1 = d2;
+    }
+    p = p1;
+    dp = d1;
+}
+
+// GLL points: +-1 and the zeros of P_N'.  Newton on P_N' with P_N'' taken
+// from Legendre's equation (1-x^2) P'' = 2x P' - N(N+1) P.
+void gll_rule(int N, std::vector<double> &x, std::vector<double> &w)
+{
+    const int n = N + 1;
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    x[0] = -1.0;
+    x[N] = 1.0;
+    const double pi = std::acos(-1.0);
+    for (int i = 1; i < N; ++i) {
+        // interior Chebyshev-Lobatto guess, refined by Newton
+        double t = -std::cos(pi * i / N);
+        for (int it = 0; it < 60; ++it) {
+            double p, dp;
+            legendre_with_deriv(N, t, p, dp);
+            double ddp = (2.0 * t * dp - N * (N + 1.0) * p) / (1.0 - t * t);
+            double step = dp / ddp;
+            t -= step;
+            if (std::fabs(step) <= 1e-16 * std::max(1.0, std::fabs(t))) break;
+        }
+        x[i] = t;
+    }
+    for (int i = 0; i < n / 2; ++i) {   // symmetric node set
+        double m = 0.5 * (x[N - i] - x[i]);
+        x[i] = -m;
+        x[N - i] = m;
+    }
+    if (N % 2 == 0) x[N / 2] = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double p, dp;
+        legendre_with_deriv(N, x[i], p, dp);
+        w[i] = 2.0 / (N * (N + 1.0) * p * p);
+    }
+}
+
+// Derivative of the Lagrange interpolant in barycentric form:
+// D_ij = (lam_j / lam_i) / (x_i - x_j), lam_j = 1 / prod_{k != j} (x_j - x_k),
+// and D_ii = -sum_{j != i} D_ij so that constants are differentiated to zero.
+void deriv_matrix(const std::vector<double> &x, std::vector<double> &D)
+{
+    const int n = (int)x.size();
+    std::vector<double> lam(n, 1.0);
+    for (int j = 0; j < n; ++j) {
+        double prod = 1.0;
+        for (int k = 0; k < n; ++k)
+            if (k != j) prod *= (x[j] - x[k]);
+        lam[j] = 1.0 / prod;
+    }
+    D.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double diag = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double v = (lam[j] / lam[i]) / (x[i] - x[j]);
+            D[(size_t)i * n + j] = v;
+            diag -= v;
+        }
+        D[(size_t)i * n + i] = diag;
+    }
+}
+
+void uniform_vertices(const int nel[3], const double lo[3], const double hi[3], std::vector<double> &vtx)
+{
+    const long vx = nel[0] + 1, vy = nel[1] + 1, vz = nel[2] + 1;
+    vtx.resize((size_t)vx * vy * vz * 3);
+    for (long c = 0; c < vz; ++c)
+        for (long b = 0; b < vy; ++b)
+            for (long a = 0; a < vx; ++a) {
+                long v = a + vx * (b + vy * c);
+                long idx[3] = {a, b, c};
+                for (int d = 0; d < 3; ++d) {
+                    double t = (double)idx[d] / nel[d];
+                    vtx[3 * v + d] = idx[d] == nel[d] ? hi[d] : lo[d] + (hi[d] - lo[d]) * t;
+                }
+            }
+}
+
+// One element: X at the GLL nodes from the 8 vertices, J = D X along r, s, t
+// (exact for a trilinear map), then G = W det(J) J^-1 J^-T and B = W det(J).
+static int element_geometry(int N, const std::vector<double> &x, const std::vector<double> &w,
+                            const std::vector<double> &D, const double V[8][3], double *g, double *B,
+                            double *X, long n3)
+{
+    const int n = N + 1;
+    std::vector<double> Xe(3 * (size_t)n3);
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                double hr[2] = {0.5 * (1 - x[i]), 0.5 * (1 + x[i])};
+                double hs[2] = {0.5 * (1 - x[j]), 0.5 * (1 + x[j])};
+                double ht[2] = {0.5 * (1 - x[k]), 0.5 * (1 + x[k])};
+                long q = i + n * (j + (long)n * k);
+                for (int d = 0; d < 3; ++d) {
+                    double s = 0.0;
+                    for (int v = 0; v < 8; ++v)
+                        s += hr[v & 1] * hs[(v >> 1) & 1] * ht[v >> 2] * V[v][d];
+                    Xe[d * n3 + q] = s;
+                }
+            }
+    int bad = 0;
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                long q = i + n * (j + (long)n * k);
+                double J[3][3];   // J[d][a] = dx_d / dr_a
+                for (int d = 0; d < 3; ++d) {
+                    const double *Xd = &Xe[d * n3];
+                    double a0 = 0, a1 = 0, a2 = 0;
+                    for (int m = 0; m < n; ++m) {
+                        a0 += D[(size_t)i * n + m] * Xd[m + n * (j + (long)n * k)];
+                        a1 += D[(size_t)j * n + m] * Xd[i + n * (m + (long)n * k)];
+                        a2 += D[(size_t)k * n + m] * Xd[i + n * (j + (long)n * m)];
+                    }
+                    J[d][0] = a0; J[d][1] = a1; J[d][2] = a2;
+                }
+                double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+                double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+                double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+                double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+                if (!(det > 0)) { bad = 1; det = 1.0; }
+                // rows of the inverse: R[a][d] = dr_a / dx_d = cofactor(d,a) / det
+                double R[3][3];
+                R[0][0] = c00 / det; R[1][0] = c01 / det; R[2][0] = c02 / det;
+                R[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+                R[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+                R[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+                R[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+                R[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+                R[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+                double wdet = w[i] * w[j] * w[k] * det;
+                auto dot = [&](int a, int b) { return R[a][0] * R[b][0] + R[a][1] * R[b][1] + R[a][2] * R[b][2]; };
+                g[0 * n3 + q] = wdet * dot(0, 0);
+                g[1 * n3 + q] = wdet * dot(1, 1);
+                g[2 * n3 + q] = wdet * dot(2, 2);
+                g[3 * n3 + q] = wdet * dot(0, 1);
+                g[4 * n3 + q] = wdet * dot(0, 2);
+                g[5 * n3 + q] = wdet * dot(1, 2);
+                B[q] = wdet;
+                if (X)
+                    for (int d = 0; d < 3; ++d) X[d * n3 + q] = Xe[d * n3 + q];
+            }
+    return bad;
+}
+
+int geometry(int N, const int nel[3], const std::vector<double> &vtx, const std::vector<double> &x,
+             const std::vector<double> &w, const std::vector<double> &D, double *g, double *B, double *X)
+{
+    const int n = N + 1;
+    const long n3 = (long)n * n * n;
+    const long E = (long)nel[0] * nel[1] * nel[2];
+    const long vx = nel[0] + 1, vy = nel[1] + 1;
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (E < 64) nt = 1;
+    std::vector<int> bad(nt, 0);
+    auto work = [&](unsigned tid) {
+        for (long e = tid; e < E; e += nt) {
+            long ex = e % nel[0], ey = (e / nel[0]) % nel[1], ez = e / ((long)nel[0] * nel[1]);
+            double V[8][3];
+            for (int v = 0; v < 8; ++v) {
+                long a = ex + (v & 1), b = ey + ((v >> 1) & 1), c = ez + (v >> 2);
+                for (int d = 0; d < 3; ++d) V[v][d] = vtx[3 * (a + vx * (b + vy * c)) + d];
+            }
+            bad[tid] |= element_geometry(N, x, w, D, V, g + e * 6 * n3, B + e * n3, X ? X + e * 3 * n3 : nullptr, n3);
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < nt; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto &t : th) t.join();
+    for (int b : bad)
+        if (b) return 1;
+    return 0;
+}
+
+// Local node l -> (element coords, i, j, k) -> global lattice id.
+static inline long global_id(long l, int N, const int nel[3], long Gx, long Gy)
+{
+    const long n = N + 1, n3 = n * n * n;
+    long e = l / n3, q = l - e * n3;
+    long i = q % n, j = (q / n) % n, k = q / (n * n);
+    long ex = e % nel[0], ey = (e / nel[0]) % nel[1], ez = e / ((long)nel[0] * nel[1]);
+    return (ex * N + i) + Gx * ((ey * N + j) + Gy * (ez * N + k));
+}
+
+// Segments by counting sort over global ids: walk the local nodes in
+// ascending order, so the copies of each node come out in ascending local
+// index and the segments in ascending global id.
+void segment_maps(int N, const int nel[3], std::vector<int32_t> &perm, std::vector<int32_t> &seg_ptr,
+                  std::vector<int8_t> &seg_flag)
+{
+    const long n = N + 1, n3 = n * n * n;
+    const long E = (long)nel[0] * nel[1] * nel[2];
+    const long nl = E * n3;
+    const long Gx = (long)nel[0] * N + 1, Gy = (long)nel[1] * N + 1, Gz = (long)nel[2] * N + 1;
+    const long ng = Gx * Gy * Gz;
+    auto on_surface = [&](long l) {
+        long q = l % n3;
+        long i = q % n, j = (q / n) % n, k = q / (n * n);
+        return i == 0 || i == N || j == 0 || j == N || k == 0 || k == N;
+    };
+    std::vector<int32_t> count(ng, 0);
+    long m = 0;
+    for (long l = 0; l < nl; ++l)
+        if (on_surface(l)) { ++count[global_id(l, N, nel, Gx, Gy)]; ++m; }
+    std::vector<int32_t> start(ng, -1);
+    seg_ptr.clear();
+    seg_flag.clear();
+    long pos = 0;
+    for (long gidx = 0; gidx < ng; ++gidx) {
+        if (!count[gidx]) continue;
+        start[gidx] = (int32_t)pos;
+        seg_ptr.push_back((int32_t)pos);
+        long gi = gidx % Gx, gj = (gidx / Gx) % Gy, gk = gidx / (Gx * Gy);
+        bool bnd = gi == 0 || gi == Gx - 1 || gj == 0 || gj == Gy - 1 || gk == 0 || gk == Gz - 1;
+        seg_flag.push_back(bnd ? 1 : 0);
+        pos += count[gidx];
+    }
+    seg_ptr.push_back((int32_t)pos);
+    perm.assign(m, 0);
+    for (long l = 0; l < nl; ++l)
+        if (on_surface(l)) perm[start[global_id(l, N, nel, Gx, Gy)]++] = (int32_t)l;
+}
+
+void numbering(int N, const int nel[3], int64_t *gid, int32_t *mult, int8_t *mask)
+{
+    const long n = N + 1, n3 = n * n * n;
+    const long E = (long)nel[0] * nel[1] * nel[2];
+    const long Gx = (long)nel[0] * N + 1, Gy = (long)nel[1] * N + 1;
+    for (long l = 0; l < E * n3; ++l) {
+        long e = l / n3, q = l - e * n3;
+        long i = q % n, j = (q / n) % n, k = q / (n * n);
+        long ex = e % nel[0], ey = (e / nel[0]) % nel[1], ez = e / ((long)nel[0] * nel[1]);
+        long c[3] = {i, j, k}, el[3] = {ex, ey, ez};
+        int m = 1, bnd = 0;
+        for (int d = 0; d < 3; ++d) {
+            bool lo = c[d] == 0, hi = c[d] == N;
+            if ((lo && el[d] == 0) || (hi && el[d] == nel[d] - 1)) bnd = 1;
+            if ((lo && el[d] > 0) || (hi && el[d] < nel[d] - 1)) m *= 2;
+        }
+        if (gid) gid[l] = global_id(l, N, nel, Gx, Gy);
+        if (mult) mult[l] = m;
+        if (mask) mask[l] = bnd ? 0 : 1;
+    }
+}
+
+}  // namespace nek
+
+// ------------------------------------------------------------ host C ABI
+#include <cstring>
+
+#include "nek_host.h"
+
+namespace {
+bool host_args_ok(int N, const int nel[3])
+{
+    if (N < 1 || N > 15 || !nel) return false;
+    for (int d = 0; d < 3; ++d)
+        if (nel[d] < 1) return false;
+    const long np = N + 1;
+    return (long)nel[0] * nel[1] * nel[2] * np * np * np < (1L << 31);
+}
+}  // namespace
+
+extern "C" {
+
+int nek_host_gll(int N, double *xi, double *w)
+{
+    if (N < 1 || N > 15 || !xi || !w) return -1;
+    std::vector<double> x, ww;
+    nek::gll_rule(N, x, ww);
+    std::memcpy(xi, x.data(), x.size() * sizeof(double));
+    std::memcpy(w, ww.data(), ww.size() * sizeof(double));
+    return 0;
+}
+
+int nek_host_deriv(int N, double *D)
+{
+    if (N < 1 || N > 15 || !D) return -1;
+    std::vector<double> x, w, d;
+    nek::gll_rule(N, x, w);
+    nek::deriv_matrix(x, d);
+    std::memcpy(D, d.data(), d.size() * sizeof(double));
+    return 0;
+}
+
+int nek_host_geometry(int N, const int nel[3], const double *vtx, double *g, double *B, double *X)
+{
+    if (!host_args_ok(N, nel) || !vtx || !g || !B) return -1;
+    std::vector<double> x, w, d;
+    nek::gll_rule(N, x, w);
+    nek::deriv_matrix(x, d);
+    const size_t nv = 3 * (size_t)(nel[0] + 1) * (nel[1] + 1) * (nel[2] + 1);
+    std::vector<double> v(vtx, vtx + nv);
+    return nek::geometry(N, nel, v, x, w, d, g, B, X) ? -4 : 0;
+}
+
+int nek_host_numbering(int N, const int nel[3], int64_t *gid, int32_t *mult, int8_t *mask)
+{
+    if (!host_args_ok(N, nel)) return -1;
+    nek::numbering(N, nel, gid, mult, mask);
+    return 0;
+}
+
+int nek_host_segment_sizes(int N, const int nel[3], int64_t *n_perm, int64_t *n_seg)
+{
+    if (!host_args_ok(N, nel) || !n_perm || !n_seg) return -1;
+    std::vector<int32_t> perm, ptr;
+    std::vector<int8_t> flag;
+    nek::segment_maps(N, nel, perm, ptr, flag);
+    *n_perm = (int64_t)perm.size();
+    *n_seg = (int64_t)flag.size();
+    return 0;
+}
+
+int nek_host_segments(int N, const int nel[3], int32_t *perm, int32_t *seg_ptr, int8_t *seg_flag)
+{
+    if (!host_args_ok(N, nel) || !perm || !seg_ptr || !seg_flag) return -1;
+    std::vector<int32_t> p, ptr;
+    std::vector<int8_t> flag;
+    nek::segment_maps(N, nel, p, ptr, flag);
+    std::memcpy(perm, p.data(), p.size() * sizeof(int32_t));
+    std::memcpy(seg_ptr, ptr.data(), ptr.size() * sizeof(int32_t));
+    std::memcpy(seg_flag, flag.data(), flag.size());
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,29 @@
+// Host-side FP64 initialisation used by libnek (internal header).
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace nek {
+
+// GLL nodes x[0..N] (ascending, x0 = -1, xN = 1) and weights w.
+void gll_rule(int N, std::vector<double> &x, std::vector<double> &w);
+
+// D[i*(N+1)+j] = derivative at x_i of the Lagrange polynomial of node j.
+void deriv_matrix(const std::vector<double> &x, std::vector<double> &D);
+
+// Uniform vertex lattice on [lo, hi], x-index fastest, 3 doubles per vertex.
+void uniform_vertices(const int nel[3], const double lo[3], const double hi[3], std::vector<double> &vtx);
+
+// g[E][6][n^3] = (G_rr, G_ss, G_tt, G_rs, G_rt, G_st), B[E][n^3] and, when X
+// is non-null, X[E][3][n^3].  Returns nonzero if any det(J) <= 0.
+int geometry(int N, const int nel[3], const std::vector<double> &vtx, const std::vector<double> &x,
+             const std::vector<double> &w, const std::vector<double> &D, double *g, double *B, double *X);
+
+// Sorted-segment gather-scatter maps over the element-surface local nodes.
+void segment_maps(int N, const int nel[3], std::vector<int32_t> &perm, std::vector<int32_t> &seg_ptr,
+                  std::vector<int8_t> &seg_flag);
+
+// Per-local-node global id, multiplicity and Dirichlet mask (any may be null).
+void numbering(int N, const int nel[3], int64_t *gid, int32_t *mult, int8_t *mask);
+
+}  // namespace nek

@@ -1,0 +1,265 @@
+"""Thin ctypes binding of libnek (include/nek.h).
+
+Argument marshalling only: every step of the solve runs in libnek's HIP
+kernels.  torch supplies device memory and the HIP stream; no torch math is
+done here on solver data.  Loading fails loudly if libnek.so is missing: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnek.so")
+
+NEK_OK, NEK_NOCONV = 0, 1
+NEK_E_ARG, NEK_E_HIP, NEK_E_OOM, NEK_E_JACOBIAN = -1, -2, -3, -4
+NEK_E_BREAKDOWN, NEK_E_NONFINITE, NEK_E_STAGNATION = -5, -6, -7
+NEK_PREC_FP64, NEK_PREC_FP32, NEK_PREC_BF16G = 0, 1, 2
+NEK_F64, NEK_F32 = 0, 1
+(NEK_GET_GLL, NEK_GET_W, NEK_GET_D, NEK_GET_G, NEK_GET_B, NEK_GET_GID, NEK_GET_MULT, NEK_GET_MASK,
+ NEK_GET_PERM, NEK_GET_SEGPTR, NEK_GET_SEGFLAG, NEK_GET_XYZ) = range(12)
+(NEK_SIZE_NLOCAL, NEK_SIZE_NGLOBAL, NEK_SIZE_E, NEK_SIZE_NPERM, NEK_SIZE_NSEG, NEK_SIZE_N) = range(6)
+
+PREC_NAMES = {"fp64": NEK_PREC_FP64, "fp32": NEK_PREC_FP32, "bf16g": NEK_PREC_BF16G}
+
+# every entry point declared in include/nek.h
+EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_ax_local", "nek_ax",
+           "nek_dssum", "nek_glsc3", "nek_cg_solve", "nek_prof_enable", "nek_prof_read", "nek_strerror")
+
+
+class nek_mesh(ctypes.Structure):
+    _fields_ = [("nel", ctypes.c_int * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("vtx", ctypes.POINTER(ctypes.c_double))]
+
+
+class nek_opts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
+                ("max_outer", ctypes.c_int), ("fp64_fallback", ctypes.c_int), ("elts_per_wg", ctypes.c_int)]
+
+
+class nek_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("fp64_iters", ctypes.c_int),
+                ("status", ctypes.c_int), ("rel_res", ctypes.c_double), ("t_solve_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class NekError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {status} ({strerror(status)})")
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libnek.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libnek.so not found at {path}: build it with `python -m paper_2405_11065_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+    lib.nek_setup.argtypes = [ctypes.POINTER(nek_mesh), ctypes.c_int, ctypes.POINTER(nek_opts), vp,
+                              ctypes.POINTER(vp)]
+    lib.nek_free.argtypes = [vp]
+    lib.nek_free.restype = None
+    lib.nek_size.argtypes = [vp, ctypes.c_int, i64p]
+    lib.nek_get.argtypes = [vp, ctypes.c_int, vp]
+    lib.nek_set_prec.argtypes = [vp, ctypes.c_int]
+    lib.nek_ax_local.argtypes = [vp, vp, vp, ctypes.c_int]
+    lib.nek_ax.argtypes = [vp, vp, vp, ctypes.c_int]
+    lib.nek_dssum.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int]
+    lib.nek_glsc3.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.nek_cg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, vp, ctypes.POINTER(nek_stats), vp]
+    lib.nek_prof_enable.argtypes = [vp, ctypes.c_int]
+    lib.nek_prof_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), i64p, ctypes.c_int]
+    lib.nek_strerror.argtypes = [ctypes.c_int]
+    lib.nek_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    try:
+        return load().nek_strerror(int(status)).decode()
+    except RuntimeError:
+        return "libnek not loaded"
+
+
+def _check(rc, what, ok=(NEK_OK,)):
+    if rc not in ok:
+        raise NekError(rc, what)
+    return rc
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """One box mesh of order N on the current GPU (nek_setup / nek_free)."""
+
+    def __init__(self, nel, N, vtx=None, lo=(0.0, 0.0, 0.0), hi=None, prec="fp64", inner_tol=0.0,
+                 inner_maxit=0, max_outer=0, fp64_fallback=1, stream=None):
+        torch = _torch()
+        self._lib = load()
+        self.N = int(N)
+        self.nel = tuple(int(v) for v in nel)
+        lo = tuple(float(v) for v in lo)
+        hi = tuple(lo[d] + self.nel[d] for d in range(3)) if hi is None else tuple(float(v) for v in hi)
+        m = nek_mesh()
+        m.nel[:] = self.nel
+        m.lo[:] = lo
+        m.hi[:] = hi
+        self._vtx = None
+        if vtx is not None:
+            v = np.ascontiguousarray(vtx, dtype=np.float64)
+            nv = (self.nel[0] + 1) * (self.nel[1] + 1) * (self.nel[2] + 1)
+            if v.shape != (nv, 3):
+                raise ValueError(f"vtx must have shape ({nv}, 3)")
+            self._vtx = v
+            m.vtx = v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        o = nek_opts()
+        o.prec = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+        o.inner_tol = float(inner_tol)
+        o.inner_maxit = int(inner_maxit)
+        o.max_outer = int(max_outer)
+        o.fp64_fallback = int(fp64_fallback)
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        h = ctypes.c_void_p()
+        _check(self._lib.nek_setup(ctypes.byref(m), self.N, ctypes.byref(o), ctypes.c_void_p(self.stream.cuda_stream),
+                                   ctypes.byref(h)), "nek_setup")
+        self._h = h
+        self.nl = self.size(NEK_SIZE_NLOCAL)
+        self.E = self.size(NEK_SIZE_E)
+        self.ng = self.size(NEK_SIZE_NGLOBAL)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.nek_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- queries
+    def size(self, what: int) -> int:
+        out = ctypes.c_int64()
+        _check(self._lib.nek_size(self._h, int(what), ctypes.byref(out)), "nek_size")
+        return out.value
+
+    def get(self, what: int) -> np.ndarray:
+        n = self.N + 1
+        shapes = {NEK_GET_GLL: (n, np.float64), NEK_GET_W: (n, np.float64), NEK_GET_D: ((n, n), np.float64),
+                  NEK_GET_G: ((self.E, 6, n ** 3), np.float64), NEK_GET_B: (self.nl, np.float64),
+                  NEK_GET_GID: (self.nl, np.int64), NEK_GET_MULT: (self.nl, np.int32),
+                  NEK_GET_MASK: (self.nl, np.int8), NEK_GET_PERM: (self.size(NEK_SIZE_NPERM), np.int32),
+                  NEK_GET_SEGPTR: (self.size(NEK_SIZE_NSEG) + 1, np.int32),
+                  NEK_GET_SEGFLAG: (self.size(NEK_SIZE_NSEG), np.int8),
+                  NEK_GET_XYZ: ((self.E, 3, n ** 3), np.float64)}
+        shape, dt = shapes[what]
+        out = np.empty(shape, dtype=dt)
+        _check(self._lib.nek_get(self._h, int(what), out.ctypes.data_as(ctypes.c_void_p)), "nek_get")
+        return out
+
+    def set_prec(self, prec):
+        _check(self._lib.nek_set_prec(self._h, PREC_NAMES[prec] if isinstance(prec, str) else int(prec)),
+               "nek_set_prec")
+
+    # -- argument checks (host side, before any kernel sees the pointers)
+    def _vec(self, t, what):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{what}: expected a CUDA tensor")
+        if t.dtype not in (torch.float64, torch.float32):
+            raise TypeError(f"{what}: dtype must be float64 or float32")
+        if t.numel() != self.nl or not t.is_contiguous():
+            raise ValueError(f"{what}: expected a contiguous vector of {self.nl} entries")
+        return NEK_F64 if t.dtype == torch.float64 else NEK_F32
+
+    def new_vector(self, dtype=None):
+        torch = _torch()
+        return torch.empty(self.nl, dtype=dtype or torch.float64, device=self.device)
+
+    # -- operator
+    def ax_local(self, u, w=None):
+        dt = self._vec(u, "u")
+        w = torch_empty_like(u) if w is None else w
+        if self._vec(w, "w") != dt or w.data_ptr() == u.data_ptr():
+            raise ValueError("w must match u's dtype and not alias it")
+        _check(self._lib.nek_ax_local(self._h, u.data_ptr(), w.data_ptr(), dt), "nek_ax_local")
+        return w
+
+    def ax(self, u, w=None):
+        dt = self._vec(u, "u")
+        w = torch_empty_like(u) if w is None else w
+        if self._vec(w, "w") != dt or w.data_ptr() == u.data_ptr():
+            raise ValueError("w must match u's dtype and not alias it")
+        _check(self._lib.nek_ax(self._h, u.data_ptr(), w.data_ptr(), dt), "nek_ax")
+        return w
+
+    def dssum(self, w, mask=True):
+        dt = self._vec(w, "w")
+        _check(self._lib.nek_dssum(self._h, w.data_ptr(), dt, int(bool(mask))), "nek_dssum")
+        return w
+
+    def glsc3(self, a, b):
+        dt = self._vec(a, "a")
+        if self._vec(b, "b") != dt:
+            raise ValueError("a and b must share a dtype")
+        out = ctypes.c_double()
+        _check(self._lib.nek_glsc3(self._h, a.data_ptr(), b.data_ptr(), dt, ctypes.byref(out)), "nek_glsc3")
+        return out.value
+
+    def prof_enable(self, every: int):
+        _check(self._lib.nek_prof_enable(self._h, int(every)), "nek_prof_enable")
+
+    def prof_read(self, kernel: int, reset: bool = True):
+        """(total ms, sampled launches) of kernel 0 (operator) or 1 (gather/update)."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(self._lib.nek_prof_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n), int(reset)),
+               "nek_prof_read")
+        return ms.value, n.value
+
+    def cg_solve(self, f, x0=None, tol=1e-8, maxit=1000, x=None, history=False, raise_on_noconv=False):
+        """Solve A x = M dssum(f).  Returns (x, stats dict, history or None)."""
+        torch = _torch()
+        for t, nm in ((f, "f"), (x0, "x0"), (x, "x")):
+            if t is not None and (self._vec(t, nm) != NEK_F64):
+                raise TypeError(f"{nm}: nek_cg_solve takes float64 vectors")
+        if x is None:
+            x = self.new_vector(torch.float64)
+        hist = np.zeros(int(maxit) + 1) if history else None
+        st = nek_stats()
+        rc = self._lib.nek_cg_solve(self._h, f.data_ptr(), x0.data_ptr() if x0 is not None else None, float(tol),
+                                    int(maxit), x.data_ptr(), ctypes.byref(st),
+                                    hist.ctypes.data_as(ctypes.c_void_p) if history else None)
+        _check(rc, "nek_cg_solve", ok=(NEK_OK,) if raise_on_noconv else (NEK_OK, NEK_NOCONV))
+        d = st.as_dict()
+        if history:
+            hist = hist[:min(int(maxit), max(0, d["iters"])) + 1]
+        return x, d, hist
+
+
+def torch_empty_like(t):
+    return _torch().empty_like(t)

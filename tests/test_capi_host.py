@@ -1,0 +1,128 @@
+"""CPU checks of libnek: every declared symbol is exported, and the host-side
+set-up (GLL rule, D, geometry, numbering, segment maps) matches the FP64
+oracle -- bit for bit on every integer map.  No GPU is touched."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_11065_amd import nek, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("nek.h", "nek_host.h")]
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"\b(nek_\w+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(nek.LIB_PATH):
+        pytest.fail("libnek.so is not built (python -m paper_2405_11065_amd.build)")
+    return ctypes.CDLL(nek.LIB_PATH)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 17
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(nek.EXPORTS) <= set(names)
+
+
+def test_strerror_covers_statuses(lib):
+    lib.nek_strerror.restype = ctypes.c_char_p
+    msgs = {s: lib.nek_strerror(s).decode() for s in range(-7, 2)}
+    assert len(set(msgs.values())) == 9
+    assert lib.nek_strerror(42).decode() == "unknown status"
+
+
+def _i3(nel):
+    return (ctypes.c_int * 3)(*nel)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def host_maps(lib, N, nel):
+    nl = int(np.prod(nel)) * (N + 1) ** 3
+    gid = np.empty(nl, np.int64)
+    mult = np.empty(nl, np.int32)
+    mask = np.empty(nl, np.int8)
+    assert lib.nek_host_numbering(N, _i3(nel), _ptr(gid), _ptr(mult), _ptr(mask)) == 0
+    npm, nsg = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.nek_host_segment_sizes(N, _i3(nel), ctypes.byref(npm), ctypes.byref(nsg)) == 0
+    perm = np.empty(npm.value, np.int32)
+    ptr = np.empty(nsg.value + 1, np.int32)
+    flag = np.empty(nsg.value, np.int8)
+    assert lib.nek_host_segments(N, _i3(nel), _ptr(perm), _ptr(ptr), _ptr(flag)) == 0
+    return gid, mult, mask, perm, ptr, flag
+
+
+@pytest.mark.parametrize("N,nel", [(1, (1, 1, 1)), (2, (3, 1, 2)), (3, (2, 2, 2)), (5, (3, 4, 2)),
+                                   (7, (4, 4, 4)), (9, (2, 3, 2)), (15, (1, 2, 1))])
+def test_host_maps_bit_exact(lib, N, nel):
+    gid, mult, mask, perm, ptr, flag = host_maps(lib, N, nel)
+    ogid, omult, omask = oracle.numbering(N, nel)
+    operm, optr, oflag = oracle.segments(N, nel, ogid, omask)
+    assert np.array_equal(gid, ogid)
+    assert np.array_equal(mult, omult)
+    assert np.array_equal(mask, omask)
+    assert np.array_equal(perm, operm)
+    assert np.array_equal(ptr, optr)
+    assert np.array_equal(flag, oflag)
+
+
+@pytest.mark.parametrize("N", list(range(1, 16)))
+def test_host_gll_and_deriv(lib, N):
+    xi, w = np.empty(N + 1), np.empty(N + 1)
+    D = np.empty((N + 1) ** 2)
+    assert lib.nek_host_gll(N, _ptr(xi), _ptr(w)) == 0
+    assert lib.nek_host_deriv(N, _ptr(D)) == 0
+    oxi, ow = oracle.gll(N)
+    np.testing.assert_allclose(xi, oxi, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(w, ow, rtol=0, atol=1e-14)
+    oD = oracle.deriv(N)
+    assert np.abs(D.reshape(N + 1, N + 1) - oD).max() <= 1e-13 * np.abs(oD).max()
+
+
+@pytest.mark.parametrize("N,nel,perturb", [(3, (2, 2, 2), 0.0), (7, (3, 2, 2), 0.1), (9, (2, 2, 3), 0.1)])
+def test_host_geometry(lib, N, nel, perturb):
+    vtx = synth.box_vertices(nel, hi=(1.0, 1.0, 1.0), perturb=perturb, seed=17)
+    E, n3 = int(np.prod(nel)), (N + 1) ** 3
+    g, B, X = np.empty((E, 6, n3)), np.empty((E, n3)), np.empty((E, 3, n3))
+    assert lib.nek_host_geometry(N, _i3(nel), _ptr(vtx), _ptr(g), _ptr(B), _ptr(X)) == 0
+    og, oB, oX = oracle.geometry(N, nel, vtx, want_X=True)
+    # G's natural scale is its diagonal; off-diagonal entries that vanish on
+    # affine elements are compared against it
+    scale = np.abs(og[:, :3]).max()
+    for q in range(6):
+        assert np.abs(g[:, q] - og[:, q]).max() <= 1e-13 * scale, q
+    assert np.abs(B - oB).max() <= 1e-13 * np.abs(oB).max()
+    assert np.abs(X - oX).max() <= 1e-15
+
+
+def test_host_geometry_rejects_inverted(lib):
+    nel = (2, 2, 2)
+    vtx = synth.box_vertices(nel)
+    vtx[13] = [2.6, 2.6, 2.6]
+    n3 = 4 ** 3
+    g, B = np.empty((8, 6, n3)), np.empty((8, n3))
+    assert lib.nek_host_geometry(3, _i3(nel), _ptr(vtx), _ptr(g), _ptr(B), None) == nek.NEK_E_JACOBIAN
+
+
+def test_host_rejects_bad_arguments(lib):
+    xi = np.empty(20)
+    assert lib.nek_host_gll(0, _ptr(xi), _ptr(xi)) == nek.NEK_E_ARG
+    assert lib.nek_host_gll(16, _ptr(xi), _ptr(xi)) == nek.NEK_E_ARG
+    assert lib.nek_host_numbering(3, _i3((0, 1, 1)), None, None, None) == nek.NEK_E_ARG
