@@ -2,42 +2,54 @@
 // nek_lib.hip.
 //
 // Hot path of one CG iteration (the loop of the paper's Table 1, no
-// preconditioner), two launches:
-//   k_cg_ax     p = beta p + r (add2s1), w_L = A_L p (ax_e: local_grad3,
-//               g1..g6, local_grad3_t), and p.w_L summed over all local
-//               points; its last workgroup forms alpha = rtz / pap.
-//   k_cg_update for every local point: S = sum of the copies of w_L at the
-//               point's global node (dssum), mask, x += alpha p,
-//               r -= alpha S, rtr = glsc3(r, c, r); its last workgroup forms
-//               beta, the residual history and the stopping decision.
+// preconditioner): two launches per iteration.
+//   k_ax<CG>(it)    beta from the previous iteration's rtr, p = beta p + r
+//                   (add2s1), w_L = A_L p (ax_e: local_grad3, g1..g6,
+//                   local_grad3_t), and per-workgroup partials of p.w_L.
+//   k_cg_update(it) alpha = rtz / pap, then for every local point:
+//                   S = sum of the copies of w_L at its global node (dssum),
+//                   mask, x += alpha p, r -= alpha S, and per-workgroup
+//                   partials of glsc3(r, c, r).
 // Because p is continuous and zero on the Dirichlet boundary,
-// glsc3(M dssum(A_L p), c, p) = sum_l p_l (A_L p)_l exactly in real
-// arithmetic, so pap needs no gather and alpha is known right after ax.
+// glsc3(M dssum(A_L p), c, p) = sum_l p_l (A_L p)_l in exact arithmetic, so
+// pap needs no gather and alpha is known right after the operator.
+//
+// Reductions without atomics or fences: a kernel writes one FP64 partial
+// per workgroup with a plain store; every workgroup of the NEXT kernel sums
+// all of them in the same fixed order (so all obtain the identical value),
+// the kernel boundary making the stores visible.  Device-scope fences would
+// write back and invalidate a whole XCD's L2 per workgroup on gfx950.  The
+// CG state is double-buffered by iteration parity; only workgroup 0 writes
+// the slot of the current iteration.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
 namespace nek {
 
-constexpr int UPD_BS = 256;     // block size of the pointwise kernels
+constexpr int UPD_BS = 256;      // block size of the pointwise kernels
 
-// Device-resident CG state.  All scalars of the solve live here so an
-// iteration never waits for the host.
-struct Scal {
-    double rtz;        // glsc3(r, c, r) of the current residual
-    double rtz_prev;
-    double alpha, beta, pap;
-    double hist_den;   // history entry = sqrt(rtz / hist_den)
-    double stop_den;   // stop when sqrt(rtz) / sqrt(stop_den) <= stop_tol
-    double stop_tol;   // <= 0: run to maxit
-    double red[4];     // results of standalone reductions
-    int iter;          // iterations completed in this CG run
-    int maxit;
-    int hist_off;      // history index of iteration 0 of this run
+// CG state entering iteration it, in slot it & 1.
+struct IterState {
+    double rtz;      // glsc3(r, c, r) of the current residual
+    double beta;
+    int iter;        // iterations completed
     int done;
-    int status;        // 0, NEK_E_BREAKDOWN or NEK_E_NONFINITE
-    int conv;          // 1 when stopped by the tolerance (or r == 0)
-    unsigned ctr[4];   // arrival counters of the last-workgroup reductions
+    int status;      // 0, -5 (breakdown) or -6 (non-finite)
+    int conv;        // stopped by the tolerance (or r == 0)
+};
+
+struct Scal {
+    IterState st[2];
+    IterState fin;        // final state, written by k_cg_finish
+    double hist_den;      // history entry = sqrt(rtz / hist_den)
+    double stop_den;      // stop when sqrt(rtz) / sqrt(stop_den) <= stop_tol
+    double stop_tol;      // <= 0: run to maxit
+    double red[4];        // results of standalone reductions
+    int maxit;
+    int hist_off;         // history index of iteration 0 of this run
+    int k2flag[2];        // status of k_cg_update(it) in slot it & 1
+    int done_host;        // set once a run is done; polled by the host
 };
 
 struct Box { int nx, ny, nz; };
@@ -49,18 +61,6 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
     const unsigned X = 8, x = b % X, slot = b / X, q = nb / X, r = nb % X;
     return x < r ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
 }
-
-template <typename GT> __device__ __forceinline__ float g_to_f32(GT v);
-template <> __device__ __forceinline__ float g_to_f32<float>(float v) { return v; }
-template <> __device__ __forceinline__ float g_to_f32<uint16_t>(uint16_t v)
-{
-    return __uint_as_float(((unsigned)v) << 16);
-}
-template <typename T, typename GT> __device__ __forceinline__ T load_g(const GT *p)
-{
-    return (T)g_to_f32<GT>(*p);
-}
-template <> __device__ __forceinline__ double load_g<double, double>(const double *p) { return *p; }
 
 // Deterministic block sum (fixed order); the result is valid in thread 0.
 template <int BS>
@@ -95,29 +95,105 @@ __device__ __forceinline__ double block_sum(double v, double *sbuf)
     }
 }
 
-// Publish this workgroup's partial and report whether it arrived last.
-__device__ __forceinline__ bool arrive_last(unsigned *ctr, double *partials, double v, int *s_flag)
+// Sum of P[0..n) in a fixed order, returned to every thread of the block.
+template <int BS>
+__device__ __forceinline__ double sum_all(const double *__restrict__ P, int n, double *sbuf)
 {
-    if (threadIdx.x == 0) {
-        __hip_atomic_store(&partials[blockIdx.x], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        unsigned prev = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        *s_flag = prev == gridDim.x - 1;
-    }
+    double v = 0.0;
+    for (int q = threadIdx.x; q < n; q += BS) v += P[q];
+    double s = block_sum<BS>(v, sbuf);
+    if (threadIdx.x == 0) sbuf[0] = s;
     __syncthreads();
-    return *s_flag != 0;
+    s = sbuf[0];
+    __syncthreads();
+    return s;
 }
 
-// Sum of all partials in a fixed order, by the last workgroup (thread 0).
+// Start of iteration it: fold the previous update kernel's rtr partials into
+// the state (identically in every workgroup) and decide whether to stop.
+// Workgroup 0, thread 0 publishes the state (and, when done, the host flag).
 template <int BS>
-__device__ __forceinline__ double sum_partials(const double *partials, double *sbuf)
+__device__ __forceinline__ IterState cg_begin(Scal *__restrict__ sc, const double *__restrict__ P2, int nb2,
+                                              int it, double *__restrict__ hist, double *sbuf, bool writer)
 {
-    __threadfence();
-    double v = 0.0;
-    for (unsigned q = threadIdx.x; q < gridDim.x; q += BS)
-        v += __hip_atomic_load(&partials[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return block_sum<BS>(v, sbuf);
+    const IterState prev = sc->st[(it - 1) & 1];
+    IterState cur = prev;
+    if (!prev.done) {
+        if (it == 1) {
+            cur.beta = 0.0;
+            cur.iter = 0;
+        } else {
+            const int f = sc->k2flag[(it - 1) & 1];
+            if (f) {
+                cur.status = f;
+                cur.done = 1;
+            } else {
+                const double rtr = sum_all<BS>(P2, nb2, sbuf);
+                cur.iter = it - 1;
+                cur.rtz = rtr;
+                cur.beta = rtr / prev.rtz;
+                if (writer && hist) hist[sc->hist_off + it - 1] = sqrt(rtr / sc->hist_den);
+                if (!__builtin_isfinite(rtr)) {
+                    cur.status = -6;
+                    cur.done = 1;
+                } else if (rtr == 0.0 || (sc->stop_tol > 0 && sqrt(rtr) / sqrt(sc->stop_den) <= sc->stop_tol)) {
+                    cur.conv = 1;
+                    cur.done = 1;
+                }
+            }
+        }
+        if (!cur.done && cur.iter >= sc->maxit) cur.done = 1;
+    }
+    if (writer) {
+        sc->st[it & 1] = cur;
+        if (cur.done) sc->done_host = 1;
+    }
+    return cur;
 }
+
+// ------------------------------------------------------ geometric factors
+
+// The six factors of one point are stored together ([E][NP^3][6], order
+// G_rr, G_ss, G_tt, G_rs, G_rt, G_st) and fetched with wide loads.
+template <typename GT> struct GLoad;
+template <> struct GLoad<double> {
+    struct Raw { double2 a, b, c; };
+    __device__ static Raw load(const double *p)
+    {
+        const double2 *q = reinterpret_cast<const double2 *>(p);
+        return Raw{q[0], q[1], q[2]};
+    }
+    template <typename T> __device__ static void unpack(const Raw &r, T o[6])
+    {
+        o[0] = r.a.x; o[1] = r.a.y; o[2] = r.b.x; o[3] = r.b.y; o[4] = r.c.x; o[5] = r.c.y;
+    }
+};
+template <> struct GLoad<float> {
+    struct Raw { float2 a, b, c; };
+    __device__ static Raw load(const float *p)
+    {
+        const float2 *q = reinterpret_cast<const float2 *>(p);
+        return Raw{q[0], q[1], q[2]};
+    }
+    template <typename T> __device__ static void unpack(const Raw &r, T o[6])
+    {
+        o[0] = r.a.x; o[1] = r.a.y; o[2] = r.b.x; o[3] = r.b.y; o[4] = r.c.x; o[5] = r.c.y;
+    }
+};
+template <> struct GLoad<uint16_t> {   // BF16 bit patterns, two per 32-bit word
+    struct Raw { uint32_t a, b, c; };
+    __device__ static Raw load(const uint16_t *p)
+    {
+        const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
+        return Raw{q[0], q[1], q[2]};
+    }
+    template <typename T> __device__ static void unpack(const Raw &r, T o[6])
+    {
+        o[0] = __uint_as_float(r.a << 16); o[1] = __uint_as_float(r.a & 0xffff0000u);
+        o[2] = __uint_as_float(r.b << 16); o[3] = __uint_as_float(r.b & 0xffff0000u);
+        o[4] = __uint_as_float(r.c << 16); o[5] = __uint_as_float(r.c & 0xffff0000u);
+    }
+};
 
 // ---------------------------------------------------------------- operator
 
@@ -126,31 +202,41 @@ __device__ __forceinline__ double sum_partials(const double *partials, double *s
 // the t derivative uses the thread's own column in registers.  wr, ws go
 // through LDS for the transposed derivatives, wt stays in registers.  The
 // uniform entries D[k][l] of the t contractions come through the scalar
-// cache.  CG mode fuses p = beta p + r before, and sum p.(A_L p) after.
-template <int NP, int EPW, typename T, typename GT, bool CG>
+// cache.  The six factors of slice k + PD are in flight while slice k is
+// computed.  CG mode fuses p = beta p + r before, and sum p.(A_L p) after.
+template <int NP, int EPW, int PD, typename T, typename GT, bool CG>
 __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T *__restrict__ p,
                                                     T *__restrict__ w, const GT *__restrict__ g,
                                                     const T *__restrict__ D, Scal *__restrict__ sc,
-                                                    double *__restrict__ partials, int E, int ngroups)
+                                                    double *__restrict__ P1, const double *__restrict__ P2,
+                                                    int nb2, int it, double *__restrict__ hist, int E,
+                                                    int ngroups)
 {
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP, BS = EPW * NP2;
+    using GL = GLoad<GT>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *su = reinterpret_cast<T *>(smem_raw);
     T *sr = su + EPW * NP3;
     T *ss = sr + EPW * NP3;
     __shared__ double sbuf[BS];
-    __shared__ int s_flag;
+    __shared__ T sD[NP * NP];
 
-    if (CG && sc->done) return;
     const int tid = threadIdx.x;
+    T beta = 0;
+    bool first = false;
+    if constexpr (CG) {
+        const IterState cur = cg_begin<BS>(sc, P2, nb2, it, hist, sbuf, blockIdx.x == 0 && tid == 0);
+        if (cur.done) return;
+        beta = (T)cur.beta;
+        first = it == 1;
+    }
     const int el = tid / NP2, ij = tid - el * NP2;
     const int i = ij % NP, j = ij / NP;
     T *sue = su + el * NP3, *sre = sr + el * NP3, *sse = ss + el * NP3;
 
-    // FP32: the thread's rows/columns of D live in registers.  FP64 has the
-    // bandwidth slack to read them from LDS instead (no register spills).
+    // FP32: the thread's rows/columns of D live in registers.  FP64 reads
+    // them from LDS instead (no register spills; FP64 has bandwidth slack).
     constexpr bool DREG = sizeof(T) == 4;
-    __shared__ T sD[NP * NP];
     T Dri[DREG ? NP : 1], Dsj[DREG ? NP : 1], DTi[DREG ? NP : 1], DTj[DREG ? NP : 1];
     if constexpr (DREG) {
 #pragma unroll
@@ -167,12 +253,6 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T
 #define NEK_DS(l) (DREG ? Dsj[DREG ? (l) : 0] : sD[j * NP + (l)])
 #define NEK_DTI(l) (DREG ? DTi[DREG ? (l) : 0] : sD[(l) * NP + i])
 #define NEK_DTJ(l) (DREG ? DTj[DREG ? (l) : 0] : sD[(l) * NP + j])
-    T beta = 0;
-    bool first = false;
-    if (CG) {
-        beta = (T)sc->beta;
-        first = sc->iter == 0;
-    }
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int g0 = (int)(((long)lb * ngroups) / gridDim.x);
     const int g1 = (int)(((long)(lb + 1) * ngroups) / gridDim.x);
@@ -183,14 +263,20 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T
         const bool valid = e < E;
         // threads past the last element compute on a copy of element E-1 and
         // store nothing
-        const long base = (valid ? e : (long)E - 1) * NP3 + ij;
+        const long ec = valid ? e : (long)E - 1;
+        const long base = ec * NP3 + ij;
+        const GT *ge = g + (size_t)base * 6;
+        typename GL::Raw gb[PD];
+#pragma unroll
+        for (int s = 0; s < PD; ++s)
+            if (s < NP) gb[s] = GL::load(ge + (size_t)s * NP2 * 6);
         T u[NP];
         __syncthreads();   // LDS of the previous group is free
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             const long idx = base + k * NP2;
             T v;
-            if (CG) {
+            if constexpr (CG) {
                 const T rv = src[idx];
                 v = first ? rv : beta * p[idx] + rv;
                 if (valid) p[idx] = v;
@@ -202,19 +288,11 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T
         }
         __syncthreads();
         T wt[NP];
-        const GT *ge = g + (base - ij) * 6 + ij;
-        // software pipeline over k: the six factors of slice k+1 are in
-        // flight while slice k is computed (bounded register use)
-        T gc[6], gn[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) gc[q] = load_g<T, GT>(ge + q * NP3);
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            if (k + 1 < NP) {
-#pragma unroll
-                for (int q = 0; q < 6; ++q) gn[q] = load_g<T, GT>(ge + q * NP3 + (k + 1) * NP2);
-            }
             __builtin_amdgcn_sched_barrier(0);
+            T gk[6];
+            GL::unpack(gb[k % PD], gk);
             T ur = 0, us = 0, ut = 0;
 #pragma unroll
             for (int l = 0; l < NP; ++l) {
@@ -222,12 +300,11 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T
                 us += NEK_DS(l) * sue[k * NP2 + l * NP + i];
                 ut += D[k * NP + l] * u[l];
             }
-            sre[k * NP2 + ij] = gc[0] * ur + gc[3] * us + gc[4] * ut;
-            sse[k * NP2 + ij] = gc[3] * ur + gc[1] * us + gc[5] * ut;
-            wt[k] = gc[4] * ur + gc[5] * us + gc[2] * ut;
+            sre[k * NP2 + ij] = gk[0] * ur + gk[3] * us + gk[4] * ut;
+            sse[k * NP2 + ij] = gk[3] * ur + gk[1] * us + gk[5] * ut;
+            wt[k] = gk[4] * ur + gk[5] * us + gk[2] * ut;
             __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int q = 0; q < 6; ++q) gc[q] = gn[q];
+            if (k + PD < NP) gb[k % PD] = GL::load(ge + (size_t)(k + PD) * NP2 * 6);
         }
         __syncthreads();
 #pragma unroll
@@ -247,25 +324,9 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T
 #undef NEK_DS
 #undef NEK_DTI
 #undef NEK_DTJ
-
-    if (CG) {
-        double s = block_sum<BS>(pap, sbuf);
-        if (arrive_last(&sc->ctr[0], partials, s, &s_flag)) {
-            double tot = sum_partials<BS>(partials, sbuf);
-            if (tid == 0) {
-                sc->pap = tot;
-                if (!__builtin_isfinite(tot)) {
-                    sc->status = -6;
-                    sc->done = 1;
-                } else if (!(tot > 0)) {
-                    sc->status = -5;
-                    sc->done = 1;
-                } else {
-                    sc->alpha = sc->rtz / tot;
-                }
-                __hip_atomic_store(&sc->ctr[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
+    if constexpr (CG) {
+        const double s = block_sum<BS>(pap, sbuf);
+        if (tid == 0) P1[blockIdx.x] = s;
     }
 }
 
@@ -307,30 +368,45 @@ __device__ __forceinline__ PointInfo<NP> locate(unsigned t, Box b)
 // Sum over the copies of the point's global node, in ascending local index
 // (copies lie in distinct elements; ascending (dz, dy, dx) is ascending e),
 // starting from 0.0 like a serial sum.  With WEIGHT each copy is scaled by
-// c = 1/mult first.
+// c = 1/mult first.  The (up to two) copies per direction are fixed-size
+// register pairs, so no private memory is used.
 template <int NP, typename T, bool WEIGHT>
 __device__ __forceinline__ double gather_copies(const T *__restrict__ w, const PointInfo<NP> &P, Box b)
 {
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = NP - 1;
-    int dxo[2], ixo[2], nxo = 0, dyo[2], jyo[2], nyo = 0, dzo[2], kzo[2], nzo = 0;
-    if (P.i == 0 && P.ex > 0) { dxo[0] = -1; ixo[0] = N; dxo[1] = 0; ixo[1] = 0; nxo = 2; }
-    else if (P.i == N && P.ex < b.nx - 1) { dxo[0] = 0; ixo[0] = N; dxo[1] = 1; ixo[1] = 0; nxo = 2; }
-    else { dxo[0] = 0; ixo[0] = P.i; nxo = 1; }
-    if (P.j == 0 && P.ey > 0) { dyo[0] = -1; jyo[0] = N; dyo[1] = 0; jyo[1] = 0; nyo = 2; }
-    else if (P.j == N && P.ey < b.ny - 1) { dyo[0] = 0; jyo[0] = N; dyo[1] = 1; jyo[1] = 0; nyo = 2; }
-    else { dyo[0] = 0; jyo[0] = P.j; nyo = 1; }
-    if (P.k == 0 && P.ez > 0) { dzo[0] = -1; kzo[0] = N; dzo[1] = 0; kzo[1] = 0; nzo = 2; }
-    else if (P.k == N && P.ez < b.nz - 1) { dzo[0] = 0; kzo[0] = N; dzo[1] = 1; kzo[1] = 0; nzo = 2; }
-    else { dzo[0] = 0; kzo[0] = P.k; nzo = 1; }
-    const double c = WEIGHT ? 1.0 / (double)(nxo * nyo * nzo) : 1.0;
+    // per direction: number of copies n?, element offsets d?0 < d?1, local coordinates c?0, c?1
+    int nx = 1, dx0 = 0, dx1 = 0, cx0 = P.i, cx1 = 0;
+    if (P.i == 0 && P.ex > 0) { nx = 2; dx0 = -1; cx0 = N; dx1 = 0; cx1 = 0; }
+    else if (P.i == N && P.ex < b.nx - 1) { nx = 2; dx0 = 0; cx0 = N; dx1 = 1; cx1 = 0; }
+    int ny = 1, dy0 = 0, dy1 = 0, cy0 = P.j, cy1 = 0;
+    if (P.j == 0 && P.ey > 0) { ny = 2; dy0 = -1; cy0 = N; dy1 = 0; cy1 = 0; }
+    else if (P.j == N && P.ey < b.ny - 1) { ny = 2; dy0 = 0; cy0 = N; dy1 = 1; cy1 = 0; }
+    int nz = 1, dz0 = 0, dz1 = 0, cz0 = P.k, cz1 = 0;
+    if (P.k == 0 && P.ez > 0) { nz = 2; dz0 = -1; cz0 = N; dz1 = 0; cz1 = 0; }
+    else if (P.k == N && P.ez < b.nz - 1) { nz = 2; dz0 = 0; cz0 = N; dz1 = 1; cz1 = 0; }
+    const double c = WEIGHT ? 1.0 / (double)(nx * ny * nz) : 1.0;
+    const long sy = b.nx, sz = (long)b.nx * b.ny;
     double s = 0.0;
-    for (int cz = 0; cz < nzo; ++cz)
-        for (int cy = 0; cy < nyo; ++cy)
-            for (int cx = 0; cx < nxo; ++cx) {
-                const long ee = P.e + dxo[cx] + (long)b.nx * (dyo[cy] + (long)b.ny * dzo[cz]);
-                const double v = (double)w[ee * NP3 + ixo[cx] + NP * jyo[cy] + NP2 * kzo[cz]];
+#pragma unroll
+    for (int az = 0; az < 2; ++az) {
+        if (az >= nz) break;
+        const long oz = (az ? dz1 : dz0) * sz;
+        const int kz = az ? cz1 : cz0;
+#pragma unroll
+        for (int ay = 0; ay < 2; ++ay) {
+            if (ay >= ny) break;
+            const long oy = (ay ? dy1 : dy0) * sy;
+            const int jy = ay ? cy1 : cy0;
+#pragma unroll
+            for (int ax = 0; ax < 2; ++ax) {
+                if (ax >= nx) break;
+                const long ee = P.e + (ax ? dx1 : dx0) + oy + oz;
+                const int ix = ax ? cx1 : cx0;
+                const double v = (double)w[ee * NP3 + ix + NP * jy + NP2 * kz];
                 s += WEIGHT ? c * v : v;
             }
+        }
+    }
     return s;
 }
 
@@ -340,8 +416,10 @@ template <typename T, typename XT> struct UpdArgs {
     T *r;
     const T *w;        // A_L p, unassembled
     Scal *sc;
-    double *partials;
-    double *hist;
+    const double *P1;  // pAp partials of k_ax(it)
+    double *P2;        // rtr partials written here
+    int nb1;
+    int it;
     Box box;
     unsigned nl;
 };
@@ -350,9 +428,15 @@ template <int NP, typename T, typename XT>
 __global__ __launch_bounds__(UPD_BS) void k_cg_update(UpdArgs<T, XT> a)
 {
     __shared__ double sbuf[UPD_BS];
-    __shared__ int s_flag;
-    if (a.sc->done) return;
-    const double alpha = a.sc->alpha;
+    const IterState cur = a.sc->st[a.it & 1];
+    if (cur.done) return;
+    const double pap = sum_all<UPD_BS>(a.P1, a.nb1, sbuf);
+    const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+    if (!__builtin_isfinite(pap) || !(pap > 0)) {
+        if (writer) a.sc->k2flag[a.it & 1] = __builtin_isfinite(pap) ? -5 : -6;
+        return;
+    }
+    const double alpha = cur.rtz / pap;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const unsigned t0 = (unsigned)(((unsigned long)lb * a.nl) / gridDim.x);
     const unsigned t1 = (unsigned)(((unsigned long)(lb + 1) * a.nl) / gridDim.x);
@@ -367,28 +451,53 @@ __global__ __launch_bounds__(UPD_BS) void k_cg_update(UpdArgs<T, XT> a)
         part += ((double)rn * (double)rn) / (double)P.mult;
     }
     const double s = block_sum<UPD_BS>(part, sbuf);
-    if (arrive_last(&a.sc->ctr[1], a.partials, s, &s_flag)) {
-        const double rtr = sum_partials<UPD_BS>(a.partials, sbuf);
-        if (threadIdx.x == 0) {
-            Scal *sc = a.sc;
-            const int it = sc->iter + 1;
-            sc->iter = it;
-            if (a.hist) a.hist[sc->hist_off + it] = sqrt(rtr / sc->hist_den);
-            sc->rtz_prev = sc->rtz;
-            sc->rtz = rtr;
-            sc->beta = rtr / sc->rtz_prev;
-            if (!__builtin_isfinite(rtr)) {
-                sc->status = -6;
-                sc->done = 1;
-            } else if (rtr == 0.0 || (sc->stop_tol > 0 && sqrt(rtr) / sqrt(sc->stop_den) <= sc->stop_tol)) {
-                sc->conv = 1;
-                sc->done = 1;
-            } else if (it >= sc->maxit) {
-                sc->done = 1;
-            }
-            __hip_atomic_store(&sc->ctr[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+    if (threadIdx.x == 0) a.P2[blockIdx.x] = s;
+    if (writer) a.sc->k2flag[a.it & 1] = 0;
+}
+
+// End of a CG run: fold the last update's partials and publish the final
+// state (one workgroup).
+__global__ __launch_bounds__(UPD_BS) void k_cg_finish(Scal *__restrict__ sc, const double *__restrict__ P2, int nb2,
+                                                      int it, double *__restrict__ hist)
+{
+    __shared__ double sbuf[UPD_BS];
+    const IterState cur = cg_begin<UPD_BS>(sc, P2, nb2, it, hist, sbuf, threadIdx.x == 0);
+    if (threadIdx.x == 0) sc->fin = cur;
+}
+
+// Start of a CG run: rtz = red[rslot]; stop and history denominators; the
+// initial residual test.
+__global__ void k_cg_start(Scal *sc, double *hist, int rslot, int hist_off, double stop_tol, int maxit,
+                           int stop_on_initial)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double bb = sc->red[0];
+    const double rtz = sc->red[rslot];
+    IterState s{};
+    s.rtz = rtz;
+    s.beta = 0.0;
+    s.iter = 0;
+    sc->hist_den = bb;
+    sc->stop_den = stop_on_initial ? rtz : bb;
+    sc->stop_tol = stop_tol;
+    sc->maxit = maxit;
+    sc->hist_off = hist_off;
+    sc->k2flag[0] = sc->k2flag[1] = 0;
+    if (hist) hist[hist_off] = bb > 0 ? sqrt(rtz / bb) : 0.0;
+    if (!__builtin_isfinite(bb) || !__builtin_isfinite(rtz)) {
+        s.status = -6;
+        s.done = 1;
+    } else if (bb == 0.0 || rtz == 0.0 ||
+               (!stop_on_initial && stop_tol > 0 && sqrt(rtz) / sqrt(sc->stop_den) <= stop_tol)) {
+        s.conv = 1;
+        s.done = 1;
+    } else if (maxit <= 0) {
+        s.done = 1;
     }
+    sc->st[0] = s;
+    sc->st[1] = s;
+    sc->fin = s;
+    sc->done_host = s.done;
 }
 
 // out = M o sum over copies of (c o) in: the right-hand side b = M dssum(f)
@@ -405,91 +514,76 @@ __global__ __launch_bounds__(UPD_BS) void k_gather(const T *__restrict__ in, T *
     }
 }
 
-// r = b - M dssum(w) (FP64) and red[slot] = glsc3(r, c, r).
+// Standalone reductions write one partial per workgroup; k_red_final sums
+// them in a fixed order into red[slot].
+__global__ __launch_bounds__(UPD_BS) void k_red_final(const double *__restrict__ P, int n, Scal *sc, int slot)
+{
+    __shared__ double sbuf[UPD_BS];
+    const double s = sum_all<UPD_BS>(P, n, sbuf);
+    if (threadIdx.x == 0) sc->red[slot] = s;
+}
+
+// r = b - M dssum(w) (FP64); partials of glsc3(r, c, r).
 template <int NP>
 __global__ __launch_bounds__(UPD_BS) void k_resid(const double *__restrict__ b, const double *__restrict__ w,
-                                                  double *__restrict__ r, Scal *sc, double *partials, int slot,
-                                                  Box box, unsigned nl)
+                                                  double *__restrict__ r, double *__restrict__ P, Box box,
+                                                  unsigned nl)
 {
     __shared__ double sbuf[UPD_BS];
-    __shared__ int s_flag;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const unsigned t0 = (unsigned)(((unsigned long)lb * nl) / gridDim.x);
     const unsigned t1 = (unsigned)(((unsigned long)(lb + 1) * nl) / gridDim.x);
     double part = 0.0;
     for (unsigned t = t0 + threadIdx.x; t < t1; t += UPD_BS) {
-        const PointInfo<NP> P = locate<NP>(t, box);
+        const PointInfo<NP> Pt = locate<NP>(t, box);
         double v = 0.0;
-        if (!P.masked) v = b[t] - gather_copies<NP, double, false>(w, P, box);
+        if (!Pt.masked) v = b[t] - gather_copies<NP, double, false>(w, Pt, box);
         r[t] = v;
-        part += (v * v) / (double)P.mult;
+        part += (v * v) / (double)Pt.mult;
     }
     const double s = block_sum<UPD_BS>(part, sbuf);
-    if (arrive_last(&sc->ctr[2], partials, s, &s_flag)) {
-        const double tot = sum_partials<UPD_BS>(partials, sbuf);
-        if (threadIdx.x == 0) {
-            sc->red[slot] = tot;
-            __hip_atomic_store(&sc->ctr[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    if (threadIdx.x == 0) P[blockIdx.x] = s;
 }
 
-// red[slot] = sum_l a_l c_l b_l with c = 1/mult (glsc3).
+// Partials of sum_l a_l c_l b_l with c = 1/mult (glsc3).
 template <int NP, typename TA, typename TB>
-__global__ __launch_bounds__(UPD_BS) void k_glsc3(const TA *__restrict__ a, const TB *__restrict__ bv, Scal *sc,
-                                                  double *partials, int slot, Box box, unsigned nl)
+__global__ __launch_bounds__(UPD_BS) void k_glsc3(const TA *__restrict__ a, const TB *__restrict__ bv,
+                                                  double *__restrict__ P, Box box, unsigned nl)
 {
     __shared__ double sbuf[UPD_BS];
-    __shared__ int s_flag;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const unsigned t0 = (unsigned)(((unsigned long)lb * nl) / gridDim.x);
     const unsigned t1 = (unsigned)(((unsigned long)(lb + 1) * nl) / gridDim.x);
     double part = 0.0;
     for (unsigned t = t0 + threadIdx.x; t < t1; t += UPD_BS) {
-        const PointInfo<NP> P = locate<NP>(t, box);
-        part += ((double)a[t] * (double)bv[t]) / (double)P.mult;
+        const PointInfo<NP> Pt = locate<NP>(t, box);
+        part += ((double)a[t] * (double)bv[t]) / (double)Pt.mult;
     }
     const double s = block_sum<UPD_BS>(part, sbuf);
-    if (arrive_last(&sc->ctr[2], partials, s, &s_flag)) {
-        const double tot = sum_partials<UPD_BS>(partials, sbuf);
-        if (threadIdx.x == 0) {
-            sc->red[slot] = tot;
-            __hip_atomic_store(&sc->ctr[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    if (threadIdx.x == 0) P[blockIdx.x] = s;
 }
 
-// Start of a CG run: rtz = red[rslot]; stop and history denominators; the
-// initial residual test.
-__global__ void k_cg_start(Scal *sc, double *hist, int rslot, int hist_off, double stop_tol, int maxit,
-                           int stop_on_initial)
+// r32 = (float) r64, d = 0, and partials of glsc3(r32, c, r32): start of an
+// inner (FP32-operator) solve of the refinement loop.
+template <int NP>
+__global__ __launch_bounds__(UPD_BS) void k_inner_start(const double *__restrict__ r64, float *__restrict__ r32,
+                                                        double *__restrict__ d, double *__restrict__ P, Box box,
+                                                        unsigned nl)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double bb = sc->red[0];
-    const double rtz = sc->red[rslot];
-    sc->rtz = rtz;
-    sc->rtz_prev = 1.0;
-    sc->alpha = sc->beta = sc->pap = 0.0;
-    sc->hist_den = bb;
-    sc->stop_den = stop_on_initial ? rtz : bb;
-    sc->stop_tol = stop_tol;
-    sc->iter = 0;
-    sc->maxit = maxit;
-    sc->hist_off = hist_off;
-    sc->status = 0;
-    sc->conv = 0;
-    sc->done = 0;
-    if (hist) hist[hist_off] = bb > 0 ? sqrt(rtz / bb) : 0.0;
-    if (!__builtin_isfinite(bb) || !__builtin_isfinite(rtz)) {
-        sc->status = -6;
-        sc->done = 1;
-    } else if (bb == 0.0 || rtz == 0.0 ||
-               (stop_tol > 0 && sqrt(rtz) / sqrt(sc->stop_den) <= stop_tol && !stop_on_initial)) {
-        sc->conv = 1;
-        sc->done = 1;
-    } else if (maxit <= 0) {
-        sc->done = 1;
+    __shared__ double sbuf[UPD_BS];
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned t0 = (unsigned)(((unsigned long)lb * nl) / gridDim.x);
+    const unsigned t1 = (unsigned)(((unsigned long)(lb + 1) * nl) / gridDim.x);
+    double part = 0.0;
+    for (unsigned t = t0 + threadIdx.x; t < t1; t += UPD_BS) {
+        const PointInfo<NP> Pt = locate<NP>(t, box);
+        const float v = (float)r64[t];
+        r32[t] = v;
+        d[t] = 0.0;
+        part += ((double)v * (double)v) / (double)Pt.mult;
     }
+    const double s = block_sum<UPD_BS>(part, sbuf);
+    if (threadIdx.x == 0) P[blockIdx.x] = s;
 }
 
 // Standalone sorted-segment dssum: one thread per segment, copies summed in
@@ -549,36 +643,6 @@ __global__ void k_fill(T *__restrict__ p, T v, unsigned long n)
 {
     for (unsigned long t = blockIdx.x * (unsigned long)blockDim.x + threadIdx.x; t < n; t += (unsigned long)gridDim.x * blockDim.x)
         p[t] = v;
-}
-
-// r32 = (float) r64, d = 0 and red[slot] = glsc3(r32, c, r32): start of an
-// inner (FP32-operator) solve of the refinement loop.
-template <int NP>
-__global__ __launch_bounds__(UPD_BS) void k_inner_start(const double *__restrict__ r64, float *__restrict__ r32,
-                                                        double *__restrict__ d, Scal *sc, double *partials, int slot,
-                                                        Box box, unsigned nl)
-{
-    __shared__ double sbuf[UPD_BS];
-    __shared__ int s_flag;
-    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
-    const unsigned t0 = (unsigned)(((unsigned long)lb * nl) / gridDim.x);
-    const unsigned t1 = (unsigned)(((unsigned long)(lb + 1) * nl) / gridDim.x);
-    double part = 0.0;
-    for (unsigned t = t0 + threadIdx.x; t < t1; t += UPD_BS) {
-        const PointInfo<NP> P = locate<NP>(t, box);
-        const float v = (float)r64[t];
-        r32[t] = v;
-        d[t] = 0.0;
-        part += ((double)v * (double)v) / (double)P.mult;
-    }
-    const double s = block_sum<UPD_BS>(part, sbuf);
-    if (arrive_last(&sc->ctr[2], partials, s, &s_flag)) {
-        const double tot = sum_partials<UPD_BS>(partials, sbuf);
-        if (threadIdx.x == 0) {
-            sc->red[slot] = tot;
-            __hip_atomic_store(&sc->ctr[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
 }
 
 // x += d (FP64).

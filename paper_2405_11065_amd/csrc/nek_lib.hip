@@ -19,7 +19,7 @@ using namespace nek;
 namespace {
 
 constexpr int MAX_NP = 16;        // N <= 15
-constexpr int MAX_RED_BLOCKS = 2048;
+constexpr int MAXB = 2048;        // cap on workgroups of any reducing kernel
 constexpr int CHUNK_ITERS = 16;   // CG iterations enqueued between flag polls
 
 // Elements per workgroup of the operator kernel for each NP = N+1, chosen so
@@ -31,23 +31,27 @@ constexpr int epw_for(int NP)
          : NP == 8 ? 4 : NP == 9 ? 4 : NP == 10 ? 3 : NP == 11 ? 2 : NP == 12 ? 2 : 1;
 }
 
-#define NEK_NP_SWITCH(np, ...)                                  \
+// Slices of geometric factors in flight per thread (register budget:
+// 12 / 6 / 3 VGPRs per slice for FP64 / FP32 / BF16 storage).
+template <typename GT> constexpr int pd_for() { return sizeof(GT) == 8 ? 2 : sizeof(GT) == 4 ? 4 : 6; }
+
+#define NEK_NP_SWITCH(np, ...)                                   \
     switch (np) {                                                \
-    case 2: { constexpr int NP = 2; __VA_ARGS__; } break;               \
-    case 3: { constexpr int NP = 3; __VA_ARGS__; } break;               \
-    case 4: { constexpr int NP = 4; __VA_ARGS__; } break;               \
-    case 5: { constexpr int NP = 5; __VA_ARGS__; } break;               \
-    case 6: { constexpr int NP = 6; __VA_ARGS__; } break;               \
-    case 7: { constexpr int NP = 7; __VA_ARGS__; } break;               \
-    case 8: { constexpr int NP = 8; __VA_ARGS__; } break;               \
-    case 9: { constexpr int NP = 9; __VA_ARGS__; } break;               \
-    case 10: { constexpr int NP = 10; __VA_ARGS__; } break;             \
-    case 11: { constexpr int NP = 11; __VA_ARGS__; } break;             \
-    case 12: { constexpr int NP = 12; __VA_ARGS__; } break;             \
-    case 13: { constexpr int NP = 13; __VA_ARGS__; } break;             \
-    case 14: { constexpr int NP = 14; __VA_ARGS__; } break;             \
-    case 15: { constexpr int NP = 15; __VA_ARGS__; } break;             \
-    case 16: { constexpr int NP = 16; __VA_ARGS__; } break;             \
+    case 2: { constexpr int NP = 2; __VA_ARGS__; } break;        \
+    case 3: { constexpr int NP = 3; __VA_ARGS__; } break;        \
+    case 4: { constexpr int NP = 4; __VA_ARGS__; } break;        \
+    case 5: { constexpr int NP = 5; __VA_ARGS__; } break;        \
+    case 6: { constexpr int NP = 6; __VA_ARGS__; } break;        \
+    case 7: { constexpr int NP = 7; __VA_ARGS__; } break;        \
+    case 8: { constexpr int NP = 8; __VA_ARGS__; } break;        \
+    case 9: { constexpr int NP = 9; __VA_ARGS__; } break;        \
+    case 10: { constexpr int NP = 10; __VA_ARGS__; } break;      \
+    case 11: { constexpr int NP = 11; __VA_ARGS__; } break;      \
+    case 12: { constexpr int NP = 12; __VA_ARGS__; } break;      \
+    case 13: { constexpr int NP = 13; __VA_ARGS__; } break;      \
+    case 14: { constexpr int NP = 14; __VA_ARGS__; } break;      \
+    case 15: { constexpr int NP = 15; __VA_ARGS__; } break;      \
+    case 16: { constexpr int NP = 16; __VA_ARGS__; } break;      \
     default: return NEK_E_ARG;                                   \
     }
 
@@ -99,7 +103,7 @@ struct nek_ctx {
 
     std::vector<double> xi, w, D, vtx;
 
-    // device data
+    // device data; g* are stored per point: [E][NP^3][6]
     double *D64 = nullptr;
     float *D32 = nullptr;
     double *g64 = nullptr;
@@ -109,7 +113,7 @@ struct nek_ctx {
     int32_t *perm = nullptr, *segptr = nullptr;
     int8_t *segflag = nullptr;
     Scal *sc = nullptr;
-    double *partials = nullptr;
+    double *partials = nullptr;   // 3 regions of MAXB: operator, update, other
     double *hist = nullptr;
     long hist_cap = 0;
     // work vectors
@@ -124,6 +128,10 @@ struct nek_ctx {
     std::vector<int> prof_pending;     // event triples awaiting resolution
     double prof_ms[2] = {0, 0};
     long prof_n[2] = {0, 0};
+
+    double *P1() { return partials; }
+    double *P2() { return partials + MAXB; }
+    double *P3() { return partials + 2 * MAXB; }
 };
 
 namespace {
@@ -131,7 +139,7 @@ namespace {
 unsigned red_grid(const nek_ctx *c)
 {
     long want = (c->nl + UPD_BS - 1) / UPD_BS;
-    long cap = std::min<long>(MAX_RED_BLOCKS, 8L * num_cu());
+    long cap = std::min<long>(MAXB / 2, 4L * num_cu());
     return (unsigned)std::max<long>(1, std::min(want, cap));
 }
 
@@ -140,30 +148,30 @@ template <int NP> int ax_groups(const nek_ctx *c) { return (int)((c->E + epw_for
 template <int NP> unsigned ax_grid(const nek_ctx *c)
 {
     long want = ax_groups<NP>(c);
-    long cap = std::min<long>(MAX_RED_BLOCKS, 16L * num_cu());
+    long cap = std::min<long>(MAXB, 8L * num_cu());
     return (unsigned)std::max<long>(1, std::min(want, cap));
 }
 
 template <int NP, typename T, typename GT, bool CG>
-int launch_ax(nek_ctx *c, const T *src, T *p, T *w, const GT *g, const T *D)
+int launch_ax(nek_ctx *c, const T *src, T *p, T *w, const GT *g, const T *D, int it)
 {
     constexpr int EPW = epw_for(NP);
+    constexpr int PD = pd_for<GT>();
     constexpr int BS = EPW * NP * NP;
     const size_t shm = 3ul * EPW * NP * NP * NP * sizeof(T);
     static bool attr_done = false;
     if (!attr_done) {
         if (shm > 65536)
-            HIP_TRY(hipFuncSetAttribute((const void *)k_ax<NP, EPW, T, GT, CG>,
+            HIP_TRY(hipFuncSetAttribute((const void *)k_ax<NP, EPW, PD, T, GT, CG>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
         attr_done = true;
     }
-    hipLaunchKernelGGL((k_ax<NP, EPW, T, GT, CG>), dim3(ax_grid<NP>(c)), dim3(BS), shm, c->stream, src, p, w, g, D,
-                       c->sc, c->partials, (int)c->E, ax_groups<NP>(c));
+    hipLaunchKernelGGL((k_ax<NP, EPW, PD, T, GT, CG>), dim3(ax_grid<NP>(c)), dim3(BS), shm, c->stream, src, p, w, g,
+                       D, c->sc, c->P1(), c->P2(), (int)red_grid(c), it, c->hist, (int)c->E, ax_groups<NP>(c));
     HIP_TRY(hipGetLastError());
     return NEK_OK;
 }
 
-// One CG iteration: operator + pAp, then gather/update + rtr.
 int prof_take(nek_ctx *c)
 {
     // index of a free event triple, creating one when the pool is exhausted
@@ -196,20 +204,21 @@ int prof_resolve(nek_ctx *c)
     return NEK_OK;
 }
 
-// One CG iteration: operator + pAp, then gather/update + rtr.  When sampled
-// timing is on, every prof_every-th iteration is bracketed by events.
+// CG iteration it (1-based): operator + pAp partials, then gather/update +
+// rtr partials.  When sampled timing is on, every prof_every-th iteration is
+// bracketed by events.
 template <int NP, typename T, typename GT, typename XT>
-int launch_cg_iter(nek_ctx *c, XT *x, T *r, T *p, T *w, const GT *g, const T *D)
+int launch_cg_iter(nek_ctx *c, int it, XT *x, T *r, T *p, T *w, const GT *g, const T *D)
 {
     int slot = -1;
     if (c->prof_every > 0 && (c->prof_tick++ % c->prof_every) == 0) {
         if ((slot = prof_take(c)) < 0) return NEK_E_HIP;
         HIP_TRY(hipEventRecord(c->prof_pool[3 * slot], c->stream));
     }
-    int rc = launch_ax<NP, T, GT, true>(c, r, p, w, g, D);
+    int rc = launch_ax<NP, T, GT, true>(c, r, p, w, g, D, it);
     if (rc) return rc;
     if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 1], c->stream));
-    UpdArgs<T, XT> u{x, p, r, w, c->sc, c->partials, c->hist, c->box, (unsigned)c->nl};
+    UpdArgs<T, XT> u{x, p, r, w, c->sc, c->P1(), c->P2(), (int)ax_grid<NP>(c), it, c->box, (unsigned)c->nl};
     hipLaunchKernelGGL((k_cg_update<NP, T, XT>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, u);
     HIP_TRY(hipGetLastError());
     if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 2], c->stream));
@@ -250,20 +259,25 @@ template <typename T> int fill(nek_ctx *c, T *p, T v, unsigned long n)
     return NEK_OK;
 }
 
+int red_final(nek_ctx *c, int slot)
+{
+    hipLaunchKernelGGL(k_red_final, dim3(1), dim3(UPD_BS), 0, c->stream, c->P3(), (int)red_grid(c), c->sc, slot);
+    HIP_TRY(hipGetLastError());
+    return NEK_OK;
+}
+
 int glsc3_to_slot(nek_ctx *c, const void *a, const void *b, int dtype, int slot)
 {
     NEK_NP_SWITCH(c->NP, {
         if (dtype == NEK_F64)
             hipLaunchKernelGGL((k_glsc3<NP, double, double>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream,
-                               (const double *)a, (const double *)b, c->sc, c->partials, slot, c->box,
-                               (unsigned)c->nl);
+                               (const double *)a, (const double *)b, c->P3(), c->box, (unsigned)c->nl);
         else
             hipLaunchKernelGGL((k_glsc3<NP, float, float>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream,
-                               (const float *)a, (const float *)b, c->sc, c->partials, slot, c->box,
-                               (unsigned)c->nl);
+                               (const float *)a, (const float *)b, c->P3(), c->box, (unsigned)c->nl);
     });
     HIP_TRY(hipGetLastError());
-    return NEK_OK;
+    return red_final(c, slot);
 }
 
 template <typename T> int gather_launch(nek_ctx *c, const T *in, T *out, bool weighted)
@@ -284,22 +298,23 @@ int ax_local_launch(nek_ctx *c, const void *u, void *w, int dtype, int prec)
 {
     NEK_NP_SWITCH(c->NP, {
         if (dtype == NEK_F64)
-            return launch_ax<NP, double, double, false>(c, (const double *)u, nullptr, (double *)w, c->g64, c->D64);
+            return launch_ax<NP, double, double, false>(c, (const double *)u, nullptr, (double *)w, c->g64, c->D64, 0);
         if (prec == NEK_PREC_BF16G)
-            return launch_ax<NP, float, uint16_t, false>(c, (const float *)u, nullptr, (float *)w, c->g16, c->D32);
-        return launch_ax<NP, float, float, false>(c, (const float *)u, nullptr, (float *)w, c->g32, c->D32);
+            return launch_ax<NP, float, uint16_t, false>(c, (const float *)u, nullptr, (float *)w, c->g16, c->D32, 0);
+        return launch_ax<NP, float, float, false>(c, (const float *)u, nullptr, (float *)w, c->g32, c->D32, 0);
     });
     return NEK_OK;
 }
 
+// r = b - M dssum(w) and red[slot] = glsc3(r, c, r)
 int resid_launch(nek_ctx *c, const double *b, const double *w, double *r, int slot)
 {
     NEK_NP_SWITCH(c->NP, {
-        hipLaunchKernelGGL((k_resid<NP>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, b, w, r, c->sc,
-                           c->partials, slot, c->box, (unsigned)c->nl);
+        hipLaunchKernelGGL((k_resid<NP>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, b, w, r, c->P3(), c->box,
+                           (unsigned)c->nl);
     });
     HIP_TRY(hipGetLastError());
-    return NEK_OK;
+    return red_final(c, slot);
 }
 
 int start_launch(nek_ctx *c, int rslot, int hist_off, double stop_tol, int maxit, int stop_on_initial)
@@ -317,19 +332,20 @@ int read_scal(nek_ctx *c, Scal &h)
     return NEK_OK;
 }
 
-// Enqueue CG iterations in chunks until the device flags completion or
-// maxit is reached.  The flag of chunk k is read while chunk k+1 runs.
+// Enqueue CG iterations it = 1, 2, ... in chunks until the device reports
+// the run done or maxit iterations are enqueued; the flag of chunk k is read
+// while chunk k+1 runs.  Then the finishing kernel publishes the final state.
 template <typename IterFn> int run_cg(nek_ctx *c, int maxit, IterFn iter)
 {
     int launched = 0, pend = -1, slot = 0;
     while (launched < maxit) {
         const int n = std::min(CHUNK_ITERS, maxit - launched);
         for (int q = 0; q < n; ++q) {
-            int rc = iter();
+            int rc = iter(launched + q + 1);
             if (rc) return rc;
         }
         launched += n;
-        HIP_TRY(hipMemcpyAsync(&c->hflags[slot], &c->sc->done, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(&c->hflags[slot], &c->sc->done_host, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipEventRecord(c->ev[slot], c->stream));
         if (pend >= 0) {
             HIP_TRY(hipEventSynchronize(c->ev[pend]));
@@ -338,6 +354,9 @@ template <typename IterFn> int run_cg(nek_ctx *c, int maxit, IterFn iter)
         pend = slot;
         slot ^= 1;
     }
+    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(UPD_BS), 0, c->stream, c->sc, c->P2(), (int)red_grid(c),
+                       launched + 1, c->hist);
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(c->stream));
     return NEK_OK;
 }
@@ -369,16 +388,18 @@ int cg_prologue(nek_ctx *c, const double *f, const double *x0, double *x, double
 
 int cg_fp64_iterations(nek_ctx *c, double *x, int maxit)
 {
-    return run_cg(c, maxit, [&]() -> int {
-        NEK_NP_SWITCH(c->NP, { return launch_cg_iter<NP, double, double, double>(c, x, c->r64, c->p64, c->w64, c->g64, c->D64); });
+    return run_cg(c, maxit, [&](int it) -> int {
+        NEK_NP_SWITCH(c->NP, {
+            return launch_cg_iter<NP, double, double, double>(c, it, x, c->r64, c->p64, c->w64, c->g64, c->D64);
+        });
         return NEK_OK;
     });
 }
 
-int finish_status(const Scal &h, double tol)
+int finish_status(const IterState &s, double tol)
 {
-    if (h.status) return h.status;
-    if (tol > 0 && !h.conv) return NEK_NOCONV;
+    if (s.status) return s.status;
+    if (tol > 0 && !s.conv) return NEK_NOCONV;
     return NEK_OK;
 }
 
@@ -391,9 +412,9 @@ int solve_fp64(nek_ctx *c, const double *f, const double *x0, double tol, int ma
     if ((rc = cg_fp64_iterations(c, x, maxit))) return rc;
     Scal h;
     if ((rc = read_scal(c, h))) return rc;
-    st->iters = h.iter;
-    st->rel_res = h.hist_den > 0 ? std::sqrt(h.rtz / h.hist_den) : 0.0;
-    return finish_status(h, tol);
+    st->iters = h.fin.iter;
+    st->rel_res = h.hist_den > 0 ? std::sqrt(h.fin.rtz / h.hist_den) : 0.0;
+    return finish_status(h.fin, tol);
 }
 
 // Iterative refinement: FP64 outer residual with FP64 g; inner CG with an
@@ -427,36 +448,40 @@ int solve_mixed(nek_ctx *c, const double *f, const double *x0, double tol, int m
             if ((rc = start_launch(c, 1, total, tol, maxit - total, 0))) return rc;
             if ((rc = cg_fp64_iterations(c, x, maxit - total))) return rc;
             if ((rc = read_scal(c, h))) return rc;
-            st->fp64_iters = h.iter;
-            total += h.iter;
+            st->fp64_iters = h.fin.iter;
+            total += h.fin.iter;
             if ((rc = ax_local_launch(c, x, c->w64, NEK_F64, NEK_PREC_FP64))) return rc;
             if ((rc = resid_launch(c, c->b, c->w64, c->r64, 1))) return rc;
             if ((rc = read_scal(c, h))) return rc;
             rho = std::sqrt(h.red[1]) / std::sqrt(bb);
-            status = h.status ? h.status : (rho <= tol ? NEK_OK : NEK_NOCONV);
+            status = h.fin.status ? h.fin.status : (rho <= tol ? NEK_OK : NEK_NOCONV);
             ++outer;
             break;
         }
         // inner solve of A d = r with the FP32 operator
         NEK_NP_SWITCH(c->NP, {
             hipLaunchKernelGGL((k_inner_start<NP>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, c->r64, c->r32,
-                               c->d64, c->sc, c->partials, 1, c->box, (unsigned)c->nl);
+                               c->d64, c->P3(), c->box, (unsigned)c->nl);
         });
         HIP_TRY(hipGetLastError());
+        if ((rc = red_final(c, 1))) return rc;
         const double tau_k = std::min(0.5, std::max(tau, 0.3 * tol / rho));
         const int cap = std::min(inner_cap, maxit - total);
         if ((rc = start_launch(c, 1, total, tau_k, cap, 1))) return rc;
-        rc = run_cg(c, cap, [&]() -> int {
+        rc = run_cg(c, cap, [&](int it) -> int {
             NEK_NP_SWITCH(c->NP, {
-                if (bf16) return launch_cg_iter<NP, float, uint16_t, double>(c, c->d64, c->r32, c->p32, c->w32, c->g16, c->D32);
-                return launch_cg_iter<NP, float, float, double>(c, c->d64, c->r32, c->p32, c->w32, c->g32, c->D32);
+                if (bf16)
+                    return launch_cg_iter<NP, float, uint16_t, double>(c, it, c->d64, c->r32, c->p32, c->w32, c->g16,
+                                                                       c->D32);
+                return launch_cg_iter<NP, float, float, double>(c, it, c->d64, c->r32, c->p32, c->w32, c->g32,
+                                                                c->D32);
             });
             return NEK_OK;
         });
         if (rc) return rc;
         if ((rc = read_scal(c, h))) return rc;
-        total += h.iter;
-        if (h.status) { status = h.status; break; }
+        total += h.fin.iter;
+        if (h.fin.status) { status = h.fin.status; break; }
         hipLaunchKernelGGL(k_axpy1, dim3(4 * num_cu()), dim3(256), 0, c->stream, x, c->d64, (unsigned long)c->nl);
         HIP_TRY(hipGetLastError());
         // true FP64 residual of the updated x
@@ -472,6 +497,21 @@ int solve_mixed(nek_ctx *c, const double *f, const double *x0, double tol, int m
     st->outer_iters = outer;
     st->rel_res = rho;
     return status;
+}
+
+// [E][6][n3] <-> [E][n3][6]
+void planes_to_points(const double *src, double *dst, long E, long n3)
+{
+    for (long e = 0; e < E; ++e)
+        for (long q = 0; q < n3; ++q)
+            for (int f = 0; f < 6; ++f) dst[(e * n3 + q) * 6 + f] = src[(e * 6 + f) * n3 + q];
+}
+
+void points_to_planes(const double *src, double *dst, long E, long n3)
+{
+    for (long e = 0; e < E; ++e)
+        for (long q = 0; q < n3; ++q)
+            for (int f = 0; f < 6; ++f) dst[(e * 6 + f) * n3 + q] = src[(e * n3 + q) * 6 + f];
 }
 
 }  // namespace
@@ -515,9 +555,11 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
     *out = nullptr;
     for (int d = 0; d < 3; ++d)
         if (mesh->nel[d] < 1) return NEK_E_ARG;
-    const long NP = N + 1;
+    const long NP = N + 1, n3 = NP * NP * NP;
     const long E = (long)mesh->nel[0] * mesh->nel[1] * mesh->nel[2];
-    if (E * NP * NP * NP >= (1L << 31)) return NEK_E_ARG;
+    if (E * n3 >= (1L << 31)) return NEK_E_ARG;
+    if (opts && (opts->prec < NEK_PREC_FP64 || opts->prec > NEK_PREC_BF16G || opts->elts_per_wg != 0))
+        return NEK_E_ARG;
     nek_ctx *c = new (std::nothrow) nek_ctx;
     if (!c) return NEK_E_OOM;
     c->N = N;
@@ -525,12 +567,11 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
     for (int d = 0; d < 3; ++d) c->nel[d] = mesh->nel[d];
     c->box = Box{mesh->nel[0], mesh->nel[1], mesh->nel[2]};
     c->E = E;
-    c->nl = E * NP * NP * NP;
+    c->nl = E * n3;
     c->ng = ((long)mesh->nel[0] * N + 1) * ((long)mesh->nel[1] * N + 1) * ((long)mesh->nel[2] * N + 1);
     c->stream = (hipStream_t)stream;
     if (opts) c->opts = *opts;
     c->prec = c->opts.prec;
-    if (c->prec < NEK_PREC_FP64 || c->prec > NEK_PREC_BF16G) { delete c; return NEK_E_ARG; }
 
     gll_rule(N, c->xi, c->w);
     deriv_matrix(c->xi, c->D);
@@ -541,8 +582,13 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
 
     int rc = NEK_OK;
     auto fail = [&](int code) { nek_free(c); return code; };
-    std::vector<double> hg((size_t)E * 6 * NP * NP * NP), hB((size_t)c->nl);
+    std::vector<double> hg((size_t)E * 6 * n3), hB((size_t)c->nl);
     if (geometry(N, c->nel, c->vtx, c->xi, c->w, c->D, hg.data(), hB.data(), nullptr)) return fail(NEK_E_JACOBIAN);
+    {
+        std::vector<double> pts(hg.size());
+        planes_to_points(hg.data(), pts.data(), E, n3);
+        hg.swap(pts);
+    }
     std::vector<int32_t> perm, segptr;
     std::vector<int8_t> segflag;
     segment_maps(N, c->nel, perm, segptr, segflag);
@@ -552,7 +598,7 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
 
     if (dalloc(c->D64, NP * NP) || dalloc(c->D32, NP * NP) || dalloc(c->g64, hg.size()) || dalloc(c->B, hB.size()) ||
         dalloc(c->perm, perm.size()) || dalloc(c->segptr, segptr.size()) || dalloc(c->segflag, segflag.size()) ||
-        dalloc(c->sc, 1) || dalloc(c->partials, MAX_RED_BLOCKS))
+        dalloc(c->sc, 1) || dalloc(c->partials, 3 * MAXB))
         return fail(NEK_E_OOM);
     if (hipHostMalloc((void **)&c->hflags, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(NEK_E_OOM);
     for (auto &e : c->ev)
@@ -565,7 +611,8 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
         hipMemcpy(c->perm, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->segptr, segptr.data(), segptr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->segflag, segflag.data(), segflag.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(c->sc, 0, sizeof(Scal)) != hipSuccess)
+        hipMemset(c->sc, 0, sizeof(Scal)) != hipSuccess ||
+        hipMemset(c->partials, 0, 3 * MAXB * sizeof(double)) != hipSuccess)
         return fail(NEK_E_HIP);
     if ((rc = ensure_g(c, c->prec))) return fail(rc);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(NEK_E_HIP);
@@ -592,22 +639,27 @@ int nek_get(nek_ctx *c, int what, void *o)
 {
     if (!c || !o) return NEK_E_ARG;
     const size_t NP = c->NP, n3 = NP * NP * NP;
-    auto d2h = [&](const void *src, size_t bytes) -> int {
+    auto d2h = [&](void *dst, const void *src, size_t bytes) -> int {
         if (hipStreamSynchronize(c->stream) != hipSuccess) return NEK_E_HIP;
-        return hipMemcpy(o, src, bytes, hipMemcpyDeviceToHost) == hipSuccess ? NEK_OK : NEK_E_HIP;
+        return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost) == hipSuccess ? NEK_OK : NEK_E_HIP;
     };
     switch (what) {
     case NEK_GET_GLL: std::memcpy(o, c->xi.data(), NP * sizeof(double)); return NEK_OK;
     case NEK_GET_W: std::memcpy(o, c->w.data(), NP * sizeof(double)); return NEK_OK;
     case NEK_GET_D: std::memcpy(o, c->D.data(), NP * NP * sizeof(double)); return NEK_OK;
-    case NEK_GET_G: return d2h(c->g64, (size_t)c->E * 6 * n3 * sizeof(double));
-    case NEK_GET_B: return d2h(c->B, (size_t)c->nl * sizeof(double));
+    case NEK_GET_G: {
+        std::vector<double> pts((size_t)c->E * 6 * n3);
+        int rc = d2h(pts.data(), c->g64, pts.size() * sizeof(double));
+        if (rc == NEK_OK) points_to_planes(pts.data(), (double *)o, c->E, (long)n3);
+        return rc;
+    }
+    case NEK_GET_B: return d2h(o, c->B, (size_t)c->nl * sizeof(double));
     case NEK_GET_GID: numbering(c->N, c->nel, (int64_t *)o, nullptr, nullptr); return NEK_OK;
     case NEK_GET_MULT: numbering(c->N, c->nel, nullptr, (int32_t *)o, nullptr); return NEK_OK;
     case NEK_GET_MASK: numbering(c->N, c->nel, nullptr, nullptr, (int8_t *)o); return NEK_OK;
-    case NEK_GET_PERM: return d2h(c->perm, (size_t)c->nperm * sizeof(int32_t));
-    case NEK_GET_SEGPTR: return d2h(c->segptr, (size_t)(c->nseg + 1) * sizeof(int32_t));
-    case NEK_GET_SEGFLAG: return d2h(c->segflag, (size_t)c->nseg);
+    case NEK_GET_PERM: return d2h(o, c->perm, (size_t)c->nperm * sizeof(int32_t));
+    case NEK_GET_SEGPTR: return d2h(o, c->segptr, (size_t)(c->nseg + 1) * sizeof(int32_t));
+    case NEK_GET_SEGFLAG: return d2h(o, c->segflag, (size_t)c->nseg);
     case NEK_GET_XYZ: {
         std::vector<double> g((size_t)c->E * 6 * n3), B((size_t)c->nl);
         return geometry(c->N, c->nel, c->vtx, c->xi, c->w, c->D, g.data(), B.data(), (double *)o) ? NEK_E_JACOBIAN
