@@ -76,12 +76,41 @@ def cpu_baseline(f, budget_s=15.0):
                       f"({dt:.1f} s), setup excluded"}
 
 
+def profile_sequence(torch, nek, synth):
+    """A short sequence for counter collection (few dispatches)."""
+    ctx = nek.Context(NEL, N, prec="fp32")
+    f = torch.from_numpy(synth.uniform_load(ctx.nl, SEED)).cuda()
+    x = ctx.new_vector()
+    out = {}
+    for prec in ("fp32", "fp64"):
+        ctx.set_prec(prec)
+        _, st, _ = ctx.cg_solve(f, tol=TOL, maxit=40, x=x)
+        out[prec] = st["iters"]
+    for prec, dt in (("fp64", torch.float64), ("fp32", torch.float32), ("bf16g", torch.float32)):
+        ctx.set_prec(prec)
+        u = torch.rand(ctx.nl, dtype=dt, device="cuda")
+        w = torch.empty_like(u)
+        for _ in range(5):
+            ctx.ax(u, w)
+    # calibration: a plain device copy of 256 MiB (read 256 MiB, write 256 MiB)
+    a = torch.empty(1 << 25, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps({"profile_sequence": out, "copy_bytes": a.numel() * 8}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile", action="store_true",
+                    help="short fixed sequence for hardware-counter runs: 40 mixed and 40 FP64 CG iterations, "
+                         "5 nek_ax per precision and a 256 MiB copy for calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -93,6 +122,9 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     nek.load()
     torch.cuda.set_device(0)
+
+    if args.profile:
+        return profile_sequence(torch, nek, synth)
 
     ctx = nek.Context(NEL, N, prec="fp32")
     nl = ctx.nl
