@@ -39,9 +39,10 @@ def ax_dssum_bytes_per_point(sv, sg, sigma):
     return 2 * sv + 6 * sg + sigma * (2 * sv + 4) + 1
 
 
-def cg_operator_bytes_per_point(sv, sg):
-    """Fused add2s1 + operator kernel: r, p read, p, w write, six g factors."""
-    return 4 * sv + 6 * sg
+def cg_operator_bytes_per_point(sv, sg, sx):
+    """Fused CG operator kernel: r, p read, p, w write, six g factors, and the
+    deferred x (or correction) update, read + write of sx-byte entries."""
+    return 4 * sv + 6 * sg + 2 * sx
 
 
 def time_ax_dssum(ctx, torch, dtype, reps=20):
@@ -76,9 +77,15 @@ def cpu_baseline(f, budget_s=15.0):
                       f"({dt:.1f} s), setup excluded"}
 
 
-def profile_sequence(torch, nek, synth):
+def profile_sequence(torch, nek, synth, variants=""):
     """A short sequence for counter collection (few dispatches)."""
     ctx = nek.Context(NEL, N, prec="fp32")
+    chosen = dict(kv.split("=") for kv in variants.split(",") if kv)
+    for prec in ("fp32", "fp64", "bf16g"):
+        if prec in chosen:
+            ctx.set_variant(prec, int(chosen[prec]))
+        else:
+            ctx.tune(prec, iters=10)
     f = torch.from_numpy(synth.uniform_load(ctx.nl, SEED)).cuda()
     x = ctx.new_vector()
     out = {}
@@ -98,8 +105,9 @@ def profile_sequence(torch, nek, synth):
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
+    print(json.dumps({"profile_sequence": out, "copy_bytes": a.numel() * 8,
+                      "variants": {p: ctx.get_variant(p) for p in ("fp32", "fp64", "bf16g")}}), flush=True)
     ctx.close()
-    print(json.dumps({"profile_sequence": out, "copy_bytes": a.numel() * 8}), flush=True)
 
 
 def main():
@@ -111,6 +119,9 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for hardware-counter runs: 40 mixed and 40 FP64 CG iterations, "
                          "5 nek_ax per precision and a 256 MiB copy for calibration")
+    ap.add_argument("--variants", default="",
+                    help="with --profile: kernel configurations to use, e.g. fp32=4,fp64=2,bf16g=5 "
+                         "(default: run the autotuner)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -124,7 +135,7 @@ def main():
     torch.cuda.set_device(0)
 
     if args.profile:
-        return profile_sequence(torch, nek, synth)
+        return profile_sequence(torch, nek, synth, args.variants)
 
     ctx = nek.Context(NEL, N, prec="fp32")
     nl = ctx.nl
@@ -135,6 +146,10 @@ def main():
     def solve():
         _, st, _ = ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
         return st
+
+    # autotuner (part of set-up, untimed): kernel configuration per precision
+    tuned = {prec: ctx.tune(prec, iters=30) for prec in ("fp32", "fp64", "bf16g")}
+    ctx.set_prec("fp32")
 
     # ---- mixed precision (the timed steps)
     for _ in range(args.warmup):
@@ -180,7 +195,7 @@ def main():
         axd[name] = {"us": round(t * 1e6, 2), "GBps": round(b / t / 1e9, 1),
                      "frac_hbm": round(b / t / 1e9 / PEAK_HBM_GBS, 3)}
 
-    bpp = cg_operator_bytes_per_point(4, 4)
+    bpp = cg_operator_bytes_per_point(4, 4, 8)
     ax_avg_s = ax_ms / max(ax_n, 1) / 1e3
     achieved = bpp * nl / ax_avg_s / 1e9 if ax_n else None
     cpu = None if args.no_cpu else cpu_baseline(f_host)
@@ -205,8 +220,9 @@ def main():
         "fp64": {"value": round(nl * it64 / t_fp64 / 1e9, 3), "iters_per_solve": it64 / args.steps,
                  "ms_per_solve": round(t_fp64 / args.steps * 1e3, 3)},
         "speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
+        "tuned_variant": {k: {"best": v[0], "us_per_iter": [round(u, 1) for u in v[1]]} for k, v in tuned.items()},
         "ax_dssum": axd,
-        "roofline": {"bound": "hbm", "kernel": "k_ax<NP=10,EPW=3,f32,f32,CG> (add2s1 + ax_e)",
+        "roofline": {"bound": "hbm", "kernel": f"k_ax<NP=10,f32,f32,CG> variant {tuned['fp32'][0]} (add2s1 + ax_e + x update)",
                      "achieved": round(achieved, 1) if achieved else None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None, "traffic": None,
                      "bytes_per_point": bpp, "avg_us": round(ax_avg_s * 1e6, 2), "sampled_launches": ax_n,

@@ -205,6 +205,25 @@ int nek_cg_solve(nek_ctx *ctx, const double *f, const double *x0, double tol, in
 int nek_prof_enable(nek_ctx *ctx, int every);
 int nek_prof_read(nek_ctx *ctx, int kernel, double *total_ms, int64_t *count, int reset);
 
+/*
+ * Autotuning of the CG kernel pair.  The operator and gather/update kernels
+ * of each order N exist in several configurations (elements per workgroup,
+ * slices of geometric factors in flight).  nek_num_variants returns their
+ * number for the context's N (or a negative status).  nek_tune times
+ * `iters` (>= 2) CG iterations of every configuration on a synthetic SPD
+ * system of the context's mesh at precision prec (nek_prec), after one
+ * warm-up pass each; it fills us_per_iter[v] (may be NULL, else at least
+ * nek_num_variants entries), selects the fastest for later solves at that
+ * precision and returns its index in *best (may be NULL).  It overwrites the
+ * context's work vectors, not caller memory; it synchronises the stream.
+ * nek_set_variant / nek_get_variant set or read the configuration directly
+ * (e.g. from a cache of earlier tuning).
+ */
+int nek_num_variants(const nek_ctx *ctx);
+int nek_tune(nek_ctx *ctx, int prec, int iters, double *us_per_iter, int *best);
+int nek_set_variant(nek_ctx *ctx, int prec, int variant);
+int nek_get_variant(const nek_ctx *ctx, int prec, int *variant);
+
 /* nek_strerror -- static description of a status code. */
 const char *nek_strerror(int status);
 

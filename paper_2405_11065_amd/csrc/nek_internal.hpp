@@ -1,0 +1,188 @@
+// Internal declarations shared by libnek's translation units: the context,
+// launch-configuration rules, and the per-order function table through which
+// the order-independent driver reaches the kernels instantiated for each
+// N + 1 = NP in its own translation unit (nek_npNN.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <type_traits>
+#include <vector>
+
+#include "nek.h"
+#include "nek_kernels.hpp"
+
+namespace nek {
+
+constexpr int MAX_NP = 16;        // N <= 15
+constexpr int MAXB = 2048;        // cap on workgroups of any reducing kernel
+constexpr int CHUNK_ITERS = 16;   // CG iterations enqueued between flag polls
+
+#define HIP_TRY(expr)                                            \
+    do {                                                         \
+        if ((expr) != hipSuccess) return NEK_E_HIP;              \
+    } while (0)
+
+// Elements per workgroup of the operator kernel for each NP = N+1, chosen so
+// EPW*NP^2 fills whole 64-lane waves where possible and the FP64 LDS
+// footprint 3*EPW*NP^3*8 stays within 160 KB.
+constexpr int epw_for(int NP)
+{
+    return NP == 2 ? 16 : NP == 3 ? 7 : NP == 4 ? 8 : NP == 5 ? 5 : NP == 6 ? 7 : NP == 7 ? 9
+         : NP == 8 ? 4 : NP == 9 ? 4 : NP == 10 ? 3 : NP == 11 ? 2 : NP == 12 ? 2 : 1;
+}
+
+// Slices of geometric factors in flight per thread (register budget:
+// 12 / 6 / 3 VGPRs per slice for FP64 / FP32 / BF16 storage).
+template <typename GT> constexpr int pd_for() { return sizeof(GT) == 8 ? 2 : sizeof(GT) == 4 ? 4 : 6; }
+template <typename GT> constexpr int pd_alt() { return sizeof(GT) == 8 ? 1 : sizeof(GT) == 4 ? 2 : 3; }
+
+// Run-time configurations of the CG kernel pair (the autotuner's search
+// space): variant v = 2 * ke + kp picks the ke-th EPW option and the default
+// (kp = 0) or alternative (kp = 1) prefetch depth.  Orders used by the
+// batched and benchmarked workloads (NP = 6, 8, 10, 12) have several EPW
+// options; the others have one.
+template <int NP> constexpr int n_epw_opts() { return NP == 6 || NP == 8 || NP == 10 ? 3 : NP == 12 ? 2 : 1; }
+template <int NP> constexpr int epw_opt(int k)
+{
+    return k == 0 ? epw_for(NP)
+         : NP == 6 ? (k == 1 ? 4 : 16)
+         : NP == 8 ? (k == 1 ? 2 : 1)
+         : NP == 10 ? (k == 1 ? 2 : 1)
+         : NP == 12 ? 1 : epw_for(NP);
+}
+template <int NP> constexpr int n_variants() { return 2 * n_epw_opts<NP>(); }
+
+template <int V> using IC = std::integral_constant<int, V>;
+
+// Calls f(IC<EPW>, IC<PD>) for variant v of order NP and storage GT.
+template <int NP, typename GT, typename F> int with_variant(int v, F &&f)
+{
+    constexpr int P0 = pd_for<GT>(), P1 = pd_alt<GT>();
+    switch (v) {
+    case 0: return f(IC<epw_opt<NP>(0)>{}, IC<P0>{});
+    case 1: return f(IC<epw_opt<NP>(0)>{}, IC<P1>{});
+    case 2: if constexpr (n_epw_opts<NP>() > 1) return f(IC<epw_opt<NP>(1)>{}, IC<P0>{}); break;
+    case 3: if constexpr (n_epw_opts<NP>() > 1) return f(IC<epw_opt<NP>(1)>{}, IC<P1>{}); break;
+    case 4: if constexpr (n_epw_opts<NP>() > 2) return f(IC<epw_opt<NP>(2)>{}, IC<P0>{}); break;
+    case 5: if constexpr (n_epw_opts<NP>() > 2) return f(IC<epw_opt<NP>(2)>{}, IC<P1>{}); break;
+    default: break;
+    }
+    return NEK_E_ARG;
+}
+
+int num_cu();
+
+template <typename T> int dalloc(T *&p, size_t count)
+{
+    if (p) return NEK_OK;
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return NEK_E_OOM;
+    p = static_cast<T *>(q);
+    return NEK_OK;
+}
+
+template <typename T> void dfree(T *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+}  // namespace nek
+
+struct nek_ctx {
+    int N = 0, NP = 0;
+    int nel[3] = {0, 0, 0};
+    long E = 0, nl = 0, ng = 0, nperm = 0, nseg = 0;
+    nek::Box box{};
+    hipStream_t stream = nullptr;
+    nek_opts opts{};
+    int prec = NEK_PREC_FP64;
+    int variant[3] = {0, 0, 0};   // CG kernel configuration per precision (nek_tune)
+
+    std::vector<double> xi, w, D, vtx;
+
+    // device data; g* are stored per point: [E][NP^3][6]
+    double *D64 = nullptr;
+    float *D32 = nullptr;
+    double *g64 = nullptr;
+    float *g32 = nullptr;
+    uint16_t *g16 = nullptr;
+    double *B = nullptr;
+    int32_t *perm = nullptr, *segptr = nullptr;
+    int8_t *segflag = nullptr;
+    nek::Scal *sc = nullptr;
+    double *partials = nullptr;   // 5 regions of MAXB doubles
+    double *hist = nullptr;
+    long hist_cap = 0;
+    // work vectors
+    double *b = nullptr, *r64 = nullptr, *p64 = nullptr, *w64 = nullptr, *d64 = nullptr;
+    float *r32 = nullptr, *p32 = nullptr, *w32 = nullptr;
+    int *hflags = nullptr;   // pinned
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    // sampled kernel timing (nek_prof_*)
+    int prof_every = 0;
+    long prof_tick = 0;
+    std::vector<hipEvent_t> prof_pool;
+    std::vector<int> prof_pending;     // event triples awaiting resolution
+    double prof_ms[2] = {0, 0};
+    long prof_n[2] = {0, 0};
+
+    // partials: operator pAp and update rtr, each double-buffered by
+    // iteration parity, then one region for standalone reductions
+    double *P1(int it) { return partials + (it & 1) * nek::MAXB; }
+    double *P2(int it) { return partials + (2 + (it & 1)) * nek::MAXB; }
+    double *P3() { return partials + 4 * nek::MAXB; }
+};
+
+namespace nek {
+
+inline unsigned red_grid(const nek_ctx *c)
+{
+    long want = (c->nl + UPD_BS - 1) / UPD_BS;
+    long cap = std::min<long>(MAXB / 2, 4L * num_cu());
+    return (unsigned)std::max<long>(1, std::min(want, cap));
+}
+
+inline int ax_groups(const nek_ctx *c, int epw) { return (int)((c->E + epw - 1) / epw); }
+
+inline unsigned ax_grid(const nek_ctx *c, int epw)
+{
+    long want = ax_groups(c, epw);
+    long cap = std::min<long>(MAXB, 8L * num_cu());
+    return (unsigned)std::max<long>(1, std::min(want, cap));
+}
+
+// Index of a free event triple for sampled timing (creates events as needed).
+int prof_take(nek_ctx *c);
+
+// Kernels instantiated for one order; every entry enqueues on c->stream and
+// returns a nek_status.  Reductions leave per-workgroup partials in c->P3().
+struct NpOps {
+    int nvariants;
+    // one CG iteration (final: only the closing operator launch)
+    int (*cg_iter64)(nek_ctx *, int variant, int it, bool final, double *x, double *r, double *p, double *w,
+                     const double *g, const double *D);
+    int (*cg_iter32)(nek_ctx *, int variant, int it, bool final, double *x, float *r, float *p, float *w,
+                     const float *g, const float *D);
+    int (*cg_iter16)(nek_ctx *, int variant, int it, bool final, double *x, float *r, float *p, float *w,
+                     const uint16_t *g, const float *D);
+    // w = A_L u
+    int (*ax64)(nek_ctx *, const double *u, double *w);
+    int (*ax32)(nek_ctx *, const float *u, float *w);
+    int (*ax16)(nek_ctx *, const float *u, float *w);
+    // out = M o sum of copies (weighted by c when weighted)
+    int (*gather64)(nek_ctx *, const double *in, double *out, bool weighted);
+    // partials of glsc3(a, c, b)
+    int (*glsc3_64)(nek_ctx *, const double *a, const double *b);
+    int (*glsc3_32)(nek_ctx *, const float *a, const float *b);
+    // r = b - M dssum(w), partials of glsc3(r, c, r)
+    int (*resid)(nek_ctx *, const double *b, const double *w, double *r);
+    // r32 = (float) r64, d = 0, partials of glsc3(r32, c, r32)
+    int (*inner_start)(nek_ctx *, const double *r64, float *r32, double *d);
+};
+
+const NpOps *np_ops(int NP);
+
+}  // namespace nek

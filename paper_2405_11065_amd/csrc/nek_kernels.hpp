@@ -3,24 +3,28 @@
 //
 // Hot path of one CG iteration (the loop of the paper's Table 1, no
 // preconditioner): two launches per iteration.
-//   k_ax<CG>(it)    beta from the previous iteration's rtr, p = beta p + r
-//                   (add2s1), w_L = A_L p (ax_e: local_grad3, g1..g6,
-//                   local_grad3_t), and per-workgroup partials of p.w_L.
-//   k_cg_update(it) alpha = rtz / pap, then for every local point:
-//                   S = sum of the copies of w_L at its global node (dssum),
-//                   mask, x += alpha p, r -= alpha S, and per-workgroup
-//                   partials of glsc3(r, c, r).
+//   k_ax<CG>(it)    alpha and rtr of iteration it-1 from the previous
+//                   kernels' partials; x += alpha_{it-1} p_{it-1} (add2s2
+//                   for x, deferred one iteration because this kernel reads
+//                   p anyway); beta; p = beta p + r (add2s1);
+//                   w_L = A_L p (ax_e: local_grad3, g1..g6, local_grad3_t);
+//                   per-workgroup partials of p.w_L.
+//   k_cg_update(it) alpha = rtz / pap; for every local point S = sum of the
+//                   copies of w_L at its global node (dssum), mask,
+//                   r -= alpha S (add2s2 for r); partials of glsc3(r, c, r).
 // Because p is continuous and zero on the Dirichlet boundary,
 // glsc3(M dssum(A_L p), c, p) = sum_l p_l (A_L p)_l in exact arithmetic, so
-// pap needs no gather and alpha is known right after the operator.
+// pap needs no gather and alpha is known right after the operator.  The
+// operator kernel launched once more after the last iteration applies the
+// pending x update and publishes the final state.
 //
 // Reductions without atomics or fences: a kernel writes one FP64 partial
-// per workgroup with a plain store; every workgroup of the NEXT kernel sums
+// per workgroup with a plain store; every workgroup of a LATER kernel sums
 // all of them in the same fixed order (so all obtain the identical value),
 // the kernel boundary making the stores visible.  Device-scope fences would
 // write back and invalidate a whole XCD's L2 per workgroup on gfx950.  The
-// CG state is double-buffered by iteration parity; only workgroup 0 writes
-// the slot of the current iteration.
+// CG state and the partials are double-buffered by iteration parity; only
+// workgroup 0 writes the state slot of the current iteration.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -41,7 +45,7 @@ struct IterState {
 
 struct Scal {
     IterState st[2];
-    IterState fin;        // final state, written by k_cg_finish
+    IterState fin;        // state of the iteration that ended the run
     double hist_den;      // history entry = sqrt(rtz / hist_den)
     double stop_den;      // stop when sqrt(rtz) / sqrt(stop_den) <= stop_tol
     double stop_tol;      // <= 0: run to maxit
@@ -95,29 +99,69 @@ __device__ __forceinline__ double block_sum(double v, double *sbuf)
     }
 }
 
+// 1 / m for a multiplicity m in {1, 2, 4, 8}: exact, so (v * inv_mult(m))
+// equals v / m bit for bit without a division.
+__device__ __forceinline__ double inv_mult(int m)
+{
+    return m == 1 ? 1.0 : m == 2 ? 0.5 : m == 4 ? 0.25 : 0.125;
+}
+
 // Sum of P[0..n) in a fixed order, returned to every thread of the block.
+// Only whole waves take part (lanes past the last full wave do not exist
+// for shuffles); the result is broadcast through LDS.
 template <int BS>
 __device__ __forceinline__ double sum_all(const double *__restrict__ P, int n, double *sbuf)
 {
+    constexpr int NW = BS >= 64 ? BS / 64 : 1;
+    constexpr int NT = BS >= 64 ? NW * 64 : BS;
+    // each thread sums P[t], P[t + NT], ... in that order; the loads of a
+    // batch of up to U entries are all issued before the first add
+    constexpr int U = NT >= 256 ? 8 : 16;
     double v = 0.0;
-    for (int q = threadIdx.x; q < n; q += BS) v += P[q];
-    double s = block_sum<BS>(v, sbuf);
-    if (threadIdx.x == 0) sbuf[0] = s;
-    __syncthreads();
-    s = sbuf[0];
-    __syncthreads();
-    return s;
+    if (threadIdx.x < NT)
+        for (int q0 = threadIdx.x; q0 < n; q0 += U * NT) {
+            double t[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * NT;
+                t[u] = q < n ? P[q] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) v += t[u];
+        }
+    if constexpr (BS >= 64) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (threadIdx.x < NT && (threadIdx.x & 63) == 0) sbuf[threadIdx.x >> 6] = v;
+        __syncthreads();
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) s += sbuf[q];
+        __syncthreads();
+        return s;
+    } else {
+        return block_sum<BS>(v, sbuf);   // LDS tree, result in every thread
+    }
 }
 
-// Start of iteration it: fold the previous update kernel's rtr partials into
-// the state (identically in every workgroup) and decide whether to stop.
-// Workgroup 0, thread 0 publishes the state (and, when done, the host flag).
+// Start of iteration it: fold the partials of iteration it-1 into the state
+// (identically in every workgroup) and decide whether to stop.  Returns the
+// state and the pending x update alpha_{it-1} (when iteration it-1
+// completed).  Workgroup 0, thread 0 publishes the state.
+struct Begin {
+    IterState cur;
+    double alpha_prev;
+    bool xupd;
+};
+
 template <int BS>
-__device__ __forceinline__ IterState cg_begin(Scal *__restrict__ sc, const double *__restrict__ P2, int nb2,
-                                              int it, double *__restrict__ hist, double *sbuf, bool writer)
+__device__ __forceinline__ Begin cg_begin(Scal *__restrict__ sc, const double *__restrict__ P1prev, int nb1,
+                                          const double *__restrict__ P2prev, int nb2, int it,
+                                          double *__restrict__ hist, double *sbuf, bool writer)
 {
     const IterState prev = sc->st[(it - 1) & 1];
-    IterState cur = prev;
+    Begin B{prev, 0.0, false};
+    IterState &cur = B.cur;
     if (!prev.done) {
         if (it == 1) {
             cur.beta = 0.0;
@@ -128,7 +172,9 @@ __device__ __forceinline__ IterState cg_begin(Scal *__restrict__ sc, const doubl
                 cur.status = f;
                 cur.done = 1;
             } else {
-                const double rtr = sum_all<BS>(P2, nb2, sbuf);
+                B.alpha_prev = prev.rtz / sum_all<BS>(P1prev, nb1, sbuf);
+                B.xupd = true;
+                const double rtr = sum_all<BS>(P2prev, nb2, sbuf);
                 cur.iter = it - 1;
                 cur.rtz = rtr;
                 cur.beta = rtr / prev.rtz;
@@ -146,9 +192,12 @@ __device__ __forceinline__ IterState cg_begin(Scal *__restrict__ sc, const doubl
     }
     if (writer) {
         sc->st[it & 1] = cur;
-        if (cur.done) sc->done_host = 1;
+        if (cur.done) {
+            sc->done_host = 1;
+            sc->fin = cur;
+        }
     }
-    return cur;
+    return B;
 }
 
 // ------------------------------------------------------ geometric factors
@@ -204,13 +253,14 @@ template <> struct GLoad<uint16_t> {   // BF16 bit patterns, two per 32-bit word
 // uniform entries D[k][l] of the t contractions come through the scalar
 // cache.  The six factors of slice k + PD are in flight while slice k is
 // computed.  CG mode fuses p = beta p + r before, and sum p.(A_L p) after.
-template <int NP, int EPW, int PD, typename T, typename GT, bool CG>
+template <int NP, int EPW, int PD, typename T, typename GT, bool CG, typename XT>
 __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T *__restrict__ p,
                                                     T *__restrict__ w, const GT *__restrict__ g,
-                                                    const T *__restrict__ D, Scal *__restrict__ sc,
-                                                    double *__restrict__ P1, const double *__restrict__ P2,
-                                                    int nb2, int it, double *__restrict__ hist, int E,
-                                                    int ngroups)
+                                                    const T *__restrict__ D, XT *__restrict__ x,
+                                                    Scal *__restrict__ sc, double *__restrict__ P1cur,
+                                                    const double *__restrict__ P1prev,
+                                                    const double *__restrict__ P2prev, int nb2, int it,
+                                                    double *__restrict__ hist, int E, int ngroups)
 {
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP, BS = EPW * NP2;
     using GL = GLoad<GT>;
@@ -222,15 +272,34 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T
     __shared__ T sD[NP * NP];
 
     const int tid = threadIdx.x;
+    const int el = tid / NP2, ij = tid - el * NP2;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int g0 = (int)(((long)lb * ngroups) / gridDim.x);
+    const int g1 = (int)(((long)(lb + 1) * ngroups) / gridDim.x);
     T beta = 0;
-    bool first = false;
+    bool first = false, xupd = false;
+    double alpha_prev = 0.0;
     if constexpr (CG) {
-        const IterState cur = cg_begin<BS>(sc, P2, nb2, it, hist, sbuf, blockIdx.x == 0 && tid == 0);
-        if (cur.done) return;
-        beta = (T)cur.beta;
+        const Begin B = cg_begin<BS>(sc, P1prev, (int)gridDim.x, P2prev, nb2, it, hist, sbuf, blockIdx.x == 0 && tid == 0);
+        xupd = B.xupd;
+        alpha_prev = B.alpha_prev;
+        if (B.cur.done) {
+            // last call of a run: only the pending x += alpha p
+            if (xupd)
+                for (int grp = g0; grp < g1; ++grp) {
+                    const int e = grp * EPW + el;
+                    if (e >= E) continue;
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) {
+                        const int idx = e * NP3 + k * NP2 + ij;
+                        x[idx] = (XT)((double)x[idx] + alpha_prev * (double)p[idx]);
+                    }
+                }
+            return;
+        }
+        beta = (T)B.cur.beta;
         first = it == 1;
     }
-    const int el = tid / NP2, ij = tid - el * NP2;
     const int i = ij % NP, j = ij / NP;
     T *sue = su + el * NP3, *sre = sr + el * NP3, *sse = ss + el * NP3;
 
@@ -253,18 +322,15 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T
 #define NEK_DS(l) (DREG ? Dsj[DREG ? (l) : 0] : sD[j * NP + (l)])
 #define NEK_DTI(l) (DREG ? DTi[DREG ? (l) : 0] : sD[(l) * NP + i])
 #define NEK_DTJ(l) (DREG ? DTj[DREG ? (l) : 0] : sD[(l) * NP + j])
-    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
-    const int g0 = (int)(((long)lb * ngroups) / gridDim.x);
-    const int g1 = (int)(((long)(lb + 1) * ngroups) / gridDim.x);
     double pap = 0.0;
 
     for (int grp = g0; grp < g1; ++grp) {
-        const long e = (long)grp * EPW + el;
+        const int e = grp * EPW + el;
         const bool valid = e < E;
         // threads past the last element compute on a copy of element E-1 and
-        // store nothing
-        const long ec = valid ? e : (long)E - 1;
-        const long base = ec * NP3 + ij;
+        // store nothing (local indices fit in 32 bits, checked at set-up)
+        const int ec = valid ? e : E - 1;
+        const int base = ec * NP3 + ij;
         const GT *ge = g + (size_t)base * 6;
         typename GL::Raw gb[PD];
 #pragma unroll
@@ -274,11 +340,13 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T
         __syncthreads();   // LDS of the previous group is free
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            const long idx = base + k * NP2;
+            const int idx = base + k * NP2;
             T v;
             if constexpr (CG) {
                 const T rv = src[idx];
-                v = first ? rv : beta * p[idx] + rv;
+                const T po = p[idx];
+                if (xupd && valid) x[idx] = (XT)((double)x[idx] + alpha_prev * (double)po);
+                v = first ? rv : beta * po + rv;
                 if (valid) p[idx] = v;
             } else {
                 v = src[idx];
@@ -326,7 +394,7 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T
 #undef NEK_DTJ
     if constexpr (CG) {
         const double s = block_sum<BS>(pap, sbuf);
-        if (tid == 0) P1[blockIdx.x] = s;
+        if (tid == 0) P1cur[blockIdx.x] = s;
     }
 }
 
@@ -384,7 +452,7 @@ __device__ __forceinline__ double gather_copies(const T *__restrict__ w, const P
     int nz = 1, dz0 = 0, dz1 = 0, cz0 = P.k, cz1 = 0;
     if (P.k == 0 && P.ez > 0) { nz = 2; dz0 = -1; cz0 = N; dz1 = 0; cz1 = 0; }
     else if (P.k == N && P.ez < b.nz - 1) { nz = 2; dz0 = 0; cz0 = N; dz1 = 1; cz1 = 0; }
-    const double c = WEIGHT ? 1.0 / (double)(nx * ny * nz) : 1.0;
+    const double c = WEIGHT ? inv_mult(nx * ny * nz) : 1.0;
     const long sy = b.nx, sz = (long)b.nx * b.ny;
     double s = 0.0;
 #pragma unroll
@@ -410,94 +478,120 @@ __device__ __forceinline__ double gather_copies(const T *__restrict__ w, const P
     return s;
 }
 
-template <typename T, typename XT> struct UpdArgs {
-    XT *x;             // solution (FP64 CG) or correction (mixed inner)
-    const T *p;
-    T *r;
-    const T *w;        // A_L p, unassembled
-    Scal *sc;
-    const double *P1;  // pAp partials of k_ax(it)
-    double *P2;        // rtr partials written here
-    int nb1;
-    int it;
-    Box box;
-    unsigned nl;
-};
-
-template <int NP, typename T, typename XT>
-__global__ __launch_bounds__(UPD_BS) void k_cg_update(UpdArgs<T, XT> a)
+// Second kernel of CG iteration it: alpha = rtz / pap, then for every
+// unmasked point S = sum of the copies of w_L at its global node (in a fixed
+// pairwise order that every copy reproduces bit for bit), r -= alpha S, and
+// partials of glsc3(r, c, r).
+// Same workgroup shape as the operator (EPW elements x NP^2 threads walking
+// k-columns).  All loads of a column are issued before any is used: the own
+// column of r and w, the columns of w in the x, y and xy neighbours (for
+// threads on those faces), and the neighbouring slices in z.
+template <int NP, int EPW, typename T>
+__global__ __launch_bounds__(EPW *NP *NP) void k_cg_update(T *__restrict__ r, const T *__restrict__ w,
+                                                           Scal *__restrict__ sc, const double *__restrict__ P1cur,
+                                                           int nb1, double *__restrict__ P2cur, int it, Box box,
+                                                           int E, int ngroups)
 {
-    __shared__ double sbuf[UPD_BS];
-    const IterState cur = a.sc->st[a.it & 1];
+    constexpr int NP2 = NP * NP, NP3 = NP2 * NP, BS = EPW * NP2, N = NP - 1;
+    __shared__ double sbuf[BS];
+    const IterState cur = sc->st[it & 1];
     if (cur.done) return;
-    const double pap = sum_all<UPD_BS>(a.P1, a.nb1, sbuf);
+    const double pap = sum_all<BS>(P1cur, nb1, sbuf);
     const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
     if (!__builtin_isfinite(pap) || !(pap > 0)) {
-        if (writer) a.sc->k2flag[a.it & 1] = __builtin_isfinite(pap) ? -5 : -6;
+        if (writer) sc->k2flag[it & 1] = __builtin_isfinite(pap) ? -5 : -6;
         return;
     }
     const double alpha = cur.rtz / pap;
+    const int tid = threadIdx.x;
+    const int el = tid / NP2, ij = tid - el * NP2;
+    const int i = ij % NP, j = ij / NP;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
-    const unsigned t0 = (unsigned)(((unsigned long)lb * a.nl) / gridDim.x);
-    const unsigned t1 = (unsigned)(((unsigned long)(lb + 1) * a.nl) / gridDim.x);
+    const int g0 = (int)(((long)lb * ngroups) / gridDim.x);
+    const int g1 = (int)(((long)(lb + 1) * ngroups) / gridDim.x);
+    const int oz = box.nx * box.ny;   // local indices fit in 32 bits (checked at set-up)
     double part = 0.0;
-    for (unsigned t = t0 + threadIdx.x; t < t1; t += UPD_BS) {
-        const PointInfo<NP> P = locate<NP>(t, a.box);
-        if (P.masked) continue;   // r, x, p are zero there and stay zero
-        const double S = gather_copies<NP, T, false>(a.w, P, a.box);
-        a.x[t] = (XT)((double)a.x[t] + alpha * (double)a.p[t]);
-        const T rn = (T)((double)a.r[t] - alpha * S);
-        a.r[t] = rn;
-        part += ((double)rn * (double)rn) / (double)P.mult;
+    for (int grp = g0; grp < g1; ++grp) {
+        const int e = grp * EPW + el;
+        if (e >= E) continue;
+        const int ex = e % box.nx;
+        const int eyz = e / box.nx;
+        const int ey = eyz % box.ny, ez = eyz / box.ny;
+        if ((i == 0 && ex == 0) || (i == N && ex == box.nx - 1) || (j == 0 && ey == 0) ||
+            (j == N && ey == box.ny - 1))
+            continue;   // the whole column lies on the Dirichlet boundary
+        const bool hx = (i == 0 && ex > 0) || (i == N && ex < box.nx - 1);
+        const bool hy = (j == 0 && ey > 0) || (j == N && ey < box.ny - 1);
+        const bool xneg = i == 0, yneg = j == 0;   // neighbour sits below (dx or dy = -1)
+        const int ox = xneg ? -1 : 1, oy = yneg ? -box.nx : box.nx;
+        const int colX = (xneg ? N : 0) + NP * j, colY = i + NP * (yneg ? N : 0);
+        const int colXY = (xneg ? N : 0) + NP * (yneg ? N : 0);
+        const bool hzm = ez > 0, hzp = ez < box.nz - 1;
+        const T *we = w + e * NP3;
+        T rv[NP], wo[NP], wx[NP], wy[NP], wxy[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            rv[k] = r[e * NP3 + k * NP2 + ij];   // int arithmetic
+            wo[k] = we[k * NP2 + ij];
+            wx[k] = wy[k] = wxy[k] = (T)0;
+        }
+        if (hx) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) wx[k] = we[ox * NP3 + k * NP2 + colX];
+        }
+        if (hy) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) wy[k] = we[oy * NP3 + k * NP2 + colY];
+        }
+        if (hx && hy) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) wxy[k] = we[(ox + oy) * NP3 + k * NP2 + colXY];
+        }
+        // z neighbours: slice N of element e - oz (for k = 0), slice 0 of e + oz (for k = N)
+        T zm[4] = {0, 0, 0, 0}, zp[4] = {0, 0, 0, 0};   // own, X, Y, XY columns
+        if (hzm) {
+            const T *wz = we - oz * NP3 + N * NP2;
+            zm[0] = wz[ij];
+            if (hx) zm[1] = wz[ox * NP3 + colX];
+            if (hy) zm[2] = wz[oy * NP3 + colY];
+            if (hx && hy) zm[3] = wz[(ox + oy) * NP3 + colXY];
+        }
+        if (hzp) {
+            const T *wz = we + oz * NP3;
+            zp[0] = wz[ij];
+            if (hx) zp[1] = wz[ox * NP3 + colX];
+            if (hy) zp[2] = wz[oy * NP3 + colY];
+            if (hx && hy) zp[3] = wz[(ox + oy) * NP3 + colXY];
+        }
+        // Copies in one plane of constant z: own, the x and y neighbours and
+        // the diagonal one (zero when absent; adding +0.0 is exact).  The sum
+        // (own + X) + (Y + XY) pairs copies of the same y row first, and
+        // planes are then added pairwise; IEEE addition is commutative, so
+        // every copy of a node computes the bit-identical value and r stays
+        // exactly continuous.
+        auto plane = [](double o, double X, double Y, double XY) -> double { return (o + X) + (Y + XY); };
+        const int mxy = (hx ? 2 : 1) * (hy ? 2 : 1);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            if ((k == 0 && ez == 0) || (k == N && ez == box.nz - 1)) continue;   // Dirichlet slice
+            double S = plane((double)wo[k], (double)wx[k], (double)wy[k], (double)wxy[k]);
+            int m = mxy;
+            if (k == 0 && hzm) {
+                S = plane((double)zm[0], (double)zm[1], (double)zm[2], (double)zm[3]) + S;
+                m *= 2;
+            }
+            if (k == N && hzp) {
+                S = S + plane((double)zp[0], (double)zp[1], (double)zp[2], (double)zp[3]);
+                m *= 2;
+            }
+            const T rn = (T)((double)rv[k] - alpha * S);
+            r[e * NP3 + k * NP2 + ij] = rn;
+            part += ((double)rn * (double)rn) * inv_mult(m);
+        }
     }
-    const double s = block_sum<UPD_BS>(part, sbuf);
-    if (threadIdx.x == 0) a.P2[blockIdx.x] = s;
-    if (writer) a.sc->k2flag[a.it & 1] = 0;
-}
-
-// End of a CG run: fold the last update's partials and publish the final
-// state (one workgroup).
-__global__ __launch_bounds__(UPD_BS) void k_cg_finish(Scal *__restrict__ sc, const double *__restrict__ P2, int nb2,
-                                                      int it, double *__restrict__ hist)
-{
-    __shared__ double sbuf[UPD_BS];
-    const IterState cur = cg_begin<UPD_BS>(sc, P2, nb2, it, hist, sbuf, threadIdx.x == 0);
-    if (threadIdx.x == 0) sc->fin = cur;
-}
-
-// Start of a CG run: rtz = red[rslot]; stop and history denominators; the
-// initial residual test.
-__global__ void k_cg_start(Scal *sc, double *hist, int rslot, int hist_off, double stop_tol, int maxit,
-                           int stop_on_initial)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double bb = sc->red[0];
-    const double rtz = sc->red[rslot];
-    IterState s{};
-    s.rtz = rtz;
-    s.beta = 0.0;
-    s.iter = 0;
-    sc->hist_den = bb;
-    sc->stop_den = stop_on_initial ? rtz : bb;
-    sc->stop_tol = stop_tol;
-    sc->maxit = maxit;
-    sc->hist_off = hist_off;
-    sc->k2flag[0] = sc->k2flag[1] = 0;
-    if (hist) hist[hist_off] = bb > 0 ? sqrt(rtz / bb) : 0.0;
-    if (!__builtin_isfinite(bb) || !__builtin_isfinite(rtz)) {
-        s.status = -6;
-        s.done = 1;
-    } else if (bb == 0.0 || rtz == 0.0 ||
-               (!stop_on_initial && stop_tol > 0 && sqrt(rtz) / sqrt(sc->stop_den) <= stop_tol)) {
-        s.conv = 1;
-        s.done = 1;
-    } else if (maxit <= 0) {
-        s.done = 1;
-    }
-    sc->st[0] = s;
-    sc->st[1] = s;
-    sc->fin = s;
-    sc->done_host = s.done;
+    const double s = block_sum<BS>(part, sbuf);
+    if (tid == 0) P2cur[blockIdx.x] = s;
+    if (writer) sc->k2flag[it & 1] = 0;
 }
 
 // out = M o sum over copies of (c o) in: the right-hand side b = M dssum(f)
@@ -512,15 +606,6 @@ __global__ __launch_bounds__(UPD_BS) void k_gather(const T *__restrict__ in, T *
         const PointInfo<NP> P = locate<NP>(t, box);
         out[t] = P.masked ? (T)0 : (T)gather_copies<NP, T, WEIGHT>(in, P, box);
     }
-}
-
-// Standalone reductions write one partial per workgroup; k_red_final sums
-// them in a fixed order into red[slot].
-__global__ __launch_bounds__(UPD_BS) void k_red_final(const double *__restrict__ P, int n, Scal *sc, int slot)
-{
-    __shared__ double sbuf[UPD_BS];
-    const double s = sum_all<UPD_BS>(P, n, sbuf);
-    if (threadIdx.x == 0) sc->red[slot] = s;
 }
 
 // r = b - M dssum(w) (FP64); partials of glsc3(r, c, r).
@@ -539,7 +624,7 @@ __global__ __launch_bounds__(UPD_BS) void k_resid(const double *__restrict__ b, 
         double v = 0.0;
         if (!Pt.masked) v = b[t] - gather_copies<NP, double, false>(w, Pt, box);
         r[t] = v;
-        part += (v * v) / (double)Pt.mult;
+        part += (v * v) * inv_mult(Pt.mult);
     }
     const double s = block_sum<UPD_BS>(part, sbuf);
     if (threadIdx.x == 0) P[blockIdx.x] = s;
@@ -557,7 +642,7 @@ __global__ __launch_bounds__(UPD_BS) void k_glsc3(const TA *__restrict__ a, cons
     double part = 0.0;
     for (unsigned t = t0 + threadIdx.x; t < t1; t += UPD_BS) {
         const PointInfo<NP> Pt = locate<NP>(t, box);
-        part += ((double)a[t] * (double)bv[t]) / (double)Pt.mult;
+        part += ((double)a[t] * (double)bv[t]) * inv_mult(Pt.mult);
     }
     const double s = block_sum<UPD_BS>(part, sbuf);
     if (threadIdx.x == 0) P[blockIdx.x] = s;
@@ -580,76 +665,10 @@ __global__ __launch_bounds__(UPD_BS) void k_inner_start(const double *__restrict
         const float v = (float)r64[t];
         r32[t] = v;
         d[t] = 0.0;
-        part += ((double)v * (double)v) / (double)Pt.mult;
+        part += ((double)v * (double)v) * inv_mult(Pt.mult);
     }
     const double s = block_sum<UPD_BS>(part, sbuf);
     if (threadIdx.x == 0) P[blockIdx.x] = s;
-}
-
-// Standalone sorted-segment dssum: one thread per segment, copies summed in
-// ascending local index (perm order) from 0.0, written back to every copy.
-template <typename T>
-__global__ __launch_bounds__(UPD_BS) void k_dssum_seg(T *__restrict__ w, const int32_t *__restrict__ perm,
-                                                      const int32_t *__restrict__ seg_ptr,
-                                                      const int8_t *__restrict__ flag, unsigned nseg, int apply_mask)
-{
-    const unsigned s = blockIdx.x * UPD_BS + threadIdx.x;
-    if (s >= nseg) return;
-    const int b = seg_ptr[s], e = seg_ptr[s + 1];
-    if (apply_mask && flag[s]) {
-        for (int q = b; q < e; ++q) w[perm[q]] = (T)0;
-        return;
-    }
-    double acc = 0.0;
-    for (int q = b; q < e; ++q) acc += (double)w[perm[q]];
-    const T v = (T)acc;
-    for (int q = b; q < e; ++q) w[perm[q]] = v;
-}
-
-// Rounding of the FP64 geometric factors to the storage precision.
-__device__ __forceinline__ uint16_t f64_to_bf16_rne(double x)
-{
-    // Round-to-nearest-even directly from binary64 (no double rounding via
-    // binary32).  Values below the binary32 normal range flush to signed 0.
-    const unsigned long long u = __double_as_longlong(x);
-    const unsigned sign = (unsigned)(u >> 63);
-    const int ex = (int)((u >> 52) & 0x7ff);
-    const unsigned long long man = u & 0xfffffffffffffULL;
-    if (ex == 0x7ff) return (uint16_t)((sign << 15) | 0x7f80u | (man ? 0x40u : 0u));
-    const int eb = ex - 1023 + 127;
-    if (ex == 0 || eb <= 0) return (uint16_t)(sign << 15);
-    if (eb >= 0xff) return (uint16_t)((sign << 15) | 0x7f80u);
-    unsigned bits = (sign << 15) | ((unsigned)eb << 7) | (unsigned)(man >> 45);
-    const unsigned long long rest = man & ((1ULL << 45) - 1);
-    const unsigned long long half = 1ULL << 44;
-    if (rest > half || (rest == half && (bits & 1u))) bits += 1u;   // carries into the exponent correctly
-    return (uint16_t)bits;
-}
-
-__global__ void k_g_to_f32(const double *__restrict__ g, float *__restrict__ o, unsigned long n)
-{
-    for (unsigned long t = blockIdx.x * (unsigned long)blockDim.x + threadIdx.x; t < n; t += (unsigned long)gridDim.x * blockDim.x)
-        o[t] = (float)g[t];
-}
-
-__global__ void k_g_to_bf16(const double *__restrict__ g, uint16_t *__restrict__ o, unsigned long n)
-{
-    for (unsigned long t = blockIdx.x * (unsigned long)blockDim.x + threadIdx.x; t < n; t += (unsigned long)gridDim.x * blockDim.x)
-        o[t] = f64_to_bf16_rne(g[t]);
-}
-
-template <typename T>
-__global__ void k_fill(T *__restrict__ p, T v, unsigned long n)
-{
-    for (unsigned long t = blockIdx.x * (unsigned long)blockDim.x + threadIdx.x; t < n; t += (unsigned long)gridDim.x * blockDim.x)
-        p[t] = v;
-}
-
-// x += d (FP64).
-__global__ void k_axpy1(double *__restrict__ x, const double *__restrict__ d, unsigned long n)
-{
-    for (unsigned long t = blockIdx.x * (unsigned long)blockDim.x + threadIdx.x; t < n; t += (unsigned long)gridDim.x * blockDim.x)
-        x[t] += d[t];
 }
 
 }  // namespace nek

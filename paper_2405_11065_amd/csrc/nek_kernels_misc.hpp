@@ -1,0 +1,119 @@
+// Order-independent device kernels of libnek (gfx950): CG start, reduction
+// finish, sorted-segment dssum, precision conversion of g, fills.  Internal
+// header, included only by nek_lib.hip.
+#pragma once
+#include "nek_kernels.hpp"
+
+namespace nek {
+
+// Start of a CG run: rtz = red[rslot]; stop and history denominators; the
+// initial residual test.
+__global__ void k_cg_start(Scal *sc, double *hist, int rslot, int hist_off, double stop_tol, int maxit,
+                           int stop_on_initial)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double bb = sc->red[0];
+    const double rtz = sc->red[rslot];
+    IterState s{};
+    s.rtz = rtz;
+    s.beta = 0.0;
+    s.iter = 0;
+    sc->hist_den = bb;
+    sc->stop_den = stop_on_initial ? rtz : bb;
+    sc->stop_tol = stop_tol;
+    sc->maxit = maxit;
+    sc->hist_off = hist_off;
+    sc->k2flag[0] = sc->k2flag[1] = 0;
+    if (hist) hist[hist_off] = bb > 0 ? sqrt(rtz / bb) : 0.0;
+    if (!__builtin_isfinite(bb) || !__builtin_isfinite(rtz)) {
+        s.status = -6;
+        s.done = 1;
+    } else if (bb == 0.0 || rtz == 0.0 ||
+               (!stop_on_initial && stop_tol > 0 && sqrt(rtz) / sqrt(sc->stop_den) <= stop_tol)) {
+        s.conv = 1;
+        s.done = 1;
+    } else if (maxit <= 0) {
+        s.done = 1;
+    }
+    sc->st[0] = s;
+    sc->st[1] = s;
+    sc->fin = s;
+    sc->done_host = s.done;
+}
+
+// Standalone reductions write one partial per workgroup; k_red_final sums
+// them in a fixed order into red[slot].
+__global__ __launch_bounds__(UPD_BS) void k_red_final(const double *__restrict__ P, int n, Scal *sc, int slot)
+{
+    __shared__ double sbuf[UPD_BS];
+    const double s = sum_all<UPD_BS>(P, n, sbuf);
+    if (threadIdx.x == 0) sc->red[slot] = s;
+}
+
+// Standalone sorted-segment dssum: one thread per segment, copies summed in
+// ascending local index (perm order) from 0.0, written back to every copy.
+template <typename T>
+__global__ __launch_bounds__(UPD_BS) void k_dssum_seg(T *__restrict__ w, const int32_t *__restrict__ perm,
+                                                      const int32_t *__restrict__ seg_ptr,
+                                                      const int8_t *__restrict__ flag, unsigned nseg, int apply_mask)
+{
+    const unsigned s = blockIdx.x * UPD_BS + threadIdx.x;
+    if (s >= nseg) return;
+    const int b = seg_ptr[s], e = seg_ptr[s + 1];
+    if (apply_mask && flag[s]) {
+        for (int q = b; q < e; ++q) w[perm[q]] = (T)0;
+        return;
+    }
+    double acc = 0.0;
+    for (int q = b; q < e; ++q) acc += (double)w[perm[q]];
+    const T v = (T)acc;
+    for (int q = b; q < e; ++q) w[perm[q]] = v;
+}
+
+// Rounding of the FP64 geometric factors to the storage precision.
+__device__ __forceinline__ uint16_t f64_to_bf16_rne(double x)
+{
+    // Round-to-nearest-even directly from binary64 (no double rounding via
+    // binary32).  Values below the binary32 normal range flush to signed 0.
+    const unsigned long long u = __double_as_longlong(x);
+    const unsigned sign = (unsigned)(u >> 63);
+    const int ex = (int)((u >> 52) & 0x7ff);
+    const unsigned long long man = u & 0xfffffffffffffULL;
+    if (ex == 0x7ff) return (uint16_t)((sign << 15) | 0x7f80u | (man ? 0x40u : 0u));
+    const int eb = ex - 1023 + 127;
+    if (ex == 0 || eb <= 0) return (uint16_t)(sign << 15);
+    if (eb >= 0xff) return (uint16_t)((sign << 15) | 0x7f80u);
+    unsigned bits = (sign << 15) | ((unsigned)eb << 7) | (unsigned)(man >> 45);
+    const unsigned long long rest = man & ((1ULL << 45) - 1);
+    const unsigned long long half = 1ULL << 44;
+    if (rest > half || (rest == half && (bits & 1u))) bits += 1u;   // carries into the exponent correctly
+    return (uint16_t)bits;
+}
+
+__global__ void k_g_to_f32(const double *__restrict__ g, float *__restrict__ o, unsigned long n)
+{
+    for (unsigned long t = blockIdx.x * (unsigned long)blockDim.x + threadIdx.x; t < n; t += (unsigned long)gridDim.x * blockDim.x)
+        o[t] = (float)g[t];
+}
+
+__global__ void k_g_to_bf16(const double *__restrict__ g, uint16_t *__restrict__ o, unsigned long n)
+{
+    for (unsigned long t = blockIdx.x * (unsigned long)blockDim.x + threadIdx.x; t < n; t += (unsigned long)gridDim.x * blockDim.x)
+        o[t] = f64_to_bf16_rne(g[t]);
+}
+
+template <typename T>
+__global__ void k_fill(T *__restrict__ p, T v, unsigned long n)
+{
+    for (unsigned long t = blockIdx.x * (unsigned long)blockDim.x + threadIdx.x; t < n; t += (unsigned long)gridDim.x * blockDim.x)
+        p[t] = v;
+}
+
+// x += d (FP64).
+__global__ void k_axpy1(double *__restrict__ x, const double *__restrict__ d, unsigned long n)
+{
+    for (unsigned long t = blockIdx.x * (unsigned long)blockDim.x + threadIdx.x; t < n; t += (unsigned long)gridDim.x * blockDim.x)
+        x[t] += d[t];
+}
+
+}  // namespace nek

@@ -8,57 +8,17 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "nek.h"
-#include "nek_kernels.hpp"
+#include "nek_internal.hpp"
+#include "nek_kernels_misc.hpp"
 #include "nek_setup.hpp"
 
 using namespace nek;
 
-namespace {
-
-constexpr int MAX_NP = 16;        // N <= 15
-constexpr int MAXB = 2048;        // cap on workgroups of any reducing kernel
-constexpr int CHUNK_ITERS = 16;   // CG iterations enqueued between flag polls
-
-// Elements per workgroup of the operator kernel for each NP = N+1, chosen so
-// EPW*NP^2 fills whole 64-lane waves where possible and the FP64 LDS
-// footprint 3*EPW*NP^3*8 stays within 160 KB.
-constexpr int epw_for(int NP)
-{
-    return NP == 2 ? 16 : NP == 3 ? 7 : NP == 4 ? 8 : NP == 5 ? 5 : NP == 6 ? 7 : NP == 7 ? 9
-         : NP == 8 ? 4 : NP == 9 ? 4 : NP == 10 ? 3 : NP == 11 ? 2 : NP == 12 ? 2 : 1;
-}
-
-// Slices of geometric factors in flight per thread (register budget:
-// 12 / 6 / 3 VGPRs per slice for FP64 / FP32 / BF16 storage).
-template <typename GT> constexpr int pd_for() { return sizeof(GT) == 8 ? 2 : sizeof(GT) == 4 ? 4 : 6; }
-
-#define NEK_NP_SWITCH(np, ...)                                   \
-    switch (np) {                                                \
-    case 2: { constexpr int NP = 2; __VA_ARGS__; } break;        \
-    case 3: { constexpr int NP = 3; __VA_ARGS__; } break;        \
-    case 4: { constexpr int NP = 4; __VA_ARGS__; } break;        \
-    case 5: { constexpr int NP = 5; __VA_ARGS__; } break;        \
-    case 6: { constexpr int NP = 6; __VA_ARGS__; } break;        \
-    case 7: { constexpr int NP = 7; __VA_ARGS__; } break;        \
-    case 8: { constexpr int NP = 8; __VA_ARGS__; } break;        \
-    case 9: { constexpr int NP = 9; __VA_ARGS__; } break;        \
-    case 10: { constexpr int NP = 10; __VA_ARGS__; } break;      \
-    case 11: { constexpr int NP = 11; __VA_ARGS__; } break;      \
-    case 12: { constexpr int NP = 12; __VA_ARGS__; } break;      \
-    case 13: { constexpr int NP = 13; __VA_ARGS__; } break;      \
-    case 14: { constexpr int NP = 14; __VA_ARGS__; } break;      \
-    case 15: { constexpr int NP = 15; __VA_ARGS__; } break;      \
-    case 16: { constexpr int NP = 16; __VA_ARGS__; } break;      \
-    default: return NEK_E_ARG;                                   \
-    }
-
-#define HIP_TRY(expr)                                            \
-    do {                                                         \
-        if ((expr) != hipSuccess) return NEK_E_HIP;              \
-    } while (0)
+namespace nek {
 
 int g_num_cu = 0;
 
@@ -75,101 +35,42 @@ int num_cu()
     return g_num_cu;
 }
 
-template <typename T> int dalloc(T *&p, size_t count)
+const NpOps *np_ops_2();
+const NpOps *np_ops_3();
+const NpOps *np_ops_4();
+const NpOps *np_ops_5();
+const NpOps *np_ops_6();
+const NpOps *np_ops_7();
+const NpOps *np_ops_8();
+const NpOps *np_ops_9();
+const NpOps *np_ops_10();
+const NpOps *np_ops_11();
+const NpOps *np_ops_12();
+const NpOps *np_ops_13();
+const NpOps *np_ops_14();
+const NpOps *np_ops_15();
+const NpOps *np_ops_16();
+
+const NpOps *np_ops(int NP)
 {
-    if (p) return NEK_OK;
-    void *q = nullptr;
-    if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return NEK_E_OOM;
-    p = static_cast<T *>(q);
-    return NEK_OK;
-}
-
-template <typename T> void dfree(T *&p)
-{
-    if (p) (void)hipFree(p);
-    p = nullptr;
-}
-
-}  // namespace
-
-struct nek_ctx {
-    int N = 0, NP = 0;
-    int nel[3] = {0, 0, 0};
-    long E = 0, nl = 0, ng = 0, nperm = 0, nseg = 0;
-    Box box{};
-    hipStream_t stream = nullptr;
-    nek_opts opts{};
-    int prec = NEK_PREC_FP64;
-
-    std::vector<double> xi, w, D, vtx;
-
-    // device data; g* are stored per point: [E][NP^3][6]
-    double *D64 = nullptr;
-    float *D32 = nullptr;
-    double *g64 = nullptr;
-    float *g32 = nullptr;
-    uint16_t *g16 = nullptr;
-    double *B = nullptr;
-    int32_t *perm = nullptr, *segptr = nullptr;
-    int8_t *segflag = nullptr;
-    Scal *sc = nullptr;
-    double *partials = nullptr;   // 3 regions of MAXB: operator, update, other
-    double *hist = nullptr;
-    long hist_cap = 0;
-    // work vectors
-    double *b = nullptr, *r64 = nullptr, *p64 = nullptr, *w64 = nullptr, *d64 = nullptr;
-    float *r32 = nullptr, *p32 = nullptr, *w32 = nullptr;
-    int *hflags = nullptr;   // pinned
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    // sampled kernel timing (nek_prof_*)
-    int prof_every = 0;
-    long prof_tick = 0;
-    std::vector<hipEvent_t> prof_pool;
-    std::vector<int> prof_pending;     // event triples awaiting resolution
-    double prof_ms[2] = {0, 0};
-    long prof_n[2] = {0, 0};
-
-    double *P1() { return partials; }
-    double *P2() { return partials + MAXB; }
-    double *P3() { return partials + 2 * MAXB; }
-};
-
-namespace {
-
-unsigned red_grid(const nek_ctx *c)
-{
-    long want = (c->nl + UPD_BS - 1) / UPD_BS;
-    long cap = std::min<long>(MAXB / 2, 4L * num_cu());
-    return (unsigned)std::max<long>(1, std::min(want, cap));
-}
-
-template <int NP> int ax_groups(const nek_ctx *c) { return (int)((c->E + epw_for(NP) - 1) / epw_for(NP)); }
-
-template <int NP> unsigned ax_grid(const nek_ctx *c)
-{
-    long want = ax_groups<NP>(c);
-    long cap = std::min<long>(MAXB, 8L * num_cu());
-    return (unsigned)std::max<long>(1, std::min(want, cap));
-}
-
-template <int NP, typename T, typename GT, bool CG>
-int launch_ax(nek_ctx *c, const T *src, T *p, T *w, const GT *g, const T *D, int it)
-{
-    constexpr int EPW = epw_for(NP);
-    constexpr int PD = pd_for<GT>();
-    constexpr int BS = EPW * NP * NP;
-    const size_t shm = 3ul * EPW * NP * NP * NP * sizeof(T);
-    static bool attr_done = false;
-    if (!attr_done) {
-        if (shm > 65536)
-            HIP_TRY(hipFuncSetAttribute((const void *)k_ax<NP, EPW, PD, T, GT, CG>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        attr_done = true;
+    switch (NP) {
+    case 2: return np_ops_2();
+    case 3: return np_ops_3();
+    case 4: return np_ops_4();
+    case 5: return np_ops_5();
+    case 6: return np_ops_6();
+    case 7: return np_ops_7();
+    case 8: return np_ops_8();
+    case 9: return np_ops_9();
+    case 10: return np_ops_10();
+    case 11: return np_ops_11();
+    case 12: return np_ops_12();
+    case 13: return np_ops_13();
+    case 14: return np_ops_14();
+    case 15: return np_ops_15();
+    case 16: return np_ops_16();
+    default: return nullptr;
     }
-    hipLaunchKernelGGL((k_ax<NP, EPW, PD, T, GT, CG>), dim3(ax_grid<NP>(c)), dim3(BS), shm, c->stream, src, p, w, g,
-                       D, c->sc, c->P1(), c->P2(), (int)red_grid(c), it, c->hist, (int)c->E, ax_groups<NP>(c));
-    HIP_TRY(hipGetLastError());
-    return NEK_OK;
 }
 
 int prof_take(nek_ctx *c)
@@ -186,6 +87,10 @@ int prof_take(nek_ctx *c)
     c->prof_pending.push_back((int)used);
     return (int)used;
 }
+
+}  // namespace nek
+
+namespace {
 
 // Fold the elapsed times of recorded triples into the totals (stream idle).
 int prof_resolve(nek_ctx *c)
@@ -204,27 +109,11 @@ int prof_resolve(nek_ctx *c)
     return NEK_OK;
 }
 
-// CG iteration it (1-based): operator + pAp partials, then gather/update +
-// rtr partials.  When sampled timing is on, every prof_every-th iteration is
+// CG iteration it (1-based): operator (+ the pending x update) and pAp
+// partials, then gather/update and rtr partials.  With final set, only the
+// operator kernel runs: it applies the last x update and publishes the final
+// state.  When sampled timing is on, every prof_every-th iteration is
 // bracketed by events.
-template <int NP, typename T, typename GT, typename XT>
-int launch_cg_iter(nek_ctx *c, int it, XT *x, T *r, T *p, T *w, const GT *g, const T *D)
-{
-    int slot = -1;
-    if (c->prof_every > 0 && (c->prof_tick++ % c->prof_every) == 0) {
-        if ((slot = prof_take(c)) < 0) return NEK_E_HIP;
-        HIP_TRY(hipEventRecord(c->prof_pool[3 * slot], c->stream));
-    }
-    int rc = launch_ax<NP, T, GT, true>(c, r, p, w, g, D, it);
-    if (rc) return rc;
-    if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 1], c->stream));
-    UpdArgs<T, XT> u{x, p, r, w, c->sc, c->P1(), c->P2(), (int)ax_grid<NP>(c), it, c->box, (unsigned)c->nl};
-    hipLaunchKernelGGL((k_cg_update<NP, T, XT>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, u);
-    HIP_TRY(hipGetLastError());
-    if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 2], c->stream));
-    return NEK_OK;
-}
-
 int ensure_hist(nek_ctx *c, long need)
 {
     if (need <= c->hist_cap) return NEK_OK;
@@ -266,55 +155,42 @@ int red_final(nek_ctx *c, int slot)
     return NEK_OK;
 }
 
+const NpOps *ops(const nek_ctx *c) { return np_ops(c->NP); }
+
 int glsc3_to_slot(nek_ctx *c, const void *a, const void *b, int dtype, int slot)
 {
-    NEK_NP_SWITCH(c->NP, {
-        if (dtype == NEK_F64)
-            hipLaunchKernelGGL((k_glsc3<NP, double, double>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream,
-                               (const double *)a, (const double *)b, c->P3(), c->box, (unsigned)c->nl);
-        else
-            hipLaunchKernelGGL((k_glsc3<NP, float, float>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream,
-                               (const float *)a, (const float *)b, c->P3(), c->box, (unsigned)c->nl);
-    });
-    HIP_TRY(hipGetLastError());
-    return red_final(c, slot);
+    const int rc = dtype == NEK_F64 ? ops(c)->glsc3_64(c, (const double *)a, (const double *)b)
+                                    : ops(c)->glsc3_32(c, (const float *)a, (const float *)b);
+    return rc ? rc : red_final(c, slot);
 }
 
-template <typename T> int gather_launch(nek_ctx *c, const T *in, T *out, bool weighted)
+int gather_launch(nek_ctx *c, const double *in, double *out, bool weighted)
 {
-    NEK_NP_SWITCH(c->NP, {
-        if (weighted)
-            hipLaunchKernelGGL((k_gather<NP, T, true>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, in, out,
-                               c->box, (unsigned)c->nl);
-        else
-            hipLaunchKernelGGL((k_gather<NP, T, false>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, in, out,
-                               c->box, (unsigned)c->nl);
-    });
-    HIP_TRY(hipGetLastError());
-    return NEK_OK;
+    return ops(c)->gather64(c, in, out, weighted);
 }
 
 int ax_local_launch(nek_ctx *c, const void *u, void *w, int dtype, int prec)
 {
-    NEK_NP_SWITCH(c->NP, {
-        if (dtype == NEK_F64)
-            return launch_ax<NP, double, double, false>(c, (const double *)u, nullptr, (double *)w, c->g64, c->D64, 0);
-        if (prec == NEK_PREC_BF16G)
-            return launch_ax<NP, float, uint16_t, false>(c, (const float *)u, nullptr, (float *)w, c->g16, c->D32, 0);
-        return launch_ax<NP, float, float, false>(c, (const float *)u, nullptr, (float *)w, c->g32, c->D32, 0);
-    });
-    return NEK_OK;
+    if (dtype == NEK_F64) return ops(c)->ax64(c, (const double *)u, (double *)w);
+    if (prec == NEK_PREC_BF16G) return ops(c)->ax16(c, (const float *)u, (float *)w);
+    return ops(c)->ax32(c, (const float *)u, (float *)w);
 }
 
 // r = b - M dssum(w) and red[slot] = glsc3(r, c, r)
 int resid_launch(nek_ctx *c, const double *b, const double *w, double *r, int slot)
 {
-    NEK_NP_SWITCH(c->NP, {
-        hipLaunchKernelGGL((k_resid<NP>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, b, w, r, c->P3(), c->box,
-                           (unsigned)c->nl);
-    });
-    HIP_TRY(hipGetLastError());
-    return red_final(c, slot);
+    const int rc = ops(c)->resid(c, b, w, r);
+    return rc ? rc : red_final(c, slot);
+}
+
+// one CG iteration of the context at precision prec on its work vectors
+int cg_iter(nek_ctx *c, int prec, int variant, int it, bool final, double *x)
+{
+    if (prec == NEK_PREC_FP64)
+        return ops(c)->cg_iter64(c, variant, it, final, x, c->r64, c->p64, c->w64, c->g64, c->D64);
+    if (prec == NEK_PREC_BF16G)
+        return ops(c)->cg_iter16(c, variant, it, final, x, c->r32, c->p32, c->w32, c->g16, c->D32);
+    return ops(c)->cg_iter32(c, variant, it, final, x, c->r32, c->p32, c->w32, c->g32, c->D32);
 }
 
 int start_launch(nek_ctx *c, int rslot, int hist_off, double stop_tol, int maxit, int stop_on_initial)
@@ -334,14 +210,15 @@ int read_scal(nek_ctx *c, Scal &h)
 
 // Enqueue CG iterations it = 1, 2, ... in chunks until the device reports
 // the run done or maxit iterations are enqueued; the flag of chunk k is read
-// while chunk k+1 runs.  Then the finishing kernel publishes the final state.
+// while chunk k+1 runs.  Then one more operator launch applies the pending x
+// update and publishes the final state.
 template <typename IterFn> int run_cg(nek_ctx *c, int maxit, IterFn iter)
 {
     int launched = 0, pend = -1, slot = 0;
     while (launched < maxit) {
         const int n = std::min(CHUNK_ITERS, maxit - launched);
         for (int q = 0; q < n; ++q) {
-            int rc = iter(launched + q + 1);
+            int rc = iter(launched + q + 1, false);
             if (rc) return rc;
         }
         launched += n;
@@ -354,9 +231,8 @@ template <typename IterFn> int run_cg(nek_ctx *c, int maxit, IterFn iter)
         pend = slot;
         slot ^= 1;
     }
-    hipLaunchKernelGGL(k_cg_finish, dim3(1), dim3(UPD_BS), 0, c->stream, c->sc, c->P2(), (int)red_grid(c),
-                       launched + 1, c->hist);
-    HIP_TRY(hipGetLastError());
+    int rc = iter(launched + 1, true);
+    if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(c->stream));
     return NEK_OK;
 }
@@ -371,10 +247,10 @@ int ensure_fp64_work(nek_ctx *c)
 // b = M dssum(f); x = M dssum(c x0) or 0; r = b - A x; red[0] = b.b, red[1] = r.r
 int cg_prologue(nek_ctx *c, const double *f, const double *x0, double *x, double *r)
 {
-    int rc = gather_launch<double>(c, f, c->b, false);
+    int rc = gather_launch(c, f, c->b, false);
     if (rc) return rc;
     if (x0) {
-        if ((rc = gather_launch<double>(c, x0, x == x0 ? c->w64 : x, true))) return rc;
+        if ((rc = gather_launch(c, x0, x == x0 ? c->w64 : x, true))) return rc;
         if (x == x0) HIP_TRY(hipMemcpyAsync(x, c->w64, c->nl * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         if ((rc = ax_local_launch(c, x, c->w64, NEK_F64, NEK_PREC_FP64))) return rc;
         if ((rc = resid_launch(c, c->b, c->w64, r, 1))) return rc;
@@ -388,11 +264,8 @@ int cg_prologue(nek_ctx *c, const double *f, const double *x0, double *x, double
 
 int cg_fp64_iterations(nek_ctx *c, double *x, int maxit)
 {
-    return run_cg(c, maxit, [&](int it) -> int {
-        NEK_NP_SWITCH(c->NP, {
-            return launch_cg_iter<NP, double, double, double>(c, it, x, c->r64, c->p64, c->w64, c->g64, c->D64);
-        });
-        return NEK_OK;
+    return run_cg(c, maxit, [&](int it, bool final) -> int {
+        return cg_iter(c, NEK_PREC_FP64, c->variant[NEK_PREC_FP64], it, final, x);
     });
 }
 
@@ -459,24 +332,13 @@ int solve_mixed(nek_ctx *c, const double *f, const double *x0, double tol, int m
             break;
         }
         // inner solve of A d = r with the FP32 operator
-        NEK_NP_SWITCH(c->NP, {
-            hipLaunchKernelGGL((k_inner_start<NP>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, c->r64, c->r32,
-                               c->d64, c->P3(), c->box, (unsigned)c->nl);
-        });
-        HIP_TRY(hipGetLastError());
+        if ((rc = ops(c)->inner_start(c, c->r64, c->r32, c->d64))) return rc;
         if ((rc = red_final(c, 1))) return rc;
         const double tau_k = std::min(0.5, std::max(tau, 0.3 * tol / rho));
         const int cap = std::min(inner_cap, maxit - total);
         if ((rc = start_launch(c, 1, total, tau_k, cap, 1))) return rc;
-        rc = run_cg(c, cap, [&](int it) -> int {
-            NEK_NP_SWITCH(c->NP, {
-                if (bf16)
-                    return launch_cg_iter<NP, float, uint16_t, double>(c, it, c->d64, c->r32, c->p32, c->w32, c->g16,
-                                                                       c->D32);
-                return launch_cg_iter<NP, float, float, double>(c, it, c->d64, c->r32, c->p32, c->w32, c->g32,
-                                                                c->D32);
-            });
-            return NEK_OK;
+        rc = run_cg(c, cap, [&](int it, bool final) -> int {
+            return cg_iter(c, c->prec, c->variant[c->prec], it, final, c->d64);
         });
         if (rc) return rc;
         if ((rc = read_scal(c, h))) return rc;
@@ -598,7 +460,7 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
 
     if (dalloc(c->D64, NP * NP) || dalloc(c->D32, NP * NP) || dalloc(c->g64, hg.size()) || dalloc(c->B, hB.size()) ||
         dalloc(c->perm, perm.size()) || dalloc(c->segptr, segptr.size()) || dalloc(c->segflag, segflag.size()) ||
-        dalloc(c->sc, 1) || dalloc(c->partials, 3 * MAXB))
+        dalloc(c->sc, 1) || dalloc(c->partials, 5 * MAXB))
         return fail(NEK_E_OOM);
     if (hipHostMalloc((void **)&c->hflags, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(NEK_E_OOM);
     for (auto &e : c->ev)
@@ -612,7 +474,7 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
         hipMemcpy(c->segptr, segptr.data(), segptr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->segflag, segflag.data(), segflag.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->sc, 0, sizeof(Scal)) != hipSuccess ||
-        hipMemset(c->partials, 0, 3 * MAXB * sizeof(double)) != hipSuccess)
+        hipMemset(c->partials, 0, 5 * MAXB * sizeof(double)) != hipSuccess)
         return fail(NEK_E_HIP);
     if ((rc = ensure_g(c, c->prec))) return fail(rc);
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(NEK_E_HIP);
@@ -738,6 +600,83 @@ int nek_prof_read(nek_ctx *c, int kernel, double *total_ms, int64_t *count, int 
         c->prof_ms[kernel] = 0;
         c->prof_n[kernel] = 0;
     }
+    return NEK_OK;
+}
+
+// Number of CG kernel configurations for this context's order.
+int nek_num_variants(const nek_ctx *c)
+{
+    if (!c) return NEK_E_ARG;
+    const NpOps *o = np_ops(c->NP);
+    return o ? o->nvariants : NEK_E_ARG;
+}
+
+int nek_set_variant(nek_ctx *c, int prec, int variant)
+{
+    if (!c || prec < NEK_PREC_FP64 || prec > NEK_PREC_BF16G) return NEK_E_ARG;
+    const int nv = nek_num_variants(c);
+    if (variant < 0 || variant >= nv) return NEK_E_ARG;
+    c->variant[prec] = variant;
+    return NEK_OK;
+}
+
+int nek_get_variant(const nek_ctx *c, int prec, int *variant)
+{
+    if (!c || !variant || prec < NEK_PREC_FP64 || prec > NEK_PREC_BF16G) return NEK_E_ARG;
+    *variant = c->variant[prec];
+    return NEK_OK;
+}
+
+int nek_tune(nek_ctx *c, int prec, int iters, double *us_per_iter, int *best)
+{
+    if (!c || prec < NEK_PREC_FP64 || prec > NEK_PREC_BF16G || iters < 2) return NEK_E_ARG;
+    int rc;
+    if ((rc = ensure_fp64_work(c)) || (rc = ensure_g(c, prec)) || (rc = ensure_hist(c, iters + 1))) return rc;
+    if (dalloc(c->d64, c->nl) || dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) || dalloc(c->w32, c->nl))
+        return NEK_E_OOM;
+    // synthetic SPD system: b = M dssum(1), x0 = 0
+    if ((rc = fill<double>(c, c->w64, 1.0, c->nl)) || (rc = gather_launch(c, c->w64, c->b, false)) ||
+        (rc = glsc3_to_slot(c, c->b, c->b, NEK_F64, 0)))
+        return rc;
+    const int nv = nek_num_variants(c);
+    const int saved_prof = c->prof_every;
+    c->prof_every = 0;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best_t = INFINITY;
+    int best_v = c->variant[prec];
+    for (int v = 0; v < nv && rc == NEK_OK; ++v) {
+        float ms = 0;
+        for (int rep = 0; rep < 2 && rc == NEK_OK; ++rep) {   // first pass warms up
+            if (prec == NEK_PREC_FP64) {
+                HIP_TRY(hipMemcpyAsync(c->r64, c->b, c->nl * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+                if ((rc = glsc3_to_slot(c, c->r64, c->r64, NEK_F64, 1)) || (rc = fill<double>(c, c->d64, 0.0, c->nl)))
+                    break;
+            } else {
+                if ((rc = ops(c)->inner_start(c, c->b, c->r32, c->d64))) break;
+                if ((rc = red_final(c, 1))) break;
+            }
+            if ((rc = start_launch(c, 1, 0, 0.0, iters, 0))) break;
+            HIP_TRY(hipEventRecord(e0, c->stream));
+            rc = run_cg(c, iters, [&](int it, bool final) -> int { return cg_iter(c, prec, v, it, final, c->d64); });
+            HIP_TRY(hipEventRecord(e1, c->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        }
+        const double t = 1e3 * ms / iters;
+        if (us_per_iter) us_per_iter[v] = t;
+        if (t < best_t) {
+            best_t = t;
+            best_v = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->prof_every = saved_prof;
+    if (rc) return rc;
+    c->variant[prec] = best_v;
+    if (best) *best = best_v;
     return NEK_OK;
 }
 

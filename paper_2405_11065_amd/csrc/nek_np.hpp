@@ -1,0 +1,144 @@
+// Launchers of the order-dependent kernels, instantiated once per order in
+// nek_npNN.hip.  Internal header.
+#pragma once
+#include "nek_internal.hpp"
+
+namespace nek {
+
+template <int NP> struct OpsImpl {
+    template <int EPW, int PD, typename T, typename GT, bool CG, typename XT = T>
+    static int launch_ax(nek_ctx *c, const T *src, T *p, T *w, const GT *g, const T *D, int it, XT *x = nullptr)
+    {
+        constexpr int BS = EPW * NP * NP;
+        const size_t shm = 3ul * EPW * NP * NP * NP * sizeof(T);
+        static bool attr_done = false;
+        if (!attr_done) {
+            if (shm > 65536)
+                HIP_TRY(hipFuncSetAttribute((const void *)k_ax<NP, EPW, PD, T, GT, CG, XT>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+            attr_done = true;
+        }
+        const unsigned grid = ax_grid(c, EPW);
+        hipLaunchKernelGGL((k_ax<NP, EPW, PD, T, GT, CG, XT>), dim3(grid), dim3(BS), shm, c->stream, src, p, w, g, D,
+                           x, c->sc, c->P1(it), c->P1(it - 1), c->P2(it - 1), (int)grid, it, c->hist, (int)c->E,
+                           ax_groups(c, EPW));
+        HIP_TRY(hipGetLastError());
+        return NEK_OK;
+    }
+
+    // CG iteration it (1-based): operator (+ the pending x update) and pAp
+    // partials, then gather/update and rtr partials.  With final set, only
+    // the operator kernel runs: it applies the last x update and publishes
+    // the final state.  Sampled timing brackets every prof_every-th
+    // iteration with events.
+    template <typename T, typename GT>
+    static int cg_iter(nek_ctx *c, int variant, int it, bool final, double *x, T *r, T *p, T *w, const GT *g,
+                       const T *D)
+    {
+        return with_variant<NP, GT>(variant, [&](auto epw_c, auto pd_c) -> int {
+            constexpr int EPW = decltype(epw_c)::value, PD = decltype(pd_c)::value;
+            if (final) return launch_ax<EPW, PD, T, GT, true, double>(c, r, p, w, g, D, it, x);
+            int slot = -1;
+            if (c->prof_every > 0 && (c->prof_tick++ % c->prof_every) == 0) {
+                if ((slot = prof_take(c)) < 0) return NEK_E_HIP;
+                HIP_TRY(hipEventRecord(c->prof_pool[3 * slot], c->stream));
+            }
+            int rc = launch_ax<EPW, PD, T, GT, true, double>(c, r, p, w, g, D, it, x);
+            if (rc) return rc;
+            if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 1], c->stream));
+            const unsigned grid = ax_grid(c, EPW);
+            hipLaunchKernelGGL((k_cg_update<NP, EPW, T>), dim3(grid), dim3(EPW * NP * NP), 0, c->stream, r, w, c->sc,
+                               c->P1(it), (int)grid, c->P2(it), it, c->box, (int)c->E, ax_groups(c, EPW));
+            HIP_TRY(hipGetLastError());
+            if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 2], c->stream));
+            return NEK_OK;
+        });
+    }
+
+    static int cg_iter64(nek_ctx *c, int v, int it, bool final, double *x, double *r, double *p, double *w,
+                         const double *g, const double *D)
+    {
+        return cg_iter<double, double>(c, v, it, final, x, r, p, w, g, D);
+    }
+    static int cg_iter32(nek_ctx *c, int v, int it, bool final, double *x, float *r, float *p, float *w,
+                         const float *g, const float *D)
+    {
+        return cg_iter<float, float>(c, v, it, final, x, r, p, w, g, D);
+    }
+    static int cg_iter16(nek_ctx *c, int v, int it, bool final, double *x, float *r, float *p, float *w,
+                         const uint16_t *g, const float *D)
+    {
+        return cg_iter<float, uint16_t>(c, v, it, final, x, r, p, w, g, D);
+    }
+
+    static int ax64(nek_ctx *c, const double *u, double *w)
+    {
+        return launch_ax<epw_for(NP), pd_for<double>(), double, double, false>(c, u, nullptr, w, c->g64, c->D64, 0);
+    }
+    static int ax32(nek_ctx *c, const float *u, float *w)
+    {
+        return launch_ax<epw_for(NP), pd_for<float>(), float, float, false>(c, u, nullptr, w, c->g32, c->D32, 0);
+    }
+    static int ax16(nek_ctx *c, const float *u, float *w)
+    {
+        return launch_ax<epw_for(NP), pd_for<uint16_t>(), float, uint16_t, false>(c, u, nullptr, w, c->g16, c->D32,
+                                                                                  0);
+    }
+
+    static int gather64(nek_ctx *c, const double *in, double *out, bool weighted)
+    {
+        if (weighted)
+            hipLaunchKernelGGL((k_gather<NP, double, true>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, in, out,
+                               c->box, (unsigned)c->nl);
+        else
+            hipLaunchKernelGGL((k_gather<NP, double, false>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, in, out,
+                               c->box, (unsigned)c->nl);
+        HIP_TRY(hipGetLastError());
+        return NEK_OK;
+    }
+
+    static int glsc3_64(nek_ctx *c, const double *a, const double *b)
+    {
+        hipLaunchKernelGGL((k_glsc3<NP, double, double>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, a, b,
+                           c->P3(), c->box, (unsigned)c->nl);
+        HIP_TRY(hipGetLastError());
+        return NEK_OK;
+    }
+    static int glsc3_32(nek_ctx *c, const float *a, const float *b)
+    {
+        hipLaunchKernelGGL((k_glsc3<NP, float, float>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, a, b, c->P3(),
+                           c->box, (unsigned)c->nl);
+        HIP_TRY(hipGetLastError());
+        return NEK_OK;
+    }
+
+    static int resid(nek_ctx *c, const double *b, const double *w, double *r)
+    {
+        hipLaunchKernelGGL((k_resid<NP>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, b, w, r, c->P3(), c->box,
+                           (unsigned)c->nl);
+        HIP_TRY(hipGetLastError());
+        return NEK_OK;
+    }
+
+    static int inner_start(nek_ctx *c, const double *r64, float *r32, double *d)
+    {
+        hipLaunchKernelGGL((k_inner_start<NP>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, r64, r32, d, c->P3(),
+                           c->box, (unsigned)c->nl);
+        HIP_TRY(hipGetLastError());
+        return NEK_OK;
+    }
+};
+
+template <int NP> const NpOps *make_np_ops()
+{
+    using I = OpsImpl<NP>;
+    static const NpOps ops{n_variants<NP>(), &I::cg_iter64, &I::cg_iter32, &I::cg_iter16, &I::ax64, &I::ax32,
+                           &I::ax16, &I::gather64, &I::glsc3_64, &I::glsc3_32, &I::resid, &I::inner_start};
+    return &ops;
+}
+
+}  // namespace nek
+
+// One translation unit per order: nek_npNN.hip expands this.
+#define NEK_DEFINE_NP_OPS(NPV) \
+    namespace nek { const NpOps *np_ops_##NPV() { return make_np_ops<NPV>(); } }

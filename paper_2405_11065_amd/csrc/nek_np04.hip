@@ -1,0 +1,4 @@
+// Kernels of libnek instantiated for N + 1 = 4.
+#include "nek_np.hpp"
+
+NEK_DEFINE_NP_OPS(4)

@@ -35,6 +35,21 @@ def kernel_stats(asm: str):
     return stats
 
 
+def check_dir(build_dir: str, report: bool = False):
+    """Scan the gfx950 device assembly that the compile kept in build_dir."""
+    files = sorted(f for f in os.listdir(build_dir) if f.endswith(".s") and "amdgcn" in f)
+    if not files:
+        raise RuntimeError("no device assembly found to check")
+    for f in files:
+        asm = open(os.path.join(build_dir, f)).read()
+        bad = FORBIDDEN.findall(asm)
+        if bad:
+            raise RuntimeError(f"{f}: device code writes through the scalar cache: {sorted(set(bad))}")
+        if report:
+            for name, st in sorted(kernel_stats(asm).items()):
+                print(f"{st['vgpr']!s:>4} vgpr {st['sgpr']!s:>4} sgpr {st['spill']!s:>4} spill {st['lds']!s:>6} lds  {name}")
+
+
 def check_sources(hipcc: str, flags: list[str], sources: list[str], report: bool = False):
     for src in sources:
         asm = device_asm(hipcc, flags, src)
@@ -48,8 +63,4 @@ def check_sources(hipcc: str, flags: list[str], sources: list[str], report: bool
 
 
 if __name__ == "__main__":
-    import sys
-    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
-    from paper_2405_11065_amd import build as b
-    check_sources(b.hipcc(), b.HIP_FLAGS + ["-I", b.INCLUDE, "-I", b.CSRC],
-                  [s for s in b.SOURCES if s.endswith(".hip")], report=True)
+    check_dir(os.path.join(os.path.dirname(os.path.abspath(__file__)), "_build"), report=True)

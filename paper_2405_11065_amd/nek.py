@@ -28,7 +28,8 @@ PREC_NAMES = {"fp64": NEK_PREC_FP64, "fp32": NEK_PREC_FP32, "bf16g": NEK_PREC_BF
 
 # every entry point declared in include/nek.h
 EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_ax_local", "nek_ax",
-           "nek_dssum", "nek_glsc3", "nek_cg_solve", "nek_prof_enable", "nek_prof_read", "nek_strerror")
+           "nek_dssum", "nek_glsc3", "nek_cg_solve", "nek_prof_enable", "nek_prof_read", "nek_num_variants",
+           "nek_tune", "nek_set_variant", "nek_get_variant", "nek_strerror")
 
 
 class nek_mesh(ctypes.Structure):
@@ -81,6 +82,11 @@ def load(path: str = LIB_PATH):
     lib.nek_cg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, vp, ctypes.POINTER(nek_stats), vp]
     lib.nek_prof_enable.argtypes = [vp, ctypes.c_int]
     lib.nek_prof_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), i64p, ctypes.c_int]
+    lib.nek_num_variants.argtypes = [vp]
+    lib.nek_tune.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_int)]
+    lib.nek_set_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.nek_get_variant.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.nek_strerror.argtypes = [ctypes.c_int]
     lib.nek_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -240,6 +246,30 @@ class Context:
         _check(self._lib.nek_prof_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n), int(reset)),
                "nek_prof_read")
         return ms.value, n.value
+
+    def num_variants(self) -> int:
+        n = self._lib.nek_num_variants(self._h)
+        _check(min(n, 0), "nek_num_variants")
+        return n
+
+    def tune(self, prec, iters: int = 20):
+        """Time every CG kernel configuration; select the fastest.  Returns (best, us_per_iter list)."""
+        pv = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+        n = self.num_variants()
+        us = (ctypes.c_double * n)()
+        best = ctypes.c_int()
+        _check(self._lib.nek_tune(self._h, pv, int(iters), us, ctypes.byref(best)), "nek_tune")
+        return best.value, list(us)
+
+    def set_variant(self, prec, variant: int):
+        pv = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+        _check(self._lib.nek_set_variant(self._h, pv, int(variant)), "nek_set_variant")
+
+    def get_variant(self, prec) -> int:
+        pv = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+        v = ctypes.c_int()
+        _check(self._lib.nek_get_variant(self._h, pv, ctypes.byref(v)), "nek_get_variant")
+        return v.value
 
     def cg_solve(self, f, x0=None, tol=1e-8, maxit=1000, x=None, history=False, raise_on_noconv=False):
         """Solve A x = M dssum(f).  Returns (x, stats dict, history or None)."""
