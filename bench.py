@@ -77,6 +77,41 @@ def cpu_baseline(f, budget_s=15.0):
                       f"({dt:.1f} s), setup excluded"}
 
 
+def big_case(torch, nek, synth, steps=2):
+    """32^3 elements on [0,1]^3, interior vertices moved up to 10 %, N=9
+    (32.8 M local points), f = B (sin pi x sin pi y sin pi z + N(0,1e-3)):
+    mixed solve with BF16-stored g against FP64 CG, tol 1e-8."""
+    nel = (32, 32, 32)
+    vtx = synth.box_vertices(nel, hi=(1.0, 1.0, 1.0), perturb=0.1, seed=synth.SEED_C3_VERTICES)
+    ctx = nek.Context(nel, 9, vtx=vtx, prec="bf16g")
+    X = ctx.get(nek.NEK_GET_XYZ)
+    B = ctx.get(nek.NEK_GET_B).reshape(ctx.E, -1)
+    noise = synth.normal_noise(ctx.nl, 1e-3, synth.SEED_C3).reshape(ctx.E, -1)
+    f = torch.from_numpy((B * (synth.sine_field(X) + noise)).ravel()).cuda()
+    del X, B, noise
+    x = ctx.new_vector()
+    out = {"local_points": ctx.nl}
+    for prec in ("bf16g", "fp64"):
+        ctx.set_prec(prec)
+        ctx.tune(prec, iters=10)
+        ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = 0
+        for _ in range(steps):
+            _, st, _ = ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+            its += st["iters"]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[prec] = {"ms_per_solve": round(dt * 1e3, 2), "iters": its / steps, "outer": st["outer_iters"],
+                     "GDOF_iter_per_s": round(ctx.nl * its / steps / dt / 1e9, 3), "true_rel_res": st["rel_res"]
+                     if prec != "fp64" else None}
+    out["speedup_vs_fp64"] = round(out["fp64"]["ms_per_solve"] / out["bf16g"]["ms_per_solve"], 3)
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def profile_sequence(torch, nek, synth, variants=""):
     """A short sequence for counter collection (few dispatches)."""
     ctx = nek.Context(NEL, N, prec="fp32")
@@ -116,6 +151,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-big", action="store_true", help="skip the 32^3 deformed-mesh BF16 measurement")
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for hardware-counter runs: 40 mixed and 40 FP64 CG iterations, "
                          "5 nek_ax per precision and a 256 MiB copy for calibration")
@@ -195,6 +231,9 @@ def main():
         axd[name] = {"us": round(t * 1e6, 2), "GBps": round(b / t / 1e9, 1),
                      "frac_hbm": round(b / t / 1e9 / PEAK_HBM_GBS, 3)}
 
+    # ---- secondary: 32^3 deformed mesh, N=9, manufactured forcing, BF16 g vs FP64
+    big = None if args.no_big else big_case(torch, nek, synth)
+
     bpp = cg_operator_bytes_per_point(4, 4, 8)
     ax_avg_s = ax_ms / max(ax_n, 1) / 1e3
     achieved = bpp * nl / ax_avg_s / 1e9 if ax_n else None
@@ -228,6 +267,7 @@ def main():
                      "bytes_per_point": bpp, "avg_us": round(ax_avg_s * 1e6, 2), "sampled_launches": ax_n,
                      "update_kernel_avg_us": round(up_ms / max(up_n, 1) * 1e3, 2)},
         "cpu_baseline": cpu,
+        "deformed_32x32x32_N9": big,
     }
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -76,13 +76,18 @@ typedef struct {
 
 typedef struct {
     int prec;                /* nek_prec of nek_cg_solve                                */
-    double inner_tol;        /* mixed: inner relative tolerance; 0 = 1e-4 (FP32 g) or
-                                1e-2 (BF16 g)                                           */
+    double inner_tol;        /* mixed: residual reduction of each inner run before the
+                                next FP64 true-residual update; 0 = 1e-4 (FP32 g,
+                                restarted) or 1e-2 (BF16 g, or reliable update)      */
     int inner_maxit;         /* mixed: inner iteration cap per refinement step; 0 = 4000 */
     int max_outer;           /* mixed: refinement steps cap; 0 = 30                      */
     int fp64_fallback;       /* mixed: 1 = when a refinement step fails to halve the
                                 true residual, finish with FP64 CG from the current x  */
     int elts_per_wg;         /* reserved, must be 0                                      */
+    int refine_mode;         /* mixed: 0 = default (1);
+                                1 = restart CG after each true-residual update;
+                                2 = reliable update: replace r by the FP64 true
+                                    residual and continue the search direction   */
 } nek_opts;
 
 typedef struct {

@@ -54,6 +54,7 @@ struct Scal {
     int hist_off;         // history index of iteration 0 of this run
     int k2flag[2];        // status of k_cg_update(it) in slot it & 1
     int done_host;        // set once a run is done; polled by the host
+    int resume;           // 1: the run continues the previous search direction
 };
 
 struct Box { int nx, ny, nz; };
@@ -164,7 +165,7 @@ __device__ __forceinline__ Begin cg_begin(Scal *__restrict__ sc, const double *_
     IterState &cur = B.cur;
     if (!prev.done) {
         if (it == 1) {
-            cur.beta = 0.0;
+            if (!sc->resume) cur.beta = 0.0;   // a resumed run keeps beta set at its start
             cur.iter = 0;
         } else {
             const int f = sc->k2flag[(it - 1) & 1];
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T
             return;
         }
         beta = (T)B.cur.beta;
-        first = it == 1;
+        first = it == 1 && !sc->resume;
     }
     const int i = ij % NP, j = ij / NP;
     T *sue = su + el * NP3, *sre = sr + el * NP3, *sse = ss + el * NP3;

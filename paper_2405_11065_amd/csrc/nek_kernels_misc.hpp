@@ -8,16 +8,19 @@ namespace nek {
 
 // Start of a CG run: rtz = red[rslot]; stop and history denominators; the
 // initial residual test.
+// A resumed run (rtz_prev > 0) keeps the search direction: its first
+// p = r + beta p with beta = rtz / rtz_prev (reliable update).
 __global__ void k_cg_start(Scal *sc, double *hist, int rslot, int hist_off, double stop_tol, int maxit,
-                           int stop_on_initial)
+                           int stop_on_initial, double rtz_prev)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double bb = sc->red[0];
     const double rtz = sc->red[rslot];
     IterState s{};
     s.rtz = rtz;
-    s.beta = 0.0;
+    s.beta = rtz_prev > 0 ? rtz / rtz_prev : 0.0;
     s.iter = 0;
+    sc->resume = rtz_prev > 0 ? 1 : 0;
     sc->hist_den = bb;
     sc->stop_den = stop_on_initial ? rtz : bb;
     sc->stop_tol = stop_tol;

@@ -193,10 +193,11 @@ int cg_iter(nek_ctx *c, int prec, int variant, int it, bool final, double *x)
     return ops(c)->cg_iter32(c, variant, it, final, x, c->r32, c->p32, c->w32, c->g32, c->D32);
 }
 
-int start_launch(nek_ctx *c, int rslot, int hist_off, double stop_tol, int maxit, int stop_on_initial)
+int start_launch(nek_ctx *c, int rslot, int hist_off, double stop_tol, int maxit, int stop_on_initial,
+                 double rtz_prev = 0.0)
 {
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(64), 0, c->stream, c->sc, c->hist, rslot, hist_off, stop_tol, maxit,
-                       stop_on_initial);
+                       stop_on_initial, rtz_prev);
     HIP_TRY(hipGetLastError());
     return NEK_OK;
 }
@@ -299,7 +300,14 @@ int solve_mixed(nek_ctx *c, const double *f, const double *x0, double tol, int m
     if (dalloc(c->d64, c->nl) || dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) || dalloc(c->w32, c->nl))
         return NEK_E_OOM;
     const bool bf16 = c->prec == NEK_PREC_BF16G;
-    const double tau = c->opts.inner_tol > 0 ? c->opts.inner_tol : (bf16 ? 1e-2 : 1e-4);
+    // Restarted refinement by default: on the benchmarked meshes it needs
+    // fewer FP32 iterations than reliable updates (which keep p across
+    // true-residual replacements and so inherit FP32 CG's loss of
+    // orthogonality), and BF16 g's ~2^-8 operator error would spoil kept
+    // directions altogether.
+    const bool keep_p = c->opts.refine_mode == 2;
+    const double tau = c->opts.inner_tol > 0 ? c->opts.inner_tol : (bf16 || keep_p ? 1e-2 : 1e-4);
+    double rtz_last = 0.0;   // recursive rtz at the end of the previous inner run
     const int inner_cap = c->opts.inner_maxit > 0 ? c->opts.inner_maxit : 4000;
     const int max_outer = c->opts.max_outer > 0 ? c->opts.max_outer : 30;
 
@@ -336,13 +344,14 @@ int solve_mixed(nek_ctx *c, const double *f, const double *x0, double tol, int m
         if ((rc = red_final(c, 1))) return rc;
         const double tau_k = std::min(0.5, std::max(tau, 0.3 * tol / rho));
         const int cap = std::min(inner_cap, maxit - total);
-        if ((rc = start_launch(c, 1, total, tau_k, cap, 1))) return rc;
+        if ((rc = start_launch(c, 1, total, tau_k, cap, 1, keep_p ? rtz_last : 0.0))) return rc;
         rc = run_cg(c, cap, [&](int it, bool final) -> int {
             return cg_iter(c, c->prec, c->variant[c->prec], it, final, c->d64);
         });
         if (rc) return rc;
         if ((rc = read_scal(c, h))) return rc;
         total += h.fin.iter;
+        rtz_last = h.fin.rtz;
         if (h.fin.status) { status = h.fin.status; break; }
         hipLaunchKernelGGL(k_axpy1, dim3(4 * num_cu()), dim3(256), 0, c->stream, x, c->d64, (unsigned long)c->nl);
         HIP_TRY(hipGetLastError());

@@ -39,7 +39,8 @@ class nek_mesh(ctypes.Structure):
 
 class nek_opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
-                ("max_outer", ctypes.c_int), ("fp64_fallback", ctypes.c_int), ("elts_per_wg", ctypes.c_int)]
+                ("max_outer", ctypes.c_int), ("fp64_fallback", ctypes.c_int), ("elts_per_wg", ctypes.c_int),
+                ("refine_mode", ctypes.c_int)]
 
 
 class nek_stats(ctypes.Structure):
@@ -115,7 +116,7 @@ class Context:
     """One box mesh of order N on the current GPU (nek_setup / nek_free)."""
 
     def __init__(self, nel, N, vtx=None, lo=(0.0, 0.0, 0.0), hi=None, prec="fp64", inner_tol=0.0,
-                 inner_maxit=0, max_outer=0, fp64_fallback=1, stream=None):
+                 inner_maxit=0, max_outer=0, fp64_fallback=1, refine_mode=0, stream=None):
         torch = _torch()
         self._lib = load()
         self.N = int(N)
@@ -140,6 +141,7 @@ class Context:
         o.inner_maxit = int(inner_maxit)
         o.max_outer = int(max_outer)
         o.fp64_fallback = int(fp64_fallback)
+        o.refine_mode = int(refine_mode)
         self.stream = torch.cuda.current_stream() if stream is None else stream
         h = ctypes.c_void_p()
         _check(self._lib.nek_setup(ctypes.byref(m), self.N, ctypes.byref(o), ctypes.c_void_p(self.stream.cuda_stream),

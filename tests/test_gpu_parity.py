@@ -228,18 +228,19 @@ def test_cg_deterministic():
     ctx.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16g"])
-def test_mixed_precision_solve(prec):
+@pytest.mark.parametrize("prec,mode", [("fp32", 0), ("fp32", 1), ("fp32", 2), ("bf16g", 0), ("bf16g", 2)])
+def test_mixed_precision_solve(prec, mode):
     """Deformed [0,1]^3 mesh, manufactured forcing: the refined mixed solve
-    reaches a true FP64 residual of 1e-8 (judged by the oracle)."""
+    (mode 1: restarted refinement, 2: reliable update, 0: default for the
+    storage) reaches a true FP64 residual of 1e-8 (judged by the oracle)."""
     N, nel = 9, (5, 4, 4)
-    ctx, P = make(N, nel, perturb=0.1, seed=33, hi=(1.0, 1.0, 1.0), prec=prec, want_X=True)
+    ctx, P = make(N, nel, perturb=0.1, seed=33, hi=(1.0, 1.0, 1.0), prec=prec, want_X=True, refine_mode=mode)
     noise = synth.normal_noise(P.nl, 1e-3, 34).reshape(P.E, -1)
     f_or = (P.B * (synth.sine_field(P.X) + noise)).ravel()
     Bg = ctx.get(nek.NEK_GET_B).reshape(P.E, -1)
     Xg = ctx.get(nek.NEK_GET_XYZ)
     f_gpu = (Bg * (synth.sine_field(Xg) + noise)).ravel()
-    _case(f"cg mixed {prec}")
+    _case(f"cg mixed {prec} mode {mode}")
     x, st, hist = ctx.cg_solve(dev(f_gpu), tol=1e-8, maxit=5000, history=True)
     xh = host(x)
     rho = P.true_residual(xh, f_or)
@@ -250,4 +251,60 @@ def test_mixed_precision_solve(prec):
     assert st["status"] == 0
     assert rho <= 1e-8
     assert dx <= 1e-7
+    ctx.close()
+
+
+def manufactured_load(ctx, P, noise):
+    """f = B (sin pi x sin pi y sin pi z + noise) for each side from its own B and X."""
+    f_or = (P.B * (synth.sine_field(P.X) + noise)).ravel()
+    Bg = ctx.get(nek.NEK_GET_B).reshape(P.E, -1)
+    Xg = ctx.get(nek.NEK_GET_XYZ)
+    return f_or, (Bg * (synth.sine_field(Xg) + noise)).ravel()
+
+
+def test_full_size_16cubed_N9():
+    """The benchmarked workload itself: 16^3 unit cubes, N=9, f ~ U[0,1) seed 2,
+    tol 1e-8; FP64 and mixed solves judged by the oracle's true residual."""
+    nel, N = (16, 16, 16), 9
+    vtx = synth.box_vertices(nel)
+    _case("setup 16^3 N=9")
+    ctx = nek.Context(nel, N, vtx=vtx, prec="fp64")
+    P = oracle.Problem(N, nel, vtx)
+    f = synth.uniform_load(P.nl, synth.SEED_C2)
+    fd = dev(f)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        ctx.set_prec(prec)
+        ctx.tune(prec, iters=10)
+        _case(f"cg 16^3 N=9 {prec}")
+        x, st, _ = ctx.cg_solve(fd, tol=1e-8, maxit=20000)
+        xh = host(x)
+        res[prec] = (xh, st)
+        rho = P.true_residual(xh, f)
+        print(f"  {prec}: iters {st['iters']} outer {st['outer_iters']} rho* {rho:.2e}")
+        assert st["status"] == 0 and rho <= 1e-8
+    dx = np.linalg.norm(res["fp32"][0] - res["fp64"][0]) / np.linalg.norm(res["fp64"][0])
+    print(f"  |x_mixed - x_fp64| / |x_fp64| = {dx:.2e}")
+    assert dx <= 1e-6
+    ctx.close()
+
+
+def test_full_size_32cubed_N9_bf16g():
+    """32^3 elements on [0,1]^3 with interior vertices moved up to 10 %, N=9
+    (32.8 M local points), manufactured forcing + N(0, 1e-3) noise, mixed
+    solve with BF16-stored g: true FP64 residual <= 1e-8 by the oracle."""
+    nel, N = (32, 32, 32), 9
+    vtx = synth.box_vertices(nel, hi=(1.0, 1.0, 1.0), perturb=0.1, seed=synth.SEED_C3_VERTICES)
+    _case("setup 32^3 N=9 bf16g")
+    ctx = nek.Context(nel, N, vtx=vtx, prec="bf16g")
+    P = oracle.Problem(N, nel, vtx, want_X=True)
+    noise = synth.normal_noise(P.nl, 1e-3, synth.SEED_C3).reshape(P.E, -1)
+    f_or, f_gpu = manufactured_load(ctx, P, noise)
+    ctx.tune("bf16g", iters=10)
+    _case("cg 32^3 N=9 bf16g")
+    x, st, _ = ctx.cg_solve(dev(f_gpu), tol=1e-8, maxit=20000)
+    rho = P.true_residual(host(x), f_or)
+    print(f"  bf16g: iters {st['iters']} outer {st['outer_iters']} fp64 {st['fp64_iters']} "
+          f"t {st['t_solve_s']:.3f}s rho* {rho:.2e}")
+    assert st["status"] == 0 and rho <= 1e-8
     ctx.close()
