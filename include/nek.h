@@ -229,6 +229,86 @@ int nek_tune(nek_ctx *ctx, int prec, int iters, double *us_per_iter, int *best);
 int nek_set_variant(nek_ctx *ctx, int prec, int variant);
 int nek_get_variant(const nek_ctx *ctx, int prec, int *variant);
 
+/* ------------------------------------------------------------------ batches
+ *
+ * A batch holds many independent problems, each with its own box mesh and
+ * order N, solved together: every CG iteration advances all of them with one
+ * launch of the operator kernel and one of the gather/update kernel per
+ * distinct order (one stream per order), a chunk of iterations is recorded
+ * once as a HIP graph and replayed, and each problem stops at its own
+ * tolerance or cap while the others continue.  Each problem computes exactly
+ * what nek_cg_solve computes on a context of the same mesh, order, options
+ * and kernel configuration: with equal configurations the results are
+ * bit-identical.
+ */
+typedef struct nek_batch nek_batch;
+
+#define NEK_MAX_VARIANTS 6       /* bound on nek_num_variants for any N          */
+#define NEK_BATCH_NO_GRAPH 1     /* nek_batch_solve flag: plain launches, no graph */
+
+/*
+ * nek_batch_setup -- one context per problem i (meshes[i], order N[i], the
+ * common opts, whose prec applies to every problem).  The batch creates and
+ * owns its streams; member contexts run on the batch's main stream.  stream
+ * is the caller's stream: setup and every solve wait for the work already
+ * enqueued on it.  1 <= nprob <= 4096.  Errors as nek_setup (nothing is left
+ * allocated).
+ */
+int nek_batch_setup(int nprob, const nek_mesh *meshes, const int *N, const nek_opts *opts, void *stream,
+                    nek_batch **out);
+
+/* nek_batch_free -- release the batch, its member contexts and streams. */
+void nek_batch_free(nek_batch *batch);
+
+/* Number of problems (or a negative status). */
+int nek_batch_size(const nek_batch *batch);
+
+/*
+ * nek_batch_ctx -- the member context of problem i, owned by the batch (do
+ * not free it).  It may be used with every nek_* call; its work runs on the
+ * batch's stream, and calls that do not synchronise need a
+ * hipDeviceSynchronize (or a later synchronising call) before the caller's
+ * stream reads their output.
+ */
+int nek_batch_ctx(nek_batch *batch, int i, nek_ctx **out);
+
+/*
+ * nek_batch_orders -- number of distinct orders in the batch; N_out (may be
+ * NULL, else at least 15 entries) receives them in ascending order.
+ */
+int nek_batch_orders(const nek_batch *batch, int *N_out);
+
+/*
+ * nek_batch_tune -- per order, time `iters` (>= 2) batched CG iterations of
+ * all problems of that order under every kernel configuration (synthetic
+ * SPD systems, one warm-up pass each) and keep the fastest for later batched
+ * solves at precision prec; the member contexts get the same configuration.
+ * us_per_iter (may be NULL) receives NEK_MAX_VARIANTS entries per order, in
+ * the order of nek_batch_orders (unused entries 0).  Overwrites the members'
+ * work vectors, not caller memory; synchronises.
+ */
+int nek_batch_tune(nek_batch *batch, int prec, int iters, double *us_per_iter);
+
+/* Set the configuration of all problems of order N, or read problem i's. */
+int nek_batch_set_variant(nek_batch *batch, int prec, int N, int variant);
+int nek_batch_get_variant(const nek_batch *batch, int prec, int i, int *variant);
+
+/*
+ * nek_batch_solve -- solve every problem i as nek_cg_solve(ctx_i, f[i],
+ * x0 ? x0[i] : NULL, tol, maxit, x[i], &stats[i], NULL) would, together.
+ * f, x0, x are HOST arrays of nprob DEVICE pointers (x0 itself or any entry
+ * may be NULL); stats (may be NULL) is a host array of nprob entries, each
+ * with its problem's status; t_solve_s is the wall time of the whole batch.
+ * flags: NEK_BATCH_NO_GRAPH enqueues every launch instead of replaying the
+ * recorded chunk.  Returns the most negative status of any problem, else
+ * NEK_NOCONV if any problem did not converge, else NEK_OK.  Synchronises.
+ */
+int nek_batch_solve(nek_batch *batch, const double *const *f, const double *const *x0, double tol, int maxit,
+                    double *const *x, nek_stats *stats, int flags);
+
+/* Totals since setup: chunks of iterations launched, graphs recorded. */
+int nek_batch_counters(const nek_batch *batch, int64_t *chunks, int64_t *captures);
+
 /* nek_strerror -- static description of a status code. */
 const char *nek_strerror(int status);
 

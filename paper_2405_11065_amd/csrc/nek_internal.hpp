@@ -16,7 +16,6 @@
 namespace nek {
 
 constexpr int MAX_NP = 16;        // N <= 15
-constexpr int MAXB = 2048;        // cap on workgroups of any reducing kernel
 constexpr int CHUNK_ITERS = 16;   // CG iterations enqueued between flag polls
 
 #define HIP_TRY(expr)                                            \
@@ -181,8 +180,51 @@ struct NpOps {
     int (*resid)(nek_ctx *, const double *b, const double *w, double *r);
     // r32 = (float) r64, d = 0, partials of glsc3(r32, c, r32)
     int (*inner_start)(nek_ctx *, const double *r64, float *r32, double *d);
+    // elements per workgroup of a CG variant
+    int (*variant_epw)(int variant);
+    // Batched CG iteration base + it_local of every active problem in tab
+    // (operator, then gather/update unless final) on stream s; with prepare
+    // set, only configures the kernels (call before any graph capture).
+    int (*batch_iter)(hipStream_t s, int prec, int variant, const BatchProb *tab, const int *owner, unsigned grid,
+                      const void *D, int it_local, const int *base, bool final, bool prepare);
 };
 
 const NpOps *np_ops(int NP);
+const NpOps *ops(const nek_ctx *c);
+
+// ---------------------------------------------- driver steps (nek_lib.hip)
+
+int ensure_hist(nek_ctx *c, long need);
+int ensure_g(nek_ctx *c, int prec);
+int ensure_fp64_work(nek_ctx *c);
+int ensure_mixed_work(nek_ctx *c);
+int fill_f64(nek_ctx *c, double *p, double v, unsigned long n);
+int red_final(nek_ctx *c, int slot);
+int glsc3_to_slot(nek_ctx *c, const void *a, const void *b, int dtype, int slot);
+int gather_launch(nek_ctx *c, const double *in, double *out, bool weighted);
+int start_launch(nek_ctx *c, int rslot, int hist_off, double stop_tol, int maxit, int stop_on_initial,
+                 double rtz_prev = 0.0);
+int cg_prologue(nek_ctx *c, const double *f, const double *x0, double *x, double *r);
+int finish_status(const IterState &s, double tol);
+int batch_advance_launch(hipStream_t s, int *base, int step);
+int batch_alldone_launch(hipStream_t s, Scal *const *scs, int nprob, int *out);
+int fill_i32(hipStream_t s, int *p, int v, unsigned long n);
+
+// Control state of one mixed-precision (iterative refinement) solve; the
+// solo and batched solvers drive it through the same steps.
+struct IrCtl {
+    double bb = 0, rho = 0, rho_prev = 0, tau = 0, rtz_last = 0;
+    int total = 0, outer = 0, fp64_iters = 0, status = NEK_OK, inner_cap = 0, max_outer = 0;
+    bool keep_p = false, finished = false;
+};
+enum IrStep { IR_DONE, IR_FALLBACK, IR_INNER };
+void ir_init(const nek_ctx *c, IrCtl &s);
+void ir_start(IrCtl &s, const Scal &h);
+IrStep ir_decide(IrCtl &s, const nek_ctx *c, double tol, int maxit);
+int ir_fallback(nek_ctx *c, IrCtl &s, double tol, int maxit, double *x);
+int ir_inner_launch(nek_ctx *c, IrCtl &s, double tol, int maxit, int *cap);
+int ir_inner_done(nek_ctx *c, IrCtl &s, const Scal &h, double *x);
+void ir_outer_done(IrCtl &s, const Scal &h);
+void ir_stats(const IrCtl &s, nek_stats *st);
 
 }  // namespace nek

@@ -32,6 +32,7 @@
 namespace nek {
 
 constexpr int UPD_BS = 256;      // block size of the pointwise kernels
+constexpr int MAXB = 2048;       // cap on workgroups of any reducing kernel (partials per region)
 
 // CG state entering iteration it, in slot it & 1.
 struct IterState {
@@ -254,14 +255,15 @@ template <> struct GLoad<uint16_t> {   // BF16 bit patterns, two per 32-bit word
 // uniform entries D[k][l] of the t contractions come through the scalar
 // cache.  The six factors of slice k + PD are in flight while slice k is
 // computed.  CG mode fuses p = beta p + r before, and sum p.(A_L p) after.
+// Body of the operator kernel for one problem: workgroup blk of the
+// problem's nblk workgroups.
 template <int NP, int EPW, int PD, typename T, typename GT, bool CG, typename XT>
-__global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T *__restrict__ p,
-                                                    T *__restrict__ w, const GT *__restrict__ g,
-                                                    const T *__restrict__ D, XT *__restrict__ x,
-                                                    Scal *__restrict__ sc, double *__restrict__ P1cur,
-                                                    const double *__restrict__ P1prev,
-                                                    const double *__restrict__ P2prev, int nb2, int it,
-                                                    double *__restrict__ hist, int E, int ngroups)
+__device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict__ p, T *__restrict__ w,
+                                        const GT *__restrict__ g, const T *__restrict__ D, XT *__restrict__ x,
+                                        Scal *__restrict__ sc, double *__restrict__ P1cur,
+                                        const double *__restrict__ P1prev, const double *__restrict__ P2prev,
+                                        int nb2, int it, double *__restrict__ hist, int E, int ngroups,
+                                        unsigned blk, unsigned nblk)
 {
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP, BS = EPW * NP2;
     using GL = GLoad<GT>;
@@ -274,14 +276,14 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T
 
     const int tid = threadIdx.x;
     const int el = tid / NP2, ij = tid - el * NP2;
-    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
-    const int g0 = (int)(((long)lb * ngroups) / gridDim.x);
-    const int g1 = (int)(((long)(lb + 1) * ngroups) / gridDim.x);
+    const unsigned lb = xcd_block(blk, nblk);
+    const int g0 = (int)(((long)lb * ngroups) / nblk);
+    const int g1 = (int)(((long)(lb + 1) * ngroups) / nblk);
     T beta = 0;
     bool first = false, xupd = false;
     double alpha_prev = 0.0;
     if constexpr (CG) {
-        const Begin B = cg_begin<BS>(sc, P1prev, (int)gridDim.x, P2prev, nb2, it, hist, sbuf, blockIdx.x == 0 && tid == 0);
+        const Begin B = cg_begin<BS>(sc, P1prev, (int)nblk, P2prev, nb2, it, hist, sbuf, blk == 0 && tid == 0);
         xupd = B.xupd;
         alpha_prev = B.alpha_prev;
         if (B.cur.done) {
@@ -395,8 +397,21 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T
 #undef NEK_DTJ
     if constexpr (CG) {
         const double s = block_sum<BS>(pap, sbuf);
-        if (tid == 0) P1cur[blockIdx.x] = s;
+        if (tid == 0) P1cur[blk] = s;
     }
+}
+
+template <int NP, int EPW, int PD, typename T, typename GT, bool CG, typename XT>
+__global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T *__restrict__ p,
+                                                    T *__restrict__ w, const GT *__restrict__ g,
+                                                    const T *__restrict__ D, XT *__restrict__ x,
+                                                    Scal *__restrict__ sc, double *__restrict__ P1cur,
+                                                    const double *__restrict__ P1prev,
+                                                    const double *__restrict__ P2prev, int nb2, int it,
+                                                    double *__restrict__ hist, int E, int ngroups)
+{
+    ax_body<NP, EPW, PD, T, GT, CG, XT>(src, p, w, g, D, x, sc, P1cur, P1prev, P2prev, nb2, it, hist, E, ngroups,
+                                        blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------- gather-scatter
@@ -488,17 +503,16 @@ __device__ __forceinline__ double gather_copies(const T *__restrict__ w, const P
 // column of r and w, the columns of w in the x, y and xy neighbours (for
 // threads on those faces), and the neighbouring slices in z.
 template <int NP, int EPW, typename T>
-__global__ __launch_bounds__(EPW *NP *NP) void k_cg_update(T *__restrict__ r, const T *__restrict__ w,
-                                                           Scal *__restrict__ sc, const double *__restrict__ P1cur,
-                                                           int nb1, double *__restrict__ P2cur, int it, Box box,
-                                                           int E, int ngroups)
+__device__ __forceinline__ void upd_body(T *__restrict__ r, const T *__restrict__ w, Scal *__restrict__ sc,
+                                         const double *__restrict__ P1cur, int nb1, double *__restrict__ P2cur,
+                                         int it, Box box, int E, int ngroups, unsigned blk, unsigned nblk)
 {
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP, BS = EPW * NP2, N = NP - 1;
     __shared__ double sbuf[BS];
     const IterState cur = sc->st[it & 1];
     if (cur.done) return;
     const double pap = sum_all<BS>(P1cur, nb1, sbuf);
-    const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool writer = blk == 0 && threadIdx.x == 0;
     if (!__builtin_isfinite(pap) || !(pap > 0)) {
         if (writer) sc->k2flag[it & 1] = __builtin_isfinite(pap) ? -5 : -6;
         return;
@@ -507,9 +521,9 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_cg_update(T *__restrict__ r, co
     const int tid = threadIdx.x;
     const int el = tid / NP2, ij = tid - el * NP2;
     const int i = ij % NP, j = ij / NP;
-    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
-    const int g0 = (int)(((long)lb * ngroups) / gridDim.x);
-    const int g1 = (int)(((long)(lb + 1) * ngroups) / gridDim.x);
+    const unsigned lb = xcd_block(blk, nblk);
+    const int g0 = (int)(((long)lb * ngroups) / nblk);
+    const int g1 = (int)(((long)(lb + 1) * ngroups) / nblk);
     const int oz = box.nx * box.ny;   // local indices fit in 32 bits (checked at set-up)
     double part = 0.0;
     for (int grp = g0; grp < g1; ++grp) {
@@ -591,8 +605,71 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_cg_update(T *__restrict__ r, co
         }
     }
     const double s = block_sum<BS>(part, sbuf);
-    if (tid == 0) P2cur[blockIdx.x] = s;
+    if (tid == 0) P2cur[blk] = s;
     if (writer) sc->k2flag[it & 1] = 0;
+}
+
+template <int NP, int EPW, typename T>
+__global__ __launch_bounds__(EPW *NP *NP) void k_cg_update(T *__restrict__ r, const T *__restrict__ w,
+                                                           Scal *__restrict__ sc, const double *__restrict__ P1cur,
+                                                           int nb1, double *__restrict__ P2cur, int it, Box box,
+                                                           int E, int ngroups)
+{
+    upd_body<NP, EPW, T>(r, w, sc, P1cur, nb1, P2cur, it, box, E, ngroups, blockIdx.x, gridDim.x);
+}
+
+// ------------------------------------------------------------- batched CG
+
+// One problem of a batch: its vectors (element type fixed by the launch), its
+// factors, CG state and partials, and the range [blk0, blk0 + nblk) of the
+// batched grid that works on it.  blk0 is a multiple of 8, so each workgroup
+// runs on the same XCD as the workgroup of the same index in a solo launch.
+struct BatchProb {
+    void *r, *p, *w;       // residual, search direction, A_L p (T)
+    const void *g;         // geometric factors (GT)
+    double *x;             // iterate or correction, accumulated in FP64
+    Scal *sc;
+    double *partials;      // pAp by parity, then rtr by parity (MAXB each)
+    double *hist;
+    Box box;
+    int E, ngroups, blk0, nblk, active;
+};
+
+// Iteration number of a batched launch: the chunk base kept on the device
+// (advanced by k_batch_advance at the start of every chunk) plus the launch's
+// position in the chunk, so one recorded chunk serves every chunk of a run.
+__device__ __forceinline__ int batch_it(const int *__restrict__ base, int it_local) { return *base + it_local; }
+
+// The operator kernel of every problem of one order in one launch: workgroup
+// b runs the solo body as workgroup b - blk0 of its problem.
+template <int NP, int EPW, int PD, typename T, typename GT>
+__global__ __launch_bounds__(EPW *NP *NP) void k_ax_batch(const BatchProb *__restrict__ tab,
+                                                          const int *__restrict__ owner, const T *__restrict__ D,
+                                                          int it_local, const int *__restrict__ base)
+{
+    const int q = owner[blockIdx.x];
+    if (q < 0) return;
+    const BatchProb P = tab[q];
+    if (!P.active) return;
+    const int it = batch_it(base, it_local);
+    ax_body<NP, EPW, PD, T, GT, true, double>(
+        (const T *)P.r, (T *)P.p, (T *)P.w, (const GT *)P.g, D, P.x, P.sc, P.partials + (it & 1) * MAXB,
+        P.partials + ((it - 1) & 1) * MAXB, P.partials + (2 + ((it - 1) & 1)) * MAXB, P.nblk, it, P.hist, P.E,
+        P.ngroups, blockIdx.x - P.blk0, P.nblk);
+}
+
+template <int NP, int EPW, typename T>
+__global__ __launch_bounds__(EPW *NP *NP) void k_cg_update_batch(const BatchProb *__restrict__ tab,
+                                                                 const int *__restrict__ owner, int it_local,
+                                                                 const int *__restrict__ base)
+{
+    const int q = owner[blockIdx.x];
+    if (q < 0) return;
+    const BatchProb P = tab[q];
+    if (!P.active) return;
+    const int it = batch_it(base, it_local);
+    upd_body<NP, EPW, T>((T *)P.r, (const T *)P.w, P.sc, P.partials + (it & 1) * MAXB, P.nblk,
+                         P.partials + (2 + (it & 1)) * MAXB, it, P.box, P.E, P.ngroups, blockIdx.x - P.blk0, P.nblk);
 }
 
 // out = M o sum over copies of (c o) in: the right-hand side b = M dssum(f)

@@ -112,6 +112,23 @@ __global__ void k_fill(T *__restrict__ p, T v, unsigned long n)
         p[t] = v;
 }
 
+// Batched runs: advance the device chunk base by one chunk.
+__global__ void k_batch_advance(int *base, int step)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *base += step;
+}
+
+// Batched runs: out = 1 when every listed problem (non-null entry) has
+// finished its run.
+__global__ __launch_bounds__(256) void k_batch_alldone(Scal *const *__restrict__ scs, int nprob, int *out)
+{
+    int pending = 0;
+    for (int i = threadIdx.x; i < nprob; i += 256)
+        if (scs[i] && !scs[i]->done_host) pending = 1;
+    pending = __syncthreads_or(pending);
+    if (threadIdx.x == 0) *out = !pending;
+}
+
 // x += d (FP64).
 __global__ void k_axpy1(double *__restrict__ x, const double *__restrict__ d, unsigned long n)
 {

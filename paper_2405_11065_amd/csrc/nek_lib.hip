@@ -88,10 +88,6 @@ int prof_take(nek_ctx *c)
     return (int)used;
 }
 
-}  // namespace nek
-
-namespace {
-
 // Fold the elapsed times of recorded triples into the totals (stream idle).
 int prof_resolve(nek_ctx *c)
 {
@@ -148,6 +144,29 @@ template <typename T> int fill(nek_ctx *c, T *p, T v, unsigned long n)
     return NEK_OK;
 }
 
+int fill_f64(nek_ctx *c, double *p, double v, unsigned long n) { return fill<double>(c, p, v, n); }
+
+int fill_i32(hipStream_t s, int *p, int v, unsigned long n)
+{
+    hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(256), 0, s, p, v, n);
+    HIP_TRY(hipGetLastError());
+    return NEK_OK;
+}
+
+int batch_advance_launch(hipStream_t s, int *base, int step)
+{
+    hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, base, step);
+    HIP_TRY(hipGetLastError());
+    return NEK_OK;
+}
+
+int batch_alldone_launch(hipStream_t s, Scal *const *scs, int nprob, int *out)
+{
+    hipLaunchKernelGGL(k_batch_alldone, dim3(1), dim3(256), 0, s, scs, nprob, out);
+    HIP_TRY(hipGetLastError());
+    return NEK_OK;
+}
+
 int red_final(nek_ctx *c, int slot)
 {
     hipLaunchKernelGGL(k_red_final, dim3(1), dim3(UPD_BS), 0, c->stream, c->P3(), (int)red_grid(c), c->sc, slot);
@@ -194,7 +213,7 @@ int cg_iter(nek_ctx *c, int prec, int variant, int it, bool final, double *x)
 }
 
 int start_launch(nek_ctx *c, int rslot, int hist_off, double stop_tol, int maxit, int stop_on_initial,
-                 double rtz_prev = 0.0)
+                 double rtz_prev)
 {
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(64), 0, c->stream, c->sc, c->hist, rslot, hist_off, stop_tol, maxit,
                        stop_on_initial, rtz_prev);
@@ -291,83 +310,163 @@ int solve_fp64(nek_ctx *c, const double *f, const double *x0, double tol, int ma
     return finish_status(h.fin, tol);
 }
 
-// Iterative refinement: FP64 outer residual with FP64 g; inner CG with an
-// FP32 operator (FP32 or BF16 g), FP64 reductions/scalars and FP64 correction.
-int solve_mixed(nek_ctx *c, const double *f, const double *x0, double tol, int maxit, double *x, nek_stats *st)
+int ensure_mixed_work(nek_ctx *c)
 {
     int rc;
     if ((rc = ensure_fp64_work(c)) || (rc = ensure_g(c, c->prec))) return rc;
     if (dalloc(c->d64, c->nl) || dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) || dalloc(c->w32, c->nl))
         return NEK_E_OOM;
-    const bool bf16 = c->prec == NEK_PREC_BF16G;
+    return NEK_OK;
+}
+
+// Iterative refinement: FP64 outer residual with FP64 g; inner CG with an
+// FP32 operator (FP32 or BF16 g), FP64 reductions/scalars and FP64 correction.
+// The control below is shared by the solo and the batched solver.
+void ir_init(const nek_ctx *c, IrCtl &s)
+{
+    s = IrCtl{};
     // Restarted refinement by default: on the benchmarked meshes it needs
     // fewer FP32 iterations than reliable updates (which keep p across
     // true-residual replacements and so inherit FP32 CG's loss of
     // orthogonality), and BF16 g's ~2^-8 operator error would spoil kept
     // directions altogether.
-    const bool keep_p = c->opts.refine_mode == 2;
-    const double tau = c->opts.inner_tol > 0 ? c->opts.inner_tol : (bf16 || keep_p ? 1e-2 : 1e-4);
-    double rtz_last = 0.0;   // recursive rtz at the end of the previous inner run
-    const int inner_cap = c->opts.inner_maxit > 0 ? c->opts.inner_maxit : 4000;
-    const int max_outer = c->opts.max_outer > 0 ? c->opts.max_outer : 30;
+    const bool bf16 = c->prec == NEK_PREC_BF16G;
+    s.keep_p = c->opts.refine_mode == 2;
+    s.tau = c->opts.inner_tol > 0 ? c->opts.inner_tol : (bf16 || s.keep_p ? 1e-2 : 1e-4);
+    s.inner_cap = c->opts.inner_maxit > 0 ? c->opts.inner_maxit : 4000;
+    s.max_outer = c->opts.max_outer > 0 ? c->opts.max_outer : 30;
+}
 
+// after cg_prologue: red[0] = b.b, red[1] = r.r
+void ir_start(IrCtl &s, const Scal &h)
+{
+    s.bb = h.red[0];
+    if (!std::isfinite(s.bb) || !std::isfinite(h.red[1])) {
+        s.status = NEK_E_NONFINITE;
+        s.finished = true;
+        return;
+    }
+    s.rho = s.bb > 0 ? std::sqrt(h.red[1]) / std::sqrt(s.bb) : 0.0;
+}
+
+IrStep ir_decide(IrCtl &s, const nek_ctx *c, double tol, int maxit)
+{
+    if (s.finished || s.bb == 0.0 || s.rho <= tol) return IR_DONE;
+    if (s.outer >= s.max_outer || s.total >= maxit) {
+        s.status = NEK_NOCONV;
+        return IR_DONE;
+    }
+    if (s.outer > 0 && s.rho > 0.5 * s.rho_prev) {
+        if (!c->opts.fp64_fallback) {
+            s.status = NEK_E_STAGNATION;
+            return IR_DONE;
+        }
+        return IR_FALLBACK;
+    }
+    return IR_INNER;
+}
+
+// Finish in FP64 CG from the current x (restart of the Krylov space);
+// synchronous.
+int ir_fallback(nek_ctx *c, IrCtl &s, double tol, int maxit, double *x)
+{
+    int rc;
+    Scal h;
+    if ((rc = start_launch(c, 1, s.total, tol, maxit - s.total, 0))) return rc;
+    if ((rc = cg_fp64_iterations(c, x, maxit - s.total))) return rc;
+    if ((rc = read_scal(c, h))) return rc;
+    s.fp64_iters = h.fin.iter;
+    s.total += h.fin.iter;
+    if ((rc = ax_local_launch(c, x, c->w64, NEK_F64, NEK_PREC_FP64))) return rc;
+    if ((rc = resid_launch(c, c->b, c->w64, c->r64, 1))) return rc;
+    if ((rc = read_scal(c, h))) return rc;
+    s.rho = std::sqrt(h.red[1]) / std::sqrt(s.bb);
+    s.status = h.fin.status ? h.fin.status : (s.rho <= tol ? NEK_OK : NEK_NOCONV);
+    ++s.outer;
+    s.finished = true;
+    return NEK_OK;
+}
+
+// Enqueue the start of an inner solve of A d = r; *cap = its iteration cap.
+int ir_inner_launch(nek_ctx *c, IrCtl &s, double tol, int maxit, int *cap)
+{
+    int rc;
+    if ((rc = ops(c)->inner_start(c, c->r64, c->r32, c->d64))) return rc;
+    if ((rc = red_final(c, 1))) return rc;
+    const double tau_k = std::min(0.5, std::max(s.tau, 0.3 * tol / s.rho));
+    *cap = std::min(s.inner_cap, maxit - s.total);
+    return start_launch(c, 1, s.total, tau_k, *cap, 1, s.keep_p ? s.rtz_last : 0.0);
+}
+
+// After an inner run (h read back): count it, then enqueue x += d and the
+// true FP64 residual.  Sets s.finished when the inner run failed.
+int ir_inner_done(nek_ctx *c, IrCtl &s, const Scal &h, double *x)
+{
+    s.total += h.fin.iter;
+    s.rtz_last = h.fin.rtz;
+    if (h.fin.status) {
+        s.status = h.fin.status;
+        s.finished = true;
+        return NEK_OK;
+    }
+    hipLaunchKernelGGL(k_axpy1, dim3(4 * num_cu()), dim3(256), 0, c->stream, x, c->d64, (unsigned long)c->nl);
+    HIP_TRY(hipGetLastError());
+    int rc;
+    if ((rc = ax_local_launch(c, x, c->w64, NEK_F64, NEK_PREC_FP64))) return rc;
+    return resid_launch(c, c->b, c->w64, c->r64, 1);
+}
+
+// After the true residual (h read back).
+void ir_outer_done(IrCtl &s, const Scal &h)
+{
+    s.rho_prev = s.rho;
+    s.rho = std::sqrt(h.red[1]) / std::sqrt(s.bb);
+    ++s.outer;
+    if (!std::isfinite(s.rho)) {
+        s.status = NEK_E_NONFINITE;
+        s.finished = true;
+    }
+}
+
+void ir_stats(const IrCtl &s, nek_stats *st)
+{
+    st->iters = s.total;
+    st->outer_iters = s.outer;
+    st->fp64_iters = s.fp64_iters;
+    st->rel_res = s.rho;
+}
+
+int solve_mixed(nek_ctx *c, const double *f, const double *x0, double tol, int maxit, double *x, nek_stats *st)
+{
+    int rc;
+    if ((rc = ensure_mixed_work(c))) return rc;
+    IrCtl s;
+    ir_init(c, s);
     if ((rc = cg_prologue(c, f, x0, x, c->r64))) return rc;
     Scal h;
     if ((rc = read_scal(c, h))) return rc;
-    const double bb = h.red[0];
-    if (!std::isfinite(bb) || !std::isfinite(h.red[1])) return NEK_E_NONFINITE;
-    double rho = bb > 0 ? std::sqrt(h.red[1]) / std::sqrt(bb) : 0.0;
-    int total = 0, outer = 0, status = NEK_OK;
-    double rho_prev = INFINITY;
-    st->rel_res = rho;
-    while (true) {
-        if (bb == 0.0 || rho <= tol) break;
-        if (outer >= max_outer || total >= maxit) { status = NEK_NOCONV; break; }
-        if (outer > 0 && rho > 0.5 * rho_prev) {
-            if (!c->opts.fp64_fallback) { status = NEK_E_STAGNATION; break; }
-            // finish in FP64 from the current x (restart of the Krylov space)
-            if ((rc = start_launch(c, 1, total, tol, maxit - total, 0))) return rc;
-            if ((rc = cg_fp64_iterations(c, x, maxit - total))) return rc;
-            if ((rc = read_scal(c, h))) return rc;
-            st->fp64_iters = h.fin.iter;
-            total += h.fin.iter;
-            if ((rc = ax_local_launch(c, x, c->w64, NEK_F64, NEK_PREC_FP64))) return rc;
-            if ((rc = resid_launch(c, c->b, c->w64, c->r64, 1))) return rc;
-            if ((rc = read_scal(c, h))) return rc;
-            rho = std::sqrt(h.red[1]) / std::sqrt(bb);
-            status = h.fin.status ? h.fin.status : (rho <= tol ? NEK_OK : NEK_NOCONV);
-            ++outer;
+    ir_start(s, h);
+    while (!s.finished) {
+        const IrStep step = ir_decide(s, c, tol, maxit);
+        if (step == IR_DONE) break;
+        if (step == IR_FALLBACK) {
+            if ((rc = ir_fallback(c, s, tol, maxit, x))) return rc;
             break;
         }
-        // inner solve of A d = r with the FP32 operator
-        if ((rc = ops(c)->inner_start(c, c->r64, c->r32, c->d64))) return rc;
-        if ((rc = red_final(c, 1))) return rc;
-        const double tau_k = std::min(0.5, std::max(tau, 0.3 * tol / rho));
-        const int cap = std::min(inner_cap, maxit - total);
-        if ((rc = start_launch(c, 1, total, tau_k, cap, 1, keep_p ? rtz_last : 0.0))) return rc;
+        int cap = 0;
+        if ((rc = ir_inner_launch(c, s, tol, maxit, &cap))) return rc;
         rc = run_cg(c, cap, [&](int it, bool final) -> int {
             return cg_iter(c, c->prec, c->variant[c->prec], it, final, c->d64);
         });
         if (rc) return rc;
         if ((rc = read_scal(c, h))) return rc;
-        total += h.fin.iter;
-        rtz_last = h.fin.rtz;
-        if (h.fin.status) { status = h.fin.status; break; }
-        hipLaunchKernelGGL(k_axpy1, dim3(4 * num_cu()), dim3(256), 0, c->stream, x, c->d64, (unsigned long)c->nl);
-        HIP_TRY(hipGetLastError());
-        // true FP64 residual of the updated x
-        if ((rc = ax_local_launch(c, x, c->w64, NEK_F64, NEK_PREC_FP64))) return rc;
-        if ((rc = resid_launch(c, c->b, c->w64, c->r64, 1))) return rc;
+        if ((rc = ir_inner_done(c, s, h, x))) return rc;
+        if (s.finished) break;
         if ((rc = read_scal(c, h))) return rc;
-        rho_prev = rho;
-        rho = std::sqrt(h.red[1]) / std::sqrt(bb);
-        ++outer;
-        if (!std::isfinite(rho)) { status = NEK_E_NONFINITE; break; }
+        ir_outer_done(s, h);
     }
-    st->iters = total;
-    st->outer_iters = outer;
-    st->rel_res = rho;
-    return status;
+    ir_stats(s, st);
+    return s.status;
 }
 
 // [E][6][n3] <-> [E][n3][6]
@@ -385,7 +484,7 @@ void points_to_planes(const double *src, double *dst, long E, long n3)
             for (int f = 0; f < 6; ++f) dst[(e * 6 + f) * n3 + q] = src[(e * n3 + q) * 6 + f];
 }
 
-}  // namespace
+}  // namespace nek
 
 extern "C" {
 

@@ -127,13 +127,56 @@ template <int NP> struct OpsImpl {
         HIP_TRY(hipGetLastError());
         return NEK_OK;
     }
+
+    static int variant_epw(int v)
+    {
+        return with_variant<NP, double>(v, [](auto epw_c, auto) -> int { return decltype(epw_c)::value; });
+    }
+
+    template <typename T, typename GT>
+    static int batch_iter_t(hipStream_t s, int v, const BatchProb *tab, const int *owner, unsigned grid, const T *D,
+                            int it_local, const int *base, bool final, bool prepare)
+    {
+        return with_variant<NP, GT>(v, [&](auto epw_c, auto pd_c) -> int {
+            constexpr int EPW = decltype(epw_c)::value, PD = decltype(pd_c)::value, BS = EPW * NP * NP;
+            const size_t shm = 3ul * EPW * NP * NP * NP * sizeof(T);
+            if (prepare) {
+                if (shm > 65536)
+                    HIP_TRY(hipFuncSetAttribute((const void *)k_ax_batch<NP, EPW, PD, T, GT>,
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+                return NEK_OK;
+            }
+            hipLaunchKernelGGL((k_ax_batch<NP, EPW, PD, T, GT>), dim3(grid), dim3(BS), shm, s, tab, owner, D, it_local,
+                               base);
+            HIP_TRY(hipGetLastError());
+            if (!final) {
+                hipLaunchKernelGGL((k_cg_update_batch<NP, EPW, T>), dim3(grid), dim3(BS), 0, s, tab, owner, it_local,
+                                   base);
+                HIP_TRY(hipGetLastError());
+            }
+            return NEK_OK;
+        });
+    }
+
+    static int batch_iter(hipStream_t s, int prec, int v, const BatchProb *tab, const int *owner, unsigned grid,
+                          const void *D, int it_local, const int *base, bool final, bool prepare)
+    {
+        if (prec == NEK_PREC_FP64)
+            return batch_iter_t<double, double>(s, v, tab, owner, grid, (const double *)D, it_local, base, final,
+                                                prepare);
+        if (prec == NEK_PREC_BF16G)
+            return batch_iter_t<float, uint16_t>(s, v, tab, owner, grid, (const float *)D, it_local, base, final,
+                                                 prepare);
+        return batch_iter_t<float, float>(s, v, tab, owner, grid, (const float *)D, it_local, base, final, prepare);
+    }
 };
 
 template <int NP> const NpOps *make_np_ops()
 {
     using I = OpsImpl<NP>;
     static const NpOps ops{n_variants<NP>(), &I::cg_iter64, &I::cg_iter32, &I::cg_iter16, &I::ax64, &I::ax32,
-                           &I::ax16, &I::gather64, &I::glsc3_64, &I::glsc3_32, &I::resid, &I::inner_start};
+                           &I::ax16, &I::gather64, &I::glsc3_64, &I::glsc3_32, &I::resid, &I::inner_start,
+                           &I::variant_epw, &I::batch_iter};
     return &ops;
 }
 

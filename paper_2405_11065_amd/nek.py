@@ -29,7 +29,12 @@ PREC_NAMES = {"fp64": NEK_PREC_FP64, "fp32": NEK_PREC_FP32, "bf16g": NEK_PREC_BF
 # every entry point declared in include/nek.h
 EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_ax_local", "nek_ax",
            "nek_dssum", "nek_glsc3", "nek_cg_solve", "nek_prof_enable", "nek_prof_read", "nek_num_variants",
-           "nek_tune", "nek_set_variant", "nek_get_variant", "nek_strerror")
+           "nek_tune", "nek_set_variant", "nek_get_variant", "nek_batch_setup", "nek_batch_free",
+           "nek_batch_size", "nek_batch_ctx", "nek_batch_orders", "nek_batch_tune", "nek_batch_set_variant",
+           "nek_batch_get_variant", "nek_batch_solve", "nek_batch_counters", "nek_strerror")
+
+NEK_MAX_VARIANTS = 6
+NEK_BATCH_NO_GRAPH = 1
 
 
 class nek_mesh(ctypes.Structure):
@@ -88,6 +93,19 @@ def load(path: str = LIB_PATH):
                              ctypes.POINTER(ctypes.c_int)]
     lib.nek_set_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.nek_get_variant.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.nek_batch_setup.argtypes = [ctypes.c_int, ctypes.POINTER(nek_mesh), ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(nek_opts), vp, ctypes.POINTER(vp)]
+    lib.nek_batch_free.argtypes = [vp]
+    lib.nek_batch_free.restype = None
+    lib.nek_batch_size.argtypes = [vp]
+    lib.nek_batch_ctx.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp)]
+    lib.nek_batch_orders.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.nek_batch_tune.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.nek_batch_set_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.nek_batch_get_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.nek_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double, ctypes.c_int,
+                                    ctypes.POINTER(vp), ctypes.POINTER(nek_stats), ctypes.c_int]
+    lib.nek_batch_counters.argtypes = [vp, i64p, i64p]
     lib.nek_strerror.argtypes = [ctypes.c_int]
     lib.nek_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -112,6 +130,36 @@ def _torch():
     return torch
 
 
+def _mesh(nel, vtx=None, lo=(0.0, 0.0, 0.0), hi=None):
+    """(nek_mesh, nel tuple, vertex array kept alive by the caller)."""
+    nel = tuple(int(v) for v in nel)
+    lo = tuple(float(v) for v in lo)
+    hi = tuple(lo[d] + nel[d] for d in range(3)) if hi is None else tuple(float(v) for v in hi)
+    m = nek_mesh()
+    m.nel[:] = nel
+    m.lo[:] = lo
+    m.hi[:] = hi
+    keep = None
+    if vtx is not None:
+        keep = np.ascontiguousarray(vtx, dtype=np.float64)
+        nv = (nel[0] + 1) * (nel[1] + 1) * (nel[2] + 1)
+        if keep.shape != (nv, 3):
+            raise ValueError(f"vtx must have shape ({nv}, 3)")
+        m.vtx = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return m, nel, keep
+
+
+def _opts(prec="fp64", inner_tol=0.0, inner_maxit=0, max_outer=0, fp64_fallback=1, refine_mode=0):
+    o = nek_opts()
+    o.prec = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+    o.inner_tol = float(inner_tol)
+    o.inner_maxit = int(inner_maxit)
+    o.max_outer = int(max_outer)
+    o.fp64_fallback = int(fp64_fallback)
+    o.refine_mode = int(refine_mode)
+    return o
+
+
 class Context:
     """One box mesh of order N on the current GPU (nek_setup / nek_free)."""
 
@@ -120,32 +168,31 @@ class Context:
         torch = _torch()
         self._lib = load()
         self.N = int(N)
-        self.nel = tuple(int(v) for v in nel)
-        lo = tuple(float(v) for v in lo)
-        hi = tuple(lo[d] + self.nel[d] for d in range(3)) if hi is None else tuple(float(v) for v in hi)
-        m = nek_mesh()
-        m.nel[:] = self.nel
-        m.lo[:] = lo
-        m.hi[:] = hi
-        self._vtx = None
-        if vtx is not None:
-            v = np.ascontiguousarray(vtx, dtype=np.float64)
-            nv = (self.nel[0] + 1) * (self.nel[1] + 1) * (self.nel[2] + 1)
-            if v.shape != (nv, 3):
-                raise ValueError(f"vtx must have shape ({nv}, 3)")
-            self._vtx = v
-            m.vtx = v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        o = nek_opts()
-        o.prec = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
-        o.inner_tol = float(inner_tol)
-        o.inner_maxit = int(inner_maxit)
-        o.max_outer = int(max_outer)
-        o.fp64_fallback = int(fp64_fallback)
-        o.refine_mode = int(refine_mode)
+        m, self.nel, self._vtx = _mesh(nel, vtx, lo, hi)
+        o = _opts(prec, inner_tol, inner_maxit, max_outer, fp64_fallback, refine_mode)
         self.stream = torch.cuda.current_stream() if stream is None else stream
         h = ctypes.c_void_p()
         _check(self._lib.nek_setup(ctypes.byref(m), self.N, ctypes.byref(o), ctypes.c_void_p(self.stream.cuda_stream),
                                    ctypes.byref(h)), "nek_setup")
+        self._owned = True
+        self._init_handle(h)
+
+    @classmethod
+    def _borrow(cls, handle, N, nel, owner):
+        """A view of a context owned by a batch (never freed here)."""
+        self = cls.__new__(cls)
+        self._lib = load()
+        self.N = int(N)
+        self.nel = tuple(nel)
+        self._vtx = None
+        self.stream = None
+        self._owned = False
+        self._owner = owner
+        self._init_handle(handle)
+        return self
+
+    def _init_handle(self, h):
+        torch = _torch()
         self._h = h
         self.nl = self.size(NEK_SIZE_NLOCAL)
         self.E = self.size(NEK_SIZE_E)
@@ -155,7 +202,8 @@ class Context:
     # -- lifetime
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
-            self._lib.nek_free(self._h)
+            if self._owned:
+                self._lib.nek_free(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):
@@ -291,6 +339,118 @@ class Context:
         if history:
             hist = hist[:min(int(maxit), max(0, d["iters"])) + 1]
         return x, d, hist
+
+
+class Batch:
+    """Many box problems solved together (nek_batch_*).
+
+    problems: sequence of dicts with keys nel, N and optionally vtx, lo, hi.
+    The options (prec, inner_tol, ...) are common to all problems.
+    """
+
+    def __init__(self, problems, prec="fp64", inner_tol=0.0, inner_maxit=0, max_outer=0, fp64_fallback=1,
+                 refine_mode=0, stream=None):
+        torch = _torch()
+        self._lib = load()
+        n = len(problems)
+        meshes = (nek_mesh * n)()
+        Ns = (ctypes.c_int * n)()
+        self._keep = []
+        self.specs = []
+        for i, p in enumerate(problems):
+            m, nel, keep = _mesh(p["nel"], p.get("vtx"), p.get("lo", (0.0, 0.0, 0.0)), p.get("hi"))
+            meshes[i] = m
+            Ns[i] = int(p["N"])
+            self._keep.append(keep)
+            self.specs.append((nel, int(p["N"])))
+        o = _opts(prec, inner_tol, inner_maxit, max_outer, fp64_fallback, refine_mode)
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        h = ctypes.c_void_p()
+        _check(self._lib.nek_batch_setup(n, meshes, Ns, ctypes.byref(o), ctypes.c_void_p(self.stream.cuda_stream),
+                                         ctypes.byref(h)), "nek_batch_setup")
+        self._h = h
+        self._keep = None
+        self.n = n
+        self.ctx = []
+        for i in range(n):
+            ch = ctypes.c_void_p()
+            _check(self._lib.nek_batch_ctx(self._h, i, ctypes.byref(ch)), "nek_batch_ctx")
+            self.ctx.append(Context._borrow(ch, self.specs[i][1], self.specs[i][0], self))
+        self.nl = [c.nl for c in self.ctx]
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            for c in self.ctx:
+                c.close()
+            self._lib.nek_batch_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def orders(self):
+        out = (ctypes.c_int * 16)()
+        k = self._lib.nek_batch_orders(self._h, out)
+        _check(min(k, 0), "nek_batch_orders")
+        return list(out[:k])
+
+    def tune(self, prec, iters: int = 20):
+        """Per order: fastest configuration (dict N -> (best, us_per_iter list))."""
+        pv = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+        orders = self.orders()
+        us = (ctypes.c_double * (NEK_MAX_VARIANTS * len(orders)))()
+        _check(self._lib.nek_batch_tune(self._h, pv, int(iters), us), "nek_batch_tune")
+        res = {}
+        for g, N in enumerate(orders):
+            i = next(k for k in range(self.n) if self.specs[k][1] == N)
+            row = [t for t in us[g * NEK_MAX_VARIANTS:(g + 1) * NEK_MAX_VARIANTS]]
+            res[N] = (self.get_variant(prec, i), row[:self.ctx[i].num_variants()])
+        return res
+
+    def set_variant(self, prec, N: int, variant: int):
+        pv = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+        _check(self._lib.nek_batch_set_variant(self._h, pv, int(N), int(variant)), "nek_batch_set_variant")
+
+    def get_variant(self, prec, i: int) -> int:
+        pv = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+        v = ctypes.c_int()
+        _check(self._lib.nek_batch_get_variant(self._h, pv, int(i), ctypes.byref(v)), "nek_batch_get_variant")
+        return v.value
+
+    def counters(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(self._lib.nek_batch_counters(self._h, ctypes.byref(a), ctypes.byref(b)), "nek_batch_counters")
+        return a.value, b.value
+
+    def solve(self, fs, x0s=None, tol=1e-8, maxit=1000, xs=None, graph=True, raise_on_noconv=False):
+        """Solve every problem; returns (xs, list of stats dicts, overall status)."""
+        torch = _torch()
+        if len(fs) != self.n or (x0s is not None and len(x0s) != self.n):
+            raise ValueError(f"expected {self.n} vectors")
+        if xs is None:
+            xs = [torch.empty(self.nl[i], dtype=torch.float64, device=self.ctx[i].device) for i in range(self.n)]
+        for i in range(self.n):
+            for t, nm in ((fs[i], "f"), (xs[i], "x")) + (((x0s[i], "x0"),) if x0s is not None else ()):
+                if t is not None and self.ctx[i]._vec(t, f"{nm}[{i}]") != NEK_F64:
+                    raise TypeError(f"{nm}[{i}]: nek_batch_solve takes float64 vectors")
+        P = ctypes.c_void_p * self.n
+        fa = P(*[t.data_ptr() for t in fs])
+        xa = P(*[t.data_ptr() for t in xs])
+        x0a = P(*[(t.data_ptr() if t is not None else None) for t in x0s]) if x0s is not None else None
+        st = (nek_stats * self.n)()
+        rc = self._lib.nek_batch_solve(self._h, fa, x0a, float(tol), int(maxit), xa, st,
+                                       0 if graph else NEK_BATCH_NO_GRAPH)
+        _check(rc, "nek_batch_solve", ok=(NEK_OK,) if raise_on_noconv else (NEK_OK, NEK_NOCONV))
+        return xs, [s.as_dict() for s in st], rc
 
 
 def torch_empty_like(t):

@@ -11,7 +11,9 @@ is synthetic):
   * load vectors f ~ U[0,1) per local node;
   * manufactured forcing sin(pi x) sin(pi y) sin(pi z) plus N(0, sigma) noise;
   * Gaussian random fields (squared-exponential kernel) by random Fourier
-    features, for training the initial-guess network.
+    features, for training the initial-guess network;
+  * batches of independent cube problems, n_e^3 elements with n_e uniform on
+    an integer range and the order uniform over a set.
 """
 from __future__ import annotations
 
@@ -22,6 +24,7 @@ SEED_C1 = 1
 SEED_C2 = 2
 SEED_C3 = 3
 SEED_C3_VERTICES = 3003
+SEED_C4 = 4
 
 
 def rng(seed: int) -> np.random.Generator:
@@ -93,3 +96,23 @@ class FourierFieldDraw:
             ph = pts[s:s + step] @ self.omega.T + self.phi[None, :]
             out[s:s + step] = self.scale * (np.cos(ph) @ self.a)
         return out.reshape(E, n3)
+
+
+def batch_draw(seed: int, nprob: int, ne_range=(2, 24), orders=(5, 7, 9, 11)):
+    """Sizes of a batch: problem i is an n_e^3 cube of unit elements of order N.
+
+    n_e ~ uniform integer on [ne_range[0], ne_range[1]], N ~ uniform over
+    ``orders``, both drawn from PCG64(seed) per problem (n_e first).
+    """
+    r = rng(seed)
+    out = []
+    for _ in range(int(nprob)):
+        ne = int(r.integers(ne_range[0], ne_range[1] + 1))
+        N = int(orders[int(r.integers(0, len(orders)))])
+        out.append({"nel": (ne, ne, ne), "N": N})
+    return out
+
+
+def batch_load_seed(seed: int, i: int) -> int:
+    """Seed of problem i's load vector in a batch drawn with ``seed``."""
+    return int(seed) * 100003 + int(i)
