@@ -112,6 +112,68 @@ def big_case(torch, nek, synth, steps=2):
     return out
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def batch_case(torch, nek, synth, nprob=64, steps=1):
+    """64 independent cubes of n_e^3 unit elements, n_e ~ U{2..24}, N ~
+    U{5,7,9,11} (PCG64 seed 4), f ~ U[0,1) per problem; one batched mixed
+    solve (FP32 operator / FP64 reductions, tol 1e-8) per step, after the
+    per-order autotuner.  Beside it: the same batch with plain launches
+    instead of graph replay, and every problem solved alone in turn on its
+    context (same kernel configuration), whose x must be bit-identical."""
+    draw = synth.batch_draw(synth.SEED_C4, nprob)
+    t0 = time.perf_counter()
+    b = nek.Batch(draw, prec="fp32")
+    t_setup = time.perf_counter() - t0
+    log(f"batch setup {t_setup:.1f} s, {sum(b.nl) / 1e6:.1f} M local points")
+    fs = [torch.from_numpy(synth.uniform_load(b.nl[i], synth.batch_load_seed(synth.SEED_C4, i))).cuda()
+          for i in range(b.n)]
+    tuned = b.tune("fp32", iters=10)
+    xs = [torch.empty(b.nl[i], dtype=torch.float64, device="cuda") for i in range(b.n)]
+    b.solve(fs, tol=TOL, maxit=20000, xs=xs, raise_on_noconv=True)   # warm-up (records the graph)
+    res = {}
+    for mode, graph in (("graph", True), ("plain", False)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st, _ = b.solve(fs, tol=TOL, maxit=20000, xs=xs, graph=graph, raise_on_noconv=True)
+        torch.cuda.synchronize()
+        res[mode] = ((time.perf_counter() - t0) / steps, st)
+        log(f"batch {mode}: {res[mode][0] * 1e3:.1f} ms")
+    dt, st = res["graph"]
+    work = sum(b.nl[i] * st[i]["iters"] for i in range(b.n))
+    xb = [x.clone() for x in xs]
+    # every problem alone, one after the other, on the same contexts
+    x1 = torch.empty(max(b.nl), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    same = True
+    for i in range(b.n):
+        xi = x1[:b.nl[i]]
+        _, s1, _ = b.ctx[i].cg_solve(fs[i], tol=TOL, maxit=20000, x=xi, raise_on_noconv=True)
+        same &= s1["iters"] == st[i]["iters"] and bool(torch.equal(xi, xb[i]))
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    log(f"sequential solo solves: {t_seq * 1e3:.1f} ms, bit-identical {same}")
+    chunks, captures = b.counters()
+    out = {"problems": b.n, "local_points": sum(b.nl), "orders": b.orders(),
+           "GDOF_iter_per_s": round(work / dt / 1e9, 3), "ms_per_solve": round(dt * 1e3, 2),
+           "ms_plain_launches": round(res["plain"][0] * 1e3, 2),
+           "ms_sequential_solo": round(t_seq * 1e3, 2), "speedup_vs_sequential": round(t_seq / dt, 3),
+           "bit_identical_to_solo": same, "max_true_rel_res": max(s["rel_res"] for s in st),
+           "iters_min_max": [min(s["iters"] for s in st), max(s["iters"] for s in st)],
+           "tuned_variant": {str(k): v[0] for k, v in tuned.items()}, "graphs_recorded": captures,
+           "setup_s": round(t_setup, 1)}
+    for c in b.ctx:
+        c.close()
+    b.close()
+    del fs, xs, xb, x1
+    torch.cuda.empty_cache()
+    return out
+
+
 def profile_sequence(torch, nek, synth, variants=""):
     """A short sequence for counter collection (few dispatches)."""
     ctx = nek.Context(NEL, N, prec="fp32")
@@ -152,6 +214,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-big", action="store_true", help="skip the 32^3 deformed-mesh BF16 measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched solve")
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for hardware-counter runs: 40 mixed and 40 FP64 CG iterations, "
                          "5 nek_ax per precision and a 256 MiB copy for calibration")
@@ -184,6 +247,7 @@ def main():
         return st
 
     # autotuner (part of set-up, untimed): kernel configuration per precision
+    log("tuning")
     tuned = {prec: ctx.tune(prec, iters=30) for prec in ("fp32", "fp64", "bf16g")}
     ctx.set_prec("fp32")
 
@@ -233,6 +297,8 @@ def main():
 
     # ---- secondary: 32^3 deformed mesh, N=9, manufactured forcing, BF16 g vs FP64
     big = None if args.no_big else big_case(torch, nek, synth)
+    log("32^3 case done")
+    batch = None if args.no_batch else batch_case(torch, nek, synth)
 
     bpp = cg_operator_bytes_per_point(4, 4, 8)
     ax_avg_s = ax_ms / max(ax_n, 1) / 1e3
@@ -268,6 +334,7 @@ def main():
                      "update_kernel_avg_us": round(up_ms / max(up_n, 1) * 1e3, 2)},
         "cpu_baseline": cpu,
         "deformed_32x32x32_N9": big,
+        "batch_64": batch,
     }
     ctx.close()
     print(json.dumps(out), flush=True)
