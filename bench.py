@@ -30,6 +30,29 @@ sys.path.insert(0, ROOT)
 NEL, N, TOL, SEED = (16, 16, 16), 9, 1e-8, 2
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the fused FP32 operator kernel measured by the
+# FETCH_SIZE and WRITE_SIZE counters (scaled by a 256 MiB copy in the same
+# runs), for the kernel sources with these SHA-256 digests and the FP32
+# configuration named; profiles/cg_16x16x16_N9_kernels.md holds the runs.
+# Reported only while the sources and the tuned configuration still match.
+COUNTER_TRAFFIC = {
+    "sources": {"paper_2405_11065_amd/csrc/nek_kernels.hpp":
+                "d03b94943cf4947c2d48f1b2f6abda277995642d53033d09a921afa30406e945",
+                "paper_2405_11065_amd/csrc/nek_np.hpp":
+                "090b5c78b2eeee0d0834a8e7e4392e23fce1ec277461cab929f4241a1606a2cf"},
+    "fp32_variant": 4,
+    "bytes_per_launch": 231_400_000,
+}
+
+
+def counter_traffic(variant):
+    import hashlib
+    for rel, digest in COUNTER_TRAFFIC["sources"].items():
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != digest:
+                return None
+    return COUNTER_TRAFFIC["bytes_per_launch"] if variant == COUNTER_TRAFFIC["fp32_variant"] else None
+
 
 def ax_dssum_bytes_per_point(sv, sg, sigma):
     """Algorithmic HBM bytes per local point of nek_ax (operator + segment
@@ -329,7 +352,9 @@ def main():
         "ax_dssum": axd,
         "roofline": {"bound": "hbm", "kernel": f"k_ax<NP=10,f32,f32,CG> variant {tuned['fp32'][0]} (add2s1 + ax_e + x update)",
                      "achieved": round(achieved, 1) if achieved else None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None, "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None,
+                     "traffic": counter_traffic(tuned["fp32"][0]), "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes_per_launch": bpp * nl,
                      "bytes_per_point": bpp, "avg_us": round(ax_avg_s * 1e6, 2), "sampled_launches": ax_n,
                      "update_kernel_avg_us": round(up_ms / max(up_n, 1) * 1e3, 2)},
         "cpu_baseline": cpu,
