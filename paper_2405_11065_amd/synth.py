@@ -25,6 +25,7 @@ SEED_C2 = 2
 SEED_C3 = 3
 SEED_C3_VERTICES = 3003
 SEED_C4 = 4
+SEED_C5 = 5
 
 
 def rng(seed: int) -> np.random.Generator:
@@ -116,3 +117,17 @@ def batch_draw(seed: int, nprob: int, ne_range=(2, 24), orders=(5, 7, 9, 11)):
 def batch_load_seed(seed: int, i: int) -> int:
     """Seed of problem i's load vector in a batch drawn with ``seed``."""
     return int(seed) * 100003 + int(i)
+
+
+def mlp_init(sizes, seed: int):
+    """Initial parameters [W1, b1, W2, b2, ...] (float32) of a perceptron with
+    layer widths ``sizes``: W_l (fan_out, fan_in) ~ U(-a, a) with
+    a = sqrt(6 / (fan_in + fan_out)), biases 0; drawn from PCG64(seed) layer
+    by layer."""
+    r = rng(seed)
+    out = []
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        a = np.sqrt(6.0 / (fi + fo))
+        out.append(r.uniform(-a, a, size=(fo, fi)).astype(np.float32))
+        out.append(np.zeros(fo, dtype=np.float32))
+    return out
