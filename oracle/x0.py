@@ -20,25 +20,38 @@ The local prediction is then made continuous and scaled:
   alpha = glsc3(x0, b) / glsc3(x0, A x0) (the A-norm best multiple of x0)
   x0 <- alpha x0,  rho0 = |b - A x0|_c / |b|_c
 and the guess is dropped for zero (plain CG from zero) when x0 vanishes after
-the projection (glsc3(x0, A x0) <= 0), alpha is not finite, or rho0 >= 1.
+the projection (glsc3(x0, A x0) <= 0) or alpha is not finite, and, under the
+residual policy, when rho0 >= 1.
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def features(P, f):
-    """(inputs [E, n3 + 6], scales [E]) of the load vector f on problem P."""
+def features(P, f, mode: int = 0):
+    """(inputs [E, n3 + 6], scales [E]) of the load vector f on problem P.
+
+    mode 0: element scale s_e = RMS of F over the element, shape numbers q;
+    mode 1: global scale S = RMS of F over all local points, shape numbers q;
+    mode 2: global scale S, centroid (sum B x / sum B) and q_rs, q_rt, q_st
+            (P must be built with want_X)."""
     n3 = P.n ** 3
     B = np.asarray(P.B, dtype=np.float64).reshape(P.E, n3)
     F = np.asarray(f, dtype=np.float64).reshape(P.E, n3) / B
-    s = np.sqrt(np.mean(F * F, axis=1))
+    if mode == 0:
+        s = np.sqrt(np.mean(F * F, axis=1))
+    else:
+        s = np.full(P.E, np.sqrt(np.mean(F * F)))
     Fh = np.zeros_like(F)
     nz = s > 0
     Fh[nz] = F[nz] / s[nz, None]
     g = np.asarray(P.g, dtype=np.float64).reshape(P.E, 6, n3)
     q = g.sum(axis=2) / B.sum(axis=1)[:, None]
     q = q / ((q[:, 0] + q[:, 1] + q[:, 2]) / 3.0)[:, None]
+    if mode == 2:
+        X = np.asarray(P.X, dtype=np.float64).reshape(P.E, 3, n3)
+        cen = (X * B[:, None, :]).sum(axis=2) / B.sum(axis=1)[:, None]
+        q = np.concatenate([cen, q[:, 3:]], axis=1)
     return np.concatenate([Fh, q], axis=1), s
 
 
@@ -51,7 +64,7 @@ def targets(P, x, s, kappa):
     return T
 
 
-def assemble(P, f, Y, s, kappa):
+def assemble(P, f, Y, s, kappa, residual_policy: bool = True):
     """(x0, alpha, rho0, used) from network outputs Y [E, n3]."""
     x0 = (np.asarray(Y, dtype=np.float64) * (s[:, None] * kappa)).ravel()
     x0 = P.dssum(P.c * x0, masked=True)
@@ -64,6 +77,6 @@ def assemble(P, f, Y, s, kappa):
     x0 = alpha * x0
     r = b - P.A(x0)
     rho0 = np.sqrt(P.glsc3(r, r)) / np.sqrt(P.glsc3(b, b))
-    if not rho0 < 1.0:
+    if residual_policy and not rho0 < 1.0:
         return np.zeros(P.nl), alpha, rho0, False
     return x0, alpha, rho0, True

@@ -32,7 +32,7 @@ HIP_FLAGS = [
 
 
 def sources():
-    hip = [os.path.join(CSRC, "nek_lib.hip"), os.path.join(CSRC, "nek_batch.hip")] + sorted(glob.glob(os.path.join(CSRC, "nek_np[0-9][0-9].hip")))
+    hip = [os.path.join(CSRC, f) for f in ("nek_lib.hip", "nek_batch.hip", "nek_mlp.hip", "nek_x0.hip")] + sorted(glob.glob(os.path.join(CSRC, "nek_np[0-9][0-9].hip")))
     return hip, [os.path.join(CSRC, "nek_setup.cpp")]
 
 

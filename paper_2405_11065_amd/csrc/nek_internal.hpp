@@ -120,6 +120,15 @@ struct nek_ctx {
     float *r32 = nullptr, *p32 = nullptr, *w32 = nullptr;
     int *hflags = nullptr;   // pinned
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // learned initial guess (nek_x0_*, nek_grf): node coordinates [E][3][NP^3]
+    // and per-element network buffers
+    double *xyz = nullptr;
+    double *gfeat = nullptr;
+    int gfeat_cap = 0;
+    uint16_t *x0_X = nullptr;
+    float *x0_Y = nullptr;
+    double *x0_s = nullptr;
+    long x0_ldx = 0, x0_ldy = 0;
     // sampled kernel timing (nek_prof_*)
     int prof_every = 0;
     long prof_tick = 0;
@@ -205,6 +214,9 @@ int gather_launch(nek_ctx *c, const double *in, double *out, bool weighted);
 int start_launch(nek_ctx *c, int rslot, int hist_off, double stop_tol, int maxit, int stop_on_initial,
                  double rtz_prev = 0.0);
 int cg_prologue(nek_ctx *c, const double *f, const double *x0, double *x, double *r);
+int ax_local_launch(nek_ctx *c, const void *u, void *w, int dtype, int prec);
+int resid_launch(nek_ctx *c, const double *b, const double *w, double *r, int slot);
+int read_scal(nek_ctx *c, Scal &h);
 int finish_status(const IterState &s, double tol);
 int batch_advance_launch(hipStream_t s, int *base, int step);
 int batch_alldone_launch(hipStream_t s, Scal *const *scs, int nprob, int *out);

@@ -2,6 +2,7 @@
 // finish, sorted-segment dssum, precision conversion of g, fills.  Internal
 // header, included only by nek_lib.hip.
 #pragma once
+#include "nek_bf16.hpp"
 #include "nek_kernels.hpp"
 
 namespace nek {
@@ -74,25 +75,6 @@ __global__ __launch_bounds__(UPD_BS) void k_dssum_seg(T *__restrict__ w, const i
 }
 
 // Rounding of the FP64 geometric factors to the storage precision.
-__device__ __forceinline__ uint16_t f64_to_bf16_rne(double x)
-{
-    // Round-to-nearest-even directly from binary64 (no double rounding via
-    // binary32).  Values below the binary32 normal range flush to signed 0.
-    const unsigned long long u = __double_as_longlong(x);
-    const unsigned sign = (unsigned)(u >> 63);
-    const int ex = (int)((u >> 52) & 0x7ff);
-    const unsigned long long man = u & 0xfffffffffffffULL;
-    if (ex == 0x7ff) return (uint16_t)((sign << 15) | 0x7f80u | (man ? 0x40u : 0u));
-    const int eb = ex - 1023 + 127;
-    if (ex == 0 || eb <= 0) return (uint16_t)(sign << 15);
-    if (eb >= 0xff) return (uint16_t)((sign << 15) | 0x7f80u);
-    unsigned bits = (sign << 15) | ((unsigned)eb << 7) | (unsigned)(man >> 45);
-    const unsigned long long rest = man & ((1ULL << 45) - 1);
-    const unsigned long long half = 1ULL << 44;
-    if (rest > half || (rest == half && (bits & 1u))) bits += 1u;   // carries into the exponent correctly
-    return (uint16_t)bits;
-}
-
 __global__ void k_g_to_f32(const double *__restrict__ g, float *__restrict__ o, unsigned long n)
 {
     for (unsigned long t = blockIdx.x * (unsigned long)blockDim.x + threadIdx.x; t < n; t += (unsigned long)gridDim.x * blockDim.x)

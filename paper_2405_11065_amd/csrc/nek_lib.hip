@@ -512,6 +512,7 @@ void nek_free(nek_ctx *c)
     dfree(c->perm); dfree(c->segptr); dfree(c->segflag); dfree(c->sc); dfree(c->partials); dfree(c->hist);
     dfree(c->b); dfree(c->r64); dfree(c->p64); dfree(c->w64); dfree(c->d64);
     dfree(c->r32); dfree(c->p32); dfree(c->w32);
+    dfree(c->xyz); dfree(c->gfeat); dfree(c->x0_X); dfree(c->x0_Y); dfree(c->x0_s);
     if (c->hflags) (void)hipHostFree(c->hflags);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);

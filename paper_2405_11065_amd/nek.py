@@ -31,7 +31,10 @@ EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_
            "nek_dssum", "nek_glsc3", "nek_cg_solve", "nek_prof_enable", "nek_prof_read", "nek_num_variants",
            "nek_tune", "nek_set_variant", "nek_get_variant", "nek_batch_setup", "nek_batch_free",
            "nek_batch_size", "nek_batch_ctx", "nek_batch_orders", "nek_batch_tune", "nek_batch_set_variant",
-           "nek_batch_get_variant", "nek_batch_solve", "nek_batch_counters", "nek_strerror")
+           "nek_batch_get_variant", "nek_batch_solve", "nek_batch_counters", "nek_strerror",
+           "nek_mlp_create", "nek_mlp_free", "nek_mlp_num_params", "nek_mlp_get_params", "nek_mlp_set_params",
+           "nek_mlp_forward", "nek_mlp_loss_grad", "nek_mlp_adam", "nek_mlp_train", "nek_x0_features",
+           "nek_x0_targets", "nek_x0_predict", "nek_grf")
 
 NEK_MAX_VARIANTS = 6
 NEK_BATCH_NO_GRAPH = 1
@@ -106,6 +109,24 @@ def load(path: str = LIB_PATH):
     lib.nek_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double, ctypes.c_int,
                                     ctypes.POINTER(vp), ctypes.POINTER(nek_stats), ctypes.c_int]
     lib.nek_batch_counters.argtypes = [vp, i64p, i64p]
+    dp, fp = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)
+    lib.nek_mlp_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, fp, vp, ctypes.POINTER(vp)]
+    lib.nek_mlp_free.argtypes = [vp]
+    lib.nek_mlp_free.restype = None
+    lib.nek_mlp_num_params.argtypes = [vp]
+    lib.nek_mlp_num_params.restype = ctypes.c_int64
+    lib.nek_mlp_get_params.argtypes = [vp, fp]
+    lib.nek_mlp_set_params.argtypes = [vp, fp]
+    lib.nek_mlp_forward.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int64, vp, ctypes.c_int]
+    lib.nek_mlp_loss_grad.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int64, dp, fp]
+    lib.nek_mlp_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]
+    lib.nek_mlp_train.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_float, ctypes.c_uint64, fp]
+    lib.nek_x0_features.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, vp]
+    lib.nek_x0_targets.argtypes = [vp, vp, vp, ctypes.c_double, vp, ctypes.c_int]
+    lib.nek_x0_predict.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, vp, dp, dp,
+                                   ctypes.POINTER(ctypes.c_int)]
+    lib.nek_grf.argtypes = [vp, ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_int, vp]
     lib.nek_strerror.argtypes = [ctypes.c_int]
     lib.nek_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -451,6 +472,182 @@ class Batch:
                                        0 if graph else NEK_BATCH_NO_GRAPH)
         _check(rc, "nek_batch_solve", ok=(NEK_OK,) if raise_on_noconv else (NEK_OK, NEK_NOCONV))
         return xs, [s.as_dict() for s in st], rc
+
+
+def _f32p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _dev2d(t, dtype, cols, what):
+    """Check a contiguous CUDA matrix with at least ``cols`` columns; returns its pitch."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or t.dim() != 2 or not t.is_contiguous():
+        raise TypeError(f"{what}: expected a contiguous 2-D CUDA tensor of {dtype}")
+    if t.shape[1] < cols:
+        raise ValueError(f"{what}: needs at least {cols} columns")
+    return int(t.shape[1])
+
+
+class Mlp:
+    """Initial-guess network n_in -> n_hidden -> n_hidden -> n_out (include/nek_mlp.h)."""
+
+    def __init__(self, n_in, n_hidden, n_out, params=None, stream=None):
+        torch = _torch()
+        self._lib = load()
+        self.n_in, self.n_hidden, self.n_out = int(n_in), int(n_hidden), int(n_out)
+        self.ld_in = (self.n_in + 7) // 8 * 8
+        self.ld_out = (self.n_out + 7) // 8 * 8
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        h = ctypes.c_void_p()
+        flat = None if params is None else self.flatten(params)
+        _check(self._lib.nek_mlp_create(self.n_in, self.n_hidden, self.n_out, None if flat is None else _f32p(flat),
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "nek_mlp_create")
+        self._h = h
+        self.num_params = int(self._lib.nek_mlp_num_params(self._h))
+
+    def shapes(self):
+        i, h, o = self.n_in, self.n_hidden, self.n_out
+        return [(h, i), (h,), (h, h), (h,), (o, h), (o,)]
+
+    def flatten(self, params):
+        out = []
+        for p, shp in zip(params, self.shapes()):
+            a = np.asarray(p, dtype=np.float32)
+            if a.shape != shp:
+                raise ValueError(f"parameter shape {a.shape} != {shp}")
+            out.append(a.ravel())
+        return np.ascontiguousarray(np.concatenate(out))
+
+    def unflatten(self, flat):
+        out, k = [], 0
+        for shp in self.shapes():
+            n = int(np.prod(shp))
+            out.append(flat[k:k + n].reshape(shp))
+            k += n
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.nek_mlp_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        flat = np.empty(self.num_params, dtype=np.float32)
+        _check(self._lib.nek_mlp_get_params(self._h, _f32p(flat)), "nek_mlp_get_params")
+        return self.unflatten(flat)
+
+    def set_params(self, params):
+        flat = self.flatten(params)
+        _check(self._lib.nek_mlp_set_params(self._h, _f32p(flat)), "nek_mlp_set_params")
+
+    def forward(self, X, rows=None, Y=None):
+        torch = _torch()
+        ldx = _dev2d(X, torch.bfloat16, self.n_in, "X")
+        rows = X.shape[0] if rows is None else int(rows)
+        if Y is None:
+            Y = torch.empty((rows, self.ld_out), dtype=torch.float32, device=X.device)
+        ldy = _dev2d(Y, torch.float32, self.n_out, "Y")
+        if ldx % 8 or X.shape[0] < rows or Y.shape[0] < rows:
+            raise ValueError("X pitch must be a multiple of 8 and X, Y must hold rows rows")
+        _check(self._lib.nek_mlp_forward(self._h, X.data_ptr(), ldx, rows, Y.data_ptr(), ldy), "nek_mlp_forward")
+        return Y
+
+    def loss_grad(self, X, T, rows=None):
+        """(loss, gradient list in parameter order)."""
+        torch = _torch()
+        ldx = _dev2d(X, torch.bfloat16, self.n_in, "X")
+        ldt = _dev2d(T, torch.float32, self.n_out, "T")
+        rows = X.shape[0] if rows is None else int(rows)
+        if ldx % 8 or X.shape[0] < rows or T.shape[0] < rows:
+            raise ValueError("X pitch must be a multiple of 8 and X, T must hold rows rows")
+        loss = ctypes.c_double()
+        g = np.empty(self.num_params, dtype=np.float32)
+        _check(self._lib.nek_mlp_loss_grad(self._h, X.data_ptr(), ldx, T.data_ptr(), ldt, rows, ctypes.byref(loss),
+                                           _f32p(g)), "nek_mlp_loss_grad")
+        return loss.value, self.unflatten(g)
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(self._lib.nek_mlp_adam(self._h, lr, beta1, beta2, eps), "nek_mlp_adam")
+
+    def train(self, X, T, nsamples, batch, steps, lr=1e-3, seed=0, history=True):
+        torch = _torch()
+        ldx = _dev2d(X, torch.bfloat16, self.n_in, "X")
+        ldt = _dev2d(T, torch.float32, self.n_out, "T")
+        if ldx % 8 or X.shape[0] < nsamples or T.shape[0] < nsamples:
+            raise ValueError("X pitch must be a multiple of 8 and X, T must hold nsamples rows")
+        hist = np.empty(int(steps), dtype=np.float32) if history else None
+        _check(self._lib.nek_mlp_train(self._h, X.data_ptr(), ldx, T.data_ptr(), ldt, int(nsamples), int(batch),
+                                       int(steps), float(lr), int(seed), None if hist is None else _f32p(hist)),
+               "nek_mlp_train")
+        return hist
+
+
+def x0_features(ctx, f, X=None, s=None, mode=0):
+    """(X bfloat16 [E, ld], s float64 [E]) of the load vector f."""
+    torch = _torch()
+    n3 = (ctx.N + 1) ** 3
+    if X is None:
+        X = torch.empty((ctx.E, (n3 + 6 + 7) // 8 * 8), dtype=torch.bfloat16, device=f.device)
+    if s is None:
+        s = torch.empty(ctx.E, dtype=torch.float64, device=f.device)
+    ldx = _dev2d(X, torch.bfloat16, n3 + 6, "X")
+    if ctx._vec(f, "f") != NEK_F64 or X.shape[0] < ctx.E or s.numel() < ctx.E or s.dtype != torch.float64:
+        raise ValueError("f must be float64 and X, s must hold E rows")
+    _check(ctx._lib.nek_x0_features(ctx._h, f.data_ptr(), int(mode), X.data_ptr(), ldx, s.data_ptr()),
+           "nek_x0_features")
+    return X, s
+
+
+def x0_targets(ctx, x, s, kappa, T=None):
+    torch = _torch()
+    n3 = (ctx.N + 1) ** 3
+    if T is None:
+        T = torch.empty((ctx.E, (n3 + 7) // 8 * 8), dtype=torch.float32, device=x.device)
+    ldt = _dev2d(T, torch.float32, n3, "T")
+    if ctx._vec(x, "x") != NEK_F64 or T.shape[0] < ctx.E:
+        raise ValueError("x must be float64 and T must hold E rows")
+    _check(ctx._lib.nek_x0_targets(ctx._h, x.data_ptr(), s.data_ptr(), float(kappa), T.data_ptr(), ldt),
+           "nek_x0_targets")
+    return T
+
+
+NEK_X0_RESIDUAL, NEK_X0_ENERGY = 0, 1
+
+
+def x0_predict(ctx, mlp, f, kappa, x0=None, policy=NEK_X0_RESIDUAL, mode=0):
+    """(x0, alpha, rho0, used) -- see nek_x0_predict."""
+    if ctx._vec(f, "f") != NEK_F64:
+        raise TypeError("f must be float64")
+    if x0 is None:
+        x0 = ctx.new_vector()
+    elif ctx._vec(x0, "x0") != NEK_F64:
+        raise TypeError("x0 must be float64")
+    a, r, u = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+    _check(ctx._lib.nek_x0_predict(ctx._h, mlp._h, f.data_ptr(), int(mode), float(kappa), int(policy), x0.data_ptr(),
+                                   ctypes.byref(a),
+                                   ctypes.byref(r), ctypes.byref(u)), "nek_x0_predict")
+    return x0, a.value, r.value, bool(u.value)
+
+
+def grf(ctx, draw, scale=1.0, times_B=True, out=None):
+    """Forcing sample of a random-Fourier-feature draw (omega, phi, a, scale attributes) on ctx's nodes."""
+    if out is None:
+        out = ctx.new_vector()
+    om = np.ascontiguousarray(draw.omega, dtype=np.float64)
+    ph = np.ascontiguousarray(draw.phi, dtype=np.float64)
+    am = np.ascontiguousarray(draw.a, dtype=np.float64)
+    if om.shape != (ph.size, 3) or am.size != ph.size:
+        raise ValueError("omega must be [nfeat, 3] with phi and a of nfeat entries")
+    d = ctypes.POINTER(ctypes.c_double)
+    _check(ctx._lib.nek_grf(ctx._h, ph.size, om.ctypes.data_as(d), ph.ctypes.data_as(d), am.ctypes.data_as(d),
+                            float(scale) * float(draw.scale), int(bool(times_B)), out.data_ptr()), "nek_grf")
+    return out
 
 
 def torch_empty_like(t):

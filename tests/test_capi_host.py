@@ -12,7 +12,7 @@ import oracle
 from paper_2405_11065_amd import nek, synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("nek.h", "nek_host.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("nek.h", "nek_host.h", "nek_mlp.h")]
 
 
 def declared_functions():
