@@ -197,6 +197,34 @@ def batch_case(torch, nek, synth, nprob=64, steps=1):
     return out
 
 
+def learned_case(torch, nsolves=10000, steps=2500, neval=4):
+    """Learned initial guess: 10,000 FP64 solves on 8^3-element N=7 meshes of
+    [0,1]^3 (+-10 % interior vertex moves, 64 distinct meshes) forced by
+    Gaussian random fields (length scale 0.2) give 5.12 M element rows; the
+    518 -> 256 -> 256 -> 512 network trains for `steps` Adam steps of 4096
+    rows on the GPU; then 16^3-element N=7 problems are solved to 1e-8 by
+    FP64 CG from zero and from the network's guess (prediction time
+    included)."""
+    from paper_2405_11065_amd import learned_x0 as lx
+    X, T, info = lx.make_dataset(torch, nsolves, log=log)
+    net, hist, t_train = lx.train(torch, X, T, steps)
+    rows = X.shape[0]
+    del X, T
+    torch.cuda.empty_cache()
+    log(f"learned x0: trained {steps} steps in {t_train:.1f} s")
+    ev = lx.evaluate(torch, net, neval=neval)
+    net.close()
+    # GEMM work of one training step: forward 3 products, backward 5 (2 m n k flops each)
+    n_in, h, n_out, bsz = 518, lx.HIDDEN, 512, 4096
+    fl = 2 * bsz * (n_in * h + h * h + h * n_out) * 3 - 2 * bsz * n_in * h
+    return {"data": info, "feature_mode": lx.MODE, "train_steps": steps, "train_rows": rows, "batch": bsz,
+            "train_s": round(t_train, 2), "ms_per_step": round(t_train / steps * 1e3, 3),
+            "train_TFLOPs_bf16": round(fl * steps / t_train / 1e12, 2),
+            "loss_first_last": [float(hist[:50].mean()), float(hist[-50:].mean())],
+            "eval": {k: v for k, v in ev.items() if k != "per_problem"},
+            "eval_per_problem": ev["per_problem"]}
+
+
 def profile_sequence(torch, nek, synth, variants=""):
     """A short sequence for counter collection (few dispatches)."""
     ctx = nek.Context(NEL, N, prec="fp32")
@@ -238,6 +266,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-big", action="store_true", help="skip the 32^3 deformed-mesh BF16 measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched solve")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned initial guess (data, training, eval)")
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for hardware-counter runs: 40 mixed and 40 FP64 CG iterations, "
                          "5 nek_ax per precision and a 256 MiB copy for calibration")
@@ -322,6 +351,7 @@ def main():
     big = None if args.no_big else big_case(torch, nek, synth)
     log("32^3 case done")
     batch = None if args.no_batch else batch_case(torch, nek, synth)
+    learned = None if args.no_learned else learned_case(torch)
 
     bpp = cg_operator_bytes_per_point(4, 4, 8)
     ax_avg_s = ax_ms / max(ax_n, 1) / 1e3
@@ -360,6 +390,7 @@ def main():
         "cpu_baseline": cpu,
         "deformed_32x32x32_N9": big,
         "batch_64": batch,
+        "learned_x0": learned,
     }
     ctx.close()
     print(json.dumps(out), flush=True)
