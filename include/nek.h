@@ -161,6 +161,11 @@ int nek_ax_local(nek_ctx *ctx, const void *u, void *w, int dtype);
 /*
  * nek_ax -- w = M o dssum(A_L u): the assembled, masked operator (the ax call
  * of Table 1 with its gather-scatter).  Same arguments as nek_ax_local.
+ * A_L u goes to a work vector of the context, then every node's copies are
+ * summed in FP64 in the fixed order of the CG update kernel (within a plane
+ * of constant k: (own + x-neighbour) + (y + xy-neighbour); the planes below
+ * and above added in turn), identical for every copy, and rounded once to
+ * dtype.  Runs in the context's CG kernel configuration for the precision.
  */
 int nek_ax(nek_ctx *ctx, const void *u, void *w, int dtype);
 

@@ -180,6 +180,10 @@ struct NpOps {
     int (*ax64)(nek_ctx *, const double *u, double *w);
     int (*ax32)(nek_ctx *, const float *u, float *w);
     int (*ax16)(nek_ctx *, const float *u, float *w);
+    // w = M dssum(A_L u) through scratch, in configuration v
+    int (*axa64)(nek_ctx *, int v, const double *u, double *scratch, double *w);
+    int (*axa32)(nek_ctx *, int v, const float *u, float *scratch, float *w);
+    int (*axa16)(nek_ctx *, int v, const float *u, float *scratch, float *w);
     // out = M o sum of copies (weighted by c when weighted)
     int (*gather64)(nek_ctx *, const double *in, double *out, bool weighted);
     // partials of glsc3(a, c, b)

@@ -502,111 +502,269 @@ __device__ __forceinline__ double gather_copies(const T *__restrict__ w, const P
 // k-columns).  All loads of a column are issued before any is used: the own
 // column of r and w, the columns of w in the x, y and xy neighbours (for
 // threads on those faces), and the neighbouring slices in z.
+// The copies that a column (e, i, j) shares with neighbouring elements, for
+// the fixed-order sums of the gather-scatter: the own column, the columns of
+// the x, y and xy neighbours in the same k-range (offsets offX, offY, offXY
+// from the element start; loaded only where the neighbour exists), and the
+// end nodes of those four columns in the elements below (slice N of e - oz,
+// meeting k = 0) and above (slice 0 of e + oz, meeting k = N).  For FP32
+// the eight end-node loads are issued without a branch from addresses that
+// are always valid (the element's own column when a neighbour is absent) and
+// absent copies are then replaced by 0: as single conditional loads they
+// would each end in a wait for every load in flight.
+template <int NP, typename T>
+__device__ __forceinline__ void load_copies(const T *__restrict__ we, int oz, bool hx, bool hy, bool hzm, bool hzp,
+                                            int ij, int offX, int offY, int offXY, T wo[NP], T wx[NP], T wy[NP],
+                                            T wxy[NP], T zm[4], T zp[4])
+{
+    constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = NP - 1;
+    const bool hxy = hx && hy;
+    const int cX = hx ? offX : ij, cY = hy ? offY : ij, cXY = hxy ? offXY : ij;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        wo[k] = we[k * NP2 + ij];
+        wx[k] = wy[k] = wxy[k] = (T)0;
+    }
+    if (hx) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) wx[k] = we[k * NP2 + offX];
+    }
+    if (hy) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) wy[k] = we[k * NP2 + offY];
+    }
+    if (hxy) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) wxy[k] = we[k * NP2 + offXY];
+    }
+    if constexpr (sizeof(T) == 8) {
+        // FP64: conditional loads (eight more values in flight would cost a
+        // wave of occupancy per SIMD)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) zm[q] = zp[q] = (T)0;
+        if (hzm) {
+            const T *wz = we - oz * NP3 + N * NP2;
+            zm[0] = wz[ij];
+            if (hx) zm[1] = wz[offX];
+            if (hy) zm[2] = wz[offY];
+            if (hxy) zm[3] = wz[offXY];
+        }
+        if (hzp) {
+            const T *wz = we + oz * NP3;
+            zp[0] = wz[ij];
+            if (hx) zp[1] = wz[offX];
+            if (hy) zp[2] = wz[offY];
+            if (hxy) zp[3] = wz[offXY];
+        }
+    } else {
+        const T *wm = hzm ? we - oz * NP3 + N * NP2 : we;
+        const T *wp = hzp ? we + oz * NP3 : we;
+        const T m0 = wm[ij], m1 = wm[cX], m2 = wm[cY], m3 = wm[cXY];
+        const T p0 = wp[ij], p1 = wp[cX], p2 = wp[cY], p3 = wp[cXY];
+        zm[0] = hzm ? m0 : (T)0;
+        zm[1] = (hzm && hx) ? m1 : (T)0;
+        zm[2] = (hzm && hy) ? m2 : (T)0;
+        zm[3] = (hzm && hxy) ? m3 : (T)0;
+        zp[0] = hzp ? p0 : (T)0;
+        zp[1] = (hzp && hx) ? p1 : (T)0;
+        zp[2] = (hzp && hy) ? p2 : (T)0;
+        zp[3] = (hzp && hxy) ? p3 : (T)0;
+    }
+}
+
+// One column (e, i, j) of the update kernel: its residual and every copy of
+// its nodes, loaded together.
+template <int NP, typename T> struct UpdCol {
+    int e, ez;
+    bool valid, hx, hy, hzm, hzp;
+    T rv[NP], wo[NP], wx[NP], wy[NP], wxy[NP], zm[4], zp[4];
+};
+
+template <int NP, int EPW, typename T>
+__device__ __forceinline__ void upd_load(UpdCol<NP, T> &c, const T *__restrict__ r, const T *__restrict__ w, int grp,
+                                         int el, int i, int j, int ij, Box box, int E)
+{
+    constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = NP - 1;
+    c.e = grp * EPW + el;
+    c.valid = false;
+    if (c.e >= E) return;
+    const int ex = c.e % box.nx;
+    const int eyz = c.e / box.nx;
+    const int ey = eyz % box.ny;
+    c.ez = eyz / box.ny;
+    if ((i == 0 && ex == 0) || (i == N && ex == box.nx - 1) || (j == 0 && ey == 0) || (j == N && ey == box.ny - 1))
+        return;   // the whole column lies on the Dirichlet boundary
+    c.valid = true;
+    c.hx = (i == 0 && ex > 0) || (i == N && ex < box.nx - 1);
+    c.hy = (j == 0 && ey > 0) || (j == N && ey < box.ny - 1);
+    const bool xneg = i == 0, yneg = j == 0;   // neighbour sits below (dx or dy = -1)
+    const int ox = xneg ? -1 : 1, oy = yneg ? -box.nx : box.nx;
+    const int colX = (xneg ? N : 0) + NP * j, colY = i + NP * (yneg ? N : 0);
+    const int colXY = (xneg ? N : 0) + NP * (yneg ? N : 0);
+    c.hzm = c.ez > 0;
+    c.hzp = c.ez < box.nz - 1;
+    const int oz = box.nx * box.ny;   // local indices fit in 32 bits (checked at set-up)
+#pragma unroll
+    for (int k = 0; k < NP; ++k) c.rv[k] = r[c.e * NP3 + k * NP2 + ij];
+    load_copies<NP>(w + c.e * NP3, oz, c.hx, c.hy, c.hzm, c.hzp, ij, ox * NP3 + colX, oy * NP3 + colY,
+                    (ox + oy) * NP3 + colXY, c.wo, c.wx, c.wy, c.wxy, c.zm, c.zp);
+}
+
+// Gathered sum S of every node of the column (fixed pairwise order, see
+// upd_body), r -= alpha S, and the column's part of sum c r^2.
+template <int NP, typename T>
+__device__ __forceinline__ void upd_apply(const UpdCol<NP, T> &c, T *__restrict__ r, double alpha, int ij, Box box,
+                                          double &part)
+{
+    constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = NP - 1;
+    auto plane = [](double o, double X, double Y, double XY) -> double { return (o + X) + (Y + XY); };
+    const int mxy = (c.hx ? 2 : 1) * (c.hy ? 2 : 1);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        if ((k == 0 && c.ez == 0) || (k == N && c.ez == box.nz - 1)) continue;   // Dirichlet slice
+        double S = plane((double)c.wo[k], (double)c.wx[k], (double)c.wy[k], (double)c.wxy[k]);
+        int m = mxy;
+        if (k == 0 && c.hzm) {
+            S = plane((double)c.zm[0], (double)c.zm[1], (double)c.zm[2], (double)c.zm[3]) + S;
+            m *= 2;
+        }
+        if (k == N && c.hzp) {
+            S = S + plane((double)c.zp[0], (double)c.zp[1], (double)c.zp[2], (double)c.zp[3]);
+            m *= 2;
+        }
+        const T rn = (T)((double)c.rv[k] - alpha * S);
+        r[c.e * NP3 + k * NP2 + ij] = rn;
+        part += ((double)rn * (double)rn) * inv_mult(m);
+    }
+}
+
+// Gather-scatter + mask of w = A_L p fused with r -= alpha M dssum(w) and the
+// partials of rtr = glsc3(r, c, r).  Copies in one plane of constant k (own,
+// x and y neighbours, the diagonal one; zero when absent, and adding +0.0 is
+// exact) are summed as (own + X) + (Y + XY), pairing copies of the same y row
+// first; the planes below and above are then added in turn.  IEEE addition
+// is commutative, so every copy of a node computes the bit-identical value
+// and r stays exactly continuous.
 template <int NP, int EPW, typename T>
 __device__ __forceinline__ void upd_body(T *__restrict__ r, const T *__restrict__ w, Scal *__restrict__ sc,
                                          const double *__restrict__ P1cur, int nb1, double *__restrict__ P2cur,
                                          int it, Box box, int E, int ngroups, unsigned blk, unsigned nblk)
 {
-    constexpr int NP2 = NP * NP, NP3 = NP2 * NP, BS = EPW * NP2, N = NP - 1;
+    constexpr int NP2 = NP * NP, BS = EPW * NP2;
     __shared__ double sbuf[BS];
     const IterState cur = sc->st[it & 1];
     if (cur.done) return;
-    const double pap = sum_all<BS>(P1cur, nb1, sbuf);
-    const bool writer = blk == 0 && threadIdx.x == 0;
-    if (!__builtin_isfinite(pap) || !(pap > 0)) {
-        if (writer) sc->k2flag[it & 1] = __builtin_isfinite(pap) ? -5 : -6;
-        return;
-    }
-    const double alpha = cur.rtz / pap;
     const int tid = threadIdx.x;
     const int el = tid / NP2, ij = tid - el * NP2;
     const int i = ij % NP, j = ij / NP;
     const unsigned lb = xcd_block(blk, nblk);
     const int g0 = (int)(((long)lb * ngroups) / nblk);
     const int g1 = (int)(((long)(lb + 1) * ngroups) / nblk);
-    const int oz = box.nx * box.ny;   // local indices fit in 32 bits (checked at set-up)
+    // FP32 columns are loaded before the reduction; FP64 ones after it (held
+    // across the reduction they would cost a wave of occupancy per SIMD)
+    constexpr bool early = sizeof(T) == 4;
+    UpdCol<NP, T> c;
+    c.valid = false;
+    if (early && g0 < g1) upd_load<NP, EPW, T>(c, r, w, g0, el, i, j, ij, box, E);
+    const double pap = sum_all<BS>(P1cur, nb1, sbuf);
+    const bool writer = blk == 0 && tid == 0;
+    if (!__builtin_isfinite(pap) || !(pap > 0)) {
+        if (writer) sc->k2flag[it & 1] = __builtin_isfinite(pap) ? -5 : -6;
+        return;
+    }
+    const double alpha = cur.rtz / pap;
     double part = 0.0;
+    if constexpr (early) {
+        for (int grp = g0; grp < g1; ++grp) {
+            if (grp > g0) upd_load<NP, EPW, T>(c, r, w, grp, el, i, j, ij, box, E);
+            if (c.valid) upd_apply<NP, T>(c, r, alpha, ij, box, part);
+        }
+    } else {
+        constexpr int NP3 = NP2 * NP, N = NP - 1;
+        const int oz = box.nx * box.ny;
+        for (int grp = g0; grp < g1; ++grp) {
+            const int e = grp * EPW + el;
+            if (e >= E) continue;
+            const int ex = e % box.nx;
+            const int eyz = e / box.nx;
+            const int ey = eyz % box.ny, ez = eyz / box.ny;
+            if ((i == 0 && ex == 0) || (i == N && ex == box.nx - 1) || (j == 0 && ey == 0) ||
+                (j == N && ey == box.ny - 1))
+                continue;   // the whole column lies on the Dirichlet boundary
+            const bool hx = (i == 0 && ex > 0) || (i == N && ex < box.nx - 1);
+            const bool hy = (j == 0 && ey > 0) || (j == N && ey < box.ny - 1);
+            const bool xneg = i == 0, yneg = j == 0;
+            const int ox = xneg ? -1 : 1, oy = yneg ? -box.nx : box.nx;
+            const int colX = (xneg ? N : 0) + NP * j, colY = i + NP * (yneg ? N : 0);
+            const int colXY = (xneg ? N : 0) + NP * (yneg ? N : 0);
+            UpdCol<NP, T> cg;
+            cg.e = e;
+            cg.ez = ez;
+            cg.hx = hx;
+            cg.hy = hy;
+            cg.hzm = ez > 0;
+            cg.hzp = ez < box.nz - 1;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) cg.rv[k] = r[e * NP3 + k * NP2 + ij];
+            load_copies<NP>(w + e * NP3, oz, hx, hy, cg.hzm, cg.hzp, ij, ox * NP3 + colX, oy * NP3 + colY,
+                            (ox + oy) * NP3 + colXY, cg.wo, cg.wx, cg.wy, cg.wxy, cg.zm, cg.zp);
+            upd_apply<NP, T>(cg, r, alpha, ij, box, part);
+        }
+    }
+    const double s = block_sum<BS>(part, sbuf);
+    if (tid == 0) P2cur[blk] = s;
+    if (writer) sc->k2flag[it & 1] = 0;
+}
+
+// wout = M o dssum(win) out of place, for whole columns: the copies of every
+// node are gathered exactly as in upd_body (same columns, same fixed pairwise
+// order), summed in FP64 and rounded once; Dirichlet nodes get 0.
+template <int NP, int EPW, typename T>
+__global__ __launch_bounds__(EPW *NP *NP) void k_assemble(const T *__restrict__ win, T *__restrict__ wout, Box box,
+                                                          int E, int ngroups)
+{
+    constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = NP - 1;
+    const int tid = threadIdx.x;
+    const int el = tid / NP2, ij = tid - el * NP2;
+    const int i = ij % NP, j = ij / NP;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int g0 = (int)(((long)lb * ngroups) / gridDim.x);
+    const int g1 = (int)(((long)(lb + 1) * ngroups) / gridDim.x);
+    const int oz = box.nx * box.ny;
     for (int grp = g0; grp < g1; ++grp) {
         const int e = grp * EPW + el;
         if (e >= E) continue;
         const int ex = e % box.nx;
         const int eyz = e / box.nx;
         const int ey = eyz % box.ny, ez = eyz / box.ny;
+        T *oe = wout + e * NP3;
         if ((i == 0 && ex == 0) || (i == N && ex == box.nx - 1) || (j == 0 && ey == 0) ||
-            (j == N && ey == box.ny - 1))
-            continue;   // the whole column lies on the Dirichlet boundary
+            (j == N && ey == box.ny - 1)) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) oe[k * NP2 + ij] = (T)0;
+            continue;
+        }
         const bool hx = (i == 0 && ex > 0) || (i == N && ex < box.nx - 1);
         const bool hy = (j == 0 && ey > 0) || (j == N && ey < box.ny - 1);
-        const bool xneg = i == 0, yneg = j == 0;   // neighbour sits below (dx or dy = -1)
+        const bool xneg = i == 0, yneg = j == 0;
         const int ox = xneg ? -1 : 1, oy = yneg ? -box.nx : box.nx;
         const int colX = (xneg ? N : 0) + NP * j, colY = i + NP * (yneg ? N : 0);
         const int colXY = (xneg ? N : 0) + NP * (yneg ? N : 0);
         const bool hzm = ez > 0, hzp = ez < box.nz - 1;
-        const T *we = w + e * NP3;
-        T rv[NP], wo[NP], wx[NP], wy[NP], wxy[NP];
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            rv[k] = r[e * NP3 + k * NP2 + ij];   // int arithmetic
-            wo[k] = we[k * NP2 + ij];
-            wx[k] = wy[k] = wxy[k] = (T)0;
-        }
-        if (hx) {
-#pragma unroll
-            for (int k = 0; k < NP; ++k) wx[k] = we[ox * NP3 + k * NP2 + colX];
-        }
-        if (hy) {
-#pragma unroll
-            for (int k = 0; k < NP; ++k) wy[k] = we[oy * NP3 + k * NP2 + colY];
-        }
-        if (hx && hy) {
-#pragma unroll
-            for (int k = 0; k < NP; ++k) wxy[k] = we[(ox + oy) * NP3 + k * NP2 + colXY];
-        }
-        // z neighbours: slice N of element e - oz (for k = 0), slice 0 of e + oz (for k = N)
-        T zm[4] = {0, 0, 0, 0}, zp[4] = {0, 0, 0, 0};   // own, X, Y, XY columns
-        if (hzm) {
-            const T *wz = we - oz * NP3 + N * NP2;
-            zm[0] = wz[ij];
-            if (hx) zm[1] = wz[ox * NP3 + colX];
-            if (hy) zm[2] = wz[oy * NP3 + colY];
-            if (hx && hy) zm[3] = wz[(ox + oy) * NP3 + colXY];
-        }
-        if (hzp) {
-            const T *wz = we + oz * NP3;
-            zp[0] = wz[ij];
-            if (hx) zp[1] = wz[ox * NP3 + colX];
-            if (hy) zp[2] = wz[oy * NP3 + colY];
-            if (hx && hy) zp[3] = wz[(ox + oy) * NP3 + colXY];
-        }
-        // Copies in one plane of constant z: own, the x and y neighbours and
-        // the diagonal one (zero when absent; adding +0.0 is exact).  The sum
-        // (own + X) + (Y + XY) pairs copies of the same y row first, and
-        // planes are then added pairwise; IEEE addition is commutative, so
-        // every copy of a node computes the bit-identical value and r stays
-        // exactly continuous.
+        const T *we = win + e * NP3;
+        T wo[NP], wx[NP], wy[NP], wxy[NP], zm[4], zp[4];
+        load_copies<NP>(we, oz, hx, hy, hzm, hzp, ij, ox * NP3 + colX, oy * NP3 + colY, (ox + oy) * NP3 + colXY, wo, wx,
+                        wy, wxy, zm, zp);
         auto plane = [](double o, double X, double Y, double XY) -> double { return (o + X) + (Y + XY); };
-        const int mxy = (hx ? 2 : 1) * (hy ? 2 : 1);
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            if ((k == 0 && ez == 0) || (k == N && ez == box.nz - 1)) continue;   // Dirichlet slice
             double S = plane((double)wo[k], (double)wx[k], (double)wy[k], (double)wxy[k]);
-            int m = mxy;
-            if (k == 0 && hzm) {
-                S = plane((double)zm[0], (double)zm[1], (double)zm[2], (double)zm[3]) + S;
-                m *= 2;
-            }
-            if (k == N && hzp) {
-                S = S + plane((double)zp[0], (double)zp[1], (double)zp[2], (double)zp[3]);
-                m *= 2;
-            }
-            const T rn = (T)((double)rv[k] - alpha * S);
-            r[e * NP3 + k * NP2 + ij] = rn;
-            part += ((double)rn * (double)rn) * inv_mult(m);
+            if (k == 0 && hzm) S = plane((double)zm[0], (double)zm[1], (double)zm[2], (double)zm[3]) + S;
+            if (k == N && hzp) S = S + plane((double)zp[0], (double)zp[1], (double)zp[2], (double)zp[3]);
+            const bool dir = (k == 0 && ez == 0) || (k == N && ez == box.nz - 1);
+            oe[k * NP2 + ij] = dir ? (T)0 : (T)S;
         }
     }
-    const double s = block_sum<BS>(part, sbuf);
-    if (tid == 0) P2cur[blk] = s;
-    if (writer) sc->k2flag[it & 1] = 0;
 }
 
 template <int NP, int EPW, typename T>

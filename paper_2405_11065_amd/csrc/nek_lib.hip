@@ -674,10 +674,17 @@ int nek_dssum(nek_ctx *c, void *w, int dtype, int apply_mask)
 
 int nek_ax(nek_ctx *c, const void *u, void *w, int dtype)
 {
-    if (u == w) return NEK_E_ARG;
-    int rc = nek_ax_local(c, u, w, dtype);
-    if (rc) return rc;
-    return nek_dssum(c, w, dtype, 1);
+    if (!c || !u || !w || u == w || (dtype != NEK_F64 && dtype != NEK_F32)) return NEK_E_ARG;
+    int rc;
+    if (dtype == NEK_F64) {
+        if ((rc = ensure_fp64_work(c))) return rc;
+        return ops(c)->axa64(c, c->variant[NEK_PREC_FP64], (const double *)u, c->w64, (double *)w);
+    }
+    const int prec = c->prec == NEK_PREC_BF16G ? NEK_PREC_BF16G : NEK_PREC_FP32;
+    if ((rc = ensure_g(c, prec))) return rc;
+    if (dalloc(c->w32, c->nl)) return NEK_E_OOM;
+    if (prec == NEK_PREC_BF16G) return ops(c)->axa16(c, c->variant[prec], (const float *)u, c->w32, (float *)w);
+    return ops(c)->axa32(c, c->variant[prec], (const float *)u, c->w32, (float *)w);
 }
 
 int nek_glsc3(nek_ctx *c, const void *a, const void *b, int dtype, double *out)

@@ -85,6 +85,34 @@ template <int NP> struct OpsImpl {
                                                                                   0);
     }
 
+    // w = M dssum(A_L u): operator into scratch, then the out-of-place
+    // column assembly, both in the configuration `variant`.
+    template <typename T, typename GT>
+    static int ax_assembled(nek_ctx *c, int variant, const T *u, T *scratch, T *w, const GT *g, const T *D)
+    {
+        return with_variant<NP, GT>(variant, [&](auto epw_c, auto pd_c) -> int {
+            constexpr int EPW = decltype(epw_c)::value, PD = decltype(pd_c)::value;
+            int rc = launch_ax<EPW, PD, T, GT, false>(c, u, nullptr, scratch, g, D, 0);
+            if (rc) return rc;
+            hipLaunchKernelGGL((k_assemble<NP, EPW, T>), dim3(ax_grid(c, EPW)), dim3(EPW * NP * NP), 0, c->stream,
+                               scratch, w, c->box, (int)c->E, ax_groups(c, EPW));
+            HIP_TRY(hipGetLastError());
+            return NEK_OK;
+        });
+    }
+    static int axa64(nek_ctx *c, int v, const double *u, double *scratch, double *w)
+    {
+        return ax_assembled<double, double>(c, v, u, scratch, w, c->g64, c->D64);
+    }
+    static int axa32(nek_ctx *c, int v, const float *u, float *scratch, float *w)
+    {
+        return ax_assembled<float, float>(c, v, u, scratch, w, c->g32, c->D32);
+    }
+    static int axa16(nek_ctx *c, int v, const float *u, float *scratch, float *w)
+    {
+        return ax_assembled<float, uint16_t>(c, v, u, scratch, w, c->g16, c->D32);
+    }
+
     static int gather64(nek_ctx *c, const double *in, double *out, bool weighted)
     {
         if (weighted)
@@ -175,7 +203,7 @@ template <int NP> const NpOps *make_np_ops()
 {
     using I = OpsImpl<NP>;
     static const NpOps ops{n_variants<NP>(), &I::cg_iter64, &I::cg_iter32, &I::cg_iter16, &I::ax64, &I::ax32,
-                           &I::ax16, &I::gather64, &I::glsc3_64, &I::glsc3_32, &I::resid, &I::inner_start,
+                           &I::ax16, &I::axa64, &I::axa32, &I::axa16, &I::gather64, &I::glsc3_64, &I::glsc3_32, &I::resid, &I::inner_start,
                            &I::variant_epw, &I::batch_iter};
     return &ops;
 }
