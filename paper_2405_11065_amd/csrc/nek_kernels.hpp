@@ -255,6 +255,37 @@ template <> struct GLoad<uint16_t> {   // BF16 bit patterns, two per 32-bit word
 // uniform entries D[k][l] of the t contractions come through the scalar
 // cache.  The six factors of slice k + PD are in flight while slice k is
 // computed.  CG mode fuses p = beta p + r before, and sum p.(A_L p) after.
+// A row of RP (a multiple of 4) 4-byte values from 16-byte aligned LDS.
+template <int RP, typename T> __device__ __forceinline__ void load_row(const T *__restrict__ src, T out[RP])
+{
+    static_assert(sizeof(T) == 4 && RP % 4 == 0, "rows of 4-byte values, pitch a multiple of 4");
+#pragma unroll
+    for (int q = 0; q < RP / 4; ++q) {
+        const float4 v = reinterpret_cast<const float4 *>(src)[q];
+        out[4 * q + 0] = __builtin_bit_cast(T, v.x);
+        out[4 * q + 1] = __builtin_bit_cast(T, v.y);
+        out[4 * q + 2] = __builtin_bit_cast(T, v.z);
+        out[4 * q + 3] = __builtin_bit_cast(T, v.w);
+    }
+}
+
+// LDS layout of the operator kernel.  4-byte types keep every slice as rows
+// of a pitch rounded up to 4 entries, with a transposed copy of u and ws
+// stored transposed, so that every derivative sum reads one contiguous,
+// 16-byte aligned row (128-bit LDS reads); FP64, bound by HBM rather than
+// LDS, keeps three plain NP^3 arrays.
+template <int NP, typename T> struct AxLds {
+    static constexpr bool ROWS = sizeof(T) == 4;
+    static constexpr int RP = ROWS ? (NP + 3) / 4 * 4 : NP;   // row pitch
+    static constexpr int SL = NP * RP;                         // one k slice
+    static constexpr int EL = NP * SL;                         // one element
+    static constexpr int NARR = ROWS ? 4 : 3;
+};
+template <int NP, int EPW, typename T> constexpr size_t ax_lds_bytes()
+{
+    return (size_t)AxLds<NP, T>::NARR * EPW * AxLds<NP, T>::EL * sizeof(T);
+}
+
 // Body of the operator kernel for one problem: workgroup blk of the
 // problem's nblk workgroups.
 template <int NP, int EPW, int PD, typename T, typename GT, bool CG, typename XT>
@@ -267,10 +298,14 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
 {
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP, BS = EPW * NP2;
     using GL = GLoad<GT>;
+    using L = AxLds<NP, T>;
+    constexpr bool ROWS = L::ROWS;
+    constexpr int RP = L::RP, SL = L::SL, EL = L::EL;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *su = reinterpret_cast<T *>(smem_raw);
-    T *sr = su + EPW * NP3;
-    T *ss = sr + EPW * NP3;
+    T *sr = su + EPW * EL;
+    T *ss = sr + EPW * EL;
+    T *sut = ROWS ? ss + EPW * EL : su;   // transposed u (rows only)
     __shared__ double sbuf[BS];
     __shared__ T sD[NP * NP];
 
@@ -304,7 +339,7 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
         first = it == 1 && !sc->resume;
     }
     const int i = ij % NP, j = ij / NP;
-    T *sue = su + el * NP3, *sre = sr + el * NP3, *sse = ss + el * NP3;
+    T *sue = su + el * EL, *sre = sr + el * EL, *sse = ss + el * EL, *sute = sut + el * EL;
 
     // FP32: the thread's rows/columns of D live in registers.  FP64 reads
     // them from LDS instead (no register spills; FP64 has bandwidth slack).
@@ -355,7 +390,8 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
                 v = src[idx];
             }
             u[k] = v;
-            sue[k * NP2 + ij] = v;
+            sue[k * SL + j * RP + i] = v;
+            if constexpr (ROWS) sute[k * SL + i * RP + j] = v;
         }
         __syncthreads();
         T wt[NP];
@@ -365,14 +401,27 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
             T gk[6];
             GL::unpack(gb[k % PD], gk);
             T ur = 0, us = 0, ut = 0;
+            if constexpr (ROWS) {
+                T rr[RP], rs[RP];
+                load_row<RP>(sue + k * SL + j * RP, rr);
+                load_row<RP>(sute + k * SL + i * RP, rs);
 #pragma unroll
-            for (int l = 0; l < NP; ++l) {
-                ur += NEK_DR(l) * sue[k * NP2 + j * NP + l];
-                us += NEK_DS(l) * sue[k * NP2 + l * NP + i];
-                ut += D[k * NP + l] * u[l];
+                for (int l = 0; l < NP; ++l) {
+                    ur += NEK_DR(l) * rr[l];
+                    us += NEK_DS(l) * rs[l];
+                    ut += D[k * NP + l] * u[l];
+                }
+            } else {
+#pragma unroll
+                for (int l = 0; l < NP; ++l) {
+                    ur += NEK_DR(l) * sue[k * NP2 + j * NP + l];
+                    us += NEK_DS(l) * sue[k * NP2 + l * NP + i];
+                    ut += D[k * NP + l] * u[l];
+                }
             }
-            sre[k * NP2 + ij] = gk[0] * ur + gk[3] * us + gk[4] * ut;
-            sse[k * NP2 + ij] = gk[3] * ur + gk[1] * us + gk[5] * ut;
+            // wr by rows of constant j; ws by rows of constant i (transposed)
+            sre[k * SL + j * RP + i] = gk[0] * ur + gk[3] * us + gk[4] * ut;
+            sse[k * SL + (ROWS ? i * RP + j : j * NP + i)] = gk[3] * ur + gk[1] * us + gk[5] * ut;
             wt[k] = gk[4] * ur + gk[5] * us + gk[2] * ut;
             __builtin_amdgcn_sched_barrier(0);
             if (k + PD < NP) gb[k % PD] = GL::load(ge + (size_t)(k + PD) * NP2 * 6);
@@ -381,10 +430,20 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             T acc = 0;
+            if constexpr (ROWS) {
+                T rr[RP], rs[RP];
+                load_row<RP>(sre + k * SL + j * RP, rr);
+                load_row<RP>(sse + k * SL + i * RP, rs);
 #pragma unroll
-            for (int l = 0; l < NP; ++l) acc += NEK_DTI(l) * sre[k * NP2 + j * NP + l];
+                for (int l = 0; l < NP; ++l) acc += NEK_DTI(l) * rr[l];
 #pragma unroll
-            for (int l = 0; l < NP; ++l) acc += NEK_DTJ(l) * sse[k * NP2 + l * NP + i];
+                for (int l = 0; l < NP; ++l) acc += NEK_DTJ(l) * rs[l];
+            } else {
+#pragma unroll
+                for (int l = 0; l < NP; ++l) acc += NEK_DTI(l) * sre[k * NP2 + j * NP + l];
+#pragma unroll
+                for (int l = 0; l < NP; ++l) acc += NEK_DTJ(l) * sse[k * NP2 + l * NP + i];
+            }
 #pragma unroll
             for (int l = 0; l < NP; ++l) acc += D[l * NP + k] * wt[l];
             if (valid) w[base + k * NP2] = acc;

@@ -10,7 +10,7 @@ template <int NP> struct OpsImpl {
     static int launch_ax(nek_ctx *c, const T *src, T *p, T *w, const GT *g, const T *D, int it, XT *x = nullptr)
     {
         constexpr int BS = EPW * NP * NP;
-        const size_t shm = 3ul * EPW * NP * NP * NP * sizeof(T);
+        const size_t shm = ax_lds_bytes<NP, EPW, T>();
         static bool attr_done = false;
         if (!attr_done) {
             if (shm > 65536)
@@ -167,7 +167,7 @@ template <int NP> struct OpsImpl {
     {
         return with_variant<NP, GT>(v, [&](auto epw_c, auto pd_c) -> int {
             constexpr int EPW = decltype(epw_c)::value, PD = decltype(pd_c)::value, BS = EPW * NP * NP;
-            const size_t shm = 3ul * EPW * NP * NP * NP * sizeof(T);
+            const size_t shm = ax_lds_bytes<NP, EPW, T>();
             if (prepare) {
                 if (shm > 65536)
                     HIP_TRY(hipFuncSetAttribute((const void *)k_ax_batch<NP, EPW, PD, T, GT>,
