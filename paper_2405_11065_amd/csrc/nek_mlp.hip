@@ -44,6 +44,8 @@ struct GemmArgs {
     const float *bias;        // HIDDEN, OUT
     const float *Z;           // DSILU: pre-activation of the layer
     int ldz;
+    int kchunk;               // split K: workgroup z covers [z kchunk, (z+1) kchunk) (0: all of K)
+    long cstride;             // split K: C of split z at C + z cstride
 };
 
 __device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
@@ -83,6 +85,9 @@ __global__ __launch_bounds__(GB) void k_gemm(GemmArgs a)
     __shared__ __align__(16) uint16_t Bs[BN * LDT];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int kb = a.kchunk ? blockIdx.z * a.kchunk : 0;
+    const int ke = a.kchunk ? min(a.K, kb + a.kchunk) : a.K;
+    float *C = a.C + (a.kchunk ? blockIdx.z * a.cstride : 0);
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int lr = lane & 15, lk = 4 * (lane >> 4);
     f32x4 acc[2][2];
@@ -91,9 +96,9 @@ __global__ __launch_bounds__(GB) void k_gemm(GemmArgs a)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < a.K; k0 += BK) {
-        load_tile<AKC>(a.A, a.lda, a.M, a.K, m0, k0, As, tid);
-        load_tile<BKC>(a.B, a.ldb, a.N, a.K, n0, k0, Bs, tid);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        load_tile<AKC>(a.A, a.lda, a.M, ke, m0, k0, As, tid);
+        load_tile<BKC>(a.B, a.ldb, a.N, ke, n0, k0, Bs, tid);
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
@@ -123,28 +128,41 @@ __global__ __launch_bounds__(GB) void k_gemm(GemmArgs a)
                 const float v = acc[i][j][r];
                 if constexpr (EPI == EPI_HIDDEN) {
                     const float z = v + a.bias[n];
-                    a.C[(size_t)m * a.ldc + n] = z;
+                    C[(size_t)m * a.ldc + n] = z;
                     a.Cb[(size_t)m * a.ldcb + n] = f32_to_bf16_rne(z * sigmoidf_(z));
                 } else if constexpr (EPI == EPI_OUT) {
-                    a.C[(size_t)m * a.ldc + n] = v + a.bias[n];
+                    C[(size_t)m * a.ldc + n] = v + a.bias[n];
                 } else if constexpr (EPI == EPI_PLAIN) {
-                    a.C[(size_t)m * a.ldc + n] = v;
+                    C[(size_t)m * a.ldc + n] = v;
                 } else {
                     const float z = a.Z[(size_t)m * a.ldz + n];
                     const float s = sigmoidf_(z);
                     const float d = v * (s * (1.0f + z * (1.0f - s)));
-                    a.C[(size_t)m * a.ldc + n] = d;
+                    C[(size_t)m * a.ldc + n] = d;
                     a.Cb[(size_t)m * a.ldcb + n] = f32_to_bf16_rne(d);
                 }
             }
 }
 
-template <bool AKC, bool BKC, int EPI> int gemm(hipStream_t s, const GemmArgs &a)
+template <bool AKC, bool BKC, int EPI> int gemm(hipStream_t s, const GemmArgs &a, int splits = 1)
 {
     if (a.M <= 0 || a.N <= 0 || a.K <= 0) return NEK_OK;
-    const dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM);
+    const dim3 grid((a.N + BN - 1) / BN, (a.M + BM - 1) / BM, splits);
     hipLaunchKernelGGL((k_gemm<AKC, BKC, EPI>), grid, dim3(GB), 0, s, a);
     return hipGetLastError() == hipSuccess ? NEK_OK : NEK_E_HIP;
+}
+
+// out[m][n] = sum over splits z (in order) of part[z][m][n] (pitch ld, split stride cs).
+__global__ __launch_bounds__(256) void k_sum_splits(const float *__restrict__ part, int nsplit, long cs, int M,
+                                                    int N, int ld, float *__restrict__ out)
+{
+    const long total = (long)M * N;
+    for (long t = blockIdx.x * 256L + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+        const int m = (int)(t / N), n = (int)(t - (long)m * N);
+        float acc = 0.0f;
+        for (int z = 0; z < nsplit; ++z) acc += part[z * cs + (size_t)m * ld + n];
+        out[(size_t)m * ld + n] = acc;
+    }
 }
 
 // dY = 2 (Y - T) / (rows n_out) (FP32 and bfloat16), partial sums of
@@ -190,14 +208,34 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
     if (threadIdx.x == 0) out[0] = sb[0] * scale;
 }
 
-// Bias gradient: column sums of D (rows x ncol, pitch ld), in row order.
-__global__ __launch_bounds__(256) void k_colsum(const float *__restrict__ D, int ld, int rows, int ncol,
-                                                float *__restrict__ out)
+// Bias gradient: column sums of D (rows x ncol, pitch ld) in two fixed-order
+// passes.  Pass 1: workgroup (x, y) sums rows [y CR, (y+1) CR) of 64 columns,
+// four row lanes per column combined in order; pass 2 adds the chunks in order.
+constexpr int CR = 128;   // rows per chunk
+__global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ D, int ld, int rows, int ncol,
+                                                     float *__restrict__ part)
+{
+    __shared__ float sb[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), rl = threadIdx.x >> 6;
+    const int r0 = blockIdx.y * CR, r1 = min(rows, r0 + CR);
+    float acc = 0.0f;
+    if (c < ncol)
+        for (int r = r0 + rl; r < r1; r += 4) acc += D[(size_t)r * ld + c];
+    sb[rl][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (rl == 0 && c < ncol) {
+        const int q = threadIdx.x & 63;
+        part[(size_t)blockIdx.y * ncol + c] = (sb[0][q] + sb[1][q]) + (sb[2][q] + sb[3][q]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_colsum_final(const float *__restrict__ part, int nchunk, int ncol,
+                                                      float *__restrict__ out)
 {
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= ncol) return;
     float acc = 0.0f;
-    for (int r = 0; r < rows; ++r) acc += D[(size_t)r * ld + c];
+    for (int q = 0; q < nchunk; ++q) acc += part[(size_t)q * ncol + c];
     out[c] = acc;
 }
 
@@ -253,6 +291,7 @@ namespace nek {
 namespace {
 
 constexpr int LOSS_BLOCKS = 1024;
+constexpr int MAX_SPLITS = 16;   // split-K pieces of a weight gradient
 
 int refresh_bf16(nek_mlp *m)
 {
@@ -291,7 +330,44 @@ int ensure_rows(nek_mlp *m, long rows)
         (rc = zalloc(m->dZ1b, nh)))
         return rc;
     m->cap = cap;
+    // column-sum chunks and split-K partial products
+    dfree(m->cpart);
+    dfree(m->kpart);
+    const long nchunk = (cap + CR - 1) / CR;
+    const long wmax = std::max({(long)m->nout * m->nh, (long)m->nh * m->nh, (long)m->nh * m->nin});
+    if ((rc = zalloc(m->cpart, nchunk * std::max(m->nout, m->nh))) || (rc = zalloc(m->kpart, MAX_SPLITS * wmax)))
+        return rc;
     return NEK_OK;
+}
+
+// out[c] = sum over rows of D[r][c] (bias gradients), deterministic.
+int colsum(nek_mlp *m, const float *D, int ld, int rows, int ncol, float *out)
+{
+    const int nchunk = (rows + CR - 1) / CR;
+    hipLaunchKernelGGL(k_colsum_part, dim3((ncol + 63) / 64, nchunk), dim3(256), 0, m->stream, D, ld, rows, ncol,
+                       m->cpart);
+    hipLaunchKernelGGL(k_colsum_final, dim3((ncol + 255) / 256), dim3(256), 0, m->stream, m->cpart, nchunk, ncol, out);
+    return hipGetLastError() == hipSuccess ? NEK_OK : NEK_E_HIP;
+}
+
+// Weight gradient C (M x N, pitch ldc) = A^T B over `rows` rows, split along
+// the rows so that enough workgroups run, the splits added in order.
+int gemm_wgrad(nek_mlp *m, GemmArgs a)
+{
+    const int rows = a.K;
+    int splits = std::min(MAX_SPLITS, std::max(1, rows / 512));
+    if (splits == 1) return gemm<false, false, EPI_PLAIN>(m->stream, a);
+    const int kchunk = ((rows + splits - 1) / splits + BK - 1) / BK * BK;
+    splits = (rows + kchunk - 1) / kchunk;
+    float *out = a.C;
+    a.C = m->kpart;
+    a.kchunk = kchunk;
+    a.cstride = (long)a.M * a.ldc;
+    int rc = gemm<false, false, EPI_PLAIN>(m->stream, a, splits);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_sum_splits, dim3(std::min<long>(1024, ((long)a.M * a.N + 255) / 256)), dim3(256), 0,
+                       m->stream, m->kpart, splits, a.cstride, a.M, a.N, a.ldc, out);
+    return hipGetLastError() == hipSuccess ? NEK_OK : NEK_E_HIP;
 }
 
 int check_rows(const nek_mlp *m, int ld, int need) { return ld >= need && ld % 8 == 0 ? NEK_OK : NEK_E_ARG; }
@@ -328,9 +404,7 @@ int loss_grad(nek_mlp *m, const uint16_t *X, int ldx, const float *T, int ldt, i
     // dW3 = dY^T H2
     a.A = m->dYb; a.lda = m->ldout; a.B = m->H2; a.ldb = m->ldh; a.M = m->nout; a.N = m->nh; a.K = rows;
     a.C = m->G + m->oW3; a.ldc = m->nh;
-    if ((rc = gemm<false, false, EPI_PLAIN>(m->stream, a))) return rc;
-    hipLaunchKernelGGL(k_colsum, dim3((m->nout + 255) / 256), dim3(256), 0, m->stream, m->dY, m->ldout, rows, m->nout,
-                       m->G + m->ob3);
+    if ((rc = gemm_wgrad(m, a)) || (rc = colsum(m, m->dY, m->ldout, rows, m->nout, m->G + m->ob3))) return rc;
     // dZ2 = (dY W3) o silu'(Z2)
     a = GemmArgs{};
     a.A = m->dYb; a.lda = m->ldout; a.B = m->W3b; a.ldb = m->ldh; a.M = rows; a.N = m->nh; a.K = m->nout;
@@ -340,9 +414,7 @@ int loss_grad(nek_mlp *m, const uint16_t *X, int ldx, const float *T, int ldt, i
     a = GemmArgs{};
     a.A = m->dZ2b; a.lda = m->ldh; a.B = m->H1; a.ldb = m->ldh; a.M = m->nh; a.N = m->nh; a.K = rows;
     a.C = m->G + m->oW2; a.ldc = m->nh;
-    if ((rc = gemm<false, false, EPI_PLAIN>(m->stream, a))) return rc;
-    hipLaunchKernelGGL(k_colsum, dim3((m->nh + 255) / 256), dim3(256), 0, m->stream, m->dZ2, m->ldh, rows, m->nh,
-                       m->G + m->ob2);
+    if ((rc = gemm_wgrad(m, a)) || (rc = colsum(m, m->dZ2, m->ldh, rows, m->nh, m->G + m->ob2))) return rc;
     // dZ1 = (dZ2 W2) o silu'(Z1)
     a = GemmArgs{};
     a.A = m->dZ2b; a.lda = m->ldh; a.B = m->W2b; a.ldb = m->ldh; a.M = rows; a.N = m->nh; a.K = m->nh;
@@ -352,10 +424,7 @@ int loss_grad(nek_mlp *m, const uint16_t *X, int ldx, const float *T, int ldt, i
     a = GemmArgs{};
     a.A = m->dZ1b; a.lda = m->ldh; a.B = X; a.ldb = ldx; a.M = m->nh; a.N = m->nin; a.K = rows;
     a.C = m->G + m->oW1; a.ldc = m->nin;
-    if ((rc = gemm<false, false, EPI_PLAIN>(m->stream, a))) return rc;
-    hipLaunchKernelGGL(k_colsum, dim3((m->nh + 255) / 256), dim3(256), 0, m->stream, m->dZ1, m->ldh, rows, m->nh,
-                       m->G + m->ob1);
-    HIP_TRY(hipGetLastError());
+    if ((rc = gemm_wgrad(m, a)) || (rc = colsum(m, m->dZ1, m->ldh, rows, m->nh, m->G + m->ob1))) return rc;
     return NEK_OK;
 }
 
@@ -382,7 +451,7 @@ void nek_mlp_free(nek_mlp *m)
     dfree(m->P); dfree(m->G); dfree(m->M); dfree(m->V); dfree(m->W1b); dfree(m->W2b); dfree(m->W3b);
     dfree(m->Z1); dfree(m->Z2); dfree(m->Y); dfree(m->dY); dfree(m->dZ2); dfree(m->dZ1);
     dfree(m->H1); dfree(m->H2); dfree(m->dYb); dfree(m->dZ2b); dfree(m->dZ1b);
-    dfree(m->part); dfree(m->dloss); dfree(m->Xb); dfree(m->Tb); dfree(m->idx);
+    dfree(m->part); dfree(m->dloss); dfree(m->Xb); dfree(m->Tb); dfree(m->idx); dfree(m->cpart); dfree(m->kpart);
     delete m;
 }
 

@@ -23,6 +23,9 @@ struct nek_mlp {
     float *Z1 = nullptr, *Z2 = nullptr, *Y = nullptr, *dY = nullptr, *dZ2 = nullptr, *dZ1 = nullptr;
     uint16_t *H1 = nullptr, *H2 = nullptr, *dYb = nullptr, *dZ2b = nullptr, *dZ1b = nullptr;
     double *part = nullptr, *dloss = nullptr;
+    float *cpart = nullptr;              // column-sum chunk partials
+    float *kpart = nullptr;              // split-K partial products
+    long cpart_cap = 0, kpart_cap = 0;
     // training staging
     long bcap = 0;
     uint16_t *Xb = nullptr;
