@@ -88,8 +88,9 @@ def test_forward_matches_oracle(sizes, rows):
     net.close()
 
 
-@pytest.mark.parametrize("sizes,rows", SHAPES[:3])
+@pytest.mark.parametrize("sizes,rows", SHAPES[:3] + [((96, 64, 64, 40), 2500)])
 def test_loss_and_gradient_match_oracle(sizes, rows):
+    """2500 rows: the weight gradients run split along the rows (four pieces, the last one ragged)."""
     if sizes[1] != sizes[2]:
         sizes = (sizes[0], sizes[1], sizes[1], sizes[3])
     _case(f"grad sizes={sizes} rows={rows}")
