@@ -33,15 +33,14 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the fused FP32 operator kernel measured by the
 # FETCH_SIZE and WRITE_SIZE counters (scaled by a 256 MiB copy in the same
 # runs), for the kernel sources with these SHA-256 digests and the FP32
-# configuration named; profiles/cg_16x16x16_N9_kernels.md holds the runs.
+# configurations listed; profiles/cg_16x16x16_N9_kernels.md holds the runs.
 # Reported only while the sources and the tuned configuration still match.
 COUNTER_TRAFFIC = {
     "sources": {"paper_2405_11065_amd/csrc/nek_kernels.hpp":
                 "b43b9af5a3301a0ee2aefbcd10f15f65088dd03646ebb00e09a156e203afbf69",
                 "paper_2405_11065_amd/csrc/nek_np.hpp":
                 "eba9879a9ae0bddf979e3ff3e6c9c9f30a453892c2e01c170ed54b1a3e11ca58"},
-    "fp32_variant": 4,
-    "bytes_per_launch": 231_300_000,
+    "bytes_per_launch": {4: 231_300_000, 5: 231_400_000},   # FP32 configuration -> bytes
 }
 
 
@@ -51,7 +50,7 @@ def counter_traffic(variant):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             if hashlib.sha256(fh.read()).hexdigest() != digest:
                 return None
-    return COUNTER_TRAFFIC["bytes_per_launch"] if variant == COUNTER_TRAFFIC["fp32_variant"] else None
+    return COUNTER_TRAFFIC["bytes_per_launch"].get(variant)
 
 
 def ax_dssum_bytes_per_point(sv, sg, sigma):
