@@ -108,42 +108,75 @@ __device__ __forceinline__ double inv_mult(int m)
     return m == 1 ? 1.0 : m == 2 ? 0.5 : m == 4 ? 0.25 : 0.125;
 }
 
-// Sum of P[0..n) in a fixed order, returned to every thread of the block.
-// Only whole waves take part (lanes past the last full wave do not exist
-// for shuffles); the result is broadcast through LDS.
-template <int BS>
-__device__ __forceinline__ double sum_all(const double *__restrict__ P, int n, double *sbuf)
+// Fixed-order sums of NA arrays of per-workgroup partials, returned to every
+// thread of the block.  The first NT threads (whole waves: lanes past the
+// last full wave do not exist for shuffles) each add the pairs
+// (P[2q], P[2q + 1]) for q = t, t + NT, t + 2 NT, ..., low entry first, with
+// a batch of U pairs per array loaded (16 bytes each) before the first add;
+// then a butterfly within each wave and the waves in order, broadcast
+// through LDS.  The order of one array's sum does not depend on NA or U, so
+// every kernel of block size BS that sums the same partials, alone or
+// together with another array, gets the bit-identical value.  Each P[a] is
+// 16-byte aligned and readable up to the next even count (P[n] when n is
+// odd, a value that is not added): the partial slots hold MAXB entries.
+template <int BS, int NA>
+__device__ __forceinline__ void sum_all_n(const double *const *P, const int *n, double *sbuf, double *out)
 {
     constexpr int NW = BS >= 64 ? BS / 64 : 1;
     constexpr int NT = BS >= 64 ? NW * 64 : BS;
-    // each thread sums P[t], P[t + NT], ... in that order; the loads of a
-    // batch of up to U entries are all issued before the first add
-    constexpr int U = NT >= 256 ? 8 : 16;
-    double v = 0.0;
-    if (threadIdx.x < NT)
-        for (int q0 = threadIdx.x; q0 < n; q0 += U * NT) {
-            double t[U];
+    constexpr int U = NT >= 256 ? 4 : 8;
+    double v[NA];
+    int nmax = 0;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int q = q0 + u * NT;
-                t[u] = q < n ? P[q] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) v += t[u];
-        }
-    if constexpr (BS >= 64) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (threadIdx.x < NT && (threadIdx.x & 63) == 0) sbuf[threadIdx.x >> 6] = v;
-        __syncthreads();
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < NW; ++q) s += sbuf[q];
-        __syncthreads();
-        return s;
-    } else {
-        return block_sum<BS>(v, sbuf);   // LDS tree, result in every thread
+    for (int a = 0; a < NA; ++a) {
+        v[a] = 0.0;
+        nmax = max(nmax, n[a]);
     }
+    if (threadIdx.x < NT)
+        for (int q0 = threadIdx.x; 2 * q0 < nmax; q0 += U * NT) {
+            double2 t[NA][U];
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int q = q0 + u * NT;
+                    t[a][u] = 2 * q < n[a] ? reinterpret_cast<const double2 *>(P[a])[q] : double2{0.0, 0.0};
+                }
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    v[a] += t[a][u].x;
+                    v[a] += 2 * (q0 + u * NT) + 1 < n[a] ? t[a][u].y : 0.0;
+                }
+        }
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        if constexpr (BS >= 64) {
+            double w = v[a];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+            if (threadIdx.x < NT && (threadIdx.x & 63) == 0) sbuf[threadIdx.x >> 6] = w;
+            __syncthreads();
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) s += sbuf[q];
+            __syncthreads();
+            out[a] = s;
+        } else {
+            out[a] = block_sum<BS>(v[a], sbuf);   // LDS tree, result in every thread
+        }
+    }
+}
+
+template <int BS>
+__device__ __forceinline__ double sum_all(const double *__restrict__ P, int n, double *sbuf)
+{
+    const double *ps[1] = {P};
+    const int ns[1] = {n};
+    double out[1];
+    sum_all_n<BS, 1>(ps, ns, sbuf, out);
+    return out[0];
 }
 
 // Start of iteration it: fold the partials of iteration it-1 into the state
@@ -174,9 +207,14 @@ __device__ __forceinline__ Begin cg_begin(Scal *__restrict__ sc, const double *_
                 cur.status = f;
                 cur.done = 1;
             } else {
-                B.alpha_prev = prev.rtz / sum_all<BS>(P1prev, nb1, sbuf);
+                // both sums with their loads in flight together
+                const double *ps[2] = {P1prev, P2prev};
+                const int ns[2] = {nb1, nb2};
+                double sums[2];
+                sum_all_n<BS, 2>(ps, ns, sbuf, sums);
+                B.alpha_prev = prev.rtz / sums[0];
                 B.xupd = true;
-                const double rtr = sum_all<BS>(P2prev, nb2, sbuf);
+                const double rtr = sums[1];
                 cur.iter = it - 1;
                 cur.rtz = rtr;
                 cur.beta = rtr / prev.rtz;
