@@ -352,6 +352,26 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
     const unsigned lb = xcd_block(blk, nblk);
     const int g0 = (int)(((long)lb * ngroups) / nblk);
     const int g1 = (int)(((long)(lb + 1) * ngroups) / nblk);
+    const int i = ij % NP, j = ij / NP;
+    T *sue = su + el * EL, *sre = sr + el * EL, *sse = ss + el * EL, *sute = sut + el * EL;
+
+    // FP32: the thread's rows/columns of D live in registers.  FP64 reads
+    // them from LDS instead (no register spills; FP64 has bandwidth slack).
+    constexpr bool DREG = sizeof(T) == 4;
+    T Dri[DREG ? NP : 1], Dsj[DREG ? NP : 1], DTi[DREG ? NP : 1], DTj[DREG ? NP : 1];
+    // The first PD slices of g of a group; those of the first group are
+    // requested before the CG prologue, so their latency overlaps its
+    // reduction.  Threads past the last element work on a copy of element
+    // E-1 and store nothing (local indices fit in 32 bits, checked at set-up).
+    typename GL::Raw gb[PD];
+    auto g_first = [&](int grp) {
+        const int e = grp * EPW + el;
+        const GT *ge = g + (size_t)((e < E ? e : E - 1) * NP3 + ij) * 6;
+#pragma unroll
+        for (int s = 0; s < PD; ++s)
+            if (s < NP) gb[s] = GL::load(ge + (size_t)s * NP2 * 6);
+    };
+    if (g0 < g1) g_first(g0);
     T beta = 0;
     bool first = false, xupd = false;
     double alpha_prev = 0.0;
@@ -376,13 +396,6 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
         beta = (T)B.cur.beta;
         first = it == 1 && !sc->resume;
     }
-    const int i = ij % NP, j = ij / NP;
-    T *sue = su + el * EL, *sre = sr + el * EL, *sse = ss + el * EL, *sute = sut + el * EL;
-
-    // FP32: the thread's rows/columns of D live in registers.  FP64 reads
-    // them from LDS instead (no register spills; FP64 has bandwidth slack).
-    constexpr bool DREG = sizeof(T) == 4;
-    T Dri[DREG ? NP : 1], Dsj[DREG ? NP : 1], DTi[DREG ? NP : 1], DTj[DREG ? NP : 1];
     if constexpr (DREG) {
 #pragma unroll
         for (int l = 0; l < NP; ++l) {
@@ -391,9 +404,9 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
             DTi[l] = D[l * NP + i];
             DTj[l] = D[l * NP + j];
         }
-    } else {
-        for (int q = tid; q < NP * NP; q += BS) sD[q] = D[q];
     }
+    else
+        for (int q = tid; q < NP * NP; q += BS) sD[q] = D[q];
 #define NEK_DR(l) (DREG ? Dri[DREG ? (l) : 0] : sD[i * NP + (l)])
 #define NEK_DS(l) (DREG ? Dsj[DREG ? (l) : 0] : sD[j * NP + (l)])
 #define NEK_DTI(l) (DREG ? DTi[DREG ? (l) : 0] : sD[(l) * NP + i])
@@ -403,15 +416,9 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
     for (int grp = g0; grp < g1; ++grp) {
         const int e = grp * EPW + el;
         const bool valid = e < E;
-        // threads past the last element compute on a copy of element E-1 and
-        // store nothing (local indices fit in 32 bits, checked at set-up)
-        const int ec = valid ? e : E - 1;
-        const int base = ec * NP3 + ij;
+        const int base = (valid ? e : E - 1) * NP3 + ij;
         const GT *ge = g + (size_t)base * 6;
-        typename GL::Raw gb[PD];
-#pragma unroll
-        for (int s = 0; s < PD; ++s)
-            if (s < NP) gb[s] = GL::load(ge + (size_t)s * NP2 * 6);
+        if (grp > g0) g_first(grp);
         T u[NP];
         __syncthreads();   // LDS of the previous group is free
 #pragma unroll
