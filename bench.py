@@ -37,10 +37,10 @@ PEAK_HBM_GBS = 8000.0
 # Reported only while the sources and the tuned configuration still match.
 COUNTER_TRAFFIC = {
     "sources": {"paper_2405_11065_amd/csrc/nek_kernels.hpp":
-                "e34092cf74d3f8d4c98b381414d7595a6bb398fe1aa0e9d056286bba9cfcef7f",
+                "3ffdb9f8ce22e60dc4efe1818b392b212101ed887c1e07713523c89578da28b4",
                 "paper_2405_11065_amd/csrc/nek_np.hpp":
-                "eba9879a9ae0bddf979e3ff3e6c9c9f30a453892c2e01c170ed54b1a3e11ca58"},
-    "bytes_per_launch": {4: 231_300_000, 5: 231_400_000},   # FP32 configuration -> bytes
+                "0df71ece03c6a9646a4779e5a3ba9d677cc97134046d6a0bcfabdefcd84873ae"},
+    "bytes_per_launch": {4: 198_700_000, 5: 198_700_000},   # FP32 configuration -> bytes
 }
 
 
@@ -352,7 +352,7 @@ def main():
     batch = None if args.no_batch else batch_case(torch, nek, synth)
     learned = None if args.no_learned else learned_case(torch)
 
-    bpp = cg_operator_bytes_per_point(4, 4, 8)
+    bpp = cg_operator_bytes_per_point(4, 4, 4)   # FP32 vectors, g and inner correction
     ax_avg_s = ax_ms / max(ax_n, 1) / 1e3
     achieved = bpp * nl / ax_avg_s / 1e9 if ax_n else None
     cpu = None if args.no_cpu else cpu_baseline(f_host)
@@ -379,7 +379,7 @@ def main():
         "speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
         "tuned_variant": {k: {"best": v[0], "us_per_iter": [round(u, 1) for u in v[1]]} for k, v in tuned.items()},
         "ax_dssum": axd,
-        "roofline": {"bound": "hbm", "kernel": f"k_ax<NP=10,f32,f32,CG> variant {tuned['fp32'][0]} (add2s1 + ax_e + x update)",
+        "roofline": {"bound": "hbm", "kernel": f"k_ax<NP=10,f32,f32,CG> variant {tuned['fp32'][0]} (add2s1 + ax_e + correction update)",
                      "achieved": round(achieved, 1) if achieved else None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None,
                      "traffic": counter_traffic(tuned["fp32"][0]), "traffic_unit": "bytes per launch",

@@ -192,8 +192,9 @@ int nek_glsc3(nek_ctx *ctx, const void *a, const void *b, int dtype, double *out
  *    iterations.
  *  - NEK_PREC_FP32 / NEK_PREC_BF16G: iterative refinement.  The outer loop
  *    forms r = b - A x in FP64 (FP64 g) and stops when the true relative
- *    residual <= tol; each inner solve is CG with an FP32 operator and FP64
- *    reductions, scalars and correction; x accumulates in FP64.
+ *    residual <= tol; each inner solve is CG with an FP32 operator, FP64
+ *    reductions and scalars, and an FP32 correction d (each update
+ *    d += alpha p formed in FP64 and rounded once); x += d in FP64.
  * f (load vector), x0 (optional, projected as M o dssum(c o x0)) and x are
  * FP64 device vectors of n_local entries; x may alias x0.  maxit caps the
  * total CG iterations.  stats and res_hist (host, length maxit+1: entry 0 is

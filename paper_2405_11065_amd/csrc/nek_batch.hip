@@ -177,7 +177,7 @@ int capture_chunk(nek_batch *b, int prec)
 // its own cap) or maxcap iterations are enqueued; then one closing operator
 // launch per order.  Synchronises.  With t set, *t = ms from the first chunk
 // to the closing launch.
-int run_batch(nek_batch *b, int prec, const std::vector<char> &act, const std::vector<double *> &xs, int maxcap,
+int run_batch(nek_batch *b, int prec, const std::vector<char> &act, const std::vector<void *> &xs, int maxcap,
               bool use_graph, float *t = nullptr)
 {
     int rc;
@@ -273,7 +273,7 @@ int batch_fp64(nek_batch *b, const double *const *f, const double *const *x0, do
     const int n = nprob(b);
     int rc;
     std::vector<char> all(n, 1);
-    std::vector<double *> xs(x, x + n);
+    std::vector<void *> xs(x, x + n);
     for (int m = 0; m < n; ++m) {
         nek_ctx *c = b->ctx[m];
         if ((rc = ensure_fp64_work(c)) || (rc = ensure_hist(c, (long)maxit + 1)) ||
@@ -300,13 +300,13 @@ int batch_mixed(nek_batch *b, const double *const *f, const double *const *x0, d
     int rc;
     std::vector<IrCtl> S(n);
     std::vector<char> all(n, 1), act(n, 0), live(n, 0);
-    std::vector<double *> xs(n, nullptr);
+    std::vector<void *> xs(n, nullptr);
     for (int m = 0; m < n; ++m) {
         nek_ctx *c = b->ctx[m];
         if ((rc = ensure_mixed_work(c)) || (rc = ensure_hist(c, (long)maxit + 1))) return rc;
         ir_init(c, S[m]);
         if ((rc = cg_prologue(c, f[m], x0 ? x0[m] : nullptr, x[m], c->r64))) return rc;
-        xs[m] = c->d64;
+        xs[m] = c->d32;
     }
     if ((rc = read_scals(b, all))) return rc;
     for (int m = 0; m < n; ++m) ir_start(S[m], b->hscal[m]);
@@ -474,17 +474,19 @@ int nek_batch_tune(nek_batch *b, int prec, int iters, double *us_per_iter)
     if (!b || prec < NEK_PREC_FP64 || prec > NEK_PREC_BF16G || iters < 2) return NEK_E_ARG;
     const int n = nprob(b);
     int rc;
-    std::vector<double *> xs(n, nullptr);
+    std::vector<void *> xs(n, nullptr);
     for (int m = 0; m < n; ++m) {
         nek_ctx *c = b->ctx[m];
         if ((rc = ensure_fp64_work(c)) || (rc = ensure_g(c, prec)) || (rc = ensure_hist(c, iters + 1))) return rc;
-        if (dalloc(c->d64, c->nl) || dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) || dalloc(c->w32, c->nl))
+        if (prec == NEK_PREC_FP64 ? dalloc(c->d64, c->nl)
+                                  : (dalloc(c->d32, c->nl) || dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) ||
+                                     dalloc(c->w32, c->nl)))
             return NEK_E_OOM;
         // synthetic SPD system: b = M dssum(1), x0 = 0
         if ((rc = fill_f64(c, c->w64, 1.0, c->nl)) || (rc = gather_launch(c, c->w64, c->b, false)) ||
             (rc = glsc3_to_slot(c, c->b, c->b, NEK_F64, 0)))
             return rc;
-        xs[m] = c->d64;
+        xs[m] = prec == NEK_PREC_FP64 ? (void *)c->d64 : (void *)c->d32;
     }
     if (us_per_iter)
         for (size_t k = 0; k < NEK_MAX_VARIANTS * b->groups.size(); ++k) us_per_iter[k] = 0.0;
@@ -508,7 +510,7 @@ int nek_batch_tune(nek_batch *b, int prec, int iters, double *us_per_iter)
                             (rc = fill_f64(c, c->d64, 0.0, c->nl)))
                             return rc;
                     } else {
-                        if ((rc = ops(c)->inner_start(c, c->b, c->r32, c->d64)) || (rc = red_final(c, 1))) return rc;
+                        if ((rc = ops(c)->inner_start(c, c->b, c->r32, c->d32)) || (rc = red_final(c, 1))) return rc;
                     }
                     if ((rc = start_launch(c, 1, 0, 0.0, iters, 0))) return rc;
                 }

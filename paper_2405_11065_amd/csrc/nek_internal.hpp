@@ -116,7 +116,9 @@ struct nek_ctx {
     double *hist = nullptr;
     long hist_cap = 0;
     // work vectors
-    double *b = nullptr, *r64 = nullptr, *p64 = nullptr, *w64 = nullptr, *d64 = nullptr;
+    double *b = nullptr, *r64 = nullptr, *p64 = nullptr, *w64 = nullptr;
+    double *d64 = nullptr;   // iterate of FP64 autotuning runs
+    float *d32 = nullptr;    // correction of an inner (FP32 / BF16-g) solve
     float *r32 = nullptr, *p32 = nullptr, *w32 = nullptr;
     int *hflags = nullptr;   // pinned
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -169,12 +171,13 @@ int prof_take(nek_ctx *c);
 // returns a nek_status.  Reductions leave per-workgroup partials in c->P3().
 struct NpOps {
     int nvariants;
-    // one CG iteration (final: only the closing operator launch)
+    // one CG iteration (final: only the closing operator launch); the
+    // iterate x has the type of the vectors
     int (*cg_iter64)(nek_ctx *, int variant, int it, bool final, double *x, double *r, double *p, double *w,
                      const double *g, const double *D);
-    int (*cg_iter32)(nek_ctx *, int variant, int it, bool final, double *x, float *r, float *p, float *w,
+    int (*cg_iter32)(nek_ctx *, int variant, int it, bool final, float *x, float *r, float *p, float *w,
                      const float *g, const float *D);
-    int (*cg_iter16)(nek_ctx *, int variant, int it, bool final, double *x, float *r, float *p, float *w,
+    int (*cg_iter16)(nek_ctx *, int variant, int it, bool final, float *x, float *r, float *p, float *w,
                      const uint16_t *g, const float *D);
     // w = A_L u
     int (*ax64)(nek_ctx *, const double *u, double *w);
@@ -192,7 +195,7 @@ struct NpOps {
     // r = b - M dssum(w), partials of glsc3(r, c, r)
     int (*resid)(nek_ctx *, const double *b, const double *w, double *r);
     // r32 = (float) r64, d = 0, partials of glsc3(r32, c, r32)
-    int (*inner_start)(nek_ctx *, const double *r64, float *r32, double *d);
+    int (*inner_start)(nek_ctx *, const double *r64, float *r32, float *d);
     // elements per workgroup of a CG variant
     int (*variant_epw)(int variant);
     // Batched CG iteration base + it_local of every active problem in tab

@@ -889,7 +889,7 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_cg_update(T *__restrict__ r, co
 struct BatchProb {
     void *r, *p, *w;       // residual, search direction, A_L p (T)
     const void *g;         // geometric factors (GT)
-    double *x;             // iterate or correction, accumulated in FP64
+    void *x;               // FP64 iterate (FP64 solve) or FP32 inner correction (T)
     Scal *sc;
     double *partials;      // pAp by parity, then rtr by parity (MAXB each)
     double *hist;
@@ -914,8 +914,8 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax_batch(const BatchProb *__res
     const BatchProb P = tab[q];
     if (!P.active) return;
     const int it = batch_it(base, it_local);
-    ax_body<NP, EPW, PD, T, GT, true, double>(
-        (const T *)P.r, (T *)P.p, (T *)P.w, (const GT *)P.g, D, P.x, P.sc, P.partials + (it & 1) * MAXB,
+    ax_body<NP, EPW, PD, T, GT, true, T>(
+        (const T *)P.r, (T *)P.p, (T *)P.w, (const GT *)P.g, D, (T *)P.x, P.sc, P.partials + (it & 1) * MAXB,
         P.partials + ((it - 1) & 1) * MAXB, P.partials + (2 + ((it - 1) & 1)) * MAXB, P.nblk, it, P.hist, P.E,
         P.ngroups, blockIdx.x - P.blk0, P.nblk);
 }
@@ -992,7 +992,7 @@ __global__ __launch_bounds__(UPD_BS) void k_glsc3(const TA *__restrict__ a, cons
 // inner (FP32-operator) solve of the refinement loop.
 template <int NP>
 __global__ __launch_bounds__(UPD_BS) void k_inner_start(const double *__restrict__ r64, float *__restrict__ r32,
-                                                        double *__restrict__ d, double *__restrict__ P, Box box,
+                                                        float *__restrict__ d, double *__restrict__ P, Box box,
                                                         unsigned nl)
 {
     __shared__ double sbuf[UPD_BS];
@@ -1004,7 +1004,7 @@ __global__ __launch_bounds__(UPD_BS) void k_inner_start(const double *__restrict
         const PointInfo<NP> Pt = locate<NP>(t, box);
         const float v = (float)r64[t];
         r32[t] = v;
-        d[t] = 0.0;
+        d[t] = 0.0f;
         part += ((double)v * (double)v) * inv_mult(Pt.mult);
     }
     const double s = block_sum<UPD_BS>(part, sbuf);

@@ -111,11 +111,11 @@ __global__ __launch_bounds__(256) void k_batch_alldone(Scal *const *__restrict__
     if (threadIdx.x == 0) *out = !pending;
 }
 
-// x += d (FP64).
-__global__ void k_axpy1(double *__restrict__ x, const double *__restrict__ d, unsigned long n)
+// x += d: FP64 iterate, FP32 correction of an inner solve.
+__global__ void k_axpy1(double *__restrict__ x, const float *__restrict__ d, unsigned long n)
 {
     for (unsigned long t = blockIdx.x * (unsigned long)blockDim.x + threadIdx.x; t < n; t += (unsigned long)gridDim.x * blockDim.x)
-        x[t] += d[t];
+        x[t] += (double)d[t];
 }
 
 }  // namespace nek

@@ -202,14 +202,15 @@ int resid_launch(nek_ctx *c, const double *b, const double *w, double *r, int sl
     return rc ? rc : red_final(c, slot);
 }
 
-// one CG iteration of the context at precision prec on its work vectors
-int cg_iter(nek_ctx *c, int prec, int variant, int it, bool final, double *x)
+// one CG iteration of the context at precision prec on its work vectors;
+// x is FP64 at FP64, else FP32 (the correction of an inner solve)
+int cg_iter(nek_ctx *c, int prec, int variant, int it, bool final, void *x)
 {
     if (prec == NEK_PREC_FP64)
-        return ops(c)->cg_iter64(c, variant, it, final, x, c->r64, c->p64, c->w64, c->g64, c->D64);
+        return ops(c)->cg_iter64(c, variant, it, final, (double *)x, c->r64, c->p64, c->w64, c->g64, c->D64);
     if (prec == NEK_PREC_BF16G)
-        return ops(c)->cg_iter16(c, variant, it, final, x, c->r32, c->p32, c->w32, c->g16, c->D32);
-    return ops(c)->cg_iter32(c, variant, it, final, x, c->r32, c->p32, c->w32, c->g32, c->D32);
+        return ops(c)->cg_iter16(c, variant, it, final, (float *)x, c->r32, c->p32, c->w32, c->g16, c->D32);
+    return ops(c)->cg_iter32(c, variant, it, final, (float *)x, c->r32, c->p32, c->w32, c->g32, c->D32);
 }
 
 int start_launch(nek_ctx *c, int rslot, int hist_off, double stop_tol, int maxit, int stop_on_initial,
@@ -314,13 +315,15 @@ int ensure_mixed_work(nek_ctx *c)
 {
     int rc;
     if ((rc = ensure_fp64_work(c)) || (rc = ensure_g(c, c->prec))) return rc;
-    if (dalloc(c->d64, c->nl) || dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) || dalloc(c->w32, c->nl))
+    if (dalloc(c->d32, c->nl) || dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) || dalloc(c->w32, c->nl))
         return NEK_E_OOM;
     return NEK_OK;
 }
 
 // Iterative refinement: FP64 outer residual with FP64 g; inner CG with an
-// FP32 operator (FP32 or BF16 g), FP64 reductions/scalars and FP64 correction.
+// FP32 operator (FP32 or BF16 g), FP64 reductions/scalars and an FP32
+// correction d (each update d += alpha p formed in FP64, rounded once), added
+// to the FP64 x after the inner solve.
 // The control below is shared by the solo and the batched solver.
 void ir_init(const nek_ctx *c, IrCtl &s)
 {
@@ -391,7 +394,7 @@ int ir_fallback(nek_ctx *c, IrCtl &s, double tol, int maxit, double *x)
 int ir_inner_launch(nek_ctx *c, IrCtl &s, double tol, int maxit, int *cap)
 {
     int rc;
-    if ((rc = ops(c)->inner_start(c, c->r64, c->r32, c->d64))) return rc;
+    if ((rc = ops(c)->inner_start(c, c->r64, c->r32, c->d32))) return rc;
     if ((rc = red_final(c, 1))) return rc;
     const double tau_k = std::min(0.5, std::max(s.tau, 0.3 * tol / s.rho));
     *cap = std::min(s.inner_cap, maxit - s.total);
@@ -409,7 +412,7 @@ int ir_inner_done(nek_ctx *c, IrCtl &s, const Scal &h, double *x)
         s.finished = true;
         return NEK_OK;
     }
-    hipLaunchKernelGGL(k_axpy1, dim3(4 * num_cu()), dim3(256), 0, c->stream, x, c->d64, (unsigned long)c->nl);
+    hipLaunchKernelGGL(k_axpy1, dim3(4 * num_cu()), dim3(256), 0, c->stream, x, c->d32, (unsigned long)c->nl);
     HIP_TRY(hipGetLastError());
     int rc;
     if ((rc = ax_local_launch(c, x, c->w64, NEK_F64, NEK_PREC_FP64))) return rc;
@@ -456,7 +459,7 @@ int solve_mixed(nek_ctx *c, const double *f, const double *x0, double tol, int m
         int cap = 0;
         if ((rc = ir_inner_launch(c, s, tol, maxit, &cap))) return rc;
         rc = run_cg(c, cap, [&](int it, bool final) -> int {
-            return cg_iter(c, c->prec, c->variant[c->prec], it, final, c->d64);
+            return cg_iter(c, c->prec, c->variant[c->prec], it, final, c->d32);
         });
         if (rc) return rc;
         if ((rc = read_scal(c, h))) return rc;
@@ -510,7 +513,7 @@ void nek_free(nek_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     dfree(c->D64); dfree(c->D32); dfree(c->g64); dfree(c->g32); dfree(c->g16); dfree(c->B);
     dfree(c->perm); dfree(c->segptr); dfree(c->segflag); dfree(c->sc); dfree(c->partials); dfree(c->hist);
-    dfree(c->b); dfree(c->r64); dfree(c->p64); dfree(c->w64); dfree(c->d64);
+    dfree(c->b); dfree(c->r64); dfree(c->p64); dfree(c->w64); dfree(c->d64); dfree(c->d32);
     dfree(c->r32); dfree(c->p32); dfree(c->w32);
     dfree(c->xyz); dfree(c->gfeat); dfree(c->x0_X); dfree(c->x0_Y); dfree(c->x0_s);
     if (c->hflags) (void)hipHostFree(c->hflags);
@@ -748,8 +751,11 @@ int nek_tune(nek_ctx *c, int prec, int iters, double *us_per_iter, int *best)
     if (!c || prec < NEK_PREC_FP64 || prec > NEK_PREC_BF16G || iters < 2) return NEK_E_ARG;
     int rc;
     if ((rc = ensure_fp64_work(c)) || (rc = ensure_g(c, prec)) || (rc = ensure_hist(c, iters + 1))) return rc;
-    if (dalloc(c->d64, c->nl) || dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) || dalloc(c->w32, c->nl))
+    if (prec == NEK_PREC_FP64 ? dalloc(c->d64, c->nl)
+                              : (dalloc(c->d32, c->nl) || dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) ||
+                                 dalloc(c->w32, c->nl)))
         return NEK_E_OOM;
+    void *xt = prec == NEK_PREC_FP64 ? (void *)c->d64 : (void *)c->d32;
     // synthetic SPD system: b = M dssum(1), x0 = 0
     if ((rc = fill<double>(c, c->w64, 1.0, c->nl)) || (rc = gather_launch(c, c->w64, c->b, false)) ||
         (rc = glsc3_to_slot(c, c->b, c->b, NEK_F64, 0)))
@@ -770,12 +776,12 @@ int nek_tune(nek_ctx *c, int prec, int iters, double *us_per_iter, int *best)
                 if ((rc = glsc3_to_slot(c, c->r64, c->r64, NEK_F64, 1)) || (rc = fill<double>(c, c->d64, 0.0, c->nl)))
                     break;
             } else {
-                if ((rc = ops(c)->inner_start(c, c->b, c->r32, c->d64))) break;
+                if ((rc = ops(c)->inner_start(c, c->b, c->r32, c->d32))) break;
                 if ((rc = red_final(c, 1))) break;
             }
             if ((rc = start_launch(c, 1, 0, 0.0, iters, 0))) break;
             HIP_TRY(hipEventRecord(e0, c->stream));
-            rc = run_cg(c, iters, [&](int it, bool final) -> int { return cg_iter(c, prec, v, it, final, c->d64); });
+            rc = run_cg(c, iters, [&](int it, bool final) -> int { return cg_iter(c, prec, v, it, final, xt); });
             HIP_TRY(hipEventRecord(e1, c->stream));
             HIP_TRY(hipEventSynchronize(e1));
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));

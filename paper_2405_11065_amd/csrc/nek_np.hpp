@@ -32,18 +32,18 @@ template <int NP> struct OpsImpl {
     // the final state.  Sampled timing brackets every prof_every-th
     // iteration with events.
     template <typename T, typename GT>
-    static int cg_iter(nek_ctx *c, int variant, int it, bool final, double *x, T *r, T *p, T *w, const GT *g,
+    static int cg_iter(nek_ctx *c, int variant, int it, bool final, T *x, T *r, T *p, T *w, const GT *g,
                        const T *D)
     {
         return with_variant<NP, GT>(variant, [&](auto epw_c, auto pd_c) -> int {
             constexpr int EPW = decltype(epw_c)::value, PD = decltype(pd_c)::value;
-            if (final) return launch_ax<EPW, PD, T, GT, true, double>(c, r, p, w, g, D, it, x);
+            if (final) return launch_ax<EPW, PD, T, GT, true, T>(c, r, p, w, g, D, it, x);
             int slot = -1;
             if (c->prof_every > 0 && (c->prof_tick++ % c->prof_every) == 0) {
                 if ((slot = prof_take(c)) < 0) return NEK_E_HIP;
                 HIP_TRY(hipEventRecord(c->prof_pool[3 * slot], c->stream));
             }
-            int rc = launch_ax<EPW, PD, T, GT, true, double>(c, r, p, w, g, D, it, x);
+            int rc = launch_ax<EPW, PD, T, GT, true, T>(c, r, p, w, g, D, it, x);
             if (rc) return rc;
             if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 1], c->stream));
             const unsigned grid = ax_grid(c, EPW);
@@ -60,12 +60,12 @@ template <int NP> struct OpsImpl {
     {
         return cg_iter<double, double>(c, v, it, final, x, r, p, w, g, D);
     }
-    static int cg_iter32(nek_ctx *c, int v, int it, bool final, double *x, float *r, float *p, float *w,
+    static int cg_iter32(nek_ctx *c, int v, int it, bool final, float *x, float *r, float *p, float *w,
                          const float *g, const float *D)
     {
         return cg_iter<float, float>(c, v, it, final, x, r, p, w, g, D);
     }
-    static int cg_iter16(nek_ctx *c, int v, int it, bool final, double *x, float *r, float *p, float *w,
+    static int cg_iter16(nek_ctx *c, int v, int it, bool final, float *x, float *r, float *p, float *w,
                          const uint16_t *g, const float *D)
     {
         return cg_iter<float, uint16_t>(c, v, it, final, x, r, p, w, g, D);
@@ -148,7 +148,7 @@ template <int NP> struct OpsImpl {
         return NEK_OK;
     }
 
-    static int inner_start(nek_ctx *c, const double *r64, float *r32, double *d)
+    static int inner_start(nek_ctx *c, const double *r64, float *r32, float *d)
     {
         hipLaunchKernelGGL((k_inner_start<NP>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, r64, r32, d, c->P3(),
                            c->box, (unsigned)c->nl);
