@@ -396,7 +396,29 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
         beta = (T)B.cur.beta;
         first = it == 1 && !sc->resume;
     }
-    if constexpr (DREG) {
+    // From NP = 12 on, keeping all four sets of D entries for the whole
+    // kernel would cost a wave per SIMD: each phase then reloads its two
+    // sets from a copy of D and of D^T in LDS, so only two are live at once.
+    constexpr bool DPH = DREG && NP >= 12;
+    __shared__ __align__(16) T sDD[DPH ? 2 * NP * NP : 1];
+    auto d_rows = [&](const T *base, T a[], T b[]) {
+        if constexpr (NP % 4 == 0 && sizeof(T) == 4) {
+            load_row<NP>(base + i * NP, a);
+            load_row<NP>(base + j * NP, b);
+        } else {
+#pragma unroll
+            for (int l = 0; l < NP; ++l) {
+                a[l] = base[i * NP + l];
+                b[l] = base[j * NP + l];
+            }
+        }
+    };
+    if constexpr (DPH) {
+        for (int q = tid; q < NP * NP; q += BS) {
+            sDD[q] = D[q];
+            sDD[NP * NP + q] = D[(q % NP) * NP + q / NP];
+        }
+    } else if constexpr (DREG) {
 #pragma unroll
         for (int l = 0; l < NP; ++l) {
             Dri[l] = D[i * NP + l];
@@ -404,9 +426,9 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
             DTi[l] = D[l * NP + i];
             DTj[l] = D[l * NP + j];
         }
-    }
-    else
+    } else {
         for (int q = tid; q < NP * NP; q += BS) sD[q] = D[q];
+    }
 #define NEK_DR(l) (DREG ? Dri[DREG ? (l) : 0] : sD[i * NP + (l)])
 #define NEK_DS(l) (DREG ? Dsj[DREG ? (l) : 0] : sD[j * NP + (l)])
 #define NEK_DTI(l) (DREG ? DTi[DREG ? (l) : 0] : sD[(l) * NP + i])
@@ -439,6 +461,7 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
             if constexpr (ROWS) sute[k * SL + i * RP + j] = v;
         }
         __syncthreads();
+        if constexpr (DPH) d_rows(sDD, Dri, Dsj);   // rows i and j of D
         T wt[NP];
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
@@ -472,6 +495,7 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
             if (k + PD < NP) gb[k % PD] = GL::load(ge + (size_t)(k + PD) * NP2 * 6);
         }
         __syncthreads();
+        if constexpr (DPH) d_rows(sDD + NP * NP, DTi, DTj);   // columns i and j of D
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             T acc = 0;

@@ -124,7 +124,8 @@ def test_glsc3():
     ctx.close()
 
 
-@pytest.mark.parametrize("N,nel", [(7, (4, 4, 4)), (9, (3, 2, 2)), (5, (2, 3, 2))])
+@pytest.mark.parametrize("N,nel", [(7, (4, 4, 4)), (9, (3, 2, 2)), (5, (2, 3, 2)), (11, (2, 3, 2)), (12, (2, 1, 2)),
+                                   (15, (1, 2, 1))])
 def test_ax_reduced_precision(N, nel):
     ctx, P = make(N, nel, perturb=0.1, prec="fp32")
     u = synth.uniform_load(P.nl, 3) - 0.5
@@ -228,19 +229,21 @@ def test_cg_deterministic():
     ctx.close()
 
 
-@pytest.mark.parametrize("prec,mode", [("fp32", 0), ("fp32", 1), ("fp32", 2), ("bf16g", 0), ("bf16g", 2)])
-def test_mixed_precision_solve(prec, mode):
+@pytest.mark.parametrize("prec,mode,N,nel", [("fp32", 0, 9, (5, 4, 4)), ("fp32", 1, 9, (5, 4, 4)),
+                                             ("fp32", 2, 9, (5, 4, 4)), ("bf16g", 0, 9, (5, 4, 4)),
+                                             ("bf16g", 2, 9, (5, 4, 4)), ("fp32", 0, 11, (3, 3, 2)),
+                                             ("bf16g", 0, 11, (3, 3, 2))])
+def test_mixed_precision_solve(prec, mode, N, nel):
     """Deformed [0,1]^3 mesh, manufactured forcing: the refined mixed solve
     (mode 1: restarted refinement, 2: reliable update, 0: default for the
     storage) reaches a true FP64 residual of 1e-8 (judged by the oracle)."""
-    N, nel = 9, (5, 4, 4)
     ctx, P = make(N, nel, perturb=0.1, seed=33, hi=(1.0, 1.0, 1.0), prec=prec, want_X=True, refine_mode=mode)
     noise = synth.normal_noise(P.nl, 1e-3, 34).reshape(P.E, -1)
     f_or = (P.B * (synth.sine_field(P.X) + noise)).ravel()
     Bg = ctx.get(nek.NEK_GET_B).reshape(P.E, -1)
     Xg = ctx.get(nek.NEK_GET_XYZ)
     f_gpu = (Bg * (synth.sine_field(Xg) + noise)).ravel()
-    _case(f"cg mixed {prec} mode {mode}")
+    _case(f"cg mixed {prec} mode {mode} N={N}")
     x, st, hist = ctx.cg_solve(dev(f_gpu), tol=1e-8, maxit=5000, history=True)
     xh = host(x)
     rho = P.true_residual(xh, f_or)
