@@ -51,7 +51,9 @@ struct nek_batch {
     hipStream_t user = nullptr;        // the caller's stream (not owned)
     Scal **dscs = nullptr, **hscs = nullptr;
     Scal *hscal = nullptr;             // pinned read-back of the members' scalars
-    int *dbase = nullptr, *dflag = nullptr, *hflags = nullptr;
+    int *dbase = nullptr;
+    int *hflags = nullptr;             // pinned; [0] = all done, written by k_batch_alldone
+    int *dflag = nullptr;              // device alias of hflags (not owned)
     hipEvent_t ev[2] = {nullptr, nullptr}, fork = nullptr, entry = nullptr, t0 = nullptr, t1 = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -237,11 +239,11 @@ int run_batch(nek_batch *b, int prec, const std::vector<char> &act, const std::v
             return rc;
         launched += CHUNK_ITERS;
         ++b->chunks;
-        HIP_TRY(hipMemcpyAsync(&b->hflags[slot], b->dflag, sizeof(int), hipMemcpyDeviceToHost, b->stream));
         HIP_TRY(hipEventRecord(b->ev[slot], b->stream));
         if (pend >= 0) {
+            // every chunk ends with k_batch_alldone writing hflags[0]
             HIP_TRY(hipEventSynchronize(b->ev[pend]));
-            if (b->hflags[pend]) break;
+            if (__atomic_load_n(&b->hflags[0], __ATOMIC_ACQUIRE)) break;
         }
         pend = slot;
         slot ^= 1;
@@ -370,7 +372,6 @@ void nek_batch_free(nek_batch *b)
     }
     dfree(b->dscs);
     dfree(b->dbase);
-    dfree(b->dflag);
     if (b->hscs) (void)hipHostFree(b->hscs);
     if (b->hscal) (void)hipHostFree(b->hscal);
     if (b->hflags) (void)hipHostFree(b->hflags);
@@ -418,11 +419,13 @@ int nek_batch_setup(int n, const nek_mesh *meshes, const int *N, const nek_opts 
             hipEventCreateWithFlags(&G.join, hipEventDisableTiming) != hipSuccess)
             return fail(NEK_E_HIP);
     }
-    if (dalloc(b->dscs, n) || dalloc(b->dbase, 1) || dalloc(b->dflag, 1)) return fail(NEK_E_OOM);
+    if (dalloc(b->dscs, n) || dalloc(b->dbase, 1)) return fail(NEK_E_OOM);
     if (hipHostMalloc((void **)&b->hscs, n * sizeof(Scal *), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&b->hscal, n * sizeof(Scal), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&b->hflags, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
         return fail(NEK_E_OOM);
+    b->hflags[0] = b->hflags[1] = 0;
+    if (hipHostGetDevicePointer((void **)&b->dflag, b->hflags, 0) != hipSuccess) return fail(NEK_E_HIP);
     for (hipEvent_t *e : {&b->ev[0], &b->ev[1], &b->fork})
         if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return fail(NEK_E_HIP);
     if (hipEventCreate(&b->t0) != hipSuccess || hipEventCreate(&b->t1) != hipSuccess) return fail(NEK_E_HIP);

@@ -120,7 +120,7 @@ struct nek_ctx {
     double *d64 = nullptr;   // iterate of FP64 autotuning runs
     float *d32 = nullptr;    // correction of an inner (FP32 / BF16-g) solve
     float *r32 = nullptr, *p32 = nullptr, *w32 = nullptr;
-    int *hflags = nullptr;   // pinned
+    int *hflags = nullptr;   // pinned; [0] mirrors the run's done flag (written by its kernels)
     hipEvent_t ev[2] = {nullptr, nullptr};
     // learned initial guess (nek_x0_*, nek_grf): node coordinates [E][3][NP^3]
     // and per-element network buffers

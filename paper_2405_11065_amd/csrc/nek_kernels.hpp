@@ -54,9 +54,17 @@ struct Scal {
     int maxit;
     int hist_off;         // history index of iteration 0 of this run
     int k2flag[2];        // status of k_cg_update(it) in slot it & 1
-    int done_host;        // set once a run is done; polled by the host
+    int done_host;        // set once a run is done
     int resume;           // 1: the run continues the previous search direction
+    int *host_done;       // device alias of a pinned host flag mirroring done_host (or null)
 };
+
+// A flag in pinned host memory, written by a system-scope store so that the
+// host sees it once the writing kernel has completed.
+__device__ __forceinline__ void set_host_flag(int *f, int v)
+{
+    __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 struct Box { int nx, ny, nz; };
 
@@ -234,6 +242,7 @@ __device__ __forceinline__ Begin cg_begin(Scal *__restrict__ sc, const double *_
         sc->st[it & 1] = cur;
         if (cur.done) {
             sc->done_host = 1;
+            if (sc->host_done) set_host_flag(sc->host_done, 1);
             sc->fin = cur;
         }
     }

@@ -43,6 +43,7 @@ __global__ void k_cg_start(Scal *sc, double *hist, int rslot, int hist_off, doub
     sc->st[1] = s;
     sc->fin = s;
     sc->done_host = s.done;
+    if (sc->host_done) set_host_flag(sc->host_done, s.done);
 }
 
 // Standalone reductions write one partial per workgroup; k_red_final sums
@@ -100,15 +101,15 @@ __global__ void k_batch_advance(int *base, int step)
     if (threadIdx.x == 0 && blockIdx.x == 0) *base += step;
 }
 
-// Batched runs: out = 1 when every listed problem (non-null entry) has
-// finished its run.
+// Batched runs: *out (a pinned host flag) = 1 when every listed problem
+// (non-null entry) has finished its run, else 0.
 __global__ __launch_bounds__(256) void k_batch_alldone(Scal *const *__restrict__ scs, int nprob, int *out)
 {
     int pending = 0;
     for (int i = threadIdx.x; i < nprob; i += 256)
         if (scs[i] && !scs[i]->done_host) pending = 1;
     pending = __syncthreads_or(pending);
-    if (threadIdx.x == 0) *out = !pending;
+    if (threadIdx.x == 0) set_host_flag(out, !pending);
 }
 
 // x += d: FP64 iterate, FP32 correction of an inner solve.

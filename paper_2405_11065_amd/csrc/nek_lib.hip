@@ -243,11 +243,12 @@ template <typename IterFn> int run_cg(nek_ctx *c, int maxit, IterFn iter)
             if (rc) return rc;
         }
         launched += n;
-        HIP_TRY(hipMemcpyAsync(&c->hflags[slot], &c->sc->done_host, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipEventRecord(c->ev[slot], c->stream));
         if (pend >= 0) {
+            // the run's kernels write hflags[0] themselves (k_cg_start, then
+            // the operator kernel that ends the run): no copy in the stream
             HIP_TRY(hipEventSynchronize(c->ev[pend]));
-            if (c->hflags[pend]) break;
+            if (__atomic_load_n(&c->hflags[0], __ATOMIC_ACQUIRE)) break;
         }
         pend = slot;
         slot ^= 1;
@@ -575,6 +576,9 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
         dalloc(c->sc, 1) || dalloc(c->partials, 5 * MAXB))
         return fail(NEK_E_OOM);
     if (hipHostMalloc((void **)&c->hflags, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(NEK_E_OOM);
+    c->hflags[0] = c->hflags[1] = 0;
+    int *hflag_dev = nullptr;
+    if (hipHostGetDevicePointer((void **)&hflag_dev, c->hflags, 0) != hipSuccess) return fail(NEK_E_HIP);
     for (auto &e : c->ev)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(NEK_E_HIP);
     // synchronous uploads: the host staging vectors die at return
@@ -586,6 +590,7 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
         hipMemcpy(c->segptr, segptr.data(), segptr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->segflag, segflag.data(), segflag.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->sc, 0, sizeof(Scal)) != hipSuccess ||
+        hipMemcpy(&c->sc->host_done, &hflag_dev, sizeof(int *), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->partials, 0, 5 * MAXB * sizeof(double)) != hipSuccess)
         return fail(NEK_E_HIP);
     if ((rc = ensure_g(c, c->prec))) return fail(rc);
