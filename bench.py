@@ -196,16 +196,16 @@ def batch_case(torch, nek, synth, nprob=64, steps=1):
     return out
 
 
-def learned_case(torch, nsolves=10000, steps=2500, neval=4):
-    """Learned initial guess: 10,000 FP64 solves on 8^3-element N=7 meshes of
-    [0,1]^3 (+-10 % interior vertex moves, 64 distinct meshes) forced by
-    Gaussian random fields (length scale 0.2) give 5.12 M element rows; the
-    518 -> 256 -> 256 -> 512 network trains for `steps` Adam steps of 4096
-    rows on the GPU; then 16^3-element N=7 problems are solved to 1e-8 by
-    FP64 CG from zero and from the network's guess (prediction time
-    included)."""
+def learned_case(torch, nsolves=10000, steps=2500, neval=16, data_tol=1e-10):
+    """Learned initial guess: 10,000 FP64 solves (to 1e-10) on 8^3-element
+    N=7 meshes of [0,1]^3 (+-10 % interior vertex moves, 64 distinct meshes)
+    forced by Gaussian random fields (length scale 0.2) give 5.12 M element
+    rows; the 518 -> 256 -> 256 -> 512 network trains for `steps` Adam steps
+    of 4096 rows on the GPU; then `neval` fresh 16^3-element N=7 problems
+    are solved to 1e-8 by FP64 CG from zero and from the network's guess
+    (prediction time included)."""
     from paper_2405_11065_amd import learned_x0 as lx
-    X, T, info = lx.make_dataset(torch, nsolves, log=log)
+    X, T, info = lx.make_dataset(torch, nsolves, tol=data_tol, log=log)
     net, hist, t_train = lx.train(torch, X, T, steps)
     rows = X.shape[0]
     del X, T
