@@ -507,6 +507,11 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
         if constexpr (DPH) d_rows(sDD + NP * NP, DTi, DTj);   // columns i and j of D
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
+            // plain form: one slice at a time.  Left free, the scheduler
+            // hoists the LDS rows of every slice ahead of the arithmetic
+            // (148-155 VGPRs at NP = 10, 220 for FP64); the CG form keeps its
+            // own order (pinning it slows the FP64 kernel by 2-5 %)
+            if constexpr (!CG) __builtin_amdgcn_sched_barrier(0);
             T acc = 0;
             if constexpr (ROWS) {
                 T rr[RP], rs[RP];

@@ -18,7 +18,10 @@ template <int NP> struct OpsImpl {
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
             attr_done = true;
         }
-        const unsigned grid = ax_grid(c, EPW);
+        // the CG form writes one partial per workgroup, read by every workgroup
+        // of the next kernel: a capped grid of persistent workgroups; the plain
+        // operator reduces nothing and takes one element group per workgroup
+        const unsigned grid = CG ? ax_grid(c, EPW) : (unsigned)ax_groups(c, EPW);
         hipLaunchKernelGGL((k_ax<NP, EPW, PD, T, GT, CG, XT>), dim3(grid), dim3(BS), shm, c->stream, src, p, w, g, D,
                            x, c->sc, c->P1(it), c->P1(it - 1), c->P2(it - 1), (int)grid, it, c->hist, (int)c->E,
                            ax_groups(c, EPW));
@@ -94,7 +97,7 @@ template <int NP> struct OpsImpl {
             constexpr int EPW = decltype(epw_c)::value, PD = decltype(pd_c)::value;
             int rc = launch_ax<EPW, PD, T, GT, false>(c, u, nullptr, scratch, g, D, 0);
             if (rc) return rc;
-            hipLaunchKernelGGL((k_assemble<NP, EPW, T>), dim3(ax_grid(c, EPW)), dim3(EPW * NP * NP), 0, c->stream,
+            hipLaunchKernelGGL((k_assemble<NP, EPW, T>), dim3(ax_groups(c, EPW)), dim3(EPW * NP * NP), 0, c->stream,
                                scratch, w, c->box, (int)c->E, ax_groups(c, EPW));
             HIP_TRY(hipGetLastError());
             return NEK_OK;

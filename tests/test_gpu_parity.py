@@ -129,15 +129,20 @@ def test_glsc3():
 def test_ax_reduced_precision(N, nel):
     ctx, P = make(N, nel, perturb=0.1, prec="fp32")
     u = synth.uniform_load(P.nl, 3) - 0.5
-    ref = P.ax_local(u)
+    ref, refA = P.ax_local(u), P.A(u)
+    u32 = dev(u, torch.float32)
     _case(f"nek_ax_local fp32 N={N}")
-    e32 = relmax(host(ctx.ax_local(dev(u, torch.float32))).astype(np.float64), ref)
+    e32 = relmax(host(ctx.ax_local(u32)).astype(np.float64), ref)
+    _case(f"nek_ax fp32 N={N}")
+    a32 = relmax(host(ctx.ax(u32)).astype(np.float64), refA)
     ctx.set_prec("bf16g")
     _case(f"nek_ax_local fp32/bf16-g N={N}")
-    e16 = relmax(host(ctx.ax_local(dev(u, torch.float32))).astype(np.float64), ref)
-    print(f"  fp32 err {e32:.2e}  bf16-g err {e16:.2e}")
-    assert e32 <= 2e-6
-    assert e16 <= 1e-2
+    e16 = relmax(host(ctx.ax_local(u32)).astype(np.float64), ref)
+    _case(f"nek_ax fp32/bf16-g N={N}")
+    a16 = relmax(host(ctx.ax(u32)).astype(np.float64), refA)
+    print(f"  fp32 err {e32:.2e} (assembled {a32:.2e})  bf16-g err {e16:.2e} (assembled {a16:.2e})")
+    assert e32 <= 2e-6 and a32 <= 2e-6
+    assert e16 <= 1e-2 and a16 <= 1e-2
     ctx.close()
 
 
