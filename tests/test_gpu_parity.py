@@ -222,6 +222,29 @@ def test_cg_initial_guess_and_edge_cases():
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16g"])
+def test_mixed_edge_cases(prec):
+    """Refinement edge cases; a run capped at 3 iterations right after a
+    converged one checks that the finished run's done flag (which the kernels
+    write to pinned host memory) cannot end the next run early."""
+    ctx, P = make(5, (3, 3, 3), perturb=0.1, prec=prec)
+    f = synth.uniform_load(P.nl, 9)
+    xo, _, _ = P.cg(f, tol=1e-12, maxit=3000)
+    _case(f"cg mixed {prec} converged")
+    x, st, _ = ctx.cg_solve(dev(f), tol=1e-8, maxit=3000)
+    assert st["status"] == 0 and P.true_residual(host(x), f) <= 1e-8
+    _case(f"cg mixed {prec} maxit 3 after a converged run")
+    x, st, _ = ctx.cg_solve(dev(f), tol=1e-12, maxit=3)
+    assert st["iters"] == 3 and st["status"] == nek.NEK_NOCONV
+    _case(f"cg mixed {prec} exact x0")
+    x, st, _ = ctx.cg_solve(dev(f), x0=dev(xo), tol=1e-8, maxit=50)
+    assert st["iters"] == 0 and st["status"] == 0
+    _case(f"cg mixed {prec} zero load")
+    x, st, _ = ctx.cg_solve(dev(np.zeros(P.nl)), tol=1e-8, maxit=10)
+    assert st["iters"] == 0 and not host(x).any()
+    ctx.close()
+
+
 def test_cg_deterministic():
     ctx, P = make(7, (3, 3, 3), perturb=0.1)
     f = dev(synth.uniform_load(P.nl, 4))
