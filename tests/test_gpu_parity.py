@@ -260,7 +260,8 @@ def test_cg_deterministic():
 @pytest.mark.parametrize("prec,mode,N,nel", [("fp32", 0, 9, (5, 4, 4)), ("fp32", 1, 9, (5, 4, 4)),
                                              ("fp32", 2, 9, (5, 4, 4)), ("bf16g", 0, 9, (5, 4, 4)),
                                              ("bf16g", 2, 9, (5, 4, 4)), ("fp32", 0, 11, (3, 3, 2)),
-                                             ("bf16g", 0, 11, (3, 3, 2))])
+                                             ("bf16g", 0, 11, (3, 3, 2)), ("fp32", 0, 12, (2, 3, 2)),
+                                             ("fp32", 0, 15, (2, 2, 2))])
 def test_mixed_precision_solve(prec, mode, N, nel):
     """Deformed [0,1]^3 mesh, manufactured forcing: the refined mixed solve
     (mode 1: restarted refinement, 2: reliable update, 0: default for the
