@@ -11,7 +11,8 @@ refinement); its FP64 CG counterpart is timed the same way next to it.
 Prints ONE JSON line: the mixed solve's CG GDOF*iter/s (local points x CG
 iterations / solve time), the FP64 solve's, the roofline of the dominant
 kernel (fused add2s1 + operator, HIP events on the solver's stream), the
-ax+dssum bandwidth at each precision, and the FP64 CPU oracle timed on a
+ax+dssum bandwidth at each precision, the energy per solve of both
+precisions (GPU package energy counter), and the FP64 CPU oracle timed on a
 bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -114,7 +115,7 @@ def cpu_baseline(f, budget_s=15.0):
                       f"({dt:.1f} s), setup excluded"}
 
 
-def big_case(torch, nek, synth, steps=2):
+def big_case(torch, nek, synth, steps=2, energy=True):
     """32^3 elements on [0,1]^3, interior vertices moved up to 10 %, N=9
     (32.8 M local points), f = B (sin pi x sin pi y sin pi z + N(0,1e-3)):
     mixed solve with BF16-stored g against FP64 CG, tol 1e-8; then nek_ax
@@ -145,6 +146,8 @@ def big_case(torch, nek, synth, steps=2):
                      "GDOF_iter_per_s": round(ctx.nl * its / steps / dt / 1e9, 3), "true_rel_res": st["rel_res"]
                      if prec != "fp64" else None}
     out["speedup_vs_fp64"] = round(out["fp64"]["ms_per_solve"] / out["bf16g"]["ms_per_solve"], 3)
+    if energy:
+        out["energy"] = big_energy(torch, ctx, f, x, {p: out[p]["ms_per_solve"] for p in ("bf16g", "fp64")})
     # ax + dssum at this size: the working set exceeds the 256 MB memory-side cache
     ctx.tune("fp32", iters=10)
     out["ax_dssum"] = ax_dssum_all(ctx, torch)
@@ -153,8 +156,123 @@ def big_case(torch, nek, synth, steps=2):
     return out
 
 
+def big_energy(torch, ctx, f, x, ms_per_solve):
+    """Energy per solve of the 32^3 case, BF16-g mixed against FP64."""
+    try:
+        meter = EnergyCounter(torch)
+    except Exception as ex:
+        return {"error": f"energy counter unavailable: {ex!r}"}
+    out = {}
+    try:
+        for prec in ("bf16g", "fp64"):
+            ctx.set_prec(prec)
+            watts, window, calls = steady_power(
+                meter.read, lambda: ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True),
+                min_window_s=4.0, max_run_s=30.0)
+            out[prec] = {"W": round(watts, 1), "window_s": round(window, 2), "solves_in_run": calls,
+                         "J_per_solve": round(watts * ms_per_solve[prec] / 1e3, 2)}
+        out["energy_reduction_pct"] = round(100 * (1 - out["bf16g"]["J_per_solve"] / out["fp64"]["J_per_solve"]), 2)
+    except Exception as ex:
+        out["error"] = repr(ex)
+    finally:
+        meter.close()
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+class EnergyCounter:
+    """The GPU package's energy accumulator, read through amdsmi.
+
+    read() returns (joules, seconds), both from the counter itself: the
+    accumulated energy and the firmware timestamp of its last update.  On
+    MI355X the accumulator advances about once per second, so energies are
+    taken between two updates, never between two arbitrary host instants.
+    """
+
+    def __init__(self, torch):
+        import amdsmi
+        self._smi = amdsmi
+        amdsmi.amdsmi_init(amdsmi.AmdSmiInitFlags.INIT_AMD_GPUS)
+        handles = amdsmi.amdsmi_get_processor_handles()
+        if len(handles) == 1:
+            self.h = handles[0]
+        else:   # the handle whose PCI bus is cuda:0's
+            bus = torch.cuda.get_device_properties(0).pci_bus_id
+            match = [h for h in handles if int(amdsmi.amdsmi_get_gpu_device_bdf(h).split(":")[1], 16) == bus]
+            if len(match) != 1:
+                raise RuntimeError("cannot match cuda:0 to an amdsmi handle")
+            self.h = match[0]
+
+    def read(self):
+        e = self._smi.amdsmi_get_energy_count(self.h)
+        return e["energy_accumulator"] * e["counter_resolution"] * 1e-6, e["timestamp"] * 1e-9
+
+    def close(self):
+        self._smi.amdsmi_shut_down()
+
+
+def steady_power(read, work, min_window_s=3.0, max_run_s=20.0, clock=time.perf_counter):
+    """Mean power while `work` runs back to back.
+
+    `read()` gives (joules, seconds) of an accumulating counter that updates
+    at its own pace.  The interval from the last update before the run to
+    the first one inside it is partly idle, so the window starts at the first
+    update seen after `work` has begun and ends at the last update seen before
+    it stops; `work` repeats until that window spans `min_window_s` seconds of
+    the counter's clock.  Returns (watts, window seconds, calls of work).
+    """
+    prev = read()
+    snaps = []
+    calls = 0
+    t0 = clock()
+    while True:
+        work()
+        calls += 1
+        cur = read()
+        if cur[1] != prev[1]:
+            snaps.append(cur)
+            prev = cur
+        if len(snaps) >= 2 and snaps[-1][1] - snaps[0][1] >= min_window_s:
+            break
+        if clock() - t0 > max_run_s:
+            break
+    if len(snaps) < 2 or snaps[-1][1] <= snaps[0][1]:
+        raise RuntimeError("energy counter did not advance twice during the run")
+    (e0, s0), (e1, s1) = snaps[0], snaps[-1]
+    return (e1 - e0) / (s1 - s0), s1 - s0, calls
+
+
+def energy_to_solution(torch, ctx, solve, ms_per_solve):
+    """Energy per solve at each precision (the paper's energy-to-solution,
+    Table 6, here for the GPU package): mean package power while the solve
+    repeats back to back, times the solve's time from the timed steps.
+    Idle power is measured beside it so the dynamic part can be separated."""
+    try:
+        meter = EnergyCounter(torch)
+    except Exception as ex:   # no amdsmi or no permission: report, do not fail the bench
+        return {"error": f"energy counter unavailable: {ex!r}"}
+    out = {"source": "amdsmi energy accumulator, GPU package (compute dies and HBM), ~1 s updates"}
+    try:
+        torch.cuda.synchronize()
+        out["idle_W"] = round(steady_power(meter.read, lambda: time.sleep(0.05), min_window_s=2.0)[0], 1)
+        for prec in ("fp32", "fp64"):
+            ctx.set_prec(prec)
+            watts, window, calls = steady_power(meter.read, solve, min_window_s=4.0)
+            ms = ms_per_solve[prec]
+            out[prec] = {"W": round(watts, 1), "window_s": round(window, 2), "solves_in_run": calls,
+                         "ms_per_solve": ms, "J_per_solve": round(watts * ms / 1e3, 3),
+                         "dynamic_J_per_solve": round((watts - out["idle_W"]) * ms / 1e3, 3)}
+        out["energy_reduction_pct"] = round(100 * (1 - out["fp32"]["J_per_solve"] / out["fp64"]["J_per_solve"]), 2)
+        out["paper_context"] = ("47.14 % energy-to-solution reduction at 128 MPI ranks on a 2x EPYC 7763 node "
+                                "(Table 6); a CPU node, not comparable hardware")
+    except Exception as ex:
+        out["error"] = repr(ex)
+    finally:
+        meter.close()
+    return out
 
 
 def batch_case(torch, nek, synth, nprob=64, steps=1):
@@ -285,6 +403,7 @@ def main():
     ap.add_argument("--no-big", action="store_true", help="skip the 32^3 deformed-mesh BF16 measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched solve")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned initial guess (data, training, eval)")
+    ap.add_argument("--no-energy", action="store_true", help="skip the energy-to-solution measurement")
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for hardware-counter runs: 40 mixed and 40 FP64 CG iterations, "
                          "5 nek_ax per precision and a 256 MiB copy for calibration")
@@ -354,11 +473,16 @@ def main():
     torch.cuda.synchronize()
     t_fp64 = time.perf_counter() - t0
 
+    # ---- energy-to-solution, mixed vs FP64, same solve
+    energy = None if args.no_energy else energy_to_solution(
+        torch, ctx, solve, {"fp32": ms_per_step, "fp64": t_fp64 / args.steps * 1e3})
+    log(f"energy: {energy}")
+
     # ---- ax + dssum bandwidth at each precision (nek_ax)
     axd = ax_dssum_all(ctx, torch)
 
     # ---- secondary: 32^3 deformed mesh, N=9, manufactured forcing, BF16 g vs FP64
-    big = None if args.no_big else big_case(torch, nek, synth)
+    big = None if args.no_big else big_case(torch, nek, synth, energy=not args.no_energy)
     log("32^3 case done")
     batch = None if args.no_batch else batch_case(torch, nek, synth)
     learned = None if args.no_learned else learned_case(torch)
@@ -390,6 +514,7 @@ def main():
         "speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
         "tuned_variant": {k: {"best": v[0], "us_per_iter": [round(u, 1) for u in v[1]]} for k, v in tuned.items()},
         "ax_dssum": axd,
+        "energy": energy,
         "roofline": {"bound": "hbm", "kernel": f"k_ax<NP=10,f32,f32,CG> variant {tuned['fp32'][0]} (add2s1 + ax_e + correction update)",
                      "achieved": round(achieved, 1) if achieved else None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None,
