@@ -31,6 +31,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nek_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "nek_vprec.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -43,10 +44,10 @@ _int3 = ctypes.c_int * 3
 
 def build(force: bool = False) -> str:
     """Compile nek_oracle.c into liboracle.so (plain gcc, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(map(os.path.getmtime, _SRCS)):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                               "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-shared", "-o", tmp] + _SRCS + ["-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -71,6 +72,12 @@ def _get():
         lib.or_apply_A.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i8, _d, _d]
         lib.or_cg.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i32, _i8, _d, _d,
                               ctypes.c_double, ctypes.c_int, _d, _d]
+        lib.vp_round.argtypes = [ctypes.c_double, ctypes.c_int]
+        lib.vp_round.restype = ctypes.c_double
+        lib.vp_perturb.argtypes = [ctypes.c_double, ctypes.c_int]
+        lib.vp_perturb.restype = ctypes.c_double
+        lib.vp_cg.argtypes = [ctypes.c_int, _int3, _d, _d, _i32, ctypes.c_int, ctypes.c_uint64,
+                              ctypes.c_double, ctypes.c_int, _d, _d, _d]
         _lib = lib
     return _lib
 
@@ -251,3 +258,47 @@ class Problem:
         b = self.rhs(f)
         r = b - self.A(x)
         return np.sqrt(self.glsc3(r, r)) / np.sqrt(self.glsc3(b, b))
+
+
+# ---------------------------------------------------------------- precision emulation
+# Region indices and hook modes of nek_vprec.c.
+VP_INIT, VP_OP, VP_VEC, VP_DOT = 0, 1, 2, 3
+VP_MODES = {"ieee": 0, "rne": 1, "rr": 2, "mca": 3}
+
+
+def vp_round(x: float, t: int) -> float:
+    """x rounded to t explicit mantissa bits (nearest, ties to even)."""
+    return _get().vp_round(float(x), int(t))
+
+
+def vp_perturb(x: float, t: int) -> float:
+    """One Monte Carlo perturbation x + 2^(e_x - t) xi (stream continues from the last vp_cg seed)."""
+    return _get().vp_perturb(float(x), int(t))
+
+
+def vprec_cg(N: int, nel, vtx, f, t=(52, 52, 52, 52), mode: str = "ieee", seed: int = 0,
+             tol: float = 0.0, maxit: int = 100, want_g: bool = False):
+    """The oracle's init and Table-1 CG with every FP operation passed through
+    the precision hook of nek_vprec.c: t = mantissa bits of the regions
+    (init, operator + dssum, vector updates, dot products and scalars); mode
+    one of 'ieee', 'rne' (round to t bits), 'rr' (random rounding of
+    results), 'mca' (perturbed operands and results).
+    Returns (x, iterations, recursive residual history[, g])."""
+    nel = tuple(int(v) for v in nel)
+    E = nel[0] * nel[1] * nel[2]
+    nl = E * (N + 1) ** 3
+    x = np.empty(nl)
+    hist = np.zeros(maxit + 1)
+    g = np.empty((E, 6, (N + 1) ** 3)) if want_g else None
+    tt = np.ascontiguousarray(t, dtype=np.int32)
+    assert tt.shape == (4,)
+    it = _get().vp_cg(N, _int3(*nel), _p(_f64(vtx), _d), _p(_f64(f), _d), _p(tt, _i32), VP_MODES[mode],
+                      int(seed) & (2 ** 64 - 1), float(tol), int(maxit), _p(x, _d), _p(hist, _d), _p(g, _d))
+    if it == -4:
+        raise ValueError("inverted element: det J <= 0")
+    if it == -1:
+        raise MemoryError
+    if it < 0:
+        # breakdown or non-finite value under the emulated precision: a result, not an error
+        return x, it, hist, g
+    return (x, it, hist[:it + 1], g) if want_g else (x, it, hist[:it + 1])
