@@ -11,6 +11,8 @@ and builds that file with gcc when its shared object is missing.
 What each function follows (paper: Chen et al., "Enabling mixed-precision with
 the help of tools: A Nekbone case study"):
   * ``cg``        -- the CG loop of Table 1 (solveM = copy, no preconditioner),
+  * ``pcg``, ``diag`` -- the same loop with solveM the diagonal (Jacobi)
+    preconditioner z = r / m, m the diagonal of the assembled operator,
   * ``ax_local``  -- ax_e of Fig. 2 (local_grad3 -> g1..g6 -> local_grad3_t),
   * ``glsc3``     -- the weighted dot product glsc3(a, c, b) of Table 1,
   * ``dssum``     -- the gather-scatter sum of copies of each shared node,
@@ -72,6 +74,9 @@ def _get():
         lib.or_apply_A.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i8, _d, _d]
         lib.or_cg.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i32, _i8, _d, _d,
                               ctypes.c_double, ctypes.c_int, _d, _d]
+        lib.or_diag.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i8, _d]
+        lib.or_pcg.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i32, _i8, _d, _d, _d,
+                               ctypes.c_double, ctypes.c_int, _d, _d]
         lib.vp_round.argtypes = [ctypes.c_double, ctypes.c_int]
         lib.vp_round.restype = ctypes.c_double
         lib.vp_perturb.argtypes = [ctypes.c_double, ctypes.c_int]
@@ -249,6 +254,31 @@ class Problem:
             raise FloatingPointError("CG breakdown: pAp <= 0")
         if it == -6:
             raise FloatingPointError("CG: non-finite value")
+        if it < 0:
+            raise MemoryError
+        return x, it, hist[:it + 1]
+
+    def diag(self):
+        """Diagonal of the assembled masked operator (1 on Dirichlet nodes), per local node."""
+        m = np.empty(self.nl)
+        if _get().or_diag(self.N, _int3(*self.nel), _p(self.D, _d), _p(self.g, _d), _p(self.gid, _i64),
+                          _p(self.mask, _i8), _p(m, _d)):
+            raise MemoryError
+        return m
+
+    def pcg(self, f, m, x0=None, tol: float = 1e-8, maxit: int = 1000):
+        """Table-1 CG with the diagonal preconditioner solveM: z = r / m.
+        Returns (x, iterations, residual history)."""
+        x = np.empty(self.nl)
+        hist = np.zeros(maxit + 1)
+        it = _get().or_pcg(self.N, _int3(*self.nel), _p(self.D, _d), _p(self.g, _d),
+                           _p(self.gid, _i64), _p(self.mult, _i32), _p(self.mask, _i8), _p(_f64(m), _d),
+                           _p(_f64(f), _d), _p(None if x0 is None else _f64(x0), _d),
+                           float(tol), int(maxit), _p(x, _d), _p(hist, _d))
+        if it == -5:
+            raise FloatingPointError("PCG breakdown: pAp <= 0")
+        if it == -6:
+            raise FloatingPointError("PCG: non-finite value")
         if it < 0:
             raise MemoryError
         return x, it, hist[:it + 1]

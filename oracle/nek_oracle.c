@@ -504,3 +504,124 @@ int or_cg(int N, const int *nel, const double *D, const double *g, const int64_t
     free(op.acc);
     return status ? status : it;
 }
+
+/*
+ * Diagonal of the assembled masked operator, the Jacobi preconditioner of
+ * the solveM step of Table 1.  For A_L = sum_{a,b in r,s,t} D_a^T G_ab D_b the
+ * entry at node p = (i,j,k) of an element is
+ *     sum_l D_li^2 G_rr(l,j,k) + sum_l D_lj^2 G_ss(i,l,k) + sum_l D_lk^2 G_tt(i,j,l)
+ *   + 2 D_ii D_jj G_rs(p) + 2 D_ii D_kk G_rt(p) + 2 D_jj D_kk G_st(p),
+ * because (D_r)_{q,p} = D_{q_i, i} when q shares j and k with p (0 otherwise),
+ * so a cross term survives only at q = p.  The element values are summed
+ * over the copies of each node (ascending local index); nodes on the
+ * Dirichlet boundary get 1 (their residual is 0, so z = r / m is 0 there).
+ */
+int or_diag(int N, const int *nel, const double *D, const double *g, const int64_t *gid, const int8_t *mask,
+            double *m)
+{
+    int n = N + 1, n3 = n * n * n;
+    int64_t E = (int64_t)nel[0] * nel[1] * nel[2], nl = E * n3;
+    int64_t ng = ((int64_t)nel[0] * N + 1) * ((int64_t)nel[1] * N + 1) * ((int64_t)nel[2] * N + 1);
+    double *acc = (double *)malloc(sizeof(double) * (size_t)ng);
+    if (!acc) return -1;
+    for (int64_t e = 0; e < E; ++e) {
+        const double *ge = g + e * 6 * n3;
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    double d = 0.0;
+                    for (int l = 0; l < n; ++l) d += D[l * n + i] * D[l * n + i] * ge[0 * n3 + l + n * (j + n * k)];
+                    for (int l = 0; l < n; ++l) d += D[l * n + j] * D[l * n + j] * ge[1 * n3 + i + n * (l + n * k)];
+                    for (int l = 0; l < n; ++l) d += D[l * n + k] * D[l * n + k] * ge[2 * n3 + i + n * (j + n * l)];
+                    int q = i + n * (j + n * k);
+                    double di = D[i * n + i], dj = D[j * n + j], dk = D[k * n + k];
+                    d += 2.0 * di * dj * ge[3 * n3 + q];
+                    d += 2.0 * di * dk * ge[4 * n3 + q];
+                    d += 2.0 * dj * dk * ge[5 * n3 + q];
+                    m[e * n3 + q] = d;
+                }
+    }
+    or_dssum(nl, ng, gid, m, acc);
+    for (int64_t l = 0; l < nl; ++l)
+        if (!mask[l]) m[l] = 1.0;
+    free(acc);
+    return 0;
+}
+
+/*
+ * Preconditioned CG in the order of Table 1 with solveM: z = r / m
+ * (diagonal preconditioner m > 0, given per local node, equal on copies):
+ *   per iteration:
+ *     z = r / m                              (solveM)
+ *     rtz2 = rtz1;  rtz1 = glsc3(r,c,z);  beta = rtz1/rtz2 (0 on the first)
+ *     p = beta p + z                         (add2s1)
+ *     w = A p;  pap = glsc3(w,c,p);  alpha = rtz1/pap
+ *     x = x + alpha p;  r = r - alpha w
+ *     rtr = glsc3(r,c,r)
+ * The stopping test, the start and the outputs are those of or_cg (the
+ * residual r itself is tested, not z).  With m = 1 every value equals
+ * or_cg's bit for bit.
+ */
+int or_pcg(int N, const int *nel, const double *D, const double *g, const int64_t *gid,
+           const int32_t *mult, const int8_t *mask, const double *m, const double *f, const double *x0,
+           double tol, int maxit, double *x, double *res_hist)
+{
+    or_op op;
+    if (or_op_init(&op, N, nel, D, g, gid, mask)) return -1;
+    int64_t nl = op.nl;
+    double *c = (double *)malloc(sizeof(double) * nl);
+    double *b = (double *)malloc(sizeof(double) * nl);
+    double *r = (double *)malloc(sizeof(double) * nl);
+    double *z = (double *)malloc(sizeof(double) * nl);
+    double *p = (double *)malloc(sizeof(double) * nl);
+    double *w = (double *)malloc(sizeof(double) * nl);
+    for (int64_t l = 0; l < nl; ++l) c[l] = 1.0 / mult[l];
+
+    for (int64_t l = 0; l < nl; ++l) b[l] = f[l];
+    or_dssum(nl, op.ng, gid, b, op.acc);
+    or_mask(nl, mask, b);
+
+    if (x0) {
+        for (int64_t l = 0; l < nl; ++l) x[l] = c[l] * x0[l];
+        or_dssum(nl, op.ng, gid, x, op.acc);
+        or_mask(nl, mask, x);
+    } else {
+        for (int64_t l = 0; l < nl; ++l) x[l] = 0.0;
+    }
+    or_apply(&op, x, w);
+    for (int64_t l = 0; l < nl; ++l) r[l] = b[l] - w[l];
+
+    double bb = or_glsc3(nl, b, c, b);
+    double rnorm0 = or_glsc3(nl, r, c, r);
+    int status = 0, it = 0;
+    if (res_hist) res_hist[0] = bb > 0 ? sqrt(rnorm0) / sqrt(bb) : 0.0;
+    int converged0 = rnorm0 == 0.0 || (tol > 0 && sqrt(rnorm0) / sqrt(bb) <= tol);
+    if (bb > 0 && !converged0) {
+        double rtz1 = 1.0, rtz2;
+        for (int64_t l = 0; l < nl; ++l) p[l] = 0.0;
+        for (it = 1; it <= maxit; ++it) {
+            for (int64_t l = 0; l < nl; ++l) z[l] = r[l] / m[l];
+            rtz2 = rtz1;
+            rtz1 = or_glsc3(nl, r, c, z);
+            if (rtz1 == 0.0) { --it; break; }
+            double beta = it == 1 ? 0.0 : rtz1 / rtz2;
+            for (int64_t l = 0; l < nl; ++l) p[l] = beta * p[l] + z[l];
+            or_apply(&op, p, w);
+            double pap = or_glsc3(nl, w, c, p);
+            if (!isfinite(pap) || !isfinite(rtz1)) { status = -6; break; }
+            if (!(pap > 0)) { status = -5; break; }
+            double alpha = rtz1 / pap;
+            for (int64_t l = 0; l < nl; ++l) x[l] = x[l] + alpha * p[l];
+            for (int64_t l = 0; l < nl; ++l) r[l] = r[l] + (-alpha) * w[l];
+            double rtr = or_glsc3(nl, r, c, r);
+            double res = sqrt(rtr) / sqrt(bb);
+            if (res_hist) res_hist[it] = res;
+            if (!isfinite(res)) { status = -6; break; }
+            if (tol > 0 && res <= tol) break;
+        }
+        if (it > maxit) it = maxit;
+    }
+    free(c); free(b); free(r); free(z); free(p); free(w);
+    free(op.acc);
+    return status ? status : it;
+}

@@ -304,9 +304,18 @@ def test_glsc3_vs_exact_sum():
 # -------------------------------------------------------------------- solves
 
 def _dense_reference(N, nel, vtx, f):
+    """Solution of the dense global system of _dense_system, mapped to local nodes."""
+    K, b, cid, free = _dense_system(N, nel, vtx, f)
+    xg = np.zeros(len(b))
+    xg[free] = np.linalg.solve(K[np.ix_(free, free)], b[free])
+    return xg[cid], int(free.sum())
+
+
+def _dense_system(N, nel, vtx, f):
     """Dense global stiffness from an independent route: Lagrange derivatives by
     NumPy polynomials, J = D X (not the analytic trilinear derivative), J^{-1}
-    and det by numpy.linalg, global identification by physical coordinates."""
+    and det by numpy.linalg, global identification by physical coordinates.
+    Returns (K, b, local -> global map, free (non-Dirichlet) global nodes)."""
     xi, w = oracle.gll(N)
     Dt = _lagrange_deriv_numpy(xi)
     n = N + 1
@@ -334,9 +343,7 @@ def _dense_reference(N, nel, vtx, f):
     lo, hi = vtx.min(0), vtx.max(0)
     P = uniq / 1e9
     free = ~np.any(np.isclose(P, lo, atol=1e-8) | np.isclose(P, hi, atol=1e-8), axis=1)
-    xg = np.zeros(ng)
-    xg[free] = np.linalg.solve(K[np.ix_(free, free)], b[free])
-    return xg[cid], int(free.sum())
+    return K, b, cid, free
 
 
 def test_cg_matches_dense_solve():
@@ -398,3 +405,65 @@ def test_manufactured_solution_converges_spectrally():
     for a, b in zip(errs, errs[1:]):
         assert b < a / 50, errs
     assert errs[-1] < 1e-9, errs
+
+
+# ------------------------------------------------- diagonal preconditioner
+
+@pytest.mark.parametrize("N,nel,perturb", [(4, (2, 2, 2), 0.1), (3, (3, 2, 1), 0.1), (5, (1, 2, 2), 0.0)])
+def test_diag_is_diagonal_of_dense_stiffness(N, nel, perturb):
+    """or_diag against the diagonal of the independently assembled dense K."""
+    vtx = synth.box_vertices(nel, hi=tuple(0.5 * v for v in nel), perturb=perturb, seed=21)
+    P = oracle.Problem(N, nel, vtx)
+    m = P.diag()
+    K, _, cid, free = _dense_system(N, nel, vtx, np.zeros(P.nl))
+    Kd = np.diag(K)[cid]
+    on = free[cid]
+    assert np.abs(m[on] - Kd[on]).max() <= 1e-12 * np.abs(Kd[on]).max()
+    assert np.all(m[~on] == 1.0) and np.all(m[on] > 0)
+    # equal on every copy of a node
+    for gval in np.unique(P.gid)[:200]:
+        assert np.unique(m[P.gid == gval]).size == 1
+
+
+def test_pcg_unit_preconditioner_is_cg_bit_for_bit():
+    nel, N = (3, 2, 2), 5
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=22)
+    P = oracle.Problem(N, nel, vtx)
+    f = synth.uniform_load(P.nl, 23)
+    x0, it0, h0 = P.cg(f, tol=0.0, maxit=50)
+    x1, it1, h1 = P.pcg(f, np.ones(P.nl), tol=0.0, maxit=50)
+    assert it1 == it0 and np.array_equal(x1, x0) and np.array_equal(h1, h0)
+
+
+def test_pcg_power_of_two_scalar_preconditioner_is_cg_bit_for_bit():
+    """m = 4: z = r/4, rtz = rtr/4, p and w scale by 1/4, pap by 1/16 and alpha
+    by 4, all exactly in binary arithmetic, so x and the residuals equal CG's.
+    A loop that mixes up r and z, or alpha's numerator, fails this."""
+    nel, N = (2, 2, 2), 4
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=24)
+    P = oracle.Problem(N, nel, vtx)
+    f = synth.uniform_load(P.nl, 25)
+    x0, it0, h0 = P.cg(f, tol=0.0, maxit=40)
+    x1, it1, h1 = P.pcg(f, np.full(P.nl, 4.0), tol=0.0, maxit=40)
+    assert it1 == it0 and np.array_equal(x1, x0) and np.array_equal(h1, h0)
+
+
+def test_pcg_matches_dense_solve_and_saves_iterations():
+    N, nel = 4, (2, 2, 2)
+    vtx = synth.box_vertices(nel, hi=(1.0, 1.0, 1.0), perturb=0.1, seed=12)
+    P = oracle.Problem(N, nel, vtx)
+    f = synth.uniform_load(P.nl, 13)
+    xd, nfree = _dense_reference(N, nel, vtx, f)
+    x, it, hist = P.pcg(f, P.diag(), tol=1e-14, maxit=2000)
+    assert np.abs(x - xd).max() <= 1e-12 * np.abs(xd).max()
+    assert it <= nfree and P.true_residual(x, f) < 1e-13
+    # Jacobi scaling helps on the spectral-element operator (GLL weights vary
+    # strongly across an element)
+    nel, N = (4, 4, 4), 7
+    vtx = synth.box_vertices(nel)
+    P = oracle.Problem(N, nel, vtx)
+    f = synth.uniform_load(P.nl, synth.SEED_C1)
+    _, it_cg, _ = P.cg(f, tol=1e-8, maxit=2000)
+    xp, it_pcg, _ = P.pcg(f, P.diag(), tol=1e-8, maxit=2000)
+    assert it_pcg < 0.92 * it_cg
+    assert P.true_residual(xp, f) <= 1e-8
