@@ -88,7 +88,16 @@ typedef struct {
                                 1 = restart CG after each true-residual update;
                                 2 = reliable update: replace r by the FP64 true
                                     residual and continue the search direction   */
+    int precond;             /* solveM of Table 1: NEK_PC_NONE (z = r) or NEK_PC_JACOBI */
 } nek_opts;
+
+/* Preconditioner of the CG loop (the solveM step of the paper's Table 1). */
+typedef enum {
+    NEK_PC_NONE = 0,         /* z = r: the unpreconditioned loop                        */
+    NEK_PC_JACOBI = 1        /* z = r / m, m = diagonal of the assembled masked operator
+                                (FP64 in FP64 solves, its FP32 rounding in the inner
+                                solves of mixed ones); 1 on Dirichlet nodes             */
+} nek_pc;
 
 typedef struct {
     int iters;               /* CG iterations (mixed: sum of inner iterations)   */
@@ -114,7 +123,10 @@ typedef enum {
     NEK_GET_PERM = 8,        /* int32 perm[n_perm]                               */
     NEK_GET_SEGPTR = 9,      /* int32 seg_ptr[n_seg+1]                           */
     NEK_GET_SEGFLAG = 10,    /* int8 seg_flag[n_seg], 1 = masked segment         */
-    NEK_GET_XYZ = 11         /* double X[E][3][(N+1)^3] node coordinates         */
+    NEK_GET_XYZ = 11,        /* double X[E][3][(N+1)^3] node coordinates         */
+    NEK_GET_DIAG = 12        /* double m[n_local]: diagonal of the assembled masked
+                                operator, 1 on Dirichlet nodes (the Jacobi
+                                preconditioner; built on first use)              */
 } nek_get_what;
 
 /* nek_size selectors. */
@@ -151,6 +163,18 @@ int nek_get(nek_ctx *ctx, int what, void *host_out);
 int nek_set_prec(nek_ctx *ctx, int prec);
 
 /*
+ * nek_set_precond -- preconditioner (nek_pc) of later nek_cg_solve calls.
+ * NEK_PC_JACOBI builds the diagonal on first use (host FP64, from the
+ * geometric factors; then an FP32 copy).  Solves follow Table 1 with solveM
+ * z = r / m; the stopping test and the reported residuals stay those of r.
+ * The work vector of the loop then holds z, updated as z -= alpha S / m, and
+ * the gather/update kernel reduces both r.z and r.r (r = m z).  Batches
+ * (nek_batch_*) run unpreconditioned and refuse members with a
+ * preconditioner (NEK_E_ARG).
+ */
+int nek_set_precond(nek_ctx *ctx, int precond);
+
+/*
  * nek_ax_local -- w = A_L u, the unassembled element operator ax_e of the
  * paper's Fig. 2 for every element (local_grad3, g1..g6, local_grad3_t).
  * dtype NEK_F64 uses FP64 g; NEK_F32 uses the context's FP32 or BF16 g.
@@ -185,8 +209,9 @@ int nek_dssum(nek_ctx *ctx, void *w, int dtype, int apply_mask);
 int nek_glsc3(nek_ctx *ctx, const void *a, const void *b, int dtype, double *out);
 
 /*
- * nek_cg_solve -- solve A x = b, b = M o dssum(f), by unpreconditioned CG in
- * the order of the paper's Table 1, in the context's precision:
+ * nek_cg_solve -- solve A x = b, b = M o dssum(f), by CG in the order of the
+ * paper's Table 1 (unpreconditioned, or with the diagonal preconditioner set
+ * by opts->precond / nek_set_precond), in the context's precision:
  *  - NEK_PREC_FP64: FP64 CG; stops when the recursive relative residual
  *    sqrt(glsc3(r,r)/glsc3(b,b)) <= tol; tol <= 0 runs exactly maxit
  *    iterations.

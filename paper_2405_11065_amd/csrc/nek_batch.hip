@@ -385,6 +385,7 @@ int nek_batch_setup(int n, const nek_mesh *meshes, const int *N, const nek_opts 
                     nek_batch **out)
 {
     if (n < 1 || n > 4096 || !meshes || !N || !out) return NEK_E_ARG;
+    if (opts && opts->precond != NEK_PC_NONE) return NEK_E_ARG;   // batches run unpreconditioned
     *out = nullptr;
     nek_batch *b = new (std::nothrow) nek_batch;
     if (!b) return NEK_E_OOM;
@@ -541,7 +542,7 @@ int nek_batch_solve(nek_batch *b, const double *const *f, const double *const *x
     const int n = nprob(b);
     const int prec = b->ctx[0]->prec;
     for (int m = 0; m < n; ++m)
-        if (!f[m] || !x[m] || b->ctx[m]->prec != prec) return NEK_E_ARG;
+        if (!f[m] || !x[m] || b->ctx[m]->prec != prec || b->ctx[m]->precond) return NEK_E_ARG;
     const bool graph = !(flags & NEK_BATCH_NO_GRAPH);
     // the solve follows the caller's earlier work on its stream
     HIP_TRY(hipEventRecord(b->entry, b->user));

@@ -112,7 +112,10 @@ struct nek_ctx {
     int32_t *perm = nullptr, *segptr = nullptr;
     int8_t *segflag = nullptr;
     nek::Scal *sc = nullptr;
-    double *partials = nullptr;   // 5 regions of MAXB doubles
+    double *partials = nullptr;   // 7 regions of MAXB doubles
+    int precond = 0;              // 1: diagonal (Jacobi) preconditioner in the CG loop
+    double *dg64 = nullptr;       // assembled diagonal, 1 on Dirichlet nodes
+    float *dg32 = nullptr;        // its FP32 rounding (mixed inner solves)
     double *hist = nullptr;
     long hist_cap = 0;
     // work vectors
@@ -139,11 +142,13 @@ struct nek_ctx {
     double prof_ms[2] = {0, 0};
     long prof_n[2] = {0, 0};
 
-    // partials: operator pAp and update rtr, each double-buffered by
-    // iteration parity, then one region for standalone reductions
+    // partials: operator pAp and update rtz (rtr without a preconditioner),
+    // each double-buffered by iteration parity, one region for standalone
+    // reductions, then the update's rtr of preconditioned runs
     double *P1(int it) { return partials + (it & 1) * nek::MAXB; }
     double *P2(int it) { return partials + (2 + (it & 1)) * nek::MAXB; }
     double *P3() { return partials + 4 * nek::MAXB; }
+    double *P4(int it) { return partials + (5 + (it & 1)) * nek::MAXB; }
 };
 
 namespace nek {
@@ -194,6 +199,9 @@ struct NpOps {
     int (*glsc3_32)(nek_ctx *, const float *a, const float *b);
     // r = b - M dssum(w), partials of glsc3(r, c, r)
     int (*resid)(nek_ctx *, const double *b, const double *w, double *r);
+    // r -> z = r / m in place, partials of glsc3(r, c, z)
+    int (*pc_start64)(nek_ctx *, double *r, const double *m);
+    int (*pc_start32)(nek_ctx *, float *r, const float *m);
     // r32 = (float) r64, d = 0, partials of glsc3(r32, c, r32)
     int (*inner_start)(nek_ctx *, const double *r64, float *r32, float *d);
     // elements per workgroup of a CG variant
@@ -219,7 +227,13 @@ int red_final(nek_ctx *c, int slot);
 int glsc3_to_slot(nek_ctx *c, const void *a, const void *b, int dtype, int slot);
 int gather_launch(nek_ctx *c, const double *in, double *out, bool weighted);
 int start_launch(nek_ctx *c, int rslot, int hist_off, double stop_tol, int maxit, int stop_on_initial,
-                 double rtz_prev = 0.0);
+                 double rtz_prev = 0.0, int rtr_slot = -1);
+// Preconditioned runs: r -> z = r / m in place and red[2] = glsc3(r, c, z)
+// (r64 with the FP64 diagonal, r32 with the FP32 one); no-op without a
+// preconditioner.  Returns the red slot of the run's rtz (2, or 1).
+int pc_start64(nek_ctx *c, double *r, int *rtz_slot);
+int pc_start32(nek_ctx *c, float *r, int *rtz_slot);
+int ensure_diag(nek_ctx *c);
 int cg_prologue(nek_ctx *c, const double *f, const double *x0, double *x, double *r);
 int ax_local_launch(nek_ctx *c, const void *u, void *w, int dtype, int prec);
 int resid_launch(nek_ctx *c, const double *b, const double *w, double *r, int slot);

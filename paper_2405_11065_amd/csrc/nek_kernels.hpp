@@ -36,7 +36,8 @@ constexpr int MAXB = 2048;       // cap on workgroups of any reducing kernel (pa
 
 // CG state entering iteration it, in slot it & 1.
 struct IterState {
-    double rtz;      // glsc3(r, c, r) of the current residual
+    double rtz;      // glsc3(r, c, z) of the current residual, z = M^-1 r (z = r without preconditioner)
+    double rtr;      // glsc3(r, c, r): the stopping test and the residual history
     double beta;
     int iter;        // iterations completed
     int done;
@@ -120,7 +121,8 @@ __device__ __forceinline__ double inv_mult(int m)
 // thread of the block.  The first NT threads (whole waves: lanes past the
 // last full wave do not exist for shuffles) each add the pairs
 // (P[2q], P[2q + 1]) for q = t, t + NT, t + 2 NT, ..., low entry first, with
-// a batch of U pairs per array loaded (16 bytes each) before the first add;
+// a batch of U pairs per array loaded (16 bytes each) before the first add
+// (U bounds the registers the loads in flight take);
 // then a butterfly within each wave and the waves in order, broadcast
 // through LDS.  The order of one array's sum does not depend on NA or U, so
 // every kernel of block size BS that sums the same partials, alone or
@@ -132,7 +134,7 @@ __device__ __forceinline__ void sum_all_n(const double *const *P, const int *n, 
 {
     constexpr int NW = BS >= 64 ? BS / 64 : 1;
     constexpr int NT = BS >= 64 ? NW * 64 : BS;
-    constexpr int U = NT >= 256 ? 4 : 8;
+    constexpr int U = NT >= 256 || NA >= 3 ? 4 : 8;   // at most 16 pairs in flight per thread
     double v[NA];
     int nmax = 0;
 #pragma unroll
@@ -197,10 +199,14 @@ struct Begin {
     bool xupd;
 };
 
-template <int BS>
+// With PC (diagonal preconditioner), P2 holds the partials of glsc3(r, c, z)
+// and P4 those of glsc3(r, c, r); without it P2 holds glsc3(r, c, r) and P4
+// is unused.
+template <int BS, bool PC = false>
 __device__ __forceinline__ Begin cg_begin(Scal *__restrict__ sc, const double *__restrict__ P1prev, int nb1,
                                           const double *__restrict__ P2prev, int nb2, int it,
-                                          double *__restrict__ hist, double *sbuf, bool writer)
+                                          double *__restrict__ hist, double *sbuf, bool writer,
+                                          const double *__restrict__ P4prev = nullptr)
 {
     const IterState prev = sc->st[(it - 1) & 1];
     Begin B{prev, 0.0, false};
@@ -215,19 +221,22 @@ __device__ __forceinline__ Begin cg_begin(Scal *__restrict__ sc, const double *_
                 cur.status = f;
                 cur.done = 1;
             } else {
-                // both sums with their loads in flight together
-                const double *ps[2] = {P1prev, P2prev};
-                const int ns[2] = {nb1, nb2};
-                double sums[2];
-                sum_all_n<BS, 2>(ps, ns, sbuf, sums);
+                // the sums with their loads in flight together
+                constexpr int NS = PC ? 3 : 2;
+                const double *ps[3] = {P1prev, P2prev, P4prev};
+                const int ns[3] = {nb1, nb2, nb2};
+                double sums[3];
+                sum_all_n<BS, NS>(ps, ns, sbuf, sums);
                 B.alpha_prev = prev.rtz / sums[0];
                 B.xupd = true;
-                const double rtr = sums[1];
+                const double rtz = sums[1];
+                const double rtr = PC ? sums[2] : rtz;
                 cur.iter = it - 1;
-                cur.rtz = rtr;
-                cur.beta = rtr / prev.rtz;
+                cur.rtz = rtz;
+                cur.rtr = rtr;
+                cur.beta = rtz / prev.rtz;
                 if (writer && hist) hist[sc->hist_off + it - 1] = sqrt(rtr / sc->hist_den);
-                if (!__builtin_isfinite(rtr)) {
+                if (!__builtin_isfinite(rtr) || !__builtin_isfinite(rtz)) {
                     cur.status = -6;
                     cur.done = 1;
                 } else if (rtr == 0.0 || (sc->stop_tol > 0 && sqrt(rtr) / sqrt(sc->stop_den) <= sc->stop_tol)) {
@@ -335,13 +344,13 @@ template <int NP, int EPW, typename T> constexpr size_t ax_lds_bytes()
 
 // Body of the operator kernel for one problem: workgroup blk of the
 // problem's nblk workgroups.
-template <int NP, int EPW, int PD, typename T, typename GT, bool CG, typename XT>
+template <int NP, int EPW, int PD, typename T, typename GT, bool CG, typename XT, bool PC = false>
 __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict__ p, T *__restrict__ w,
                                         const GT *__restrict__ g, const T *__restrict__ D, XT *__restrict__ x,
                                         Scal *__restrict__ sc, double *__restrict__ P1cur,
                                         const double *__restrict__ P1prev, const double *__restrict__ P2prev,
                                         int nb2, int it, double *__restrict__ hist, int E, int ngroups,
-                                        unsigned blk, unsigned nblk)
+                                        unsigned blk, unsigned nblk, const double *__restrict__ P4prev = nullptr)
 {
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP, BS = EPW * NP2;
     using GL = GLoad<GT>;
@@ -385,7 +394,8 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
     bool first = false, xupd = false;
     double alpha_prev = 0.0;
     if constexpr (CG) {
-        const Begin B = cg_begin<BS>(sc, P1prev, (int)nblk, P2prev, nb2, it, hist, sbuf, blk == 0 && tid == 0);
+        const Begin B =
+            cg_begin<BS, PC>(sc, P1prev, (int)nblk, P2prev, nb2, it, hist, sbuf, blk == 0 && tid == 0, P4prev);
         xupd = B.xupd;
         alpha_prev = B.alpha_prev;
         if (B.cur.done) {
@@ -543,17 +553,18 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
     }
 }
 
-template <int NP, int EPW, int PD, typename T, typename GT, bool CG, typename XT>
+template <int NP, int EPW, int PD, typename T, typename GT, bool CG, typename XT, bool PC = false>
 __global__ __launch_bounds__(EPW *NP *NP) void k_ax(const T *__restrict__ src, T *__restrict__ p,
                                                     T *__restrict__ w, const GT *__restrict__ g,
                                                     const T *__restrict__ D, XT *__restrict__ x,
                                                     Scal *__restrict__ sc, double *__restrict__ P1cur,
                                                     const double *__restrict__ P1prev,
                                                     const double *__restrict__ P2prev, int nb2, int it,
-                                                    double *__restrict__ hist, int E, int ngroups)
+                                                    double *__restrict__ hist, int E, int ngroups,
+                                                    const double *__restrict__ P4prev)
 {
-    ax_body<NP, EPW, PD, T, GT, CG, XT>(src, p, w, g, D, x, sc, P1cur, P1prev, P2prev, nb2, it, hist, E, ngroups,
-                                        blockIdx.x, gridDim.x);
+    ax_body<NP, EPW, PD, T, GT, CG, XT, PC>(src, p, w, g, D, x, sc, P1cur, P1prev, P2prev, nb2, it, hist, E,
+                                            ngroups, blockIdx.x, gridDim.x, P4prev);
 }
 
 // ----------------------------------------------------------- gather-scatter
@@ -716,15 +727,18 @@ __device__ __forceinline__ void load_copies(const T *__restrict__ we, int oz, bo
 
 // One column (e, i, j) of the update kernel: its residual and every copy of
 // its nodes, loaded together.
-template <int NP, typename T> struct UpdCol {
+// With PC the column also holds the preconditioner diagonal m of its nodes.
+template <int NP, typename T, bool PC = false> struct UpdCol {
     int e, ez;
     bool valid, hx, hy, hzm, hzp;
     T rv[NP], wo[NP], wx[NP], wy[NP], wxy[NP], zm[4], zp[4];
+    T dv[PC ? NP : 1];
 };
 
-template <int NP, int EPW, typename T>
-__device__ __forceinline__ void upd_load(UpdCol<NP, T> &c, const T *__restrict__ r, const T *__restrict__ w, int grp,
-                                         int el, int i, int j, int ij, Box box, int E)
+template <int NP, int EPW, typename T, bool PC>
+__device__ __forceinline__ void upd_load(UpdCol<NP, T, PC> &c, const T *__restrict__ r, const T *__restrict__ w,
+                                         const T *__restrict__ dg, int grp, int el, int i, int j, int ij, Box box,
+                                         int E)
 {
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = NP - 1;
     c.e = grp * EPW + el;
@@ -748,15 +762,21 @@ __device__ __forceinline__ void upd_load(UpdCol<NP, T> &c, const T *__restrict__
     const int oz = box.nx * box.ny;   // local indices fit in 32 bits (checked at set-up)
 #pragma unroll
     for (int k = 0; k < NP; ++k) c.rv[k] = r[c.e * NP3 + k * NP2 + ij];
+    if constexpr (PC) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) c.dv[k] = dg[c.e * NP3 + k * NP2 + ij];
+    }
     load_copies<NP>(w + c.e * NP3, oz, c.hx, c.hy, c.hzm, c.hzp, ij, ox * NP3 + colX, oy * NP3 + colY,
                     (ox + oy) * NP3 + colXY, c.wo, c.wx, c.wy, c.wxy, c.zm, c.zp);
 }
 
 // Gathered sum S of every node of the column (fixed pairwise order, see
 // upd_body), r -= alpha S, and the column's part of sum c r^2.
-template <int NP, typename T>
-__device__ __forceinline__ void upd_apply(const UpdCol<NP, T> &c, T *__restrict__ r, double alpha, int ij, Box box,
-                                          double &part)
+// With PC the vector is z = r / m instead of r: z -= alpha S / m, and the
+// parts of sum c r z (into part) and sum c r^2 (into part2), r = m z.
+template <int NP, typename T, bool PC>
+__device__ __forceinline__ void upd_apply(const UpdCol<NP, T, PC> &c, T *__restrict__ r, double alpha, int ij,
+                                          Box box, double &part, double &part2)
 {
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = NP - 1;
     auto plane = [](double o, double X, double Y, double XY) -> double { return (o + X) + (Y + XY); };
@@ -774,9 +794,23 @@ __device__ __forceinline__ void upd_apply(const UpdCol<NP, T> &c, T *__restrict_
             S = S + plane((double)c.zp[0], (double)c.zp[1], (double)c.zp[2], (double)c.zp[3]);
             m *= 2;
         }
-        const T rn = (T)((double)c.rv[k] - alpha * S);
-        r[c.e * NP3 + k * NP2 + ij] = rn;
-        part += ((double)rn * (double)rn) * inv_mult(m);
+        if constexpr (PC) {
+            const double d = (double)c.dv[k];
+            // FP32 vectors: the quotient in FP32 (the FP64 division sequence
+            // would cost a wave of occupancy); identical on every copy
+            double q;
+            if constexpr (sizeof(T) == 4) q = (double)((float)S / c.dv[k]);
+            else q = S / d;
+            const T zn = (T)((double)c.rv[k] - alpha * q);
+            r[c.e * NP3 + k * NP2 + ij] = zn;
+            const double rn = d * (double)zn;
+            part += (rn * (double)zn) * inv_mult(m);
+            part2 += (rn * rn) * inv_mult(m);
+        } else {
+            const T rn = (T)((double)c.rv[k] - alpha * S);
+            r[c.e * NP3 + k * NP2 + ij] = rn;
+            part += ((double)rn * (double)rn) * inv_mult(m);
+        }
     }
 }
 
@@ -787,10 +821,14 @@ __device__ __forceinline__ void upd_apply(const UpdCol<NP, T> &c, T *__restrict_
 // first; the planes below and above are then added in turn.  IEEE addition
 // is commutative, so every copy of a node computes the bit-identical value
 // and r stays exactly continuous.
-template <int NP, int EPW, typename T>
+// With PC (diagonal preconditioner dg, 1 on Dirichlet nodes) r holds z =
+// r / m and the kernel writes the partials of glsc3(r, c, z) to P2cur and
+// of glsc3(r, c, r) to P4cur.
+template <int NP, int EPW, typename T, bool PC = false>
 __device__ __forceinline__ void upd_body(T *__restrict__ r, const T *__restrict__ w, Scal *__restrict__ sc,
                                          const double *__restrict__ P1cur, int nb1, double *__restrict__ P2cur,
-                                         int it, Box box, int E, int ngroups, unsigned blk, unsigned nblk)
+                                         int it, Box box, int E, int ngroups, unsigned blk, unsigned nblk,
+                                         const T *__restrict__ dg = nullptr, double *__restrict__ P4cur = nullptr)
 {
     constexpr int NP2 = NP * NP, BS = EPW * NP2;
     __shared__ double sbuf[BS];
@@ -805,9 +843,9 @@ __device__ __forceinline__ void upd_body(T *__restrict__ r, const T *__restrict_
     // FP32 columns are loaded before the reduction; FP64 ones after it (held
     // across the reduction they would cost a wave of occupancy per SIMD)
     constexpr bool early = sizeof(T) == 4;
-    UpdCol<NP, T> c;
+    UpdCol<NP, T, PC> c;
     c.valid = false;
-    if (early && g0 < g1) upd_load<NP, EPW, T>(c, r, w, g0, el, i, j, ij, box, E);
+    if (early && g0 < g1) upd_load<NP, EPW, T, PC>(c, r, w, dg, g0, el, i, j, ij, box, E);
     const double pap = sum_all<BS>(P1cur, nb1, sbuf);
     const bool writer = blk == 0 && tid == 0;
     if (!__builtin_isfinite(pap) || !(pap > 0)) {
@@ -815,11 +853,11 @@ __device__ __forceinline__ void upd_body(T *__restrict__ r, const T *__restrict_
         return;
     }
     const double alpha = cur.rtz / pap;
-    double part = 0.0;
+    double part = 0.0, part2 = 0.0;
     if constexpr (early) {
         for (int grp = g0; grp < g1; ++grp) {
-            if (grp > g0) upd_load<NP, EPW, T>(c, r, w, grp, el, i, j, ij, box, E);
-            if (c.valid) upd_apply<NP, T>(c, r, alpha, ij, box, part);
+            if (grp > g0) upd_load<NP, EPW, T, PC>(c, r, w, dg, grp, el, i, j, ij, box, E);
+            if (c.valid) upd_apply<NP, T, PC>(c, r, alpha, ij, box, part, part2);
         }
     } else {
         constexpr int NP3 = NP2 * NP, N = NP - 1;
@@ -839,7 +877,7 @@ __device__ __forceinline__ void upd_body(T *__restrict__ r, const T *__restrict_
             const int ox = xneg ? -1 : 1, oy = yneg ? -box.nx : box.nx;
             const int colX = (xneg ? N : 0) + NP * j, colY = i + NP * (yneg ? N : 0);
             const int colXY = (xneg ? N : 0) + NP * (yneg ? N : 0);
-            UpdCol<NP, T> cg;
+            UpdCol<NP, T, PC> cg;
             cg.e = e;
             cg.ez = ez;
             cg.hx = hx;
@@ -848,13 +886,21 @@ __device__ __forceinline__ void upd_body(T *__restrict__ r, const T *__restrict_
             cg.hzp = ez < box.nz - 1;
 #pragma unroll
             for (int k = 0; k < NP; ++k) cg.rv[k] = r[e * NP3 + k * NP2 + ij];
+            if constexpr (PC) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) cg.dv[k] = dg[e * NP3 + k * NP2 + ij];
+            }
             load_copies<NP>(w + e * NP3, oz, hx, hy, cg.hzm, cg.hzp, ij, ox * NP3 + colX, oy * NP3 + colY,
                             (ox + oy) * NP3 + colXY, cg.wo, cg.wx, cg.wy, cg.wxy, cg.zm, cg.zp);
-            upd_apply<NP, T>(cg, r, alpha, ij, box, part);
+            upd_apply<NP, T, PC>(cg, r, alpha, ij, box, part, part2);
         }
     }
     const double s = block_sum<BS>(part, sbuf);
     if (tid == 0) P2cur[blk] = s;
+    if constexpr (PC) {
+        const double s2 = block_sum<BS>(part2, sbuf);
+        if (tid == 0) P4cur[blk] = s2;
+    }
     if (writer) sc->k2flag[it & 1] = 0;
 }
 
@@ -909,13 +955,14 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_assemble(const T *__restrict__ 
     }
 }
 
-template <int NP, int EPW, typename T>
+template <int NP, int EPW, typename T, bool PC = false>
 __global__ __launch_bounds__(EPW *NP *NP) void k_cg_update(T *__restrict__ r, const T *__restrict__ w,
                                                            Scal *__restrict__ sc, const double *__restrict__ P1cur,
                                                            int nb1, double *__restrict__ P2cur, int it, Box box,
-                                                           int E, int ngroups)
+                                                           int E, int ngroups, const T *__restrict__ dg,
+                                                           double *__restrict__ P4cur)
 {
-    upd_body<NP, EPW, T>(r, w, sc, P1cur, nb1, P2cur, it, box, E, ngroups, blockIdx.x, gridDim.x);
+    upd_body<NP, EPW, T, PC>(r, w, sc, P1cur, nb1, P2cur, it, box, E, ngroups, blockIdx.x, gridDim.x, dg, P4cur);
 }
 
 // ------------------------------------------------------------- batched CG
@@ -1044,6 +1091,29 @@ __global__ __launch_bounds__(UPD_BS) void k_inner_start(const double *__restrict
         r32[t] = v;
         d[t] = 0.0f;
         part += ((double)v * (double)v) * inv_mult(Pt.mult);
+    }
+    const double s = block_sum<UPD_BS>(part, sbuf);
+    if (threadIdx.x == 0) P[blockIdx.x] = s;
+}
+
+// Start of a preconditioned run: r -> z = r / m in place (m the diagonal,
+// 1 on Dirichlet nodes), each quotient formed in FP64 and rounded once, and
+// partials of glsc3(r, c, z).
+template <int NP, typename T>
+__global__ __launch_bounds__(UPD_BS) void k_pc_start(T *__restrict__ r, const T *__restrict__ dg,
+                                                     double *__restrict__ P, Box box, unsigned nl)
+{
+    __shared__ double sbuf[UPD_BS];
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned t0 = (unsigned)(((unsigned long)lb * nl) / gridDim.x);
+    const unsigned t1 = (unsigned)(((unsigned long)(lb + 1) * nl) / gridDim.x);
+    double part = 0.0;
+    for (unsigned t = t0 + threadIdx.x; t < t1; t += UPD_BS) {
+        const PointInfo<NP> Pt = locate<NP>(t, box);
+        const double rv = (double)r[t];
+        const T z = (T)(rv / (double)dg[t]);
+        r[t] = z;
+        part += (rv * (double)z) * inv_mult(Pt.mult);
     }
     const double s = block_sum<UPD_BS>(part, sbuf);
     if (threadIdx.x == 0) P[blockIdx.x] = s;

@@ -7,33 +7,36 @@
 
 namespace nek {
 
-// Start of a CG run: rtz = red[rslot]; stop and history denominators; the
-// initial residual test.
+// Start of a CG run: rtz = red[rslot] (glsc3(r, c, z); for an
+// unpreconditioned run z = r), rtr = red[rtr_slot] (glsc3(r, c, r)); stop
+// and history denominators; the initial residual test on rtr.
 // A resumed run (rtz_prev > 0) keeps the search direction: its first
-// p = r + beta p with beta = rtz / rtz_prev (reliable update).
-__global__ void k_cg_start(Scal *sc, double *hist, int rslot, int hist_off, double stop_tol, int maxit,
+// p = z + beta p with beta = rtz / rtz_prev (reliable update).
+__global__ void k_cg_start(Scal *sc, double *hist, int rslot, int rtr_slot, int hist_off, double stop_tol, int maxit,
                            int stop_on_initial, double rtz_prev)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double bb = sc->red[0];
     const double rtz = sc->red[rslot];
+    const double rtr = sc->red[rtr_slot];
     IterState s{};
     s.rtz = rtz;
+    s.rtr = rtr;
     s.beta = rtz_prev > 0 ? rtz / rtz_prev : 0.0;
     s.iter = 0;
     sc->resume = rtz_prev > 0 ? 1 : 0;
     sc->hist_den = bb;
-    sc->stop_den = stop_on_initial ? rtz : bb;
+    sc->stop_den = stop_on_initial ? rtr : bb;
     sc->stop_tol = stop_tol;
     sc->maxit = maxit;
     sc->hist_off = hist_off;
     sc->k2flag[0] = sc->k2flag[1] = 0;
-    if (hist) hist[hist_off] = bb > 0 ? sqrt(rtz / bb) : 0.0;
-    if (!__builtin_isfinite(bb) || !__builtin_isfinite(rtz)) {
+    if (hist) hist[hist_off] = bb > 0 ? sqrt(rtr / bb) : 0.0;
+    if (!__builtin_isfinite(bb) || !__builtin_isfinite(rtz) || !__builtin_isfinite(rtr)) {
         s.status = -6;
         s.done = 1;
-    } else if (bb == 0.0 || rtz == 0.0 ||
-               (!stop_on_initial && stop_tol > 0 && sqrt(rtz) / sqrt(sc->stop_den) <= stop_tol)) {
+    } else if (bb == 0.0 || rtr == 0.0 || rtz == 0.0 ||
+               (!stop_on_initial && stop_tol > 0 && sqrt(rtr) / sqrt(sc->stop_den) <= stop_tol)) {
         s.conv = 1;
         s.done = 1;
     } else if (maxit <= 0) {

@@ -202,6 +202,43 @@ int resid_launch(nek_ctx *c, const double *b, const double *w, double *r, int sl
     return rc ? rc : red_final(c, slot);
 }
 
+int ensure_diag(nek_ctx *c)
+{
+    if (c->dg64 && c->dg32) return NEK_OK;
+    const long n3 = (long)c->NP * c->NP * c->NP;
+    std::vector<double> hg((size_t)c->E * 6 * n3), hB((size_t)c->nl), m((size_t)c->nl);
+    if (geometry(c->N, c->nel, c->vtx, c->xi, c->w, c->D, hg.data(), hB.data(), nullptr)) return NEK_E_JACOBIAN;
+    assembled_diagonal(c->N, c->nel, c->D, hg.data(), m.data());
+    std::vector<float> m32(m.begin(), m.end());   // round to nearest even
+    if (dalloc(c->dg64, c->nl) || dalloc(c->dg32, c->nl)) return NEK_E_OOM;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(c->dg64, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->dg32, m32.data(), m32.size() * sizeof(float), hipMemcpyHostToDevice));
+    return NEK_OK;
+}
+
+int pc_start64(nek_ctx *c, double *r, int *rtz_slot)
+{
+    *rtz_slot = 1;
+    if (!c->precond) return NEK_OK;
+    if (!c->dg64) return NEK_E_ARG;
+    const int rc = ops(c)->pc_start64(c, r, c->dg64);
+    if (rc) return rc;
+    *rtz_slot = 2;
+    return red_final(c, 2);
+}
+
+int pc_start32(nek_ctx *c, float *r, int *rtz_slot)
+{
+    *rtz_slot = 1;
+    if (!c->precond) return NEK_OK;
+    if (!c->dg32) return NEK_E_ARG;
+    const int rc = ops(c)->pc_start32(c, r, c->dg32);
+    if (rc) return rc;
+    *rtz_slot = 2;
+    return red_final(c, 2);
+}
+
 // one CG iteration of the context at precision prec on its work vectors;
 // x is FP64 at FP64, else FP32 (the correction of an inner solve)
 int cg_iter(nek_ctx *c, int prec, int variant, int it, bool final, void *x)
@@ -214,10 +251,10 @@ int cg_iter(nek_ctx *c, int prec, int variant, int it, bool final, void *x)
 }
 
 int start_launch(nek_ctx *c, int rslot, int hist_off, double stop_tol, int maxit, int stop_on_initial,
-                 double rtz_prev)
+                 double rtz_prev, int rtr_slot)
 {
-    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(64), 0, c->stream, c->sc, c->hist, rslot, hist_off, stop_tol, maxit,
-                       stop_on_initial, rtz_prev);
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(64), 0, c->stream, c->sc, c->hist, rslot,
+                       rtr_slot < 0 ? rslot : rtr_slot, hist_off, stop_tol, maxit, stop_on_initial, rtz_prev);
     HIP_TRY(hipGetLastError());
     return NEK_OK;
 }
@@ -303,12 +340,14 @@ int solve_fp64(nek_ctx *c, const double *f, const double *x0, double tol, int ma
     int rc = ensure_fp64_work(c);
     if (rc) return rc;
     if ((rc = cg_prologue(c, f, x0, x, c->r64))) return rc;
-    if ((rc = start_launch(c, 1, 0, tol, maxit, 0))) return rc;
+    int rs = 1;
+    if ((rc = pc_start64(c, c->r64, &rs))) return rc;
+    if ((rc = start_launch(c, rs, 0, tol, maxit, 0, 0.0, 1))) return rc;
     if ((rc = cg_fp64_iterations(c, x, maxit))) return rc;
     Scal h;
     if ((rc = read_scal(c, h))) return rc;
     st->iters = h.fin.iter;
-    st->rel_res = h.hist_den > 0 ? std::sqrt(h.fin.rtz / h.hist_den) : 0.0;
+    st->rel_res = h.hist_den > 0 ? std::sqrt(h.fin.rtr / h.hist_den) : 0.0;
     return finish_status(h.fin, tol);
 }
 
@@ -376,7 +415,9 @@ int ir_fallback(nek_ctx *c, IrCtl &s, double tol, int maxit, double *x)
 {
     int rc;
     Scal h;
-    if ((rc = start_launch(c, 1, s.total, tol, maxit - s.total, 0))) return rc;
+    int rs = 1;
+    if ((rc = pc_start64(c, c->r64, &rs))) return rc;
+    if ((rc = start_launch(c, rs, s.total, tol, maxit - s.total, 0, 0.0, 1))) return rc;
     if ((rc = cg_fp64_iterations(c, x, maxit - s.total))) return rc;
     if ((rc = read_scal(c, h))) return rc;
     s.fp64_iters = h.fin.iter;
@@ -397,9 +438,11 @@ int ir_inner_launch(nek_ctx *c, IrCtl &s, double tol, int maxit, int *cap)
     int rc;
     if ((rc = ops(c)->inner_start(c, c->r64, c->r32, c->d32))) return rc;
     if ((rc = red_final(c, 1))) return rc;
+    int rs = 1;
+    if ((rc = pc_start32(c, c->r32, &rs))) return rc;
     const double tau_k = std::min(0.5, std::max(s.tau, 0.3 * tol / s.rho));
     *cap = std::min(s.inner_cap, maxit - s.total);
-    return start_launch(c, 1, s.total, tau_k, *cap, 1, s.keep_p ? s.rtz_last : 0.0);
+    return start_launch(c, rs, s.total, tau_k, *cap, 1, s.keep_p ? s.rtz_last : 0.0, 1);
 }
 
 // After an inner run (h read back): count it, then enqueue x += d and the
@@ -515,7 +558,7 @@ void nek_free(nek_ctx *c)
     dfree(c->D64); dfree(c->D32); dfree(c->g64); dfree(c->g32); dfree(c->g16); dfree(c->B);
     dfree(c->perm); dfree(c->segptr); dfree(c->segflag); dfree(c->sc); dfree(c->partials); dfree(c->hist);
     dfree(c->b); dfree(c->r64); dfree(c->p64); dfree(c->w64); dfree(c->d64); dfree(c->d32);
-    dfree(c->r32); dfree(c->p32); dfree(c->w32);
+    dfree(c->r32); dfree(c->p32); dfree(c->w32); dfree(c->dg64); dfree(c->dg32);
     dfree(c->xyz); dfree(c->gfeat); dfree(c->x0_X); dfree(c->x0_Y); dfree(c->x0_s);
     if (c->hflags) (void)hipHostFree(c->hflags);
     for (auto &e : c->ev)
@@ -533,7 +576,8 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
     const long NP = N + 1, n3 = NP * NP * NP;
     const long E = (long)mesh->nel[0] * mesh->nel[1] * mesh->nel[2];
     if (E * n3 >= (1L << 31)) return NEK_E_ARG;
-    if (opts && (opts->prec < NEK_PREC_FP64 || opts->prec > NEK_PREC_BF16G || opts->elts_per_wg != 0))
+    if (opts && (opts->prec < NEK_PREC_FP64 || opts->prec > NEK_PREC_BF16G || opts->elts_per_wg != 0 ||
+                 opts->precond < NEK_PC_NONE || opts->precond > NEK_PC_JACOBI))
         return NEK_E_ARG;
     nek_ctx *c = new (std::nothrow) nek_ctx;
     if (!c) return NEK_E_OOM;
@@ -573,7 +617,7 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
 
     if (dalloc(c->D64, NP * NP) || dalloc(c->D32, NP * NP) || dalloc(c->g64, hg.size()) || dalloc(c->B, hB.size()) ||
         dalloc(c->perm, perm.size()) || dalloc(c->segptr, segptr.size()) || dalloc(c->segflag, segflag.size()) ||
-        dalloc(c->sc, 1) || dalloc(c->partials, 5 * MAXB))
+        dalloc(c->sc, 1) || dalloc(c->partials, 7 * MAXB))
         return fail(NEK_E_OOM);
     if (hipHostMalloc((void **)&c->hflags, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(NEK_E_OOM);
     c->hflags[0] = c->hflags[1] = 0;
@@ -591,9 +635,13 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
         hipMemcpy(c->segflag, segflag.data(), segflag.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->sc, 0, sizeof(Scal)) != hipSuccess ||
         hipMemcpy(&c->sc->host_done, &hflag_dev, sizeof(int *), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(c->partials, 0, 5 * MAXB * sizeof(double)) != hipSuccess)
+        hipMemset(c->partials, 0, 7 * MAXB * sizeof(double)) != hipSuccess)
         return fail(NEK_E_HIP);
     if ((rc = ensure_g(c, c->prec))) return fail(rc);
+    if (c->opts.precond == NEK_PC_JACOBI) {
+        if ((rc = ensure_diag(c))) return fail(rc);
+        c->precond = 1;
+    }
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(NEK_E_HIP);
     *out = c;
     return NEK_OK;
@@ -639,6 +687,10 @@ int nek_get(nek_ctx *c, int what, void *o)
     case NEK_GET_PERM: return d2h(o, c->perm, (size_t)c->nperm * sizeof(int32_t));
     case NEK_GET_SEGPTR: return d2h(o, c->segptr, (size_t)(c->nseg + 1) * sizeof(int32_t));
     case NEK_GET_SEGFLAG: return d2h(o, c->segflag, (size_t)c->nseg);
+    case NEK_GET_DIAG: {
+        const int rc = ensure_diag(c);
+        return rc ? rc : d2h(o, c->dg64, (size_t)c->nl * sizeof(double));
+    }
     case NEK_GET_XYZ: {
         std::vector<double> g((size_t)c->E * 6 * n3), B((size_t)c->nl);
         return geometry(c->N, c->nel, c->vtx, c->xi, c->w, c->D, g.data(), B.data(), (double *)o) ? NEK_E_JACOBIAN
@@ -654,6 +706,18 @@ int nek_set_prec(nek_ctx *c, int prec)
     int rc = ensure_g(c, prec);
     if (rc) return rc;
     c->prec = prec;
+    return NEK_OK;
+}
+
+int nek_set_precond(nek_ctx *c, int precond)
+{
+    if (!c || precond < NEK_PC_NONE || precond > NEK_PC_JACOBI) return NEK_E_ARG;
+    if (precond == NEK_PC_JACOBI) {
+        const int rc = ensure_diag(c);
+        if (rc) return rc;
+    }
+    c->precond = precond;
+    c->opts.precond = precond;
     return NEK_OK;
 }
 

@@ -6,7 +6,7 @@
 namespace nek {
 
 template <int NP> struct OpsImpl {
-    template <int EPW, int PD, typename T, typename GT, bool CG, typename XT = T>
+    template <int EPW, int PD, typename T, typename GT, bool CG, typename XT = T, bool PC = false>
     static int launch_ax(nek_ctx *c, const T *src, T *p, T *w, const GT *g, const T *D, int it, XT *x = nullptr)
     {
         constexpr int BS = EPW * NP * NP;
@@ -14,7 +14,7 @@ template <int NP> struct OpsImpl {
         static bool attr_done = false;
         if (!attr_done) {
             if (shm > 65536)
-                HIP_TRY(hipFuncSetAttribute((const void *)k_ax<NP, EPW, PD, T, GT, CG, XT>,
+                HIP_TRY(hipFuncSetAttribute((const void *)k_ax<NP, EPW, PD, T, GT, CG, XT, PC>,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
             attr_done = true;
         }
@@ -22,9 +22,9 @@ template <int NP> struct OpsImpl {
         // of the next kernel: a capped grid of persistent workgroups; the plain
         // operator reduces nothing and takes one element group per workgroup
         const unsigned grid = CG ? ax_grid(c, EPW) : (unsigned)ax_groups(c, EPW);
-        hipLaunchKernelGGL((k_ax<NP, EPW, PD, T, GT, CG, XT>), dim3(grid), dim3(BS), shm, c->stream, src, p, w, g, D,
-                           x, c->sc, c->P1(it), c->P1(it - 1), c->P2(it - 1), (int)grid, it, c->hist, (int)c->E,
-                           ax_groups(c, EPW));
+        hipLaunchKernelGGL((k_ax<NP, EPW, PD, T, GT, CG, XT, PC>), dim3(grid), dim3(BS), shm, c->stream, src, p, w, g,
+                           D, x, c->sc, c->P1(it), c->P1(it - 1), c->P2(it - 1), (int)grid, it, c->hist, (int)c->E,
+                           ax_groups(c, EPW), c->P4(it - 1));
         HIP_TRY(hipGetLastError());
         return NEK_OK;
     }
@@ -34,28 +34,45 @@ template <int NP> struct OpsImpl {
     // the operator kernel runs: it applies the last x update and publishes
     // the final state.  Sampled timing brackets every prof_every-th
     // iteration with events.
-    template <typename T, typename GT>
-    static int cg_iter(nek_ctx *c, int variant, int it, bool final, T *x, T *r, T *p, T *w, const GT *g,
-                       const T *D)
+    template <typename T, typename GT, bool PC>
+    static int cg_iter_pc(nek_ctx *c, int variant, int it, bool final, T *x, T *r, T *p, T *w, const GT *g,
+                          const T *D, const T *dg)
     {
         return with_variant<NP, GT>(variant, [&](auto epw_c, auto pd_c) -> int {
             constexpr int EPW = decltype(epw_c)::value, PD = decltype(pd_c)::value;
-            if (final) return launch_ax<EPW, PD, T, GT, true, T>(c, r, p, w, g, D, it, x);
+            if (final) return launch_ax<EPW, PD, T, GT, true, T, PC>(c, r, p, w, g, D, it, x);
             int slot = -1;
             if (c->prof_every > 0 && (c->prof_tick++ % c->prof_every) == 0) {
                 if ((slot = prof_take(c)) < 0) return NEK_E_HIP;
                 HIP_TRY(hipEventRecord(c->prof_pool[3 * slot], c->stream));
             }
-            int rc = launch_ax<EPW, PD, T, GT, true, T>(c, r, p, w, g, D, it, x);
+            int rc = launch_ax<EPW, PD, T, GT, true, T, PC>(c, r, p, w, g, D, it, x);
             if (rc) return rc;
             if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 1], c->stream));
             const unsigned grid = ax_grid(c, EPW);
-            hipLaunchKernelGGL((k_cg_update<NP, EPW, T>), dim3(grid), dim3(EPW * NP * NP), 0, c->stream, r, w, c->sc,
-                               c->P1(it), (int)grid, c->P2(it), it, c->box, (int)c->E, ax_groups(c, EPW));
+            hipLaunchKernelGGL((k_cg_update<NP, EPW, T, PC>), dim3(grid), dim3(EPW * NP * NP), 0, c->stream, r, w,
+                               c->sc, c->P1(it), (int)grid, c->P2(it), it, c->box, (int)c->E, ax_groups(c, EPW), dg,
+                               c->P4(it));
             HIP_TRY(hipGetLastError());
             if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 2], c->stream));
             return NEK_OK;
         });
+    }
+
+    // With the diagonal preconditioner on, r holds z = M^-1 r and the update
+    // kernel reads the diagonal of the vectors' precision.
+    template <typename T, typename GT>
+    static int cg_iter(nek_ctx *c, int variant, int it, bool final, T *x, T *r, T *p, T *w, const GT *g,
+                       const T *D)
+    {
+        if (c->precond) {
+            const T *dg;
+            if constexpr (sizeof(T) == 8) dg = c->dg64;
+            else dg = c->dg32;
+            if (!dg) return NEK_E_ARG;
+            return cg_iter_pc<T, GT, true>(c, variant, it, final, x, r, p, w, g, D, dg);
+        }
+        return cg_iter_pc<T, GT, false>(c, variant, it, final, x, r, p, w, g, D, nullptr);
     }
 
     static int cg_iter64(nek_ctx *c, int v, int it, bool final, double *x, double *r, double *p, double *w,
@@ -151,6 +168,16 @@ template <int NP> struct OpsImpl {
         return NEK_OK;
     }
 
+    template <typename T> static int pc_start(nek_ctx *c, T *r, const T *m)
+    {
+        hipLaunchKernelGGL((k_pc_start<NP, T>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, r, m, c->P3(), c->box,
+                           (unsigned)c->nl);
+        HIP_TRY(hipGetLastError());
+        return NEK_OK;
+    }
+    static int pc_start64(nek_ctx *c, double *r, const double *m) { return pc_start<double>(c, r, m); }
+    static int pc_start32(nek_ctx *c, float *r, const float *m) { return pc_start<float>(c, r, m); }
+
     static int inner_start(nek_ctx *c, const double *r64, float *r32, float *d)
     {
         hipLaunchKernelGGL((k_inner_start<NP>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, r64, r32, d, c->P3(),
@@ -206,7 +233,8 @@ template <int NP> const NpOps *make_np_ops()
 {
     using I = OpsImpl<NP>;
     static const NpOps ops{n_variants<NP>(), &I::cg_iter64, &I::cg_iter32, &I::cg_iter16, &I::ax64, &I::ax32,
-                           &I::ax16, &I::axa64, &I::axa32, &I::axa16, &I::gather64, &I::glsc3_64, &I::glsc3_32, &I::resid, &I::inner_start,
+                           &I::ax16, &I::axa64, &I::axa32, &I::axa16, &I::gather64, &I::glsc3_64, &I::glsc3_32, &I::resid, &I::pc_start64, &I::pc_start32,
+                           &I::inner_start,
                            &I::variant_epw, &I::batch_iter};
     return &ops;
 }

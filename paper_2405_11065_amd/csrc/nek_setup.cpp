@@ -273,6 +273,47 @@ void numbering(int N, const int nel[3], int64_t *gid, int32_t *mult, int8_t *mas
     }
 }
 
+// Diagonal of the assembled masked operator M o dssum(A_L), the Jacobi
+// preconditioner of Table 1's solveM step.  Per element node (i,j,k), with
+// A_L = sum_{a,b} D_a^T G_ab D_b: the squared entries of D's columns i, j, k
+// against G_rr, G_ss, G_tt along the node's three lines, plus 2 D_ii D_jj
+// G_rs + 2 D_ii D_kk G_rt + 2 D_jj D_kk G_st at the node (the only place a
+// mixed term survives).  Copies of a node are summed in ascending local
+// index; Dirichlet nodes get 1.  g is [E][6][n^3]; m has E n^3 entries.
+void assembled_diagonal(int N, const int nel[3], const std::vector<double> &D, const double *g, double *m)
+{
+    const long n = N + 1, n2 = n * n, n3 = n2 * n;
+    const long E = (long)nel[0] * nel[1] * nel[2], nl = E * n3;
+    std::vector<double> sq(n * n), dd(n);   // sq[a*n + i] = D[a][i]^2
+    for (long a = 0; a < n; ++a) {
+        dd[a] = D[a * n + a];
+        for (long i = 0; i < n; ++i) sq[a * n + i] = D[a * n + i] * D[a * n + i];
+    }
+    for (long e = 0; e < E; ++e) {
+        const double *grr = g + e * 6 * n3, *gss = grr + n3, *gtt = gss + n3;
+        const double *grs = gtt + n3, *grt = grs + n3, *gst = grt + n3;
+        double *me = m + e * n3;
+        for (long k = 0; k < n; ++k)
+            for (long j = 0; j < n; ++j)
+                for (long i = 0; i < n; ++i) {
+                    const long q = i + n * j + n2 * k;
+                    double v = 0.0;
+                    for (long a = 0; a < n; ++a) v += sq[a * n + i] * grr[a + n * j + n2 * k];
+                    for (long a = 0; a < n; ++a) v += sq[a * n + j] * gss[i + n * a + n2 * k];
+                    for (long a = 0; a < n; ++a) v += sq[a * n + k] * gtt[i + n * j + n2 * a];
+                    v += 2.0 * dd[i] * dd[j] * grs[q] + 2.0 * dd[i] * dd[k] * grt[q] + 2.0 * dd[j] * dd[k] * gst[q];
+                    me[q] = v;
+                }
+    }
+    std::vector<int64_t> gid(nl);
+    std::vector<int8_t> mask(nl);
+    numbering(N, nel, gid.data(), nullptr, mask.data());
+    const long ng = ((long)nel[0] * N + 1) * ((long)nel[1] * N + 1) * ((long)nel[2] * N + 1);
+    std::vector<double> acc(ng, 0.0);
+    for (long l = 0; l < nl; ++l) acc[gid[l]] += m[l];
+    for (long l = 0; l < nl; ++l) m[l] = mask[l] ? acc[gid[l]] : 1.0;
+}
+
 }  // namespace nek
 
 // ------------------------------------------------------------ host C ABI

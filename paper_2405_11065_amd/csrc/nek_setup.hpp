@@ -23,6 +23,10 @@ int geometry(int N, const int nel[3], const std::vector<double> &vtx, const std:
 void segment_maps(int N, const int nel[3], std::vector<int32_t> &perm, std::vector<int32_t> &seg_ptr,
                   std::vector<int8_t> &seg_flag);
 
+// Diagonal of the assembled masked operator (1 on Dirichlet nodes) from
+// g[E][6][n^3]: the Jacobi preconditioner.
+void assembled_diagonal(int N, const int nel[3], const std::vector<double> &D, const double *g, double *m);
+
 // Per-local-node global id, multiplicity and Dirichlet mask (any may be null).
 void numbering(int N, const int nel[3], int64_t *gid, int32_t *mult, int8_t *mask);
 

@@ -21,13 +21,15 @@ NEK_E_BREAKDOWN, NEK_E_NONFINITE, NEK_E_STAGNATION = -5, -6, -7
 NEK_PREC_FP64, NEK_PREC_FP32, NEK_PREC_BF16G = 0, 1, 2
 NEK_F64, NEK_F32 = 0, 1
 (NEK_GET_GLL, NEK_GET_W, NEK_GET_D, NEK_GET_G, NEK_GET_B, NEK_GET_GID, NEK_GET_MULT, NEK_GET_MASK,
- NEK_GET_PERM, NEK_GET_SEGPTR, NEK_GET_SEGFLAG, NEK_GET_XYZ) = range(12)
+ NEK_GET_PERM, NEK_GET_SEGPTR, NEK_GET_SEGFLAG, NEK_GET_XYZ, NEK_GET_DIAG) = range(13)
+NEK_PC_NONE, NEK_PC_JACOBI = 0, 1
+PC_NAMES = {"none": NEK_PC_NONE, "jacobi": NEK_PC_JACOBI}
 (NEK_SIZE_NLOCAL, NEK_SIZE_NGLOBAL, NEK_SIZE_E, NEK_SIZE_NPERM, NEK_SIZE_NSEG, NEK_SIZE_N) = range(6)
 
 PREC_NAMES = {"fp64": NEK_PREC_FP64, "fp32": NEK_PREC_FP32, "bf16g": NEK_PREC_BF16G}
 
 # every entry point declared in include/nek.h
-EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_ax_local", "nek_ax",
+EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_set_precond", "nek_ax_local", "nek_ax",
            "nek_dssum", "nek_glsc3", "nek_cg_solve", "nek_prof_enable", "nek_prof_read", "nek_num_variants",
            "nek_tune", "nek_set_variant", "nek_get_variant", "nek_batch_setup", "nek_batch_free",
            "nek_batch_size", "nek_batch_ctx", "nek_batch_orders", "nek_batch_tune", "nek_batch_set_variant",
@@ -48,7 +50,7 @@ class nek_mesh(ctypes.Structure):
 class nek_opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("fp64_fallback", ctypes.c_int), ("elts_per_wg", ctypes.c_int),
-                ("refine_mode", ctypes.c_int)]
+                ("refine_mode", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 class nek_stats(ctypes.Structure):
@@ -84,6 +86,7 @@ def load(path: str = LIB_PATH):
     lib.nek_size.argtypes = [vp, ctypes.c_int, i64p]
     lib.nek_get.argtypes = [vp, ctypes.c_int, vp]
     lib.nek_set_prec.argtypes = [vp, ctypes.c_int]
+    lib.nek_set_precond.argtypes = [vp, ctypes.c_int]
     lib.nek_ax_local.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_ax.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_dssum.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int]
@@ -170,7 +173,7 @@ def _mesh(nel, vtx=None, lo=(0.0, 0.0, 0.0), hi=None):
     return m, nel, keep
 
 
-def _opts(prec="fp64", inner_tol=0.0, inner_maxit=0, max_outer=0, fp64_fallback=1, refine_mode=0):
+def _opts(prec="fp64", inner_tol=0.0, inner_maxit=0, max_outer=0, fp64_fallback=1, refine_mode=0, precond="none"):
     o = nek_opts()
     o.prec = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
     o.inner_tol = float(inner_tol)
@@ -178,6 +181,7 @@ def _opts(prec="fp64", inner_tol=0.0, inner_maxit=0, max_outer=0, fp64_fallback=
     o.max_outer = int(max_outer)
     o.fp64_fallback = int(fp64_fallback)
     o.refine_mode = int(refine_mode)
+    o.precond = PC_NAMES[precond] if isinstance(precond, str) else int(precond)
     return o
 
 
@@ -185,12 +189,12 @@ class Context:
     """One box mesh of order N on the current GPU (nek_setup / nek_free)."""
 
     def __init__(self, nel, N, vtx=None, lo=(0.0, 0.0, 0.0), hi=None, prec="fp64", inner_tol=0.0,
-                 inner_maxit=0, max_outer=0, fp64_fallback=1, refine_mode=0, stream=None):
+                 inner_maxit=0, max_outer=0, fp64_fallback=1, refine_mode=0, precond="none", stream=None):
         torch = _torch()
         self._lib = load()
         self.N = int(N)
         m, self.nel, self._vtx = _mesh(nel, vtx, lo, hi)
-        o = _opts(prec, inner_tol, inner_maxit, max_outer, fp64_fallback, refine_mode)
+        o = _opts(prec, inner_tol, inner_maxit, max_outer, fp64_fallback, refine_mode, precond)
         self.stream = torch.cuda.current_stream() if stream is None else stream
         h = ctypes.c_void_p()
         _check(self._lib.nek_setup(ctypes.byref(m), self.N, ctypes.byref(o), ctypes.c_void_p(self.stream.cuda_stream),
@@ -253,7 +257,7 @@ class Context:
                   NEK_GET_MASK: (self.nl, np.int8), NEK_GET_PERM: (self.size(NEK_SIZE_NPERM), np.int32),
                   NEK_GET_SEGPTR: (self.size(NEK_SIZE_NSEG) + 1, np.int32),
                   NEK_GET_SEGFLAG: (self.size(NEK_SIZE_NSEG), np.int8),
-                  NEK_GET_XYZ: ((self.E, 3, n ** 3), np.float64)}
+                  NEK_GET_XYZ: ((self.E, 3, n ** 3), np.float64), NEK_GET_DIAG: (self.nl, np.float64)}
         shape, dt = shapes[what]
         out = np.empty(shape, dtype=dt)
         _check(self._lib.nek_get(self._h, int(what), out.ctypes.data_as(ctypes.c_void_p)), "nek_get")
@@ -262,6 +266,11 @@ class Context:
     def set_prec(self, prec):
         _check(self._lib.nek_set_prec(self._h, PREC_NAMES[prec] if isinstance(prec, str) else int(prec)),
                "nek_set_prec")
+
+    def set_precond(self, precond):
+        """'none' (Table 1 with solveM a copy) or 'jacobi' (z = r / diagonal)."""
+        _check(self._lib.nek_set_precond(self._h, PC_NAMES[precond] if isinstance(precond, str) else int(precond)),
+               "nek_set_precond")
 
     # -- argument checks (host side, before any kernel sees the pointers)
     def _vec(self, t, what):

@@ -1,0 +1,173 @@
+"""GPU parity of the diagonal (Jacobi) preconditioned CG against the oracle.
+
+solveM of Table 1 as z = r / m, m the diagonal of the assembled masked
+operator.  The library keeps z in its work vector (z -= alpha S / m) and
+forms r = m z for the reductions; the oracle runs the textbook order
+(r -= alpha w, then z = r / m), so the two agree to rounding:
+  * the diagonal: 1e-12 of its scale (it is built from g1..g6, which agree
+    to 1e-13), exactly 1 on Dirichlet nodes;
+  * FP64, 100 fixed iterations: x within 1e-12 relative, residual history
+    within 1e-10 relative plus 1e-14 absolute (histories are relative to |b|;
+    the small meshes reach the rounding floor within 100 iterations); where
+    the oracle itself moves further when its diagonal is changed by one ulp
+    (measured in the test), the bound is 10x that movement;
+  * converged solves (FP64 and both mixed precisions): the oracle's true
+    FP64 residual of the GPU's x <= tol, FP64 iteration count within 1 of
+    the oracle's, and fewer iterations than without the preconditioner.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_11065_amd import nek, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    nek.load()
+
+
+def make(N, nel, perturb=0.0, seed=7, hi=None, prec="fp64", **kw):
+    vtx = synth.box_vertices(nel, hi=hi, perturb=perturb, seed=seed)
+    _case(f"setup N={N} nel={nel} perturb={perturb} prec={prec} {kw}")
+    return nek.Context(nel, N, vtx=vtx, prec=prec, **kw), oracle.Problem(N, nel, vtx)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+CASES = [(7, (4, 4, 4), 0.0), (5, (3, 2, 2), 0.1), (9, (2, 2, 2), 0.1), (3, (2, 3, 2), 0.1), (12, (1, 2, 2), 0.1),
+         (1, (3, 2, 2), 0.0)]
+
+
+@pytest.mark.parametrize("N,nel,perturb", CASES)
+def test_diagonal_matches_oracle(N, nel, perturb):
+    ctx, P = make(N, nel, perturb, precond="jacobi")
+    m = ctx.get(nek.NEK_GET_DIAG)
+    mo = P.diag()
+    err = rel(m, mo)
+    print(f"diag rel err {err:.2e}")
+    assert err <= 1e-12
+    assert np.all(m[P.mask == 0] == 1.0)
+    ctx.close()
+
+
+@pytest.mark.parametrize("N,nel,perturb", CASES)
+def test_pcg_fixed_iterations_fp64(N, nel, perturb):
+    ctx, P = make(N, nel, perturb, precond="jacobi")
+    f = synth.uniform_load(P.nl, 31)
+    fd = torch.from_numpy(f).cuda()
+    it = 100
+    x, st, h = ctx.cg_solve(fd, tol=0.0, maxit=it, history=True)
+    m = P.diag()
+    xo, ito, ho = P.pcg(f, m, tol=0.0, maxit=it)
+    # How far rounding alone moves this run: the oracle again with m moved by
+    # one ulp at random nodes (equal on copies).  Where CG amplifies rounding
+    # (small high-order meshes, past their first convergence phase) the bound
+    # widens to 10x that; elsewhere the fixed bounds apply.
+    eps = np.random.default_rng(0).integers(-1, 2, size=P.ng)
+    xs, _, hs = P.pcg(f, m * (1 + eps[P.gid] * 2.0 ** -52), tol=0.0, maxit=it)
+    sx, sh = rel(xs, xo), float(np.max(np.abs(hs - ho)))
+    xg = x.cpu().numpy()
+    n = min(len(h), len(ho))
+    # relative 1e-10 plus an absolute floor of 1e-14 (the histories are
+    # relative to |b|): near convergence the last digits are rounding noise
+    excess = float(np.max(np.abs(h[:n] - ho[:n]) - np.maximum(1e-10 * ho[:n] + 1e-14, 10 * sh)))
+    err = rel(xg, xo)
+    print(f"its gpu {st['iters']} oracle {ito}: x rel err {err:.2e} (oracle 1-ulp sensitivity {sx:.1e}), "
+          f"history excess over bound {excess:.2e} (sensitivity {sh:.1e})")
+    if ho[-1] > 1e-13:
+        assert st["iters"] == ito
+    else:   # solved to the rounding floor: the run ends where r or z first rounds to exactly 0
+        assert abs(st["iters"] - ito) <= 2
+    assert err <= max(1e-12, 10 * sx) and excess <= 0.0
+    if (N, nel) == (7, (4, 4, 4)):
+        assert err <= 1e-12   # the 4^3 N=7 box: the fixed bound, no widening
+    ctx.close()
+
+
+@pytest.mark.parametrize("N,nel,perturb", [(7, (4, 4, 4), 0.0), (5, (3, 3, 2), 0.1), (9, (3, 2, 2), 0.1)])
+def test_pcg_converged_all_precisions(N, nel, perturb):
+    vtx = synth.box_vertices(nel, perturb=perturb, seed=7)
+    P = oracle.Problem(N, nel, vtx)
+    f = synth.uniform_load(P.nl, 32)
+    fd = torch.from_numpy(f).cuda()
+    tol = 1e-8
+    _, it_cg, _ = P.cg(f, tol=tol, maxit=5000)
+    _, it_pcg, _ = P.pcg(f, P.diag(), tol=tol, maxit=5000)
+    assert it_pcg < it_cg
+    for prec in ("fp64", "fp32", "bf16g"):
+        _case(f"converged PCG N={N} nel={nel} prec={prec}")
+        ctx = nek.Context(nel, N, vtx=vtx, prec=prec, precond="jacobi")
+        x, st, _ = ctx.cg_solve(fd, tol=tol, maxit=5000, raise_on_noconv=True)
+        res = P.true_residual(x.cpu().numpy(), f)
+        print(f"{prec}: {st['iters']} its ({st['outer_iters']} outer; oracle PCG {it_pcg}, CG {it_cg}), "
+              f"true residual {res:.3e}")
+        assert res <= tol
+        if prec == "fp64":
+            assert abs(st["iters"] - it_pcg) <= 1
+        ctx.close()
+
+
+def test_pcg_reliable_update_mode():
+    N, nel = 7, (3, 3, 3)
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=9)
+    P = oracle.Problem(N, nel, vtx)
+    f = synth.uniform_load(P.nl, 33)
+    ctx = nek.Context(nel, N, vtx=vtx, prec="fp32", precond="jacobi", refine_mode=2)
+    x, st, _ = ctx.cg_solve(torch.from_numpy(f).cuda(), tol=1e-8, maxit=5000, raise_on_noconv=True)
+    res = P.true_residual(x.cpu().numpy(), f)
+    print(f"reliable update + Jacobi: {st['iters']} its, {st['outer_iters']} outer, true residual {res:.3e}")
+    assert res <= 1e-8
+    ctx.close()
+
+
+def test_switching_preconditioner_on_one_context():
+    """none -> jacobi -> none on one context: the unpreconditioned solves are
+    bit-identical to each other, the preconditioned one to a fresh context's."""
+    N, nel = 5, (3, 2, 2)
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=10)
+    f = torch.from_numpy(synth.uniform_load(3 * 2 * 2 * 216, 34)).cuda()
+    for prec in ("fp64", "fp32"):
+        ctx = nek.Context(nel, N, vtx=vtx, prec=prec)
+        a, sa, _ = ctx.cg_solve(f, tol=1e-8, maxit=3000)
+        a = a.clone()
+        ctx.set_precond("jacobi")
+        b, sb, _ = ctx.cg_solve(f, tol=1e-8, maxit=3000)
+        b = b.clone()
+        ctx.set_precond("none")
+        c, sc, _ = ctx.cg_solve(f, tol=1e-8, maxit=3000)
+        fresh = nek.Context(nel, N, vtx=vtx, prec=prec, precond="jacobi")
+        d, sd, _ = fresh.cg_solve(f, tol=1e-8, maxit=3000)
+        print(f"{prec}: none {sa['iters']} its, jacobi {sb['iters']}, none again {sc['iters']}")
+        assert torch.equal(a, c) and sa["iters"] == sc["iters"]
+        assert torch.equal(b, d) and sb["iters"] == sd["iters"]
+        assert sb["iters"] < sa["iters"]
+        ctx.close()
+        fresh.close()
+
+
+def test_batch_refuses_preconditioner():
+    """Batches run unpreconditioned: a member context switched to Jacobi makes
+    nek_batch_solve return NEK_E_ARG before any kernel runs."""
+    b = nek.Batch([{"nel": (2, 2, 2), "N": 5}, {"nel": (3, 3, 3), "N": 7}], prec="fp32")
+    try:
+        b.ctx[1].set_precond("jacobi")
+        fs = [torch.rand(b.nl[i], dtype=torch.float64, device="cuda") for i in range(b.n)]
+        xs = [torch.empty_like(t) for t in fs]
+        with pytest.raises(nek.NekError):
+            b.solve(fs, tol=1e-8, maxit=100, xs=xs)
+    finally:
+        for c in b.ctx:
+            c.close()
+        b.close()
