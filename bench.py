@@ -179,6 +179,46 @@ def big_energy(torch, ctx, f, x, ms_per_solve):
     return out
 
 
+def jacobi_case(torch, ctx, f, steps, base):
+    """The diagonal (Jacobi) preconditioner on the same solve: iterations,
+    time and per-kernel sampled durations for FP64 CG and the mixed solve,
+    against the unpreconditioned runs in `base` (prec -> (ms, iters))."""
+    out = {}
+    saved = {p: ctx.get_variant(p) for p in ("fp32", "fp64")}
+    x = ctx.new_vector()
+    ctx.set_precond("jacobi")
+    try:
+        for prec in ("fp32", "fp64"):
+            ctx.set_prec(prec)
+            tuned = ctx.tune(prec, iters=30)   # the configuration of the preconditioned kernel pair
+            _, st, _ = ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+            ctx.prof_read(0, reset=True)
+            ctx.prof_read(1, reset=True)
+            ctx.prof_enable(16)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its = 0
+            for _ in range(steps):
+                _, st, _ = ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+                its += st["iters"]
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            ctx.prof_enable(0)
+            k0, n0 = ctx.prof_read(0)
+            k1, n1 = ctx.prof_read(1)
+            ms0, it0 = base[prec]
+            out[prec] = {"ms_per_solve": round(dt * 1e3, 3), "iters": its / steps, "outer": st["outer_iters"],
+                         "rel_res": st["rel_res"], "tuned_variant": tuned[0],
+                         "operator_us": round(k0 / max(n0, 1) * 1e3, 2), "update_us": round(k1 / max(n1, 1) * 1e3, 2),
+                         "unpreconditioned_ms": round(ms0, 3), "unpreconditioned_iters": it0,
+                         "speedup": round(ms0 / (dt * 1e3), 3)}
+    finally:
+        ctx.set_precond("none")
+        for p, v in saved.items():
+            ctx.set_variant(p, v)
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -404,6 +444,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched solve")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned initial guess (data, training, eval)")
     ap.add_argument("--no-energy", action="store_true", help="skip the energy-to-solution measurement")
+    ap.add_argument("--no-jacobi", action="store_true", help="skip the diagonal-preconditioner measurement")
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for hardware-counter runs: 40 mixed and 40 FP64 CG iterations, "
                          "5 nek_ax per precision and a 256 MiB copy for calibration")
@@ -473,6 +514,12 @@ def main():
     torch.cuda.synchronize()
     t_fp64 = time.perf_counter() - t0
 
+    # ---- the diagonal preconditioner on the same solve
+    jac = None if args.no_jacobi else jacobi_case(
+        torch, ctx, f, args.steps, {"fp32": (ms_per_step, iters / args.steps),
+                                    "fp64": (t_fp64 / args.steps * 1e3, it64 / args.steps)})
+    log(f"jacobi: {jac}")
+
     # ---- energy-to-solution, mixed vs FP64, same solve
     energy = None if args.no_energy else energy_to_solution(
         torch, ctx, solve, {"fp32": ms_per_step, "fp64": t_fp64 / args.steps * 1e3})
@@ -515,6 +562,7 @@ def main():
         "tuned_variant": {k: {"best": v[0], "us_per_iter": [round(u, 1) for u in v[1]]} for k, v in tuned.items()},
         "ax_dssum": axd,
         "energy": energy,
+        "jacobi": jac,
         "roofline": {"bound": "hbm", "kernel": f"k_ax<NP=10,f32,f32,CG> variant {tuned['fp32'][0]} (add2s1 + ax_e + correction update)",
                      "achieved": round(achieved, 1) if achieved else None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None,

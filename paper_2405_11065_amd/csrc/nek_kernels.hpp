@@ -840,9 +840,10 @@ __device__ __forceinline__ void upd_body(T *__restrict__ r, const T *__restrict_
     const unsigned lb = xcd_block(blk, nblk);
     const int g0 = (int)(((long)lb * ngroups) / nblk);
     const int g1 = (int)(((long)(lb + 1) * ngroups) / nblk);
-    // FP32 columns are loaded before the reduction; FP64 ones after it (held
-    // across the reduction they would cost a wave of occupancy per SIMD)
-    constexpr bool early = sizeof(T) == 4;
+    // FP32 columns are loaded before the reduction; FP64 ones, and those of
+    // the preconditioned kernel, after it (held across the reduction they
+    // would cost a wave of occupancy per SIMD)
+    constexpr bool early = sizeof(T) == 4 && !PC;
     UpdCol<NP, T, PC> c;
     c.valid = false;
     if (early && g0 < g1) upd_load<NP, EPW, T, PC>(c, r, w, dg, g0, el, i, j, ij, box, E);
@@ -955,14 +956,34 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_assemble(const T *__restrict__ 
     }
 }
 
-template <int NP, int EPW, typename T, bool PC = false>
+// Occupancy target of the preconditioned update kernel (waves per SIMD).
+// Its FP32 columns plus the diagonal take 134 VGPRs at NP = 10, one wave
+// per SIMD fewer than the unpreconditioned kernel; the target brings it
+// back at the cost of 4 spilled registers (25.1 instead of 26.7 us at 16^3
+// N=9), and stays at what fits without heavy spilling for higher orders.
+// FP64 (173 VGPRs at NP = 10) is left free: forcing 3 waves spilled 6
+// registers and ran slower (47.1 against 43.2 us).
+template <int NP, typename T> constexpr int pc_update_waves()
+{
+    return sizeof(T) == 4 ? (NP <= 10 ? 4 : NP <= 12 ? 3 : 2) : 1;
+}
+
+template <int NP, int EPW, typename T>
+__global__ __launch_bounds__(EPW *NP *NP) __attribute__((amdgpu_waves_per_eu(pc_update_waves<NP, T>())))
+void k_cg_update_pc(T *__restrict__ r, const T *__restrict__ w, Scal *__restrict__ sc, const double *__restrict__ P1cur,
+                    int nb1, double *__restrict__ P2cur, int it, Box box, int E, int ngroups, const T *__restrict__ dg,
+                    double *__restrict__ P4cur)
+{
+    upd_body<NP, EPW, T, true>(r, w, sc, P1cur, nb1, P2cur, it, box, E, ngroups, blockIdx.x, gridDim.x, dg, P4cur);
+}
+
+template <int NP, int EPW, typename T>
 __global__ __launch_bounds__(EPW *NP *NP) void k_cg_update(T *__restrict__ r, const T *__restrict__ w,
                                                            Scal *__restrict__ sc, const double *__restrict__ P1cur,
                                                            int nb1, double *__restrict__ P2cur, int it, Box box,
-                                                           int E, int ngroups, const T *__restrict__ dg,
-                                                           double *__restrict__ P4cur)
+                                                           int E, int ngroups)
 {
-    upd_body<NP, EPW, T, PC>(r, w, sc, P1cur, nb1, P2cur, it, box, E, ngroups, blockIdx.x, gridDim.x, dg, P4cur);
+    upd_body<NP, EPW, T>(r, w, sc, P1cur, nb1, P2cur, it, box, E, ngroups, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------- batched CG

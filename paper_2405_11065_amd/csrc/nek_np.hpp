@@ -50,9 +50,13 @@ template <int NP> struct OpsImpl {
             if (rc) return rc;
             if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 1], c->stream));
             const unsigned grid = ax_grid(c, EPW);
-            hipLaunchKernelGGL((k_cg_update<NP, EPW, T, PC>), dim3(grid), dim3(EPW * NP * NP), 0, c->stream, r, w,
-                               c->sc, c->P1(it), (int)grid, c->P2(it), it, c->box, (int)c->E, ax_groups(c, EPW), dg,
-                               c->P4(it));
+            if constexpr (PC)
+                hipLaunchKernelGGL((k_cg_update_pc<NP, EPW, T>), dim3(grid), dim3(EPW * NP * NP), 0, c->stream, r, w,
+                                   c->sc, c->P1(it), (int)grid, c->P2(it), it, c->box, (int)c->E, ax_groups(c, EPW), dg,
+                                   c->P4(it));
+            else
+                hipLaunchKernelGGL((k_cg_update<NP, EPW, T>), dim3(grid), dim3(EPW * NP * NP), 0, c->stream, r, w,
+                                   c->sc, c->P1(it), (int)grid, c->P2(it), it, c->box, (int)c->E, ax_groups(c, EPW));
             HIP_TRY(hipGetLastError());
             if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 2], c->stream));
             return NEK_OK;
