@@ -129,12 +129,16 @@ __device__ __forceinline__ double inv_mult(int m)
 // together with another array, gets the bit-identical value.  Each P[a] is
 // 16-byte aligned and readable up to the next even count (P[n] when n is
 // odd, a value that is not added): the partial slots hold MAXB entries.
-template <int BS, int NA>
+template <int BS, int NA, bool WIDE = false>
 __device__ __forceinline__ void sum_all_n(const double *const *P, const int *n, double *sbuf, double *out)
 {
     constexpr int NW = BS >= 64 ? BS / 64 : 1;
     constexpr int NT = BS >= 64 ? NW * 64 : BS;
-    constexpr int U = NT >= 256 || NA >= 3 ? 4 : 8;   // at most 16 pairs in flight per thread
+    // pairs in flight per thread: 8 per array below 256 threads, except three
+    // arrays without WIDE (4 each), which would cost 4-byte operator kernels
+    // a wave per SIMD; FP64 ones have the registers (WIDE) and then sum 2048
+    // partials in one batch of loads instead of two
+    constexpr int U = NT >= 256 || (NA >= 3 && !WIDE) ? 4 : 8;
     double v[NA];
     int nmax = 0;
 #pragma unroll
@@ -202,7 +206,7 @@ struct Begin {
 // With PC (diagonal preconditioner), P2 holds the partials of glsc3(r, c, z)
 // and P4 those of glsc3(r, c, r); without it P2 holds glsc3(r, c, r) and P4
 // is unused.
-template <int BS, bool PC = false>
+template <int BS, bool PC = false, bool WIDE = false>
 __device__ __forceinline__ Begin cg_begin(Scal *__restrict__ sc, const double *__restrict__ P1prev, int nb1,
                                           const double *__restrict__ P2prev, int nb2, int it,
                                           double *__restrict__ hist, double *sbuf, bool writer,
@@ -226,7 +230,7 @@ __device__ __forceinline__ Begin cg_begin(Scal *__restrict__ sc, const double *_
                 const double *ps[3] = {P1prev, P2prev, P4prev};
                 const int ns[3] = {nb1, nb2, nb2};
                 double sums[3];
-                sum_all_n<BS, NS>(ps, ns, sbuf, sums);
+                sum_all_n<BS, NS, WIDE>(ps, ns, sbuf, sums);
                 B.alpha_prev = prev.rtz / sums[0];
                 B.xupd = true;
                 const double rtz = sums[1];
@@ -395,7 +399,8 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
     double alpha_prev = 0.0;
     if constexpr (CG) {
         const Begin B =
-            cg_begin<BS, PC>(sc, P1prev, (int)nblk, P2prev, nb2, it, hist, sbuf, blk == 0 && tid == 0, P4prev);
+            cg_begin<BS, PC, sizeof(T) == 8>(sc, P1prev, (int)nblk, P2prev, nb2, it, hist, sbuf, blk == 0 && tid == 0,
+                                             P4prev);
         xupd = B.xupd;
         alpha_prev = B.alpha_prev;
         if (B.cur.done) {
