@@ -115,7 +115,7 @@ def cpu_baseline(f, budget_s=15.0):
                       f"({dt:.1f} s), setup excluded"}
 
 
-def big_case(torch, nek, synth, steps=2, energy=True):
+def big_case(torch, nek, synth, steps=2, energy=True, jacobi=True):
     """32^3 elements on [0,1]^3, interior vertices moved up to 10 %, N=9
     (32.8 M local points), f = B (sin pi x sin pi y sin pi z + N(0,1e-3)):
     mixed solve with BF16-stored g against FP64 CG, tol 1e-8; then nek_ax
@@ -148,6 +148,28 @@ def big_case(torch, nek, synth, steps=2, energy=True):
     out["speedup_vs_fp64"] = round(out["fp64"]["ms_per_solve"] / out["bf16g"]["ms_per_solve"], 3)
     if energy:
         out["energy"] = big_energy(torch, ctx, f, x, {p: out[p]["ms_per_solve"] for p in ("bf16g", "fp64")})
+    if jacobi:
+        # the same solves with the diagonal preconditioner (kernels autotuned for it)
+        saved = {p: ctx.get_variant(p) for p in ("bf16g", "fp64")}
+        ctx.set_precond("jacobi")
+        jac = {}
+        for prec in ("bf16g", "fp64"):
+            ctx.set_prec(prec)
+            ctx.tune(prec, iters=10)
+            ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, st, _ = ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            jac[prec] = {"ms_per_solve": round(dt * 1e3, 2), "iters": st["iters"], "outer": st["outer_iters"],
+                         "rel_res": st["rel_res"], "speedup_vs_unpreconditioned":
+                         round(out[prec]["ms_per_solve"] / (dt * 1e3), 3)}
+        ctx.set_precond("none")
+        for p, v in saved.items():
+            ctx.set_variant(p, v)
+        out["jacobi"] = jac
     # ax + dssum at this size: the working set exceeds the 256 MB memory-side cache
     ctx.tune("fp32", iters=10)
     out["ax_dssum"] = ax_dssum_all(ctx, torch)
@@ -529,7 +551,7 @@ def main():
     axd = ax_dssum_all(ctx, torch)
 
     # ---- secondary: 32^3 deformed mesh, N=9, manufactured forcing, BF16 g vs FP64
-    big = None if args.no_big else big_case(torch, nek, synth, energy=not args.no_energy)
+    big = None if args.no_big else big_case(torch, nek, synth, energy=not args.no_energy, jacobi=not args.no_jacobi)
     log("32^3 case done")
     batch = None if args.no_batch else batch_case(torch, nek, synth)
     learned = None if args.no_learned else learned_case(torch)
