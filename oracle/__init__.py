@@ -82,7 +82,7 @@ def _get():
         lib.vp_perturb.argtypes = [ctypes.c_double, ctypes.c_int]
         lib.vp_perturb.restype = ctypes.c_double
         lib.vp_cg.argtypes = [ctypes.c_int, _int3, _d, _d, _i32, ctypes.c_int, ctypes.c_uint64,
-                              ctypes.c_double, ctypes.c_int, _d, _d, _d]
+                              ctypes.c_double, ctypes.c_int, _d, _d, _d, _d]
         _lib = lib
     return _lib
 
@@ -307,12 +307,13 @@ def vp_perturb(x: float, t: int) -> float:
 
 
 def vprec_cg(N: int, nel, vtx, f, t=(52, 52, 52, 52), mode: str = "ieee", seed: int = 0,
-             tol: float = 0.0, maxit: int = 100, want_g: bool = False):
+             tol: float = 0.0, maxit: int = 100, want_g: bool = False, m=None):
     """The oracle's init and Table-1 CG with every FP operation passed through
     the precision hook of nek_vprec.c: t = mantissa bits of the regions
     (init, operator + dssum, vector updates, dot products and scalars); mode
     one of 'ieee', 'rne' (round to t bits), 'rr' (random rounding of
-    results), 'mca' (perturbed operands and results).
+    results), 'mca' (perturbed operands and results).  With m (a diagonal
+    per local node) the loop is the preconditioned one of Problem.pcg.
     Returns (x, iterations, recursive residual history[, g])."""
     nel = tuple(int(v) for v in nel)
     E = nel[0] * nel[1] * nel[2]
@@ -323,7 +324,8 @@ def vprec_cg(N: int, nel, vtx, f, t=(52, 52, 52, 52), mode: str = "ieee", seed: 
     tt = np.ascontiguousarray(t, dtype=np.int32)
     assert tt.shape == (4,)
     it = _get().vp_cg(N, _int3(*nel), _p(_f64(vtx), _d), _p(_f64(f), _d), _p(tt, _i32), VP_MODES[mode],
-                      int(seed) & (2 ** 64 - 1), float(tol), int(maxit), _p(x, _d), _p(hist, _d), _p(g, _d))
+                      int(seed) & (2 ** 64 - 1), float(tol), int(maxit), _p(x, _d), _p(hist, _d), _p(g, _d),
+                      _p(None if m is None else _f64(m), _d))
     if it == -4:
         raise ValueError("inverted element: det J <= 0")
     if it == -1:

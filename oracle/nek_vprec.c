@@ -321,6 +321,8 @@ static double vp_glsc3(int64_t nl, const double *a, const double *c, const doubl
  *   t[4]   precision per region (INIT, OP, VEC, DOT); mode one of VP_*;
  *   seed   stream of the random perturbations;
  *   tol    relative residual to stop at (<= 0: exactly maxit iterations).
+ * m (optional): a diagonal preconditioner per local node; the loop is then
+ * or_pcg's (solveM z = r / m, the division in region VEC).
  * Outputs: x (n_local), hist (maxit+1 recursive relative residuals, entry 0
  * the initial one), g_out (optional, E*6*n^3 geometric factors as the hook
  * left them) and the iteration count as return value (-4 inverted element,
@@ -328,7 +330,7 @@ static double vp_glsc3(int64_t nl, const double *a, const double *c, const doubl
  * returned x is left to the exact oracle.
  */
 int vp_cg(int N, const int *nel, const double *vtx, const double *f, const int *t, int mode, uint64_t seed,
-          double tol, int maxit, double *x, double *hist, double *g_out)
+          double tol, int maxit, double *x, double *hist, double *g_out, const double *m)
 {
     if (N < 1 || N > 63) return -1;
     for (int q = 0; q < VP_NREG; ++q) vp_t[q] = t[q];
@@ -350,8 +352,10 @@ int vp_cg(int N, const int *nel, const double *vtx, const double *f, const int *
     double *r = (double *)malloc(sizeof(double) * nl);
     double *p = (double *)malloc(sizeof(double) * nl);
     double *wv = (double *)malloc(sizeof(double) * nl);
+    double *z = m ? (double *)malloc(sizeof(double) * nl) : r;
     int status = 0, it = 0;
-    if (!g || !gid || !mult || !mask || !acc || !wr || !c || !b || !r || !p || !wv || or_numbering(N, nel, gid, mult, mask)) {
+    if (!g || !gid || !mult || !mask || !acc || !wr || !c || !b || !r || !p || !wv || !z ||
+        or_numbering(N, nel, gid, mult, mask)) {
         status = -1;
         goto out;
     }
@@ -382,13 +386,17 @@ int vp_cg(int N, const int *nel, const double *vtx, const double *f, const int *
         double rtz1 = 1.0, rtz2;
         for (int64_t l = 0; l < nl; ++l) p[l] = 0.0;
         for (it = 1; it <= maxit; ++it) {
+            if (m) {
+                vp_reg = VP_VEC;
+                for (int64_t l = 0; l < nl; ++l) z[l] = dvd(r[l], m[l]);
+            }
             vp_reg = VP_DOT;
             rtz2 = rtz1;
-            rtz1 = vp_glsc3(nl, r, c, r);
+            rtz1 = vp_glsc3(nl, r, c, z);
             if (rtz1 == 0.0) { --it; break; }
             double beta = it == 1 ? 0.0 : dvd(rtz1, rtz2);
             vp_reg = VP_VEC;
-            for (int64_t l = 0; l < nl; ++l) p[l] = add(mul(beta, p[l]), r[l]);
+            for (int64_t l = 0; l < nl; ++l) p[l] = add(mul(beta, p[l]), z[l]);
             vp_apply(&op, p, wv);
             vp_reg = VP_DOT;
             double pap = vp_glsc3(nl, wv, c, p);
@@ -410,6 +418,7 @@ int vp_cg(int N, const int *nel, const double *vtx, const double *f, const int *
 out:
     free(g); free(gid); free(mult); free(mask); free(acc); free(wr);
     free(c); free(b); free(r); free(p); free(wv);
+    if (m) free(z);
     vp_mode = VP_IEEE;
     return status ? status : it;
 }

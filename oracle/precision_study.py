@@ -18,7 +18,8 @@ experiments of the paper's Sect. 4:
 Then, to the 1e-8 stopping tolerance of the solver, it compares the paper's
 layout (the whole CG loop in 23-bit precision) with the one the GPU path
 uses inside its FP64 refinement (operator, dssum and vectors in 23 bits;
-dot products and scalars in FP64).
+dot products and scalars in FP64), without and with the diagonal (Jacobi)
+preconditioner.
 
 TEST INFRASTRUCTURE / ANALYSIS ONLY: it calls the oracle and the seeded input
 generators, nothing of the GPU path.  Output: one JSON object on stdout.
@@ -112,6 +113,15 @@ def main():
                          "true_res": float(P.true_residual(x, f)) if it >= 0 else None}
         x, it, h = P.cg(f, tol=1e-8, maxit=3000)
         lay["fp64"] = {"iters": int(it), "rec_res": float(h[-1]), "true_res": float(P.true_residual(x, f))}
+        # the same with the diagonal (Jacobi) preconditioner, solveM z = r / m
+        m = P.diag()
+        for name, bits in layouts.items():
+            x, it, h = oracle.vprec_cg(N, NEL, vtx, f, t=bits, mode="rne", tol=1e-8, maxit=3000, m=m)[:3]
+            lay[name + "_jacobi"] = {"t_init_op_vec_dot": bits, "iters": int(it),
+                                     "rec_res": float(h[-1]) if it >= 0 else None,
+                                     "true_res": float(P.true_residual(x, f)) if it >= 0 else None}
+        x, it, h = P.pcg(f, m, tol=1e-8, maxit=3000)
+        lay["fp64_jacobi"] = {"iters": int(it), "rec_res": float(h[-1]), "true_res": float(P.true_residual(x, f))}
         out["to_tol_1e-8"] = lay
     print(json.dumps(out, default=float))
 

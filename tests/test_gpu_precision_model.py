@@ -59,3 +59,37 @@ def test_fp32_inner_cg_stall_matches_emulation():
     assert res <= tol
     one.close()
     full.close()
+
+
+def test_fp32_inner_pcg_stall_matches_emulation():
+    """The same with the diagonal (Jacobi) preconditioner: the 23-bit
+    preconditioned loop stalls too, the GPU's FP32 inner PCG at the level the
+    emulation predicts (factor 5), and refinement removes the stall."""
+    nel, N, tol = (4, 4, 4), 7, 1e-8
+    vtx = synth.box_vertices(nel)
+    P = oracle.Problem(N, nel, vtx)
+    f = synth.uniform_load(P.nl, synth.SEED_C1)
+    m = P.diag()
+    print(f"[case] 4^3 N=7 f seed {synth.SEED_C1}: emulated 23-bit PCG loop, FP64 dots", flush=True)
+    xe, ite, he = oracle.vprec_cg(N, nel, vtx, f, t=(52, 23, 23, 52), mode="rne", tol=tol, maxit=3000, m=m)
+    emu = P.true_residual(xe, f)
+    print(f"emulation: {ite} its, recursive {he[-1]:.3e}, true {emu:.3e}", flush=True)
+    assert he[-1] <= tol and emu > 100 * tol
+
+    fd = torch.from_numpy(f).cuda()
+    one = nek.Context(nel, N, vtx=vtx, prec="fp32", inner_tol=tol, max_outer=1, precond="jacobi")
+    x, st, _ = one.cg_solve(fd, tol=tol, maxit=3000)
+    gpu = P.true_residual(x.cpu().numpy(), f)
+    print(f"GPU one refinement step: {st['iters']} inner its, returned {st['rel_res']:.3e}, oracle {gpu:.3e}",
+          flush=True)
+    assert st["outer_iters"] == 1
+    assert emu / 5 <= gpu <= emu * 5
+    assert abs(st["iters"] - ite) <= 0.1 * ite
+
+    full = nek.Context(nel, N, vtx=vtx, prec="fp32", precond="jacobi")
+    x, st, _ = full.cg_solve(fd, tol=tol, maxit=3000, raise_on_noconv=True)
+    res = P.true_residual(x.cpu().numpy(), f)
+    print(f"GPU refinement: {st['outer_iters']} steps, {st['iters']} its, oracle true residual {res:.3e}", flush=True)
+    assert res <= tol
+    one.close()
+    full.close()

@@ -125,3 +125,16 @@ def test_rounding_only_the_cg_regions_keeps_init_exact():
     _, _, _, g = oracle.vprec_cg(N, nel, vtx, f, t=(10, 52, 52, 52), mode="rne", maxit=5, want_g=True)
     assert not np.array_equal(g, P.g)
     assert np.max(np.abs(g - P.g)) <= 2.0 ** -8 * np.max(np.abs(P.g))
+
+
+def test_hook_off_preconditioned_is_or_pcg_bit_for_bit():
+    nel, N = (3, 2, 2), 5
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=12)
+    P = oracle.Problem(N, nel, vtx)
+    f = synth.uniform_load(P.nl, 6)
+    m = P.diag()
+    x0, it0, h0 = P.pcg(f, m, tol=0.0, maxit=40)
+    x1, it1, h1 = oracle.vprec_cg(N, nel, vtx, f, mode="ieee", maxit=40, m=m)
+    assert it1 == it0 and np.array_equal(x1, x0) and np.array_equal(h1, h0)
+    x2, it2, h2 = oracle.vprec_cg(N, nel, vtx, f, mode="rne", t=(52, 52, 52, 52), maxit=40, m=m)
+    assert np.array_equal(x2, x0)
