@@ -98,6 +98,28 @@ def ax_dssum_all(ctx, torch):
     return axd
 
 
+def copy_bandwidth(torch, mib=512, reps=10):
+    """Device-to-device copy of `mib` MiB (read + write counted), beyond the
+    256 MB memory-side cache: the practical streaming ceiling that the
+    ax + dssum fraction is read against."""
+    a = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    t = s.elapsed_time(e) / reps / 1e3
+    gbps = 2 * a.numel() * 4 / t / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"MiB": mib, "GBps": round(gbps, 1), "frac_hbm": round(gbps / PEAK_HBM_GBS, 3)}
+
+
 def cpu_baseline(f, budget_s=15.0):
     """The FP64 oracle (serial C) on the same workload, fixed iteration count."""
     import oracle
@@ -547,8 +569,9 @@ def main():
         torch, ctx, solve, {"fp32": ms_per_step, "fp64": t_fp64 / args.steps * 1e3})
     log(f"energy: {energy}")
 
-    # ---- ax + dssum bandwidth at each precision (nek_ax)
+    # ---- ax + dssum bandwidth at each precision (nek_ax), and a plain copy beside it
     axd = ax_dssum_all(ctx, torch)
+    axd["copy_512MiB"] = copy_bandwidth(torch)
 
     # ---- secondary: 32^3 deformed mesh, N=9, manufactured forcing, BF16 g vs FP64
     big = None if args.no_big else big_case(torch, nek, synth, energy=not args.no_energy, jacobi=not args.no_jacobi)
