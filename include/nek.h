@@ -94,9 +94,14 @@ typedef struct {
 /* Preconditioner of the CG loop (the solveM step of the paper's Table 1). */
 typedef enum {
     NEK_PC_NONE = 0,         /* z = r: the unpreconditioned loop                        */
-    NEK_PC_JACOBI = 1        /* z = r / m, m = diagonal of the assembled masked operator
+    NEK_PC_JACOBI = 1,       /* z = r / m, m = diagonal of the assembled masked operator
                                 (FP64 in FP64 solves, its FP32 rounding in the inner
                                 solves of mixed ones); 1 on Dirichlet nodes             */
+    NEK_PC_FDM = 2           /* element-interior block solve by fast diagonalization on
+                                each element's (N-1)^3 interior nodes (the element's
+                                separable stiffness block with factors from its mean
+                                edge lengths: exact for axis-aligned boxes), z = r / m
+                                on the other nodes: the non-overlapping Schwarz stage  */
 } nek_pc;
 
 typedef struct {
@@ -165,7 +170,10 @@ int nek_set_prec(nek_ctx *ctx, int prec);
 /*
  * nek_set_precond -- preconditioner (nek_pc) of later nek_cg_solve calls.
  * NEK_PC_JACOBI builds the diagonal on first use (host FP64, from the
- * geometric factors; then an FP32 copy).  Solves follow Table 1 with solveM
+ * geometric factors; then an FP32 copy); NEK_PC_FDM builds the diagonal and
+ * the 1-D interior modes and element factors, and runs each iteration as the
+ * operator kernel, the gather/update kernel and the block-solve kernel, with
+ * z in its own vector.  Solves follow Table 1 with solveM
  * z = r / m; the stopping test and the reported residuals stay those of r.
  * The work vector of the loop then holds z, updated as z -= alpha S / m, and
  * the gather/update kernel reduces both r.z and r.r (r = m z).  Batches
@@ -173,6 +181,14 @@ int nek_set_prec(nek_ctx *ctx, int prec);
  * preconditioner (NEK_E_ARG).
  */
 int nek_set_precond(nek_ctx *ctx, int precond);
+
+/*
+ * nek_precond_apply -- z = M^-1 r with the context's preconditioner (a copy
+ * without one); r and z are device vectors of n_local entries of dtype
+ * (NEK_F64: the FP64 data, NEK_F32: the FP32 copies), not overlapping.
+ * Asynchronous on the context's stream.
+ */
+int nek_precond_apply(nek_ctx *ctx, const void *r, void *z, int dtype);
 
 /*
  * nek_ax_local -- w = A_L u, the unassembled element operator ax_e of the

@@ -37,6 +37,14 @@ int nek_host_numbering(int N, const int nel[3], int64_t *gid, int32_t *mult, int
 int nek_host_segment_sizes(int N, const int nel[3], int64_t *n_perm, int64_t *n_seg);
 int nek_host_segments(int N, const int nel[3], int32_t *perm, int32_t *seg_ptr, int8_t *seg_flag);
 
+/* Fast-diagonalization data of the element-interior block solve (the
+ * non-overlapping Schwarz stage of the solveM step): S[(N-1)^2] row-major
+ * [node][mode] and lam[N-1] with K_I S = W_I S diag(lam), S^T W_I S = I
+ * (K = D^T W D, interior nodes only); cf[3 E] = (hy hz/hx, hx hz/hy,
+ * hx hy/hz) per element from the mean edge lengths of the vertex lattice vtx.
+ * N >= 2. */
+int nek_host_fdm(int N, const int nel[3], const double *vtx, double *S, double *lam, double *cf);
+
 #ifdef __cplusplus
 }
 #endif

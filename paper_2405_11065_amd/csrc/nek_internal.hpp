@@ -116,6 +116,13 @@ struct nek_ctx {
     int precond = 0;              // 1: diagonal (Jacobi) preconditioner in the CG loop
     double *dg64 = nullptr;       // assembled diagonal, 1 on Dirichlet nodes
     float *dg32 = nullptr;        // its FP32 rounding (mixed inner solves)
+    // fast-diagonalization preconditioner: 1-D interior modes S [(N-1)^2],
+    // lambda [N-1], element factors [3 E]; the preconditioned residual z of
+    // the FP64 loop and of the inner FP32 loop
+    double *fdmS64 = nullptr, *fdmL64 = nullptr, *fdmC64 = nullptr;
+    float *fdmS32 = nullptr, *fdmL32 = nullptr, *fdmC32 = nullptr;
+    double *z64 = nullptr;
+    float *z32 = nullptr;
     double *hist = nullptr;
     long hist_cap = 0;
     // work vectors
@@ -202,6 +209,10 @@ struct NpOps {
     // r -> z = r / m in place, partials of glsc3(r, c, z)
     int (*pc_start64)(nek_ctx *, double *r, const double *m);
     int (*pc_start32)(nek_ctx *, float *r, const float *m);
+    // z = M^-1 r (fast diagonalization), partials of glsc3(r, c, z) in P;
+    // with step set, as the third kernel of CG iteration it
+    int (*pc_fdm64)(nek_ctx *, const double *r, double *z, double *P, unsigned grid, bool step, int it);
+    int (*pc_fdm32)(nek_ctx *, const float *r, float *z, double *P, unsigned grid, bool step, int it);
     // r32 = (float) r64, d = 0, partials of glsc3(r32, c, r32)
     int (*inner_start)(nek_ctx *, const double *r64, float *r32, float *d);
     // elements per workgroup of a CG variant
@@ -228,12 +239,14 @@ int glsc3_to_slot(nek_ctx *c, const void *a, const void *b, int dtype, int slot)
 int gather_launch(nek_ctx *c, const double *in, double *out, bool weighted);
 int start_launch(nek_ctx *c, int rslot, int hist_off, double stop_tol, int maxit, int stop_on_initial,
                  double rtz_prev = 0.0, int rtr_slot = -1);
-// Preconditioned runs: r -> z = r / m in place and red[2] = glsc3(r, c, z)
-// (r64 with the FP64 diagonal, r32 with the FP32 one); no-op without a
-// preconditioner.  Returns the red slot of the run's rtz (2, or 1).
+// Preconditioned runs: red[2] = glsc3(r, c, z) with z = M^-1 r, in place
+// (diagonal: r64 with the FP64 diagonal, r32 with the FP32 one) or into z64
+// / z32 (fast diagonalization); no-op without a preconditioner.  Returns the
+// red slot of the run's rtz (2, or 1).
 int pc_start64(nek_ctx *c, double *r, int *rtz_slot);
 int pc_start32(nek_ctx *c, float *r, int *rtz_slot);
 int ensure_diag(nek_ctx *c);
+int ensure_fdm(nek_ctx *c);
 int cg_prologue(nek_ctx *c, const double *f, const double *x0, double *x, double *r);
 int ax_local_launch(nek_ctx *c, const void *u, void *w, int dtype, int prec);
 int resid_launch(nek_ctx *c, const double *b, const double *w, double *r, int slot);

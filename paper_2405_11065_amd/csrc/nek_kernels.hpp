@@ -1122,6 +1122,138 @@ __global__ __launch_bounds__(UPD_BS) void k_inner_start(const double *__restrict
     if (threadIdx.x == 0) P[blockIdx.x] = s;
 }
 
+// Element-interior fast-diagonalization preconditioner (solveM): z = M^-1 r
+// with, on the (N-1)^3 interior nodes of every element, the inverse of the
+// element's separable interior stiffness block,
+//   2 (S (x) S (x) S) diag(1 / (cx l_i + cy l_j + cz l_k)) (S (x) S (x) S)^T,
+// (S, l: the 1-D interior modes, S^T W_I S = I; cx, cy, cz: the element's
+// factors), and z = r / m on the other nodes (m the assembled diagonal, 1 on
+// Dirichlet nodes).  A workgroup of NP^2 threads walks a contiguous range of
+// elements; thread (i, j) holds the k-column (i, j).  S^T is applied along k
+// in registers, then along j and i through LDS; the way back runs along i
+// and j through LDS and along k in registers.  Writes z and, per workgroup,
+// the partial of glsc3(r, c, z) to P[blockIdx.x].  With sc set the kernel is
+// a CG step of iteration it and does nothing once the run has ended.
+template <int NP, typename T>
+__global__ __launch_bounds__(NP *NP) void k_pc_fdm(const T *__restrict__ r, T *__restrict__ z,
+                                                   const T *__restrict__ m, const T *__restrict__ S,
+                                                   const T *__restrict__ lam, const T *__restrict__ cf,
+                                                   double *__restrict__ P, Box box, int E,
+                                                   const Scal *__restrict__ sc, int it)
+{
+    constexpr int N = NP - 1, NI = NP - 2, NP2 = NP * NP, NP3 = NP2 * NP, BS = NP2;
+    constexpr int NIa = NI > 0 ? NI : 1, NI2 = NIa * NIa, NI3 = NI2 * NIa;
+    __shared__ T sS[NI2];   // S[node * NI + mode]
+    __shared__ T sl[NIa];
+    __shared__ T bufA[NI3], bufB[NI3];
+    __shared__ double sbuf[BS];
+    if (sc && sc->st[it & 1].done) return;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < NI * NI; q += BS) sS[q] = S[q];
+    for (int q = tid; q < NI; q += BS) sl[q] = lam[q];
+    const int i = tid % NP, j = tid / NP;
+    const bool inner = NI > 0 && i >= 1 && i <= N - 1 && j >= 1 && j <= N - 1;
+    const int ii = i - 1, jj = j - 1;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int e0 = (int)(((long)lb * E) / gridDim.x), e1 = (int)(((long)(lb + 1) * E) / gridDim.x);
+    double part = 0.0;
+    __syncthreads();
+    for (int e = e0; e < e1; ++e) {
+        const int ex = e % box.nx, eyz = e / box.nx;
+        const int ey = eyz % box.ny, ez = eyz / box.ny;
+        const T *re = r + (long)e * NP3;
+        const T *me = m + (long)e * NP3;
+        T rv[NP], zv[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) rv[k] = re[k * NP2 + tid];
+        if (inner) {
+            zv[0] = rv[0] / me[tid];
+            zv[N] = rv[N] / me[N * NP2 + tid];
+        } else {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) zv[k] = rv[k] / me[k * NP2 + tid];
+        }
+        T t[NIa];
+        if (inner) {   // S^T along k (registers)
+#pragma unroll
+            for (int a = 0; a < NI; ++a) {
+                T acc = 0;
+#pragma unroll
+                for (int kk = 0; kk < NI; ++kk) acc += sS[kk * NI + a] * rv[kk + 1];
+                bufA[a * NI2 + jj * NI + ii] = acc;
+            }
+        }
+        __syncthreads();
+        if (inner) {   // S^T along j: thread (ii, b = jj)
+#pragma unroll
+            for (int a = 0; a < NI; ++a) {
+                T acc = 0;
+#pragma unroll
+                for (int jp = 0; jp < NI; ++jp) acc += sS[jp * NI + jj] * bufA[a * NI2 + jp * NI + ii];
+                t[a] = acc;
+            }
+#pragma unroll
+            for (int a = 0; a < NI; ++a) bufB[a * NI2 + jj * NI + ii] = t[a];
+        }
+        __syncthreads();
+        if (inner) {   // S^T along i: thread (c = ii, b = jj); scale the modes
+            const T cx = cf[3 * e], cy = cf[3 * e + 1], cz = cf[3 * e + 2];
+            const T lxy = cx * sl[ii] + cy * sl[jj];
+#pragma unroll
+            for (int a = 0; a < NI; ++a) {
+                T acc = 0;
+#pragma unroll
+                for (int ip = 0; ip < NI; ++ip) acc += sS[ip * NI + ii] * bufB[a * NI2 + jj * NI + ip];
+                t[a] = (T)2 * acc / (lxy + cz * sl[a]);
+            }
+#pragma unroll
+            for (int a = 0; a < NI; ++a) bufA[a * NI2 + jj * NI + ii] = t[a];
+        }
+        __syncthreads();
+        if (inner) {   // S along i: thread (i = ii, b = jj)
+#pragma unroll
+            for (int a = 0; a < NI; ++a) {
+                T acc = 0;
+#pragma unroll
+                for (int c = 0; c < NI; ++c) acc += sS[ii * NI + c] * bufA[a * NI2 + jj * NI + c];
+                t[a] = acc;
+            }
+#pragma unroll
+            for (int a = 0; a < NI; ++a) bufB[a * NI2 + jj * NI + ii] = t[a];
+        }
+        __syncthreads();
+        if (inner) {   // S along j, then along k (registers)
+#pragma unroll
+            for (int a = 0; a < NI; ++a) {
+                T acc = 0;
+#pragma unroll
+                for (int b = 0; b < NI; ++b) acc += sS[jj * NI + b] * bufB[a * NI2 + b * NI + ii];
+                t[a] = acc;
+            }
+#pragma unroll
+            for (int kk = 0; kk < NI; ++kk) {
+                T acc = 0;
+#pragma unroll
+                for (int a = 0; a < NI; ++a) acc += sS[kk * NI + a] * t[a];
+                zv[kk + 1] = acc;
+            }
+        }
+        // next element: its first LDS writes (bufA) follow every thread's last
+        // reads of bufA above; its bufB writes follow its first barrier
+        T *ze = z + (long)e * NP3;
+        const int mx = ((i == 0 && ex > 0) || (i == N && ex < box.nx - 1)) ? 2 : 1;
+        const int my = ((j == 0 && ey > 0) || (j == N && ey < box.ny - 1)) ? 2 : 1;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            ze[k * NP2 + tid] = zv[k];
+            const int mz = ((k == 0 && ez > 0) || (k == N && ez < box.nz - 1)) ? 2 : 1;
+            part += ((double)rv[k] * (double)zv[k]) * inv_mult(mx * my * mz);
+        }
+    }
+    const double sum = block_sum<BS>(part, sbuf);
+    if (tid == 0) P[blockIdx.x] = sum;
+}
+
 // Start of a preconditioned run: r -> z = r / m in place (m the diagonal,
 // 1 on Dirichlet nodes), each quotient formed in FP64 and rounded once, and
 // partials of glsc3(r, c, z).

@@ -217,12 +217,43 @@ int ensure_diag(nek_ctx *c)
     return NEK_OK;
 }
 
+int ensure_fdm(nek_ctx *c)
+{
+    int rc = ensure_diag(c);
+    if (rc) return rc;
+    if (c->fdmS64 && c->z64 && c->z32) return NEK_OK;
+    std::vector<double> S, L, C((size_t)3 * c->E);
+    fdm_modes(c->N, c->w, c->D, S, L);
+    fdm_scales(c->nel, c->vtx, C.data());
+    std::vector<float> S32(S.begin(), S.end()), L32(L.begin(), L.end()), C32(C.begin(), C.end());
+    if (dalloc(c->fdmS64, S.size()) || dalloc(c->fdmL64, L.size()) || dalloc(c->fdmC64, C.size()) ||
+        dalloc(c->fdmS32, S.size()) || dalloc(c->fdmL32, L.size()) || dalloc(c->fdmC32, C.size()) ||
+        dalloc(c->z64, c->nl) || dalloc(c->z32, c->nl))
+        return NEK_E_OOM;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (!S.empty()) {
+        HIP_TRY(hipMemcpy(c->fdmS64, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->fdmL64, L.data(), L.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->fdmS32, S32.data(), S32.size() * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->fdmL32, L32.data(), L32.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    HIP_TRY(hipMemcpy(c->fdmC64, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->fdmC32, C32.data(), C32.size() * sizeof(float), hipMemcpyHostToDevice));
+    return NEK_OK;
+}
+
 int pc_start64(nek_ctx *c, double *r, int *rtz_slot)
 {
     *rtz_slot = 1;
     if (!c->precond) return NEK_OK;
-    if (!c->dg64) return NEK_E_ARG;
-    const int rc = ops(c)->pc_start64(c, r, c->dg64);
+    int rc;
+    if (c->precond == NEK_PC_FDM) {
+        if (!c->z64) return NEK_E_ARG;
+        rc = ops(c)->pc_fdm64(c, r, c->z64, c->P3(), red_grid(c), false, 0);
+    } else {
+        if (!c->dg64) return NEK_E_ARG;
+        rc = ops(c)->pc_start64(c, r, c->dg64);
+    }
     if (rc) return rc;
     *rtz_slot = 2;
     return red_final(c, 2);
@@ -232,8 +263,14 @@ int pc_start32(nek_ctx *c, float *r, int *rtz_slot)
 {
     *rtz_slot = 1;
     if (!c->precond) return NEK_OK;
-    if (!c->dg32) return NEK_E_ARG;
-    const int rc = ops(c)->pc_start32(c, r, c->dg32);
+    int rc;
+    if (c->precond == NEK_PC_FDM) {
+        if (!c->z32) return NEK_E_ARG;
+        rc = ops(c)->pc_fdm32(c, r, c->z32, c->P3(), red_grid(c), false, 0);
+    } else {
+        if (!c->dg32) return NEK_E_ARG;
+        rc = ops(c)->pc_start32(c, r, c->dg32);
+    }
     if (rc) return rc;
     *rtz_slot = 2;
     return red_final(c, 2);
@@ -559,6 +596,8 @@ void nek_free(nek_ctx *c)
     dfree(c->perm); dfree(c->segptr); dfree(c->segflag); dfree(c->sc); dfree(c->partials); dfree(c->hist);
     dfree(c->b); dfree(c->r64); dfree(c->p64); dfree(c->w64); dfree(c->d64); dfree(c->d32);
     dfree(c->r32); dfree(c->p32); dfree(c->w32); dfree(c->dg64); dfree(c->dg32);
+    dfree(c->fdmS64); dfree(c->fdmL64); dfree(c->fdmC64); dfree(c->fdmS32); dfree(c->fdmL32); dfree(c->fdmC32);
+    dfree(c->z64); dfree(c->z32);
     dfree(c->xyz); dfree(c->gfeat); dfree(c->x0_X); dfree(c->x0_Y); dfree(c->x0_s);
     if (c->hflags) (void)hipHostFree(c->hflags);
     for (auto &e : c->ev)
@@ -577,7 +616,7 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
     const long E = (long)mesh->nel[0] * mesh->nel[1] * mesh->nel[2];
     if (E * n3 >= (1L << 31)) return NEK_E_ARG;
     if (opts && (opts->prec < NEK_PREC_FP64 || opts->prec > NEK_PREC_BF16G || opts->elts_per_wg != 0 ||
-                 opts->precond < NEK_PC_NONE || opts->precond > NEK_PC_JACOBI))
+                 opts->precond < NEK_PC_NONE || opts->precond > NEK_PC_FDM))
         return NEK_E_ARG;
     nek_ctx *c = new (std::nothrow) nek_ctx;
     if (!c) return NEK_E_OOM;
@@ -638,9 +677,9 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
         hipMemset(c->partials, 0, 7 * MAXB * sizeof(double)) != hipSuccess)
         return fail(NEK_E_HIP);
     if ((rc = ensure_g(c, c->prec))) return fail(rc);
-    if (c->opts.precond == NEK_PC_JACOBI) {
-        if ((rc = ensure_diag(c))) return fail(rc);
-        c->precond = 1;
+    if (c->opts.precond != NEK_PC_NONE) {
+        if ((rc = c->opts.precond == NEK_PC_FDM ? ensure_fdm(c) : ensure_diag(c))) return fail(rc);
+        c->precond = c->opts.precond;
     }
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(NEK_E_HIP);
     *out = c;
@@ -711,13 +750,29 @@ int nek_set_prec(nek_ctx *c, int prec)
 
 int nek_set_precond(nek_ctx *c, int precond)
 {
-    if (!c || precond < NEK_PC_NONE || precond > NEK_PC_JACOBI) return NEK_E_ARG;
-    if (precond == NEK_PC_JACOBI) {
-        const int rc = ensure_diag(c);
+    if (!c || precond < NEK_PC_NONE || precond > NEK_PC_FDM) return NEK_E_ARG;
+    if (precond != NEK_PC_NONE) {
+        const int rc = precond == NEK_PC_FDM ? ensure_fdm(c) : ensure_diag(c);
         if (rc) return rc;
     }
     c->precond = precond;
     c->opts.precond = precond;
+    return NEK_OK;
+}
+
+int nek_precond_apply(nek_ctx *c, const void *r, void *z, int dtype)
+{
+    if (!c || !r || !z || r == z || (dtype != NEK_F64 && dtype != NEK_F32)) return NEK_E_ARG;
+    const size_t bytes = (size_t)c->nl * (dtype == NEK_F64 ? sizeof(double) : sizeof(float));
+    if (c->precond == NEK_PC_FDM) {
+        if (dtype == NEK_F64) return ops(c)->pc_fdm64(c, (const double *)r, (double *)z, c->P3(), red_grid(c), false, 0);
+        return ops(c)->pc_fdm32(c, (const float *)r, (float *)z, c->P3(), red_grid(c), false, 0);
+    }
+    HIP_TRY(hipMemcpyAsync(z, r, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (c->precond == NEK_PC_JACOBI) {
+        if (dtype == NEK_F64) return ops(c)->pc_start64(c, (double *)z, c->dg64);
+        return ops(c)->pc_start32(c, (float *)z, c->dg32);
+    }
     return NEK_OK;
 }
 

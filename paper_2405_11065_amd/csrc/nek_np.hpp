@@ -63,12 +63,71 @@ template <int NP> struct OpsImpl {
         });
     }
 
+    template <typename T>
+    static int pc_fdm(nek_ctx *c, const T *r, T *z, double *P, unsigned grid, bool step, int it)
+    {
+        const T *m, *S, *L, *C;
+        if constexpr (sizeof(T) == 8) {
+            m = c->dg64; S = c->fdmS64; L = c->fdmL64; C = c->fdmC64;
+        } else {
+            m = c->dg32; S = c->fdmS32; L = c->fdmL32; C = c->fdmC32;
+        }
+        if (!m || !S || !L || !C) return NEK_E_ARG;
+        hipLaunchKernelGGL((k_pc_fdm<NP, T>), dim3(grid), dim3(NP * NP), 0, c->stream, r, z, m, S, L, C, P, c->box,
+                           (int)c->E, step ? c->sc : nullptr, it);
+        HIP_TRY(hipGetLastError());
+        return NEK_OK;
+    }
+    static int pc_fdm64(nek_ctx *c, const double *r, double *z, double *P, unsigned grid, bool step, int it)
+    {
+        return pc_fdm<double>(c, r, z, P, grid, step, it);
+    }
+    static int pc_fdm32(nek_ctx *c, const float *r, float *z, double *P, unsigned grid, bool step, int it)
+    {
+        return pc_fdm<float>(c, r, z, P, grid, step, it);
+    }
+
+    // Fast-diagonalization iteration: the operator kernel forms p = z + beta p
+    // from the z vector, the gather/update kernel updates r and writes the
+    // r.r partials to P4, the block-solve kernel forms z = M^-1 r and writes
+    // the r.z partials to P2 (the prologue of the next operator kernel sums
+    // both, as for the diagonal preconditioner).
+    template <typename T, typename GT>
+    static int cg_iter_fdm(nek_ctx *c, int variant, int it, bool final, T *x, T *r, T *p, T *w, const GT *g,
+                           const T *D)
+    {
+        T *zb;
+        if constexpr (sizeof(T) == 8) zb = c->z64;
+        else zb = c->z32;
+        if (!zb) return NEK_E_ARG;
+        return with_variant<NP, GT>(variant, [&](auto epw_c, auto pd_c) -> int {
+            constexpr int EPW = decltype(epw_c)::value, PD = decltype(pd_c)::value;
+            if (final) return launch_ax<EPW, PD, T, GT, true, T, true>(c, zb, p, w, g, D, it, x);
+            int slot = -1;
+            if (c->prof_every > 0 && (c->prof_tick++ % c->prof_every) == 0) {
+                if ((slot = prof_take(c)) < 0) return NEK_E_HIP;
+                HIP_TRY(hipEventRecord(c->prof_pool[3 * slot], c->stream));
+            }
+            int rc = launch_ax<EPW, PD, T, GT, true, T, true>(c, zb, p, w, g, D, it, x);
+            if (rc) return rc;
+            if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 1], c->stream));
+            const unsigned grid = ax_grid(c, EPW);
+            hipLaunchKernelGGL((k_cg_update<NP, EPW, T>), dim3(grid), dim3(EPW * NP * NP), 0, c->stream, r, w, c->sc,
+                               c->P1(it), (int)grid, c->P4(it), it, c->box, (int)c->E, ax_groups(c, EPW));
+            HIP_TRY(hipGetLastError());
+            if ((rc = pc_fdm<T>(c, r, zb, c->P2(it), grid, true, it))) return rc;
+            if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 2], c->stream));
+            return NEK_OK;
+        });
+    }
+
     // With the diagonal preconditioner on, r holds z = M^-1 r and the update
     // kernel reads the diagonal of the vectors' precision.
     template <typename T, typename GT>
     static int cg_iter(nek_ctx *c, int variant, int it, bool final, T *x, T *r, T *p, T *w, const GT *g,
                        const T *D)
     {
+        if (c->precond == NEK_PC_FDM) return cg_iter_fdm<T, GT>(c, variant, it, final, x, r, p, w, g, D);
         if (c->precond) {
             const T *dg;
             if constexpr (sizeof(T) == 8) dg = c->dg64;
@@ -237,7 +296,7 @@ template <int NP> const NpOps *make_np_ops()
 {
     using I = OpsImpl<NP>;
     static const NpOps ops{n_variants<NP>(), &I::cg_iter64, &I::cg_iter32, &I::cg_iter16, &I::ax64, &I::ax32,
-                           &I::ax16, &I::axa64, &I::axa32, &I::axa16, &I::gather64, &I::glsc3_64, &I::glsc3_32, &I::resid, &I::pc_start64, &I::pc_start32,
+                           &I::ax16, &I::axa64, &I::axa32, &I::axa16, &I::gather64, &I::glsc3_64, &I::glsc3_32, &I::resid, &I::pc_start64, &I::pc_start32, &I::pc_fdm64, &I::pc_fdm32,
                            &I::inner_start,
                            &I::variant_epw, &I::batch_iter};
     return &ops;

@@ -273,6 +273,96 @@ void numbering(int N, const int nel[3], int64_t *gid, int32_t *mult, int8_t *mas
     }
 }
 
+// Interior modes of the 1-D GLL stiffness for the fast-diagonalization
+// block solve: K_I S = W_I S Lambda with S^T W_I S = I, where K = D^T W D and
+// the subscript I keeps the N-1 interior nodes.  W_I is diagonal, so this is
+// the symmetric eigenproblem of C = W_I^-1/2 K_I W_I^-1/2, solved by cyclic
+// Jacobi rotations; S = W_I^-1/2 V.  S is row-major S[i * (N-1) + a] (node i,
+// mode a).
+void fdm_modes(int N, const std::vector<double> &w, const std::vector<double> &D, std::vector<double> &S,
+               std::vector<double> &lam)
+{
+    const int n = N + 1, m = N - 1;
+    S.assign((size_t)std::max(m, 0) * std::max(m, 0), 0.0);
+    lam.assign(std::max(m, 0), 0.0);
+    if (m <= 0) return;
+    std::vector<double> C((size_t)m * m), V((size_t)m * m, 0.0), s(m);
+    for (int a = 0; a < m; ++a) s[a] = 1.0 / std::sqrt(w[a + 1]);
+    for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+            double k = 0.0;   // K[a+1][b+1] = sum_l D[l][a+1] w[l] D[l][b+1]
+            for (int l = 0; l < n; ++l) k += D[l * n + a + 1] * w[l] * D[l * n + b + 1];
+            C[a * m + b] = s[a] * k * s[b];
+        }
+    for (int a = 0; a < m; ++a) V[a * m + a] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) (a == b ? diag : off) += C[a * m + b] * C[a * m + b];
+        if (off <= 1e-30 * diag) break;
+        for (int p = 0; p < m - 1; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                const double apq = C[p * m + q];
+                if (apq == 0.0) continue;
+                // rotation that zeroes C[p][q]: tan(2 theta) = 2 apq / (aqq - app)
+                const double theta = 0.5 * std::atan2(2.0 * apq, C[q * m + q] - C[p * m + p]);
+                const double c = std::cos(theta), sn = std::sin(theta);
+                for (int k = 0; k < m; ++k) {   // C <- C G (columns p, q)
+                    const double ckp = C[k * m + p], ckq = C[k * m + q];
+                    C[k * m + p] = c * ckp - sn * ckq;
+                    C[k * m + q] = sn * ckp + c * ckq;
+                }
+                for (int k = 0; k < m; ++k) {   // C <- G^T C (rows p, q)
+                    const double cpk = C[p * m + k], cqk = C[q * m + k];
+                    C[p * m + k] = c * cpk - sn * cqk;
+                    C[q * m + k] = sn * cpk + c * cqk;
+                }
+                for (int k = 0; k < m; ++k) {   // V <- V G
+                    const double vkp = V[k * m + p], vkq = V[k * m + q];
+                    V[k * m + p] = c * vkp - sn * vkq;
+                    V[k * m + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    for (int a = 0; a < m; ++a) {
+        lam[a] = C[a * m + a];
+        for (int i = 0; i < m; ++i) S[i * m + a] = s[i] * V[i * m + a];
+    }
+}
+
+// Per element (cx, cy, cz) = (hy hz / hx, hx hz / hy, hx hy / hz), h_d the
+// mean length of the element's four edges along direction d, from the vertex
+// lattice (x-index fastest).  cf has 3 E entries.
+void fdm_scales(const int nel[3], const std::vector<double> &vtx, double *cf)
+{
+    const long vx = nel[0] + 1, vy = nel[1] + 1;
+    auto V = [&](long a, long b, long c, int d) { return vtx[3 * (a + vx * (b + vy * c)) + d]; };
+    auto len = [&](long a0, long b0, long c0, long a1, long b1, long c1) {
+        double s2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double t = V(a1, b1, c1, d) - V(a0, b0, c0, d);
+            s2 += t * t;
+        }
+        return std::sqrt(s2);
+    };
+    for (long ez = 0; ez < nel[2]; ++ez)
+        for (long ey = 0; ey < nel[1]; ++ey)
+            for (long ex = 0; ex < nel[0]; ++ex) {
+                double h[3] = {0.0, 0.0, 0.0};
+                for (int u = 0; u < 2; ++u)
+                    for (int v = 0; v < 2; ++v) {
+                        h[0] += len(ex, ey + u, ez + v, ex + 1, ey + u, ez + v);
+                        h[1] += len(ex + u, ey, ez + v, ex + u, ey + 1, ez + v);
+                        h[2] += len(ex + u, ey + v, ez, ex + u, ey + v, ez + 1);
+                    }
+                for (double &t : h) t *= 0.25;
+                double *c = cf + 3 * (ex + nel[0] * (ey + nel[1] * ez));
+                c[0] = h[1] * h[2] / h[0];
+                c[1] = h[0] * h[2] / h[1];
+                c[2] = h[0] * h[1] / h[2];
+            }
+}
+
 // Diagonal of the assembled masked operator M o dssum(A_L), the Jacobi
 // preconditioner of Table 1's solveM step.  Per element node (i,j,k), with
 // A_L = sum_{a,b} D_a^T G_ab D_b: the squared entries of D's columns i, j, k
@@ -392,6 +482,21 @@ int nek_host_segments(int N, const int nel[3], int32_t *perm, int32_t *seg_ptr, 
     std::memcpy(perm, p.data(), p.size() * sizeof(int32_t));
     std::memcpy(seg_ptr, ptr.data(), ptr.size() * sizeof(int32_t));
     std::memcpy(seg_flag, flag.data(), flag.size());
+    return 0;
+}
+
+int nek_host_fdm(int N, const int nel[3], const double *vtx, double *S, double *lam, double *cf)
+{
+    if (!host_args_ok(N, nel) || N < 2 || !vtx || !S || !lam || !cf) return -1;
+    std::vector<double> x, w, d, s, l;
+    nek::gll_rule(N, x, w);
+    nek::deriv_matrix(x, d);
+    nek::fdm_modes(N, w, d, s, l);
+    std::memcpy(S, s.data(), s.size() * sizeof(double));
+    std::memcpy(lam, l.data(), l.size() * sizeof(double));
+    const size_t nv = 3 * (size_t)(nel[0] + 1) * (nel[1] + 1) * (nel[2] + 1);
+    std::vector<double> v(vtx, vtx + nv);
+    nek::fdm_scales(nel, v, cf);
     return 0;
 }
 

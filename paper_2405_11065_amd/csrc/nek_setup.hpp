@@ -27,6 +27,13 @@ void segment_maps(int N, const int nel[3], std::vector<int32_t> &perm, std::vect
 // g[E][6][n^3]: the Jacobi preconditioner.
 void assembled_diagonal(int N, const int nel[3], const std::vector<double> &D, const double *g, double *m);
 
+// Fast-diagonalization data of the element-interior block solve: the 1-D
+// interior modes (K_I S = W_I S Lambda, S^T W_I S = I; S row-major [node][mode])
+// and per-element factors (cx, cy, cz) = (hy hz/hx, hx hz/hy, hx hy/hz).
+void fdm_modes(int N, const std::vector<double> &w, const std::vector<double> &D, std::vector<double> &S,
+               std::vector<double> &lam);
+void fdm_scales(const int nel[3], const std::vector<double> &vtx, double *cf);
+
 // Per-local-node global id, multiplicity and Dirichlet mask (any may be null).
 void numbering(int N, const int nel[3], int64_t *gid, int32_t *mult, int8_t *mask);
 

@@ -22,14 +22,14 @@ NEK_PREC_FP64, NEK_PREC_FP32, NEK_PREC_BF16G = 0, 1, 2
 NEK_F64, NEK_F32 = 0, 1
 (NEK_GET_GLL, NEK_GET_W, NEK_GET_D, NEK_GET_G, NEK_GET_B, NEK_GET_GID, NEK_GET_MULT, NEK_GET_MASK,
  NEK_GET_PERM, NEK_GET_SEGPTR, NEK_GET_SEGFLAG, NEK_GET_XYZ, NEK_GET_DIAG) = range(13)
-NEK_PC_NONE, NEK_PC_JACOBI = 0, 1
-PC_NAMES = {"none": NEK_PC_NONE, "jacobi": NEK_PC_JACOBI}
+NEK_PC_NONE, NEK_PC_JACOBI, NEK_PC_FDM = 0, 1, 2
+PC_NAMES = {"none": NEK_PC_NONE, "jacobi": NEK_PC_JACOBI, "fdm": NEK_PC_FDM}
 (NEK_SIZE_NLOCAL, NEK_SIZE_NGLOBAL, NEK_SIZE_E, NEK_SIZE_NPERM, NEK_SIZE_NSEG, NEK_SIZE_N) = range(6)
 
 PREC_NAMES = {"fp64": NEK_PREC_FP64, "fp32": NEK_PREC_FP32, "bf16g": NEK_PREC_BF16G}
 
 # every entry point declared in include/nek.h
-EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_set_precond", "nek_ax_local", "nek_ax",
+EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_set_precond", "nek_precond_apply", "nek_ax_local", "nek_ax",
            "nek_dssum", "nek_glsc3", "nek_cg_solve", "nek_prof_enable", "nek_prof_read", "nek_num_variants",
            "nek_tune", "nek_set_variant", "nek_get_variant", "nek_batch_setup", "nek_batch_free",
            "nek_batch_size", "nek_batch_ctx", "nek_batch_orders", "nek_batch_tune", "nek_batch_set_variant",
@@ -87,6 +87,7 @@ def load(path: str = LIB_PATH):
     lib.nek_get.argtypes = [vp, ctypes.c_int, vp]
     lib.nek_set_prec.argtypes = [vp, ctypes.c_int]
     lib.nek_set_precond.argtypes = [vp, ctypes.c_int]
+    lib.nek_precond_apply.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_ax_local.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_ax.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_dssum.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int]
@@ -268,9 +269,19 @@ class Context:
                "nek_set_prec")
 
     def set_precond(self, precond):
-        """'none' (Table 1 with solveM a copy) or 'jacobi' (z = r / diagonal)."""
+        """'none' (Table 1 with solveM a copy), 'jacobi' (z = r / diagonal) or 'fdm'
+        (element-interior fast-diagonalization block solve, diagonal elsewhere)."""
         _check(self._lib.nek_set_precond(self._h, PC_NAMES[precond] if isinstance(precond, str) else int(precond)),
                "nek_set_precond")
+
+    def precond_apply(self, r, z=None):
+        """z = M^-1 r with the context's preconditioner."""
+        dt = self._vec(r, "r")
+        z = torch_empty_like(r) if z is None else z
+        if self._vec(z, "z") != dt or z.data_ptr() == r.data_ptr():
+            raise ValueError("z must match r's dtype and not alias it")
+        _check(self._lib.nek_precond_apply(self._h, r.data_ptr(), z.data_ptr(), dt), "nek_precond_apply")
+        return z
 
     # -- argument checks (host side, before any kernel sees the pointers)
     def _vec(self, t, what):

@@ -126,3 +126,23 @@ def test_host_rejects_bad_arguments(lib):
     assert lib.nek_host_gll(0, _ptr(xi), _ptr(xi)) == nek.NEK_E_ARG
     assert lib.nek_host_gll(16, _ptr(xi), _ptr(xi)) == nek.NEK_E_ARG
     assert lib.nek_host_numbering(3, _i3((0, 1, 1)), None, None, None) == nek.NEK_E_ARG
+
+
+@pytest.mark.parametrize("N", [2, 3, 5, 7, 9, 11, 15])
+def test_host_fdm_matches_oracle(lib, N):
+    """Interior modes by the library's Jacobi rotations against the oracle's
+    NumPy eigensolver: eigenvalues, and S Lambda^-1 S^T = K_I^-1 (independent
+    of the order and signs of the modes); element factors from the lattice."""
+    from oracle import fdm
+    nel = (3, 2, 2)
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=4)
+    m = N - 1
+    S, lam, cf = np.empty(m * m), np.empty(m), np.empty(3 * 12)
+    assert lib.nek_host_fdm(N, _i3(nel), _ptr(vtx), _ptr(S), _ptr(lam), _ptr(cf)) == 0
+    xi, w = oracle.gll(N)
+    So, lo = fdm.interior_eig(N, oracle.deriv(N), w)
+    np.testing.assert_allclose(np.sort(lam), np.sort(lo), rtol=1e-12)
+    S = S.reshape(m, m)
+    np.testing.assert_allclose(S @ np.diag(1 / lam) @ S.T, So @ np.diag(1 / lo) @ So.T, rtol=0,
+                               atol=1e-12 * np.abs(So @ np.diag(1 / lo) @ So.T).max())
+    np.testing.assert_allclose(cf.reshape(-1, 3), fdm.element_scales(nel, vtx), rtol=1e-14)
