@@ -170,10 +170,10 @@ def big_case(torch, nek, synth, steps=2, energy=True, jacobi=True):
     out["speedup_vs_fp64"] = round(out["fp64"]["ms_per_solve"] / out["bf16g"]["ms_per_solve"], 3)
     if energy:
         out["energy"] = big_energy(torch, ctx, f, x, {p: out[p]["ms_per_solve"] for p in ("bf16g", "fp64")})
-    if jacobi:
-        # the same solves with the diagonal preconditioner (kernels autotuned for it)
+    for pc in (("jacobi", "fdm") if jacobi else ()):
+        # the same solves with a preconditioner (kernels autotuned for it)
         saved = {p: ctx.get_variant(p) for p in ("bf16g", "fp64")}
-        ctx.set_precond("jacobi")
+        ctx.set_precond(pc)
         jac = {}
         for prec in ("bf16g", "fp64"):
             ctx.set_prec(prec)
@@ -191,7 +191,7 @@ def big_case(torch, nek, synth, steps=2, energy=True, jacobi=True):
         ctx.set_precond("none")
         for p, v in saved.items():
             ctx.set_variant(p, v)
-        out["jacobi"] = jac
+        out[pc] = jac
     # ax + dssum at this size: the working set exceeds the 256 MB memory-side cache
     ctx.tune("fp32", iters=10)
     out["ax_dssum"] = ax_dssum_all(ctx, torch)
@@ -223,14 +223,17 @@ def big_energy(torch, ctx, f, x, ms_per_solve):
     return out
 
 
-def jacobi_case(torch, ctx, f, steps, base):
-    """The diagonal (Jacobi) preconditioner on the same solve: iterations,
-    time and per-kernel sampled durations for FP64 CG and the mixed solve,
-    against the unpreconditioned runs in `base` (prec -> (ms, iters))."""
+def precond_case(torch, ctx, f, steps, base, pc="jacobi"):
+    """A preconditioner (pc: 'jacobi' diagonal, or 'fdm' element-interior fast
+    diagonalization with the diagonal elsewhere) on the same solve:
+    iterations, time and per-kernel sampled durations (for 'fdm' the second
+    figure brackets the update and block-solve kernels together) for FP64 CG
+    and the mixed solve, against the unpreconditioned runs in `base`
+    (prec -> (ms, iters))."""
     out = {}
     saved = {p: ctx.get_variant(p) for p in ("fp32", "fp64")}
     x = ctx.new_vector()
-    ctx.set_precond("jacobi")
+    ctx.set_precond(pc)
     try:
         for prec in ("fp32", "fp64"):
             ctx.set_prec(prec)
@@ -488,7 +491,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched solve")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned initial guess (data, training, eval)")
     ap.add_argument("--no-energy", action="store_true", help="skip the energy-to-solution measurement")
-    ap.add_argument("--no-jacobi", action="store_true", help="skip the diagonal-preconditioner measurement")
+    ap.add_argument("--no-jacobi", action="store_true",
+                    help="skip the preconditioner measurements (diagonal and fast diagonalization)")
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for hardware-counter runs: 40 mixed and 40 FP64 CG iterations, "
                          "5 nek_ax per precision and a 256 MiB copy for calibration")
@@ -558,11 +562,12 @@ def main():
     torch.cuda.synchronize()
     t_fp64 = time.perf_counter() - t0
 
-    # ---- the diagonal preconditioner on the same solve
-    jac = None if args.no_jacobi else jacobi_case(
-        torch, ctx, f, args.steps, {"fp32": (ms_per_step, iters / args.steps),
-                                    "fp64": (t_fp64 / args.steps * 1e3, it64 / args.steps)})
+    # ---- the preconditioners on the same solve
+    base = {"fp32": (ms_per_step, iters / args.steps), "fp64": (t_fp64 / args.steps * 1e3, it64 / args.steps)}
+    jac = None if args.no_jacobi else precond_case(torch, ctx, f, args.steps, base, "jacobi")
     log(f"jacobi: {jac}")
+    fdmc = None if args.no_jacobi else precond_case(torch, ctx, f, args.steps, base, "fdm")
+    log(f"fdm: {fdmc}")
 
     # ---- energy-to-solution, mixed vs FP64, same solve
     energy = None if args.no_energy else energy_to_solution(
@@ -608,6 +613,7 @@ def main():
         "ax_dssum": axd,
         "energy": energy,
         "jacobi": jac,
+        "fdm": fdmc,
         "roofline": {"bound": "hbm", "kernel": f"k_ax<NP=10,f32,f32,CG> variant {tuned['fp32'][0]} (add2s1 + ax_e + correction update)",
                      "achieved": round(achieved, 1) if achieved else None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None,
