@@ -263,8 +263,9 @@ int nek_prof_read(nek_ctx *ctx, int kernel, double *total_ms, int64_t *count, in
  * slices of geometric factors in flight).  nek_num_variants returns their
  * number for the context's N (or a negative status).  nek_tune times
  * `iters` (>= 2) CG iterations of every configuration on a synthetic SPD
- * system of the context's mesh at precision prec (nek_prec), after one
- * warm-up pass each; it fills us_per_iter[v] (may be NULL, else at least
+ * system of the context's mesh at precision prec (nek_prec), with the
+ * context's preconditioner (the kernels of a preconditioned loop differ),
+ * after one warm-up pass each; it fills us_per_iter[v] (may be NULL, else at least
  * nek_num_variants entries), selects the fastest for later solves at that
  * precision and returns its index in *best (may be NULL).  It overwrites the
  * context's work vectors, not caller memory; it synchronises the stream.

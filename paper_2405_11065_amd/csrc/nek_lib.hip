@@ -895,15 +895,18 @@ int nek_tune(nek_ctx *c, int prec, int iters, double *us_per_iter, int *best)
     for (int v = 0; v < nv && rc == NEK_OK; ++v) {
         float ms = 0;
         for (int rep = 0; rep < 2 && rc == NEK_OK; ++rep) {   // first pass warms up
+            // the run starts as a solve does, through the preconditioner (if any)
+            int rs = 1;
             if (prec == NEK_PREC_FP64) {
                 HIP_TRY(hipMemcpyAsync(c->r64, c->b, c->nl * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-                if ((rc = glsc3_to_slot(c, c->r64, c->r64, NEK_F64, 1)) || (rc = fill<double>(c, c->d64, 0.0, c->nl)))
+                if ((rc = glsc3_to_slot(c, c->r64, c->r64, NEK_F64, 1)) || (rc = fill<double>(c, c->d64, 0.0, c->nl)) ||
+                    (rc = pc_start64(c, c->r64, &rs)))
                     break;
             } else {
                 if ((rc = ops(c)->inner_start(c, c->b, c->r32, c->d32))) break;
-                if ((rc = red_final(c, 1))) break;
+                if ((rc = red_final(c, 1)) || (rc = pc_start32(c, c->r32, &rs))) break;
             }
-            if ((rc = start_launch(c, 1, 0, 0.0, iters, 0))) break;
+            if ((rc = start_launch(c, rs, 0, 0.0, iters, 0, 0.0, 1))) break;
             HIP_TRY(hipEventRecord(e0, c->stream));
             rc = run_cg(c, iters, [&](int it, bool final) -> int { return cg_iter(c, prec, v, it, final, xt); });
             HIP_TRY(hipEventRecord(e1, c->stream));

@@ -94,3 +94,26 @@ def test_high_orders(N, nel, pc):
         print(f"  {st['iters']} its, true residual {res:.3e}")
         assert res <= 1e-8
         ctx.close()
+
+
+@pytest.mark.parametrize("pc", ["jacobi", "fdm"])
+def test_tuning_with_preconditioner(pc):
+    """The autotuner starts its timing runs as a solve does (z = M^-1 r), so
+    the preconditioned kernels never read a z vector nothing has written:
+    every configuration gives a finite time of a whole iteration (none of
+    the runs ends at once on a non-finite value), and the tuned context
+    solves to the tolerance."""
+    N, nel = 9, (4, 4, 4)
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=13)
+    P = oracle.Problem(N, nel, vtx)
+    f = dev(synth.uniform_load(P.nl, 36))
+    ctx = nek.Context(nel, N, vtx=vtx, prec="fp32", precond=pc)
+    _case(f"tune with {pc}")
+    best, us = ctx.tune("fp32", iters=8)
+    print(f"  us per iteration {[round(u, 1) for u in us]}, best {best}")
+    assert all(np.isfinite(u) and u > 0 for u in us)
+    # each configuration runs a whole iteration: none of them ends at once
+    assert min(us) > 0.3 * max(us)
+    x, st, _ = ctx.cg_solve(f, tol=1e-8, maxit=5000, raise_on_noconv=True)
+    assert P.true_residual(x.cpu().numpy(), f.cpu().numpy()) <= 1e-8
+    ctx.close()
