@@ -318,6 +318,17 @@ def test_full_size_16cubed_N9():
     dx = np.linalg.norm(res["fp32"][0] - res["fp64"][0]) / np.linalg.norm(res["fp64"][0])
     print(f"  |x_mixed - x_fp64| / |x_fp64| = {dx:.2e}")
     assert dx <= 1e-6
+    # both preconditioners on the benchmarked workload, FP64 and mixed
+    for pc in ("jacobi", "fdm"):
+        ctx.set_precond(pc)
+        for prec in ("fp64", "fp32"):
+            ctx.set_prec(prec)
+            ctx.tune(prec, iters=10)
+            _case(f"cg 16^3 N=9 {prec} {pc}")
+            x, st, _ = ctx.cg_solve(fd, tol=1e-8, maxit=20000)
+            rho = P.true_residual(host(x), f)
+            print(f"  {prec} {pc}: iters {st['iters']} outer {st['outer_iters']} rho* {rho:.2e}")
+            assert st["status"] == 0 and rho <= 1e-8 and st["iters"] < res[prec][1]["iters"]
     ctx.close()
 
 
@@ -339,4 +350,13 @@ def test_full_size_32cubed_N9_bf16g():
     print(f"  bf16g: iters {st['iters']} outer {st['outer_iters']} fp64 {st['fp64_iters']} "
           f"t {st['t_solve_s']:.3f}s rho* {rho:.2e}")
     assert st["status"] == 0 and rho <= 1e-8
+    # the same solve with each preconditioner, as the benchmark times it
+    for pc in ("jacobi", "fdm"):
+        ctx.set_precond(pc)
+        ctx.tune("bf16g", iters=10)
+        _case(f"cg 32^3 N=9 bf16g {pc}")
+        xp, sp, _ = ctx.cg_solve(dev(f_gpu), tol=1e-8, maxit=20000)
+        rho = P.true_residual(host(xp), f_or)
+        print(f"  bf16g {pc}: iters {sp['iters']} outer {sp['outer_iters']} t {sp['t_solve_s']:.3f}s rho* {rho:.2e}")
+        assert sp["status"] == 0 and rho <= 1e-8 and sp["iters"] < st["iters"]
     ctx.close()
