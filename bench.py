@@ -481,6 +481,37 @@ def profile_sequence(torch, nek, synth, variants=""):
     ctx.close()
 
 
+def profile_ax(torch, nek, synth, ne, variants=""):
+    """nek_ax on the ne^3 deformed mesh of [0,1]^3 (N=9, the 32^3 workload's
+    mesh at ne = 32), five calls per precision in the given (else the tuned)
+    configuration, then a 256 MiB copy for counter calibration: the sequence
+    for hardware-counter runs of the operator and assembly passes."""
+    nel = (ne, ne, ne)
+    vtx = synth.box_vertices(nel, hi=(1.0, 1.0, 1.0), perturb=0.1, seed=synth.SEED_C3_VERTICES)
+    ctx = nek.Context(nel, 9, vtx=vtx, prec="fp32")
+    chosen = dict(kv.split("=") for kv in variants.split(",") if kv)
+    out = {}
+    for prec, dt in (("fp32", torch.float32), ("bf16g", torch.float32), ("fp64", torch.float64)):
+        ctx.set_prec(prec)
+        if prec in chosen:
+            ctx.set_variant(prec, int(chosen[prec]))
+        else:
+            ctx.tune(prec, iters=5)
+        u = torch.rand(ctx.nl, dtype=dt, device="cuda")
+        w = torch.empty_like(u)
+        for _ in range(5):
+            ctx.ax(u, w)
+        out[prec] = ctx.get_variant(prec)
+    a = torch.empty(1 << 25, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_ax": {"nel": ne, "local_points": ctx.nl, "variants": out},
+                      "copy_bytes": a.numel() * 8}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -496,8 +527,11 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for hardware-counter runs: 40 mixed and 40 FP64 CG iterations, "
                          "5 nek_ax per precision and a 256 MiB copy for calibration")
+    ap.add_argument("--profile-ax", type=int, default=0, metavar="NE",
+                    help="short nek_ax sequence on the NE^3 deformed N=9 mesh (5 calls per precision) and a "
+                         "256 MiB copy, for counter runs of the operator and assembly passes")
     ap.add_argument("--variants", default="",
-                    help="with --profile: kernel configurations to use, e.g. fp32=4,fp64=2,bf16g=5 "
+                    help="with --profile or --profile-ax: kernel configurations to use, e.g. fp32=4,fp64=2,bf16g=5 "
                          "(default: run the autotuner)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -513,6 +547,8 @@ def main():
 
     if args.profile:
         return profile_sequence(torch, nek, synth, args.variants)
+    if args.profile_ax:
+        return profile_ax(torch, nek, synth, args.profile_ax, args.variants)
 
     ctx = nek.Context(NEL, N, prec="fp32")
     nl = ctx.nl
