@@ -104,6 +104,16 @@ typedef enum {
                                 on the other nodes: the non-overlapping Schwarz stage  */
 } nek_pc;
 
+/* Source of the geometric factors g1..g6 in the operator kernels. */
+typedef enum {
+    NEK_GEOM_STORED = 0,     /* read per point from memory: the FP64 array, or its
+                                FP32 / BF16 copy                                        */
+    NEK_GEOM_TRILINEAR = 1   /* recomputed in the kernel, in the vectors' precision,
+                                from each element's trilinear map (21 coefficients per
+                                element): FP64 and FP32 operators; BF16-g solves keep
+                                their stored factors                                   */
+} nek_geom;
+
 typedef struct {
     int iters;               /* CG iterations (mixed: sum of inner iterations)   */
     int outer_iters;         /* mixed: refinement steps (true-residual checks)   */
@@ -181,6 +191,22 @@ int nek_set_prec(nek_ctx *ctx, int prec);
  * preconditioner (NEK_E_ARG).
  */
 int nek_set_precond(nek_ctx *ctx, int precond);
+
+/*
+ * nek_set_geometry -- source (nek_geom) of the geometric factors of the
+ * element operator ax_e (Fig. 2: g1..g6 between local_grad3 and
+ * local_grad3_t) in every later operator call and solve of the context.
+ * The paper's Nekbone computes the factors once at set-up from the
+ * trilinear element map and reads six per point in every ax_e; with
+ * NEK_GEOM_TRILINEAR the kernels compute the same quantities per point
+ * (J from the map's coefficients, G = w det(J) J^-1 J^-T), trading six
+ * loads per point for about 60 arithmetic operations.  Builds the
+ * coefficients on first use (host FP64; an FP32 copy for FP32 operators).
+ * Returns NEK_E_JACOBIAN if an element's map is not orientation-preserving
+ * at a GLL node, NEK_E_ARG for an unknown mode.  Batches refuse member
+ * contexts with NEK_GEOM_TRILINEAR (NEK_E_ARG).
+ */
+int nek_set_geometry(nek_ctx *ctx, int geom);
 
 /*
  * nek_precond_apply -- z = M^-1 r with the context's preconditioner (a copy

@@ -542,7 +542,7 @@ int nek_batch_solve(nek_batch *b, const double *const *f, const double *const *x
     const int n = nprob(b);
     const int prec = b->ctx[0]->prec;
     for (int m = 0; m < n; ++m)
-        if (!f[m] || !x[m] || b->ctx[m]->prec != prec || b->ctx[m]->precond) return NEK_E_ARG;
+        if (!f[m] || !x[m] || b->ctx[m]->prec != prec || b->ctx[m]->precond || b->ctx[m]->geom) return NEK_E_ARG;
     const bool graph = !(flags & NEK_BATCH_NO_GRAPH);
     // the solve follows the caller's earlier work on its stream
     HIP_TRY(hipEventRecord(b->entry, b->user));

@@ -108,6 +108,11 @@ struct nek_ctx {
     double *g64 = nullptr;
     float *g32 = nullptr;
     uint16_t *g16 = nullptr;
+    // NEK_GEOM_TRILINEAR: the operator kernels recompute the factors from
+    // per-element trilinear coefficients (header + [E][24], FP64 and FP32)
+    int geom = 0;
+    double *tri64 = nullptr;
+    float *tri32 = nullptr;
     double *B = nullptr;
     int32_t *perm = nullptr, *segptr = nullptr;
     int8_t *segflag = nullptr;
@@ -168,6 +173,13 @@ inline unsigned red_grid(const nek_ctx *c)
 }
 
 inline int ax_groups(const nek_ctx *c, int epw) { return (int)((c->E + epw - 1) / epw); }
+
+// Trilinear-coefficient buffer of the vectors' type, as the operator's tag type.
+template <typename T> inline const TriG<T> *tri_ptr(const nek_ctx *c)
+{
+    if constexpr (sizeof(T) == 8) return reinterpret_cast<const TriG<T> *>(c->tri64);
+    else return reinterpret_cast<const TriG<T> *>(c->tri32);
+}
 
 inline unsigned ax_grid(const nek_ctx *c, int epw)
 {
@@ -247,6 +259,7 @@ int pc_start64(nek_ctx *c, double *r, int *rtz_slot);
 int pc_start32(nek_ctx *c, float *r, int *rtz_slot);
 int ensure_diag(nek_ctx *c);
 int ensure_fdm(nek_ctx *c);
+int ensure_tri(nek_ctx *c);
 int cg_prologue(nek_ctx *c, const double *f, const double *x0, double *x, double *r);
 int ax_local_launch(nek_ctx *c, const void *u, void *w, int dtype, int prec);
 int resid_launch(nek_ctx *c, const double *b, const double *w, double *r, int slot);

@@ -28,6 +28,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 namespace nek {
 
@@ -306,6 +307,126 @@ template <> struct GLoad<uint16_t> {   // BF16 bit patterns, two per 32-bit word
     }
 };
 
+// Geometric factors recomputed in the kernel from each element's trilinear
+// map instead of read from memory.  Every element is the trilinear image of
+// its 8 vertices, x(r,s,t) = a0 + a1 r + a2 s + a3 t + a4 rs + a5 rt + a6 st
+// + a7 rst per coordinate, so with J = [x_r x_s x_t]
+//   x_r = (a1 + a4 s) + (a5 + a7 s) t,  x_s = (a2 + a4 r) + (a6 + a7 r) t,
+//   x_t = a3 + a5 r + a6 s + a7 r s,
+// and with c_r = x_s x x_t, c_s = x_t x x_r, c_t = x_r x x_s (the rows of
+// det(J) J^-1) and det(J) = x_r . c_r the factors are
+//   G_ab = w_i w_j w_k (c_a . c_b) / det(J),
+// the same quantities the stored arrays hold (applied without forming them).  Buffer layout, in the
+// vector type: a header of TRI_HDR entries (GLL nodes xi[NP], then weights
+// w[NP]), then per element 3 records of 8 (a1..a7 and a zero, one record per
+// coordinate).  The tag type selects this path wherever a factor-storage
+// type is expected; it is never dereferenced as such.
+template <typename T> struct TriG { T v; };
+template <typename GT> struct TriOf { static constexpr bool value = false; using type = void; };
+template <typename T> struct TriOf<TriG<T>> { static constexpr bool value = true; using type = T; };
+constexpr int TRI_HDR = 32;   // 2 * MAX_NP
+constexpr int TRI_REC = 24;   // entries per element
+
+template <typename T> struct GLoad<TriG<T>> {
+    struct Raw {};
+    __device__ static Raw load(const TriG<T> *) { return Raw{}; }
+    template <typename U> __device__ static void unpack(const Raw &, U o[6])
+    {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) o[q] = 0;
+    }
+};
+
+// The 24 coefficients of one element, loaded with 16-byte loads.
+template <typename T> struct TriRaw { T a[TRI_REC]; };
+template <typename T> __device__ __forceinline__ TriRaw<T> tri_load(const T *__restrict__ rec)
+{
+    TriRaw<T> o;
+    if constexpr (sizeof(T) == 4) {
+        const float4 *q = reinterpret_cast<const float4 *>(rec);
+#pragma unroll
+        for (int m = 0; m < TRI_REC / 4; ++m) {
+            const float4 v = q[m];
+            o.a[4 * m + 0] = v.x; o.a[4 * m + 1] = v.y; o.a[4 * m + 2] = v.z; o.a[4 * m + 3] = v.w;
+        }
+    } else {
+        const double2 *q = reinterpret_cast<const double2 *>(rec);
+#pragma unroll
+        for (int m = 0; m < TRI_REC / 2; ++m) {
+            const double2 v = q[m];
+            o.a[2 * m + 0] = v.x; o.a[2 * m + 1] = v.y;
+        }
+    }
+    return o;
+}
+
+// Column (r, s) = (xi_i, xi_j) of one element: the parts of x_r and x_s
+// that do not depend on t, and x_t.
+template <typename T> struct TriCol { T pr[3], qr[3], ps[3], qs[3], xt[3]; };
+template <typename T> __device__ __forceinline__ TriCol<T> tri_col(const TriRaw<T> &R, T r, T s)
+{
+    TriCol<T> c;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T *a = R.a + 8 * d;   // a1..a7 at a[0..6]
+        c.pr[d] = a[0] + a[3] * s;
+        c.qr[d] = a[4] + a[6] * s;
+        c.ps[d] = a[1] + a[3] * r;
+        c.qs[d] = a[5] + a[6] * r;
+        c.xt[d] = a[2] + a[4] * r + (a[5] + a[6] * r) * s;
+    }
+    return c;
+}
+
+// 1 / d: the hardware reciprocal, refined by two Newton steps in FP64.
+__device__ __forceinline__ float tri_rcp(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double tri_rcp(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// At t = xi_k: the rows c_r, c_s, c_t of det(J) J^-1 (K[a][d] = c_a[d]) and
+// f = w_i w_j w_k / det(J).  Applied to the reference gradient
+// (u_r, u_s, u_t) the factors give G (u_r, u_s, u_t) = f K (K^T (u_r, u_s, u_t)),
+// 21 operations instead of forming the six factors (24) and applying them (9).
+template <typename T> __device__ __forceinline__ void tri_rows(const TriCol<T> &c, T t, T wijk, T K[3][3], T &f)
+{
+    T xr[3], xs[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        xr[d] = c.pr[d] + c.qr[d] * t;
+        xs[d] = c.ps[d] + c.qs[d] * t;
+    }
+    const T *xt = c.xt;
+    K[0][0] = xs[1] * xt[2] - xs[2] * xt[1];
+    K[0][1] = xs[2] * xt[0] - xs[0] * xt[2];
+    K[0][2] = xs[0] * xt[1] - xs[1] * xt[0];
+    K[1][0] = xt[1] * xr[2] - xt[2] * xr[1];
+    K[1][1] = xt[2] * xr[0] - xt[0] * xr[2];
+    K[1][2] = xt[0] * xr[1] - xt[1] * xr[0];
+    K[2][0] = xr[1] * xs[2] - xr[2] * xs[1];
+    K[2][1] = xr[2] * xs[0] - xr[0] * xs[2];
+    K[2][2] = xr[0] * xs[1] - xr[1] * xs[0];
+    const T det = xr[0] * K[0][0] + xr[1] * K[0][1] + xr[2] * K[0][2];
+    f = wijk * tri_rcp(det);
+}
+
+// (w_r, w_s, w_t) = f K K^T (u_r, u_s, u_t).
+template <typename T>
+__device__ __forceinline__ void tri_apply(const T K[3][3], T f, T ur, T us, T ut, T &wr, T &ws, T &wt)
+{
+    T v[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) v[d] = f * (K[0][d] * ur + K[1][d] * us + K[2][d] * ut);
+    wr = K[0][0] * v[0] + K[0][1] * v[1] + K[0][2] * v[2];
+    ws = K[1][0] * v[0] + K[1][1] * v[1] + K[1][2] * v[2];
+    wt = K[2][0] * v[0] + K[2][1] * v[1] + K[2][2] * v[2];
+}
+
 // ---------------------------------------------------------------- operator
 
 // One workgroup = EPW elements x (NP x NP) threads; thread (i, j) walks the
@@ -386,12 +507,30 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
     // reduction.  Threads past the last element work on a copy of element
     // E-1 and store nothing (local indices fit in 32 bits, checked at set-up).
     typename GL::Raw gb[PD];
+    // in-kernel factors: the element's coefficients are requested where the
+    // stored path requests its first slices
+    constexpr bool TRI = TriOf<GT>::value;
+    using TV = std::conditional_t<TRI, T, float>;
+    const TV *tg = reinterpret_cast<const TV *>(g);
+    TriRaw<TV> traw;
+    TV txi = 0, txj = 0, twij = 0;
+    if constexpr (TRI) {
+        static_assert(std::is_same_v<typename TriOf<GT>::type, T>, "factors in the vectors' type");
+        txi = tg[i];
+        txj = tg[j];
+        twij = tg[NP + i] * tg[NP + j];
+    }
     auto g_first = [&](int grp) {
         const int e = grp * EPW + el;
-        const GT *ge = g + (size_t)((e < E ? e : E - 1) * NP3 + ij) * 6;
+        const int ec = e < E ? e : E - 1;
+        if constexpr (TRI) {
+            traw = tri_load<TV>(tg + TRI_HDR + (size_t)ec * TRI_REC);
+        } else {
+            const GT *ge = g + (size_t)(ec * NP3 + ij) * 6;
 #pragma unroll
-        for (int s = 0; s < PD; ++s)
-            if (s < NP) gb[s] = GL::load(ge + (size_t)s * NP2 * 6);
+            for (int s = 0; s < PD; ++s)
+                if (s < NP) gb[s] = GL::load(ge + (size_t)s * NP2 * 6);
+        }
     };
     if (g0 < g1) g_first(g0);
     T beta = 0;
@@ -463,7 +602,7 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
         const int e = grp * EPW + el;
         const bool valid = e < E;
         const int base = (valid ? e : E - 1) * NP3 + ij;
-        const GT *ge = g + (size_t)base * 6;
+        const GT *ge = TRI ? g : g + (size_t)base * 6;
         if (grp > g0) g_first(grp);
         T u[NP];
         __syncthreads();   // LDS of the previous group is free
@@ -486,12 +625,16 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
         }
         __syncthreads();
         if constexpr (DPH) d_rows(sDD, Dri, Dsj);   // rows i and j of D
+        TriCol<TV> tcol;
+        if constexpr (TRI) tcol = tri_col<TV>(traw, txi, txj);
         T wt[NP];
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             __builtin_amdgcn_sched_barrier(0);
             T gk[6];
-            GL::unpack(gb[k % PD], gk);
+            TV tK[3][3], tf = 0;
+            if constexpr (TRI) tri_rows<TV>(tcol, tg[k], twij * tg[NP + k], tK, tf);
+            else GL::unpack(gb[k % PD], gk);
             T ur = 0, us = 0, ut = 0;
             if constexpr (ROWS) {
                 T rr[RP], rs[RP];
@@ -512,11 +655,20 @@ __device__ __forceinline__ void ax_body(const T *__restrict__ src, T *__restrict
                 }
             }
             // wr by rows of constant j; ws by rows of constant i (transposed)
-            sre[k * SL + j * RP + i] = gk[0] * ur + gk[3] * us + gk[4] * ut;
-            sse[k * SL + (ROWS ? i * RP + j : j * NP + i)] = gk[3] * ur + gk[1] * us + gk[5] * ut;
-            wt[k] = gk[4] * ur + gk[5] * us + gk[2] * ut;
+            T gr, gs, gt;
+            if constexpr (TRI) {
+                tri_apply<TV>(tK, tf, ur, us, ut, gr, gs, gt);
+            } else {
+                gr = gk[0] * ur + gk[3] * us + gk[4] * ut;
+                gs = gk[3] * ur + gk[1] * us + gk[5] * ut;
+                gt = gk[4] * ur + gk[5] * us + gk[2] * ut;
+            }
+            sre[k * SL + j * RP + i] = gr;
+            sse[k * SL + (ROWS ? i * RP + j : j * NP + i)] = gs;
+            wt[k] = gt;
             __builtin_amdgcn_sched_barrier(0);
-            if (k + PD < NP) gb[k % PD] = GL::load(ge + (size_t)(k + PD) * NP2 * 6);
+            if constexpr (!TRI)
+                if (k + PD < NP) gb[k % PD] = GL::load(ge + (size_t)(k + PD) * NP2 * 6);
         }
         __syncthreads();
         if constexpr (DPH) d_rows(sDD + NP * NP, DTi, DTj);   // columns i and j of D

@@ -217,6 +217,19 @@ int ensure_diag(nek_ctx *c)
     return NEK_OK;
 }
 
+int ensure_tri(nek_ctx *c)
+{
+    if (c->tri64 && c->tri32) return NEK_OK;
+    std::vector<double> t;
+    if (trilinear_coefs(c->N, c->nel, c->vtx, c->xi, c->w, TRI_HDR, t)) return NEK_E_JACOBIAN;
+    std::vector<float> t32(t.begin(), t.end());   // round to nearest even
+    if (dalloc(c->tri64, t.size()) || dalloc(c->tri32, t.size())) return NEK_E_OOM;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(c->tri64, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->tri32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
+    return NEK_OK;
+}
+
 int ensure_fdm(nek_ctx *c)
 {
     int rc = ensure_diag(c);
@@ -592,7 +605,7 @@ void nek_free(nek_ctx *c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    dfree(c->D64); dfree(c->D32); dfree(c->g64); dfree(c->g32); dfree(c->g16); dfree(c->B);
+    dfree(c->D64); dfree(c->D32); dfree(c->g64); dfree(c->g32); dfree(c->g16); dfree(c->tri64); dfree(c->tri32); dfree(c->B);
     dfree(c->perm); dfree(c->segptr); dfree(c->segflag); dfree(c->sc); dfree(c->partials); dfree(c->hist);
     dfree(c->b); dfree(c->r64); dfree(c->p64); dfree(c->w64); dfree(c->d64); dfree(c->d32);
     dfree(c->r32); dfree(c->p32); dfree(c->w32); dfree(c->dg64); dfree(c->dg32);
@@ -757,6 +770,17 @@ int nek_set_precond(nek_ctx *c, int precond)
     }
     c->precond = precond;
     c->opts.precond = precond;
+    return NEK_OK;
+}
+
+int nek_set_geometry(nek_ctx *c, int geom)
+{
+    if (!c || geom < NEK_GEOM_STORED || geom > NEK_GEOM_TRILINEAR) return NEK_E_ARG;
+    if (geom == NEK_GEOM_TRILINEAR) {
+        const int rc = ensure_tri(c);
+        if (rc) return rc;
+    }
+    c->geom = geom;
     return NEK_OK;
 }
 

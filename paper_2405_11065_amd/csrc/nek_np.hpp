@@ -138,14 +138,20 @@ template <int NP> struct OpsImpl {
         return cg_iter_pc<T, GT, false>(c, variant, it, final, x, r, p, w, g, D, nullptr);
     }
 
+    // FP64 and FP32 operators read the stored factors, or recompute them in
+    // the kernel from the elements' trilinear coefficients (c->geom).
     static int cg_iter64(nek_ctx *c, int v, int it, bool final, double *x, double *r, double *p, double *w,
                          const double *g, const double *D)
     {
+        if (c->geom == NEK_GEOM_TRILINEAR)
+            return cg_iter<double, TriG<double>>(c, v, it, final, x, r, p, w, tri_ptr<double>(c), D);
         return cg_iter<double, double>(c, v, it, final, x, r, p, w, g, D);
     }
     static int cg_iter32(nek_ctx *c, int v, int it, bool final, float *x, float *r, float *p, float *w,
                          const float *g, const float *D)
     {
+        if (c->geom == NEK_GEOM_TRILINEAR)
+            return cg_iter<float, TriG<float>>(c, v, it, final, x, r, p, w, tri_ptr<float>(c), D);
         return cg_iter<float, float>(c, v, it, final, x, r, p, w, g, D);
     }
     static int cg_iter16(nek_ctx *c, int v, int it, bool final, float *x, float *r, float *p, float *w,
@@ -156,10 +162,16 @@ template <int NP> struct OpsImpl {
 
     static int ax64(nek_ctx *c, const double *u, double *w)
     {
+        if (c->geom == NEK_GEOM_TRILINEAR)
+            return launch_ax<epw_for(NP), pd_for<double>(), double, TriG<double>, false>(c, u, nullptr, w,
+                                                                                         tri_ptr<double>(c), c->D64, 0);
         return launch_ax<epw_for(NP), pd_for<double>(), double, double, false>(c, u, nullptr, w, c->g64, c->D64, 0);
     }
     static int ax32(nek_ctx *c, const float *u, float *w)
     {
+        if (c->geom == NEK_GEOM_TRILINEAR)
+            return launch_ax<epw_for(NP), pd_for<float>(), float, TriG<float>, false>(c, u, nullptr, w,
+                                                                                      tri_ptr<float>(c), c->D32, 0);
         return launch_ax<epw_for(NP), pd_for<float>(), float, float, false>(c, u, nullptr, w, c->g32, c->D32, 0);
     }
     static int ax16(nek_ctx *c, const float *u, float *w)
@@ -185,10 +197,14 @@ template <int NP> struct OpsImpl {
     }
     static int axa64(nek_ctx *c, int v, const double *u, double *scratch, double *w)
     {
+        if (c->geom == NEK_GEOM_TRILINEAR)
+            return ax_assembled<double, TriG<double>>(c, v, u, scratch, w, tri_ptr<double>(c), c->D64);
         return ax_assembled<double, double>(c, v, u, scratch, w, c->g64, c->D64);
     }
     static int axa32(nek_ctx *c, int v, const float *u, float *scratch, float *w)
     {
+        if (c->geom == NEK_GEOM_TRILINEAR)
+            return ax_assembled<float, TriG<float>>(c, v, u, scratch, w, tri_ptr<float>(c), c->D32);
         return ax_assembled<float, float>(c, v, u, scratch, w, c->g32, c->D32);
     }
     static int axa16(nek_ctx *c, int v, const float *u, float *scratch, float *w)

@@ -172,6 +172,62 @@ static int element_geometry(int N, const std::vector<double> &x, const std::vect
     return bad;
 }
 
+int trilinear_coefs(int N, const int nel[3], const std::vector<double> &vtx, const std::vector<double> &x,
+                    const std::vector<double> &w, int hdr, std::vector<double> &out)
+{
+    const int n = N + 1;
+    const long E = (long)nel[0] * nel[1] * nel[2];
+    const long vx = nel[0] + 1, vy = nel[1] + 1;
+    out.assign((size_t)hdr + (size_t)E * 24, 0.0);
+    for (int i = 0; i < n; ++i) {
+        out[i] = x[i];
+        out[n + i] = w[i];
+    }
+    int bad = 0;
+    for (long e = 0; e < E; ++e) {
+        const long ex = e % nel[0], ey = (e / nel[0]) % nel[1], ez = e / ((long)nel[0] * nel[1]);
+        double *rec = &out[hdr + (size_t)e * 24];
+        double A[3][8];
+        for (int d = 0; d < 3; ++d) {
+            // a_m = 1/8 sum_v (product of the vertex's signs in m's variables) X_v
+            double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int v = 0; v < 8; ++v) {
+                const long ia = ex + (v & 1), ib = ey + ((v >> 1) & 1), ic = ez + (v >> 2);
+                const double X = vtx[3 * (ia + vx * (ib + vy * ic)) + d];
+                const double sr = (v & 1) ? 1.0 : -1.0, ss = (v & 2) ? 1.0 : -1.0, st = (v & 4) ? 1.0 : -1.0;
+                a[0] += X;
+                a[1] += sr * X;
+                a[2] += ss * X;
+                a[3] += st * X;
+                a[4] += sr * ss * X;
+                a[5] += sr * st * X;
+                a[6] += ss * st * X;
+                a[7] += sr * ss * st * X;
+            }
+            for (int m = 0; m < 8; ++m) A[d][m] = 0.125 * a[m];
+            for (int m = 0; m < 7; ++m) rec[8 * d + m] = A[d][m + 1];
+        }
+        // the Jacobian determinant at every GLL node must be positive
+        for (int k = 0; k < n && !bad; ++k)
+            for (int j = 0; j < n && !bad; ++j)
+                for (int i = 0; i < n; ++i) {
+                    const double r = x[i], s = x[j], t = x[k];
+                    double J[3][3];
+                    for (int d = 0; d < 3; ++d) {
+                        const double *a = A[d];
+                        J[d][0] = a[1] + a[4] * s + a[5] * t + a[7] * s * t;
+                        J[d][1] = a[2] + a[4] * r + a[6] * t + a[7] * r * t;
+                        J[d][2] = a[3] + a[5] * r + a[6] * s + a[7] * r * s;
+                    }
+                    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                    if (!(det > 0)) { bad = 1; break; }
+                }
+    }
+    return bad;
+}
+
 int geometry(int N, const int nel[3], const std::vector<double> &vtx, const std::vector<double> &x,
              const std::vector<double> &w, const std::vector<double> &D, double *g, double *B, double *X)
 {

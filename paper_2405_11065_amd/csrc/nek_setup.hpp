@@ -34,6 +34,14 @@ void fdm_modes(int N, const std::vector<double> &w, const std::vector<double> &D
                std::vector<double> &lam);
 void fdm_scales(const int nel[3], const std::vector<double> &vtx, double *cf);
 
+// Coefficients of every element's trilinear map for the in-kernel factors:
+// out = [hdr entries: x[0..N], w[0..N], zeros] then per element, per
+// coordinate d, (a1..a7, 0) of x_d(r,s,t) = a0 + a1 r + a2 s + a3 t + a4 rs
+// + a5 rt + a6 st + a7 rst.  Returns nonzero if any element's Jacobian
+// determinant is not positive at a GLL node.
+int trilinear_coefs(int N, const int nel[3], const std::vector<double> &vtx, const std::vector<double> &x,
+                    const std::vector<double> &w, int hdr, std::vector<double> &out);
+
 // Per-local-node global id, multiplicity and Dirichlet mask (any may be null).
 void numbering(int N, const int nel[3], int64_t *gid, int32_t *mult, int8_t *mask);
 

@@ -27,9 +27,11 @@ PC_NAMES = {"none": NEK_PC_NONE, "jacobi": NEK_PC_JACOBI, "fdm": NEK_PC_FDM}
 (NEK_SIZE_NLOCAL, NEK_SIZE_NGLOBAL, NEK_SIZE_E, NEK_SIZE_NPERM, NEK_SIZE_NSEG, NEK_SIZE_N) = range(6)
 
 PREC_NAMES = {"fp64": NEK_PREC_FP64, "fp32": NEK_PREC_FP32, "bf16g": NEK_PREC_BF16G}
+NEK_GEOM_STORED, NEK_GEOM_TRILINEAR = 0, 1
+GEOM_NAMES = {"stored": NEK_GEOM_STORED, "trilinear": NEK_GEOM_TRILINEAR}
 
 # every entry point declared in include/nek.h
-EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_set_precond", "nek_precond_apply", "nek_ax_local", "nek_ax",
+EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_set_precond", "nek_set_geometry", "nek_precond_apply", "nek_ax_local", "nek_ax",
            "nek_dssum", "nek_glsc3", "nek_cg_solve", "nek_prof_enable", "nek_prof_read", "nek_num_variants",
            "nek_tune", "nek_set_variant", "nek_get_variant", "nek_batch_setup", "nek_batch_free",
            "nek_batch_size", "nek_batch_ctx", "nek_batch_orders", "nek_batch_tune", "nek_batch_set_variant",
@@ -87,6 +89,7 @@ def load(path: str = LIB_PATH):
     lib.nek_get.argtypes = [vp, ctypes.c_int, vp]
     lib.nek_set_prec.argtypes = [vp, ctypes.c_int]
     lib.nek_set_precond.argtypes = [vp, ctypes.c_int]
+    lib.nek_set_geometry.argtypes = [vp, ctypes.c_int]
     lib.nek_precond_apply.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_ax_local.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_ax.argtypes = [vp, vp, vp, ctypes.c_int]
@@ -273,6 +276,12 @@ class Context:
         (element-interior fast-diagonalization block solve, diagonal elsewhere)."""
         _check(self._lib.nek_set_precond(self._h, PC_NAMES[precond] if isinstance(precond, str) else int(precond)),
                "nek_set_precond")
+
+    def set_geometry(self, geom):
+        """'stored' (read g1..g6 per point) or 'trilinear' (FP64 and FP32 operators
+        recompute them in the kernel from each element's trilinear map)."""
+        _check(self._lib.nek_set_geometry(self._h, GEOM_NAMES[geom] if isinstance(geom, str) else int(geom)),
+               "nek_set_geometry")
 
     def precond_apply(self, r, z=None):
         """z = M^-1 r with the context's preconditioner."""
