@@ -266,6 +266,40 @@ def precond_case(torch, ctx, f, steps, base, pc="jacobi"):
     return out
 
 
+def geometry_case(torch, ctx, f, steps, base):
+    """The same solves with the geometric factors recomputed in the kernel
+    from each element's trilinear map (nek_set_geometry) instead of read from
+    memory: FP64 CG and the mixed solve, against the stored-factor runs in
+    `base` (prec -> (ms, iters))."""
+    out = {}
+    saved = {p: ctx.get_variant(p) for p in ("fp32", "fp64")}
+    x = ctx.new_vector()
+    ctx.set_geometry("trilinear")
+    try:
+        for prec in ("fp32", "fp64"):
+            ctx.set_prec(prec)
+            tuned = ctx.tune(prec, iters=30)
+            _, st, _ = ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its = 0
+            for _ in range(steps):
+                _, st, _ = ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+                its += st["iters"]
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            ms0, _ = base[prec]
+            out[prec] = {"ms_per_solve": round(dt * 1e3, 3), "iters": its / steps, "rel_res": st["rel_res"],
+                         "GDOF_iter_per_s": round(ctx.nl * its / steps / dt / 1e9, 3),
+                         "tuned_variant": tuned[0], "stored_factors_ms": round(ms0, 3),
+                         "speedup": round(ms0 / (dt * 1e3), 3)}
+    finally:
+        ctx.set_geometry("stored")
+        for p, v in saved.items():
+            ctx.set_variant(p, v)
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -523,7 +557,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned initial guess (data, training, eval)")
     ap.add_argument("--no-energy", action="store_true", help="skip the energy-to-solution measurement")
     ap.add_argument("--no-jacobi", action="store_true",
-                    help="skip the preconditioner measurements (diagonal and fast diagonalization)")
+                    help="skip the preconditioner (diagonal, fast diagonalization) and in-kernel geometry measurements")
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for hardware-counter runs: 40 mixed and 40 FP64 CG iterations, "
                          "5 nek_ax per precision and a 256 MiB copy for calibration")
@@ -604,6 +638,8 @@ def main():
     log(f"jacobi: {jac}")
     fdmc = None if args.no_jacobi else precond_case(torch, ctx, f, args.steps, base, "fdm")
     log(f"fdm: {fdmc}")
+    geo = None if args.no_jacobi else geometry_case(torch, ctx, f, args.steps, base)
+    log(f"trilinear geometry: {geo}")
 
     # ---- energy-to-solution, mixed vs FP64, same solve
     energy = None if args.no_energy else energy_to_solution(
@@ -650,6 +686,7 @@ def main():
         "energy": energy,
         "jacobi": jac,
         "fdm": fdmc,
+        "geometry_trilinear": geo,
         "roofline": {"bound": "hbm", "kernel": f"k_ax<NP=10,f32,f32,CG> variant {tuned['fp32'][0]} (add2s1 + ax_e + correction update)",
                      "achieved": round(achieved, 1) if achieved else None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None,
