@@ -45,6 +45,14 @@ int nek_host_segments(int N, const int nel[3], int32_t *perm, int32_t *seg_ptr, 
  * N >= 2. */
 int nek_host_fdm(int N, const int nel[3], const double *vtx, double *S, double *lam, double *cf);
 
+/* Trilinear map of every element, the input of the in-kernel geometric
+ * factors (nek_set_geometry): coef[E][3][8] = (a0..a7) of
+ * x_d(r,s,t) = a0 + a1 r + a2 s + a3 t + a4 rs + a5 rt + a6 st + a7 rst on
+ * [-1,1]^3, d = 0..2, from the vertex lattice vtx (as in nek_mesh).  Returns
+ * NEK_E_JACOBIAN (-4) when det(J) is not positive at some GLL node of order
+ * N (coef is still filled). */
+int nek_host_trilinear(int N, const int nel[3], const double *vtx, double *coef);
+
 #ifdef __cplusplus
 }
 #endif

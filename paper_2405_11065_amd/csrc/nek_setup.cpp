@@ -172,12 +172,72 @@ static int element_geometry(int N, const std::vector<double> &x, const std::vect
     return bad;
 }
 
+// A[d][m]: coefficient m of x_d(r,s,t) = a0 + a1 r + a2 s + a3 t + a4 rs
+// + a5 rt + a6 st + a7 rst for element e; a_m = 1/8 sum over the 8 vertices
+// of (the product of the vertex's +-1 coordinates in m's variables) X_v.
+// Returns nonzero if det(J) is not positive at some GLL node x^3.
+static int element_trilinear(const int nel[3], const std::vector<double> &vtx, const std::vector<double> &x, long e,
+                             double A[3][8])
+{
+    const long vx = nel[0] + 1, vy = nel[1] + 1;
+    const long ex = e % nel[0], ey = (e / nel[0]) % nel[1], ez = e / ((long)nel[0] * nel[1]);
+    for (int d = 0; d < 3; ++d) {
+        double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int v = 0; v < 8; ++v) {
+            const long ia = ex + (v & 1), ib = ey + ((v >> 1) & 1), ic = ez + (v >> 2);
+            const double X = vtx[3 * (ia + vx * (ib + vy * ic)) + d];
+            const double sr = (v & 1) ? 1.0 : -1.0, ss = (v & 2) ? 1.0 : -1.0, st = (v & 4) ? 1.0 : -1.0;
+            a[0] += X;
+            a[1] += sr * X;
+            a[2] += ss * X;
+            a[3] += st * X;
+            a[4] += sr * ss * X;
+            a[5] += sr * st * X;
+            a[6] += ss * st * X;
+            a[7] += sr * ss * st * X;
+        }
+        for (int m = 0; m < 8; ++m) A[d][m] = 0.125 * a[m];
+    }
+    const int n = (int)x.size();
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const double r = x[i], s = x[j], t = x[k];
+                double J[3][3];
+                for (int d = 0; d < 3; ++d) {
+                    const double *a = A[d];
+                    J[d][0] = a[1] + a[4] * s + a[5] * t + a[7] * s * t;
+                    J[d][1] = a[2] + a[4] * r + a[6] * t + a[7] * r * t;
+                    J[d][2] = a[3] + a[5] * r + a[6] * s + a[7] * r * s;
+                }
+                const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                   J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                   J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                if (!(det > 0)) return 1;
+            }
+    return 0;
+}
+
+int trilinear_all(int N, const int nel[3], const std::vector<double> &vtx, double *coef)
+{
+    std::vector<double> x, w;
+    gll_rule(N, x, w);
+    const long E = (long)nel[0] * nel[1] * nel[2];
+    int bad = 0;
+    for (long e = 0; e < E; ++e) {
+        double A[3][8];
+        bad |= element_trilinear(nel, vtx, x, e, A);
+        for (int d = 0; d < 3; ++d)
+            for (int m = 0; m < 8; ++m) coef[(e * 3 + d) * 8 + m] = A[d][m];
+    }
+    return bad;
+}
+
 int trilinear_coefs(int N, const int nel[3], const std::vector<double> &vtx, const std::vector<double> &x,
                     const std::vector<double> &w, int hdr, std::vector<double> &out)
 {
     const int n = N + 1;
     const long E = (long)nel[0] * nel[1] * nel[2];
-    const long vx = nel[0] + 1, vy = nel[1] + 1;
     out.assign((size_t)hdr + (size_t)E * 24, 0.0);
     for (int i = 0; i < n; ++i) {
         out[i] = x[i];
@@ -185,45 +245,11 @@ int trilinear_coefs(int N, const int nel[3], const std::vector<double> &vtx, con
     }
     int bad = 0;
     for (long e = 0; e < E; ++e) {
-        const long ex = e % nel[0], ey = (e / nel[0]) % nel[1], ez = e / ((long)nel[0] * nel[1]);
-        double *rec = &out[hdr + (size_t)e * 24];
         double A[3][8];
-        for (int d = 0; d < 3; ++d) {
-            // a_m = 1/8 sum_v (product of the vertex's signs in m's variables) X_v
-            double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            for (int v = 0; v < 8; ++v) {
-                const long ia = ex + (v & 1), ib = ey + ((v >> 1) & 1), ic = ez + (v >> 2);
-                const double X = vtx[3 * (ia + vx * (ib + vy * ic)) + d];
-                const double sr = (v & 1) ? 1.0 : -1.0, ss = (v & 2) ? 1.0 : -1.0, st = (v & 4) ? 1.0 : -1.0;
-                a[0] += X;
-                a[1] += sr * X;
-                a[2] += ss * X;
-                a[3] += st * X;
-                a[4] += sr * ss * X;
-                a[5] += sr * st * X;
-                a[6] += ss * st * X;
-                a[7] += sr * ss * st * X;
-            }
-            for (int m = 0; m < 8; ++m) A[d][m] = 0.125 * a[m];
+        bad |= element_trilinear(nel, vtx, x, e, A);
+        double *rec = &out[hdr + (size_t)e * 24];
+        for (int d = 0; d < 3; ++d)
             for (int m = 0; m < 7; ++m) rec[8 * d + m] = A[d][m + 1];
-        }
-        // the Jacobian determinant at every GLL node must be positive
-        for (int k = 0; k < n && !bad; ++k)
-            for (int j = 0; j < n && !bad; ++j)
-                for (int i = 0; i < n; ++i) {
-                    const double r = x[i], s = x[j], t = x[k];
-                    double J[3][3];
-                    for (int d = 0; d < 3; ++d) {
-                        const double *a = A[d];
-                        J[d][0] = a[1] + a[4] * s + a[5] * t + a[7] * s * t;
-                        J[d][1] = a[2] + a[4] * r + a[6] * t + a[7] * r * t;
-                        J[d][2] = a[3] + a[5] * r + a[6] * s + a[7] * r * s;
-                    }
-                    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
-                                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
-                                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-                    if (!(det > 0)) { bad = 1; break; }
-                }
     }
     return bad;
 }
@@ -554,6 +580,14 @@ int nek_host_fdm(int N, const int nel[3], const double *vtx, double *S, double *
     std::vector<double> v(vtx, vtx + nv);
     nek::fdm_scales(nel, v, cf);
     return 0;
+}
+
+int nek_host_trilinear(int N, const int nel[3], const double *vtx, double *coef)
+{
+    if (!host_args_ok(N, nel) || !vtx || !coef) return -1;
+    const size_t nv = 3 * (size_t)(nel[0] + 1) * (nel[1] + 1) * (nel[2] + 1);
+    std::vector<double> v(vtx, vtx + nv);
+    return nek::trilinear_all(N, nel, v, coef) ? -4 : 0;
 }
 
 }  // extern "C"

@@ -41,6 +41,8 @@ void fdm_scales(const int nel[3], const std::vector<double> &vtx, double *cf);
 // determinant is not positive at a GLL node.
 int trilinear_coefs(int N, const int nel[3], const std::vector<double> &vtx, const std::vector<double> &x,
                     const std::vector<double> &w, int hdr, std::vector<double> &out);
+// The same maps with a0, as coef[E][3][8] (a0..a7 per coordinate).
+int trilinear_all(int N, const int nel[3], const std::vector<double> &vtx, double *coef);
 
 // Per-local-node global id, multiplicity and Dirichlet mask (any may be null).
 void numbering(int N, const int nel[3], int64_t *gid, int32_t *mult, int8_t *mask);

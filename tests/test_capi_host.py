@@ -146,3 +146,61 @@ def test_host_fdm_matches_oracle(lib, N):
     np.testing.assert_allclose(S @ np.diag(1 / lam) @ S.T, So @ np.diag(1 / lo) @ So.T, rtol=0,
                                atol=1e-12 * np.abs(So @ np.diag(1 / lo) @ So.T).max())
     np.testing.assert_allclose(cf.reshape(-1, 3), fdm.element_scales(nel, vtx), rtol=1e-14)
+
+
+@pytest.mark.parametrize("N,nel,perturb", [(1, (2, 2, 1), 0.1), (5, (3, 2, 2), 0.1), (9, (2, 3, 2), 0.2),
+                                           (15, (1, 2, 1), 0.1), (4, (2, 2, 2), 0.0)])
+def test_host_trilinear_matches_oracle(lib, N, nel, perturb):
+    """The element maps behind the in-kernel geometric factors: they reproduce
+    the 8 vertices at the reference corners, and the factors the kernels form
+    from them -- rows K = det(J) J^-1 from cross products of the map's
+    derivatives, f = w_i w_j w_k / det(J), G = f K K^T -- equal the oracle's g
+    (J by GLL differentiation of the mapped nodes) to rounding."""
+    vtx = synth.box_vertices(nel, perturb=perturb, seed=11)
+    E = nel[0] * nel[1] * nel[2]
+    coef = np.empty(E * 24)
+    assert lib.nek_host_trilinear(N, _i3(nel), _ptr(vtx), _ptr(coef)) == 0
+    A = coef.reshape(E, 3, 8)
+    V = vtx.reshape(nel[2] + 1, nel[1] + 1, nel[0] + 1, 3)
+    scale = np.abs(vtx).max()
+    for e in range(E):
+        ex, ey, ez = e % nel[0], (e // nel[0]) % nel[1], e // (nel[0] * nel[1])
+        for v in range(8):
+            r, s, t = (1.0 if v & 1 else -1.0), (1.0 if v & 2 else -1.0), (1.0 if v & 4 else -1.0)
+            mono = np.array([1, r, s, t, r * s, r * t, s * t, r * s * t])
+            want = V[ez + (v >> 2), ey + ((v >> 1) & 1), ex + (v & 1)]
+            assert np.abs(A[e] @ mono - want).max() <= 1e-15 * scale
+    xi, w = oracle.gll(N)
+    P = oracle.Problem(N, nel, vtx)
+    n = N + 1
+    t, s, r = np.meshgrid(xi, xi, xi, indexing="ij")          # [k][j][i]
+    W = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    G = np.empty((E, 6, n, n, n))
+    for e in range(E):
+        a = A[e]                                                 # [d][m]
+        xr = a[:, 1, None, None, None] + a[:, 4, None, None, None] * s + a[:, 5, None, None, None] * t \
+            + a[:, 7, None, None, None] * s * t
+        xs = a[:, 2, None, None, None] + a[:, 4, None, None, None] * r + a[:, 6, None, None, None] * t \
+            + a[:, 7, None, None, None] * r * t
+        xt = a[:, 3, None, None, None] + a[:, 5, None, None, None] * r + a[:, 6, None, None, None] * s \
+            + a[:, 7, None, None, None] * r * s
+        cr, cs, ct = np.cross(xs, xt, axis=0), np.cross(xt, xr, axis=0), np.cross(xr, xs, axis=0)
+        det = np.sum(xr * cr, axis=0)
+        assert (det > 0).all()
+        f = W / det
+        for q, (p1, p2) in enumerate(((cr, cr), (cs, cs), (ct, ct), (cr, cs), (cr, ct), (cs, ct))):
+            G[e, q] = f * np.sum(p1 * p2, axis=0)
+    g = P.g.reshape(E, 6, n, n, n)
+    err = np.abs(G - g).max() / np.abs(g[:, :3]).max()
+    print(f"  factors from the maps vs oracle g: {err:.2e}")
+    assert err <= 1e-13
+
+
+def test_host_trilinear_inverted_element(lib):
+    nel = (2, 1, 1)
+    vtx = synth.box_vertices(nel)
+    V = vtx.reshape(2, 2, 3, 3)
+    V[:, :, 1, 0] = 2.5          # the middle vertex plane past the right face: element 1 inverted
+    coef = np.empty(2 * 24)
+    assert lib.nek_host_trilinear(3, _i3(nel), _ptr(V.ravel()), _ptr(coef)) == nek.NEK_E_JACOBIAN
+    assert lib.nek_host_trilinear(0, _i3(nel), _ptr(vtx), _ptr(coef)) == nek.NEK_E_ARG
