@@ -482,9 +482,11 @@ def learned_case(torch, nsolves=10000, steps=2500, neval=16, data_tol=1e-10):
             "eval_per_problem": ev["per_problem"]}
 
 
-def profile_sequence(torch, nek, synth, variants=""):
-    """A short sequence for counter collection (few dispatches)."""
+def profile_sequence(torch, nek, synth, variants="", geometry="stored"):
+    """A short sequence for counter collection (few dispatches); geometry
+    'trilinear' runs it with the factors recomputed in the kernels."""
     ctx = nek.Context(NEL, N, prec="fp32")
+    ctx.set_geometry(geometry)
     chosen = dict(kv.split("=") for kv in variants.split(",") if kv)
     for prec in ("fp32", "fp64", "bf16g"):
         if prec in chosen:
@@ -510,7 +512,7 @@ def profile_sequence(torch, nek, synth, variants=""):
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"profile_sequence": out, "copy_bytes": a.numel() * 8,
+    print(json.dumps({"profile_sequence": out, "geometry": geometry, "copy_bytes": a.numel() * 8,
                       "variants": {p: ctx.get_variant(p) for p in ("fp32", "fp64", "bf16g")}}), flush=True)
     ctx.close()
 
@@ -558,6 +560,8 @@ def main():
     ap.add_argument("--no-energy", action="store_true", help="skip the energy-to-solution measurement")
     ap.add_argument("--no-jacobi", action="store_true",
                     help="skip the preconditioner (diagonal, fast diagonalization) and in-kernel geometry measurements")
+    ap.add_argument("--geometry", default="stored", choices=("stored", "trilinear"),
+                    help="with --profile: stored geometric factors or factors recomputed in the kernels")
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for hardware-counter runs: 40 mixed and 40 FP64 CG iterations, "
                          "5 nek_ax per precision and a 256 MiB copy for calibration")
@@ -580,7 +584,7 @@ def main():
     torch.cuda.set_device(0)
 
     if args.profile:
-        return profile_sequence(torch, nek, synth, args.variants)
+        return profile_sequence(torch, nek, synth, args.variants, args.geometry)
     if args.profile_ax:
         return profile_ax(torch, nek, synth, args.profile_ax, args.variants)
 
