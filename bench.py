@@ -40,7 +40,7 @@ COUNTER_TRAFFIC = {
     "sources": {"paper_2405_11065_amd/csrc/nek_kernels.hpp":
                 "4f63564d9a0b339f765ea149ca539193d1d7e0510c031303a2e9fe190a43d87f",
                 "paper_2405_11065_amd/csrc/nek_np.hpp":
-                "dc36ddd0efef71da36466fa19b8e91fd6781722b5ba6c487db92cc0f170c5965"},
+                "187cf6986b8c564fc49e5943867ed495046dd7794433c5ac2f933092fb41109d"},
     "bytes_per_launch": {4: 198_700_000, 5: 198_700_000},   # FP32 configuration -> bytes
 }
 

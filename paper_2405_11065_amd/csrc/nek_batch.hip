@@ -86,7 +86,7 @@ int layout(nek_batch *b, Group &G, int v, const std::vector<char> &act)
         blk = (blk + 7) / 8 * 8;
         G.blk0[q] = (int)blk;
         G.ngroups[q] = ax_groups(c, epw);
-        G.nblk[q] = ga[q] ? (int)ax_grid(c, epw) : 0;
+        G.nblk[q] = ga[q] ? (int)ax_grid(c, epw, 0) : 0;   // batches read stored factors
         blk += G.nblk[q];
     }
     if (blk >= (1L << 31)) return NEK_E_ARG;

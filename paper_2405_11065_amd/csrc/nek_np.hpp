@@ -21,7 +21,7 @@ template <int NP> struct OpsImpl {
         // the CG form writes one partial per workgroup, read by every workgroup
         // of the next kernel: a capped grid of persistent workgroups; the plain
         // operator reduces nothing and takes one element group per workgroup
-        const unsigned grid = CG ? ax_grid(c, EPW) : (unsigned)ax_groups(c, EPW);
+        const unsigned grid = CG ? ax_grid(c, EPW, (int)sizeof(T)) : (unsigned)ax_groups(c, EPW);
         hipLaunchKernelGGL((k_ax<NP, EPW, PD, T, GT, CG, XT, PC>), dim3(grid), dim3(BS), shm, c->stream, src, p, w, g,
                            D, x, c->sc, c->P1(it), c->P1(it - 1), c->P2(it - 1), (int)grid, it, c->hist, (int)c->E,
                            ax_groups(c, EPW), c->P4(it - 1));
@@ -49,7 +49,7 @@ template <int NP> struct OpsImpl {
             int rc = launch_ax<EPW, PD, T, GT, true, T, PC>(c, r, p, w, g, D, it, x);
             if (rc) return rc;
             if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 1], c->stream));
-            const unsigned grid = ax_grid(c, EPW);
+            const unsigned grid = ax_grid(c, EPW, (int)sizeof(T));
             if constexpr (PC)
                 hipLaunchKernelGGL((k_cg_update_pc<NP, EPW, T>), dim3(grid), dim3(EPW * NP * NP), 0, c->stream, r, w,
                                    c->sc, c->P1(it), (int)grid, c->P2(it), it, c->box, (int)c->E, ax_groups(c, EPW), dg,
@@ -111,7 +111,7 @@ template <int NP> struct OpsImpl {
             int rc = launch_ax<EPW, PD, T, GT, true, T, true>(c, zb, p, w, g, D, it, x);
             if (rc) return rc;
             if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 1], c->stream));
-            const unsigned grid = ax_grid(c, EPW);
+            const unsigned grid = ax_grid(c, EPW, (int)sizeof(T));
             hipLaunchKernelGGL((k_cg_update<NP, EPW, T>), dim3(grid), dim3(EPW * NP * NP), 0, c->stream, r, w, c->sc,
                                c->P1(it), (int)grid, c->P4(it), it, c->box, (int)c->E, ax_groups(c, EPW));
             HIP_TRY(hipGetLastError());
