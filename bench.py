@@ -165,8 +165,8 @@ def big_case(torch, nek, synth, steps=2, energy=True, jacobi=True):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         out[prec] = {"ms_per_solve": round(dt * 1e3, 2), "iters": its / steps, "outer": st["outer_iters"],
-                     "GDOF_iter_per_s": round(ctx.nl * its / steps / dt / 1e9, 3), "true_rel_res": st["rel_res"]
-                     if prec != "fp64" else None}
+                     "GDOF_iter_per_s": round(ctx.nl * its / steps / dt / 1e9, 3),
+                     "true_rel_res": st["true_rel_res"], "last_rec_res": st["last_rec_res"]}
     out["speedup_vs_fp64"] = round(out["fp64"]["ms_per_solve"] / out["bf16g"]["ms_per_solve"], 3)
     if energy:
         out["energy"] = big_energy(torch, ctx, f, x, {p: out[p]["ms_per_solve"] for p in ("bf16g", "fp64")})
@@ -186,7 +186,7 @@ def big_case(torch, nek, synth, steps=2, energy=True, jacobi=True):
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / steps
             jac[prec] = {"ms_per_solve": round(dt * 1e3, 2), "iters": st["iters"], "outer": st["outer_iters"],
-                         "rel_res": st["rel_res"], "speedup_vs_unpreconditioned":
+                         "true_rel_res": st["true_rel_res"], "speedup_vs_unpreconditioned":
                          round(out[prec]["ms_per_solve"] / (dt * 1e3), 3)}
         ctx.set_precond("none")
         for p, v in saved.items():
@@ -255,7 +255,7 @@ def precond_case(torch, ctx, f, steps, base, pc="jacobi"):
             k1, n1 = ctx.prof_read(1)
             ms0, it0 = base[prec]
             out[prec] = {"ms_per_solve": round(dt * 1e3, 3), "iters": its / steps, "outer": st["outer_iters"],
-                         "rel_res": st["rel_res"], "tuned_variant": tuned[0],
+                         "true_rel_res": st["true_rel_res"], "tuned_variant": tuned[0],
                          "operator_us": round(k0 / max(n0, 1) * 1e3, 2), "update_us": round(k1 / max(n1, 1) * 1e3, 2),
                          "unpreconditioned_ms": round(ms0, 3), "unpreconditioned_iters": it0,
                          "speedup": round(ms0 / (dt * 1e3), 3)}
@@ -289,7 +289,7 @@ def geometry_case(torch, ctx, f, steps, base):
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / steps
             ms0, _ = base[prec]
-            out[prec] = {"ms_per_solve": round(dt * 1e3, 3), "iters": its / steps, "rel_res": st["rel_res"],
+            out[prec] = {"ms_per_solve": round(dt * 1e3, 3), "iters": its / steps, "true_rel_res": st["true_rel_res"],
                          "GDOF_iter_per_s": round(ctx.nl * its / steps / dt / 1e9, 3),
                          "tuned_variant": tuned[0], "stored_factors_ms": round(ms0, 3),
                          "speedup": round(ms0 / (dt * 1e3), 3)}
@@ -442,7 +442,7 @@ def batch_case(torch, nek, synth, nprob=64, steps=1):
            "GDOF_iter_per_s": round(work / dt / 1e9, 3), "ms_per_solve": round(dt * 1e3, 2),
            "ms_plain_launches": round(res["plain"][0] * 1e3, 2),
            "ms_sequential_solo": round(t_seq * 1e3, 2), "speedup_vs_sequential": round(t_seq / dt, 3),
-           "bit_identical_to_solo": same, "max_true_rel_res": max(s["rel_res"] for s in st),
+           "bit_identical_to_solo": same, "max_true_rel_res": max(s["true_rel_res"] for s in st),
            "iters_min_max": [min(s["iters"] for s in st), max(s["iters"] for s in st)],
            "tuned_variant": {str(k): v[0] for k, v in tuned.items()}, "graphs_recorded": captures,
            "setup_s": round(t_setup, 1)}
@@ -681,7 +681,7 @@ def main():
         "config": {"workload": "box 16x16x16 unit-cube hexahedra, N=9, f~U[0,1) seed 2, tol 1e-8 relative",
                    "local_points": nl, "precision": "FP32 operator/dssum, FP64 glsc3/scalars/x/refinement"},
         "mixed": {"iters_per_solve": iters / args.steps, "outer_per_solve": stats[-1]["outer_iters"],
-                  "true_rel_res": stats[-1]["rel_res"], "ms_per_solve": round(ms_per_step, 3)},
+                  "true_rel_res": stats[-1]["true_rel_res"], "ms_per_solve": round(ms_per_step, 3)},
         "fp64": {"value": round(nl * it64 / t_fp64 / 1e9, 3), "iters_per_solve": it64 / args.steps,
                  "ms_per_solve": round(t_fp64 / args.steps * 1e3, 3)},
         "speedup_vs_fp64": round(t_fp64 / t_mixed, 3),

@@ -83,12 +83,25 @@ typedef struct {
     int max_outer;           /* mixed: refinement steps cap; 0 = 30                      */
     int fp64_fallback;       /* mixed: 1 = when a refinement step fails to halve the
                                 true residual, finish with FP64 CG from the current x  */
-    int elts_per_wg;         /* reserved, must be 0                                      */
+    int elts_per_wg;         /* configuration of the CG kernel pair:
+                                 0 = autotune: the first solve at each precision times
+                                     every configuration on the context's mesh (as
+                                     nek_tune with 20 iterations) and keeps the fastest;
+                                > 0 = the configuration with that many elements per
+                                     workgroup and the default prefetch depth
+                                     (NEK_E_ARG when the order has none);
+                                -1 = the order's default configuration, untuned.
+                                nek_tune and nek_set_variant override it.              */
     int refine_mode;         /* mixed: 0 = default (1);
                                 1 = restart CG after each true-residual update;
                                 2 = reliable update: replace r by the FP64 true
                                     residual and continue the search direction   */
-    int precond;             /* solveM of Table 1: NEK_PC_NONE (z = r) or NEK_PC_JACOBI */
+    int precond;             /* solveM of Table 1: NEK_PC_NONE (z = r), NEK_PC_JACOBI or
+                                NEK_PC_FDM                                              */
+    int corr_fp32;           /* mixed: 0 = the inner correction d is FP64 (each
+                                d += alpha p in FP64); 1 = d stored in FP32 (each
+                                update formed in FP64 and rounded once: 8 B per point
+                                and inner iteration less)                               */
 } nek_opts;
 
 /* Preconditioner of the CG loop (the solveM step of the paper's Table 1). */
@@ -106,22 +119,24 @@ typedef enum {
 
 /* Source of the geometric factors g1..g6 in the operator kernels. */
 typedef enum {
-    NEK_GEOM_STORED = 0,     /* read per point from memory: the FP64 array, or its
+    NEK_GSRC_STORED = 0,     /* read per point from memory: the FP64 array, or its
                                 FP32 / BF16 copy                                        */
-    NEK_GEOM_TRILINEAR = 1   /* recomputed in the kernel, in the vectors' precision,
+    NEK_GSRC_TRILINEAR = 1   /* recomputed in the kernel, in the vectors' precision,
                                 from each element's trilinear map (21 coefficients per
                                 element): FP64 and FP32 operators; BF16-g solves keep
                                 their stored factors                                   */
-} nek_geom;
+} nek_geom_src;
 
 typedef struct {
-    int iters;               /* CG iterations (mixed: sum of inner iterations)   */
-    int outer_iters;         /* mixed: refinement steps (true-residual checks)   */
-    int fp64_iters;          /* mixed: iterations of the FP64 fallback, if used  */
-    int status;              /* nek_status of the solve                          */
-    double rel_res;          /* FP64: last recursive relative residual;
-                                mixed: last true FP64 relative residual          */
-    double t_solve_s;        /* wall time of the solve on the context's stream   */
+    int iters;               /* CG iterations (mixed: sum of inner iterations)          */
+    int outer_iters;         /* mixed: refinement steps (true-residual checks)          */
+    int fp64_iters;          /* mixed: iterations of the FP64 fallback, if used         */
+    int status;              /* nek_status of the solve                                 */
+    double true_rel_res;     /* sqrt(glsc3(r*,c,r*) / glsc3(b,b)) with r* = b - A x
+                                formed in FP64 (FP64 g) from the returned x; 0 if b = 0 */
+    double last_rec_res;     /* the CG loop's last recursive residual relative to |b|
+                                (mixed: of the last inner or fallback run)              */
+    double t_solve_s;        /* wall time of the solve on the context's stream          */
 } nek_stats;
 
 /* nek_get selectors (host output sizes in parentheses). */
@@ -154,7 +169,7 @@ typedef enum {
  * nek_setup -- build a context for one box mesh of order N (1 <= N <= 15).
  * On the host, in FP64: GLL nodes and weights, D, geometry (trilinear map,
  * J = D X, G, B), global numbering and the sorted-segment gather-scatter maps
- * (the initialisation that the paper's mixed build keeps in double, Sect. 5).
+ * (the initialisation that the paper's mixed build keeps in double, Sect. 6).
  * These are uploaded once; the FP32 / BF16 copies of g that opts->prec needs
  * are rounded on the device.
  * opts may be NULL (FP64 defaults).  stream is a hipStream_t or NULL.
@@ -193,20 +208,33 @@ int nek_set_prec(nek_ctx *ctx, int prec);
 int nek_set_precond(nek_ctx *ctx, int precond);
 
 /*
- * nek_set_geometry -- source (nek_geom) of the geometric factors of the
+ * nek_set_geometry -- source (nek_geom_src) of the geometric factors of the
  * element operator ax_e (Fig. 2: g1..g6 between local_grad3 and
  * local_grad3_t) in every later operator call and solve of the context.
- * The paper's Nekbone computes the factors once at set-up from the
- * trilinear element map and reads six per point in every ax_e; with
- * NEK_GEOM_TRILINEAR the kernels compute the same quantities per point
- * (J from the map's coefficients, G = w det(J) J^-1 J^-T), trading six
- * loads per point for about 60 arithmetic operations.  Builds the
- * coefficients on first use (host FP64; an FP32 copy for FP32 operators).
- * Returns NEK_E_JACOBIAN if an element's map is not orientation-preserving
- * at a GLL node, NEK_E_ARG for an unknown mode.  Batches refuse member
- * contexts with NEK_GEOM_TRILINEAR (NEK_E_ARG).
+ * By default (NEK_GSRC_STORED) the factors computed at set-up are read per
+ * point; with NEK_GSRC_TRILINEAR the kernels compute the same quantities
+ * per point from each element's trilinear map (J from the map's
+ * coefficients, G = w det(J) J^-1 J^-T), trading six loads per point for
+ * about 60 arithmetic operations.  Builds the coefficients on first use
+ * (host FP64; an FP32 copy for FP32 operators).  Returns NEK_E_JACOBIAN if
+ * an element's map is not orientation-preserving at a GLL node, NEK_E_ARG
+ * for an unknown mode.  Batches refuse member contexts with
+ * NEK_GSRC_TRILINEAR (NEK_E_ARG).
  */
 int nek_set_geometry(nek_ctx *ctx, int geom);
+
+/*
+ * nek_set_max_workgroups -- cap on the workgroups of the context's
+ * persistent CG kernels and of its reduction kernels (1 <= n <= 2048;
+ * 0 restores the default of 8 per compute unit, 4 for FP64 operators with
+ * in-kernel factors).  Each workgroup then walks a contiguous share of the
+ * element groups, so a low cap makes every workgroup walk several groups
+ * even on a small mesh, or leaves compute units to concurrent work.  The
+ * per-workgroup partials of the reductions follow the grid, so results at
+ * different caps agree to rounding, not bit for bit.  NEK_E_ARG for n out of
+ * range or a batch member context (a batch lays out its grid once).
+ */
+int nek_set_max_workgroups(nek_ctx *ctx, int n);
 
 /*
  * nek_precond_apply -- z = M^-1 r with the context's preconditioner (a copy
@@ -252,16 +280,21 @@ int nek_glsc3(nek_ctx *ctx, const void *a, const void *b, int dtype, double *out
 
 /*
  * nek_cg_solve -- solve A x = b, b = M o dssum(f), by CG in the order of the
- * paper's Table 1 (unpreconditioned, or with the diagonal preconditioner set
- * by opts->precond / nek_set_precond), in the context's precision:
+ * paper's Table 1 (unpreconditioned, or with the preconditioner set by
+ * opts->precond / nek_set_precond), in the context's precision:
  *  - NEK_PREC_FP64: FP64 CG; stops when the recursive relative residual
  *    sqrt(glsc3(r,r)/glsc3(b,b)) <= tol; tol <= 0 runs exactly maxit
- *    iterations.
- *  - NEK_PREC_FP32 / NEK_PREC_BF16G: iterative refinement.  The outer loop
- *    forms r = b - A x in FP64 (FP64 g) and stops when the true relative
- *    residual <= tol; each inner solve is CG with an FP32 operator, FP64
- *    reductions and scalars, and an FP32 correction d (each update
- *    d += alpha p formed in FP64 and rounded once); x += d in FP64.
+ *    iterations.  The true residual of the returned x is formed once at
+ *    exit (one FP64 operator application, inside t_solve_s).
+ *  - NEK_PREC_FP32 / NEK_PREC_BF16G: iterative refinement (Sect. 6 lowers
+ *    the CG loop, here wrapped in FP64 refinement).  The outer loop forms
+ *    r = b - A x in FP64 (FP64 g) and stops when the true relative residual
+ *    <= tol; each inner solve is CG with an FP32 operator, FP64 reductions
+ *    and scalars, and a correction d accumulated in FP64 (opts->corr_fp32:
+ *    stored in FP32, each update formed in FP64 and rounded once); x += d
+ *    in FP64.
+ * With opts->elts_per_wg == 0 the first solve at a precision autotunes the
+ * CG kernel pair first (nek_tune; its time is inside t_solve_s).
  * f (load vector), x0 (optional, projected as M o dssum(c o x0)) and x are
  * FP64 device vectors of n_local entries; x may alias x0.  maxit caps the
  * total CG iterations.  stats and res_hist (host, length maxit+1: entry 0 is
@@ -318,17 +351,22 @@ int nek_get_variant(const nek_ctx *ctx, int prec, int *variant);
 typedef struct nek_batch nek_batch;
 
 #define NEK_MAX_VARIANTS 6       /* bound on nek_num_variants for any N          */
-#define NEK_BATCH_NO_GRAPH 1     /* nek_batch_solve flag: plain launches, no graph */
+#define NEK_BATCH_NO_GRAPH 1     /* nek_cg_solve_batch flag: plain launches, no graph */
 
 /*
- * nek_batch_setup -- one context per problem i (meshes[i], order N[i], the
+ * nek_setup_batch -- one context per problem i (meshes[i], order N[i], the
  * common opts, whose prec applies to every problem).  The batch creates and
  * owns its streams; member contexts run on the batch's main stream.  stream
  * is the caller's stream: setup and every solve wait for the work already
- * enqueued on it.  1 <= nprob <= 4096.  Errors as nek_setup (nothing is left
- * allocated).
+ * enqueued on it.  1 <= nprob <= 4096.  opts->elts_per_wg applies per
+ * order: 0 autotunes every order's configuration at the first batched solve
+ * of each precision (nek_batch_tune with 20 iterations), > 0 selects that
+ * many elements per workgroup (NEK_E_ARG if some order has no such
+ * configuration), -1 keeps the defaults.  Member contexts take the batch's
+ * configuration and do not tune on their own.  Errors as nek_setup (nothing
+ * is left allocated).
  */
-int nek_batch_setup(int nprob, const nek_mesh *meshes, const int *N, const nek_opts *opts, void *stream,
+int nek_setup_batch(int nprob, const nek_mesh *meshes, const int *N, const nek_opts *opts, void *stream,
                     nek_batch **out);
 
 /* nek_batch_free -- release the batch, its member contexts and streams. */
@@ -368,7 +406,7 @@ int nek_batch_set_variant(nek_batch *batch, int prec, int N, int variant);
 int nek_batch_get_variant(const nek_batch *batch, int prec, int i, int *variant);
 
 /*
- * nek_batch_solve -- solve every problem i as nek_cg_solve(ctx_i, f[i],
+ * nek_cg_solve_batch -- solve every problem i as nek_cg_solve(ctx_i, f[i],
  * x0 ? x0[i] : NULL, tol, maxit, x[i], &stats[i], NULL) would, together.
  * f, x0, x are HOST arrays of nprob DEVICE pointers (x0 itself or any entry
  * may be NULL); stats (may be NULL) is a host array of nprob entries, each
@@ -377,8 +415,8 @@ int nek_batch_get_variant(const nek_batch *batch, int prec, int i, int *variant)
  * recorded chunk.  Returns the most negative status of any problem, else
  * NEK_NOCONV if any problem did not converge, else NEK_OK.  Synchronises.
  */
-int nek_batch_solve(nek_batch *batch, const double *const *f, const double *const *x0, double tol, int maxit,
-                    double *const *x, nek_stats *stats, int flags);
+int nek_cg_solve_batch(nek_batch *batch, const double *const *f, const double *const *x0, double tol, int maxit,
+                       double *const *x, nek_stats *stats, int flags);
 
 /* Totals since setup: chunks of iterations launched, graphs recorded. */
 int nek_batch_counters(const nek_batch *batch, int64_t *chunks, int64_t *captures);

@@ -2,7 +2,7 @@
  * nek_host.h -- host-only setup routines of libnek, callable without a GPU.
  *
  * They compute the FP64 initialisation that nek_setup uploads to the device
- * (the part the paper keeps in double precision, Sect. 5): the GLL rule, the
+ * (the part the paper keeps in double precision, Sect. 6): the GLL rule, the
  * differentiation matrix, trilinear geometry, global numbering and the
  * sorted-segment gather-scatter maps.  All pointers are HOST pointers owned
  * by the caller and sized as stated; nothing is retained.  Each returns

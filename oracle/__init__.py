@@ -17,7 +17,7 @@ the help of tools: A Nekbone case study"):
   * ``glsc3``     -- the weighted dot product glsc3(a, c, b) of Table 1,
   * ``dssum``     -- the gather-scatter sum of copies of each shared node,
   * ``gll``, ``deriv``, ``geometry``, ``numbering`` -- the FP64 initialisation
-    (kept in double precision in the paper's mixed build, Sect. 5).
+    (kept in double precision in the paper's mixed build, Sect. 6).
 The discretisation itself (GLL spectral elements, trilinear hexahedra,
 homogeneous Dirichlet box) is not written in the paper; it is pinned by the
 closed forms and invariants in tests/test_oracle_pins.py.

@@ -5,7 +5,7 @@ code with the GPU path.
 
 The preconditioner is a hybrid block-Jacobi form of the solveM step of the
 paper's Table 1, the non-overlapping stage of the Schwarz smoother that
-Nekbone's multigrid builds with the fast diagonalization method (Sect. 3.1,
+Nekbone's multigrid builds with the fast diagonalization method (Sect. 4.1,
 Fig. 3): on the (N-1)^3 interior nodes of every element the element's own
 stiffness block is inverted, the other nodes (faces, edges, vertices, shared
 between elements) are scaled by the inverse diagonal of the assembled

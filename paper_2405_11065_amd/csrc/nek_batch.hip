@@ -59,6 +59,8 @@ struct nek_batch {
     hipGraphExec_t exec = nullptr;
     std::vector<int> graph_key;
     int64_t chunks = 0, captures = 0;
+    int epw_opt = 0;                   // opts.elts_per_wg of the setup
+    bool tuned[3] = {false, false, false};
 };
 
 namespace nek {
@@ -118,6 +120,7 @@ const void *group_D(const nek_batch *b, const Group &G, int prec)
 int enqueue_chunk(nek_batch *b, int prec)
 {
     int rc;
+    const bool x64 = prec != NEK_PREC_FP64 && !b->ctx[0]->opts.corr_fp32;
     if ((rc = batch_advance_launch(b->stream, b->dbase, CHUNK_ITERS))) return rc;
     std::vector<Group *> act;
     for (auto &G : b->groups)
@@ -132,8 +135,8 @@ int enqueue_chunk(nek_batch *b, int prec)
         const hipStream_t s = fork ? G->s : b->stream;
         const void *D = group_D(b, *G, prec);
         for (int q = 1; q <= CHUNK_ITERS; ++q)
-            if ((rc = o->batch_iter(s, prec, G->variant[prec], G->dtab, G->downer, G->grid, D, q, b->dbase, false,
-                                    false)))
+            if ((rc = o->batch_iter(s, prec, G->variant[prec], x64, G->dtab, G->downer, G->grid, D, q, b->dbase,
+                                    false, false)))
                 return rc;
     }
     if (fork)
@@ -184,7 +187,8 @@ int run_batch(nek_batch *b, int prec, const std::vector<char> &act, const std::v
 {
     int rc;
     const int n = nprob(b);
-    std::vector<int> key{prec};
+    const bool x64 = prec != NEK_PREC_FP64 && !b->ctx[0]->opts.corr_fp32;
+    std::vector<int> key{prec, x64 ? 1 : 0};
     HIP_TRY(hipStreamSynchronize(b->stream));   // staging buffers below are free
     for (auto &G : b->groups) {
         const int v = G.variant[prec];
@@ -216,8 +220,8 @@ int run_batch(nek_batch *b, int prec, const std::vector<char> &act, const std::v
         HIP_TRY(hipMemcpyAsync(G.dtab, G.htab, G.members.size() * sizeof(BatchProb), hipMemcpyHostToDevice,
                                b->stream));
         if (G.active &&
-            (rc = np_ops(G.NP)->batch_iter(b->stream, prec, v, G.dtab, G.downer, G.grid, group_D(b, G, prec), 0,
-                                           b->dbase, false, true)))
+            (rc = np_ops(G.NP)->batch_iter(b->stream, prec, v, x64, G.dtab, G.downer, G.grid, group_D(b, G, prec),
+                                           0, b->dbase, false, true)))
             return rc;
         key.push_back(v);
         key.push_back((int)G.grid);
@@ -250,7 +254,7 @@ int run_batch(nek_batch *b, int prec, const std::vector<char> &act, const std::v
     }
     for (auto &G : b->groups)
         if (G.active &&
-            (rc = np_ops(G.NP)->batch_iter(b->stream, prec, G.variant[prec], G.dtab, G.downer, G.grid,
+            (rc = np_ops(G.NP)->batch_iter(b->stream, prec, G.variant[prec], x64, G.dtab, G.downer, G.grid,
                                            group_D(b, G, prec), CHUNK_ITERS + 1, b->dbase, true, false)))
             return rc;
     if (t) HIP_TRY(hipEventRecord(b->t1, b->stream));
@@ -285,12 +289,24 @@ int batch_fp64(nek_batch *b, const double *const *f, const double *const *x0, do
     }
     if ((rc = run_batch(b, NEK_PREC_FP64, all, xs, maxit, graph))) return rc;
     if ((rc = read_scals(b, all))) return rc;
+    std::vector<double> bb(n);
     for (int m = 0; m < n; ++m) {
         const Scal &h = b->hscal[m];
         st[m].iters = h.fin.iter;
-        st[m].rel_res = h.hist_den > 0 ? std::sqrt(h.fin.rtz / h.hist_den) : 0.0;
+        st[m].last_rec_res = h.hist_den > 0 ? std::sqrt(h.fin.rtz / h.hist_den) : 0.0;
         st[m].status = finish_status(h.fin, tol);
+        bb[m] = h.hist_den;
     }
+    // true residuals of the returned iterates, read back together
+    for (int m = 0; m < n; ++m) {
+        nek_ctx *c = b->ctx[m];
+        if ((rc = ax_local_launch(c, x[m], c->w64, NEK_F64, NEK_PREC_FP64)) ||
+            (rc = resid_launch(c, c->b, c->w64, c->r64, 1)))
+            return rc;
+    }
+    if ((rc = read_scals(b, all))) return rc;
+    for (int m = 0; m < n; ++m)
+        st[m].true_rel_res = bb[m] > 0 ? std::sqrt(b->hscal[m].red[1]) / std::sqrt(bb[m]) : 0.0;
     return NEK_OK;
 }
 
@@ -308,7 +324,7 @@ int batch_mixed(nek_batch *b, const double *const *f, const double *const *x0, d
         if ((rc = ensure_mixed_work(c)) || (rc = ensure_hist(c, (long)maxit + 1))) return rc;
         ir_init(c, S[m]);
         if ((rc = cg_prologue(c, f[m], x0 ? x0[m] : nullptr, x[m], c->r64))) return rc;
-        xs[m] = c->d32;
+        xs[m] = inner_x(c);
     }
     if ((rc = read_scals(b, all))) return rc;
     for (int m = 0; m < n; ++m) ir_start(S[m], b->hscal[m]);
@@ -381,7 +397,7 @@ void nek_batch_free(nek_batch *b)
     delete b;
 }
 
-int nek_batch_setup(int n, const nek_mesh *meshes, const int *N, const nek_opts *opts, void *stream,
+int nek_setup_batch(int n, const nek_mesh *meshes, const int *N, const nek_opts *opts, void *stream,
                     nek_batch **out)
 {
     if (n < 1 || n > 4096 || !meshes || !N || !out) return NEK_E_ARG;
@@ -398,9 +414,13 @@ int nek_batch_setup(int n, const nek_mesh *meshes, const int *N, const nek_opts 
         hipStreamWaitEvent(b->stream, b->entry, 0) != hipSuccess)
         return fail(NEK_E_HIP);
     b->ctx.assign(n, nullptr);
+    b->epw_opt = opts ? opts->elts_per_wg : 0;
     for (int m = 0; m < n; ++m) {
         const int rc = nek_setup(&meshes[m], N[m], opts, b->stream, &b->ctx[m]);
         if (rc) return fail(rc);
+        // members follow the batch's configuration and never tune alone
+        b->ctx[m]->batch_member = true;
+        for (int q = 0; q < 3; ++q) b->ctx[m]->tuned[q] = true;
     }
     b->group_of.assign(n, -1);
     for (int NP = 2; NP <= MAX_NP; ++NP) {
@@ -413,6 +433,11 @@ int nek_batch_setup(int n, const nek_mesh *meshes, const int *N, const nek_opts 
         b->groups.push_back(std::move(G));
     }
     for (auto &G : b->groups) {
+        if (b->epw_opt != 0) {
+            const int v = b->ctx[G.members[0]]->variant[0];   // set by nek_setup from elts_per_wg
+            for (int q = 0; q < 3; ++q) G.variant[q] = v;
+            b->tuned[0] = b->tuned[1] = b->tuned[2] = true;
+        }
         if (dalloc(G.dtab, G.members.size())) return fail(NEK_E_OOM);
         if (hipHostMalloc((void **)&G.htab, G.members.size() * sizeof(BatchProb), hipHostMallocDefault) != hipSuccess)
             return fail(NEK_E_OOM);
@@ -452,6 +477,7 @@ int nek_batch_set_variant(nek_batch *b, int prec, int N, int variant)
         if (variant < 0 || variant >= np_ops(G.NP)->nvariants) return NEK_E_ARG;
         G.variant[prec] = variant;
         for (int m : G.members) b->ctx[m]->variant[prec] = variant;
+        b->tuned[prec] = true;   // an explicit choice: no autotuning at the next solve
         return NEK_OK;
     }
     return NEK_E_ARG;
@@ -483,14 +509,14 @@ int nek_batch_tune(nek_batch *b, int prec, int iters, double *us_per_iter)
         nek_ctx *c = b->ctx[m];
         if ((rc = ensure_fp64_work(c)) || (rc = ensure_g(c, prec)) || (rc = ensure_hist(c, iters + 1))) return rc;
         if (prec == NEK_PREC_FP64 ? dalloc(c->d64, c->nl)
-                                  : (dalloc(c->d32, c->nl) || dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) ||
-                                     dalloc(c->w32, c->nl)))
+                                  : ((c->opts.corr_fp32 ? dalloc(c->d32, c->nl) : dalloc(c->d64, c->nl)) ||
+                                     dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) || dalloc(c->w32, c->nl)))
             return NEK_E_OOM;
         // synthetic SPD system: b = M dssum(1), x0 = 0
         if ((rc = fill_f64(c, c->w64, 1.0, c->nl)) || (rc = gather_launch(c, c->w64, c->b, false)) ||
             (rc = glsc3_to_slot(c, c->b, c->b, NEK_F64, 0)))
             return rc;
-        xs[m] = prec == NEK_PREC_FP64 ? (void *)c->d64 : (void *)c->d32;
+        xs[m] = prec == NEK_PREC_FP64 ? (void *)c->d64 : inner_x(c);
     }
     if (us_per_iter)
         for (size_t k = 0; k < NEK_MAX_VARIANTS * b->groups.size(); ++k) us_per_iter[k] = 0.0;
@@ -514,7 +540,9 @@ int nek_batch_tune(nek_batch *b, int prec, int iters, double *us_per_iter)
                             (rc = fill_f64(c, c->d64, 0.0, c->nl)))
                             return rc;
                     } else {
-                        if ((rc = ops(c)->inner_start(c, c->b, c->r32, c->d32)) || (rc = red_final(c, 1))) return rc;
+                        if ((rc = ops(c)->inner_start(c, c->b, c->r32, inner_x(c), !c->opts.corr_fp32)) ||
+                            (rc = red_final(c, 1)))
+                            return rc;
                     }
                     if ((rc = start_launch(c, 1, 0, 0.0, iters, 0))) return rc;
                 }
@@ -531,12 +559,13 @@ int nek_batch_tune(nek_batch *b, int prec, int iters, double *us_per_iter)
         for (int m : G.members) b->ctx[m]->variant[prec] = best_v;
         slot += NEK_MAX_VARIANTS;
     }
+    b->tuned[prec] = true;
     drop_graph(b);
     return NEK_OK;
 }
 
-int nek_batch_solve(nek_batch *b, const double *const *f, const double *const *x0, double tol, int maxit,
-                    double *const *x, nek_stats *stats, int flags)
+int nek_cg_solve_batch(nek_batch *b, const double *const *f, const double *const *x0, double tol, int maxit,
+                       double *const *x, nek_stats *stats, int flags)
 {
     if (!b || !f || !x || maxit < 0) return NEK_E_ARG;
     const int n = nprob(b);
@@ -549,6 +578,10 @@ int nek_batch_solve(nek_batch *b, const double *const *f, const double *const *x
     HIP_TRY(hipStreamWaitEvent(b->stream, b->entry, 0));
     std::vector<nek_stats> st(n);
     const auto t0 = std::chrono::steady_clock::now();
+    if (b->epw_opt == 0 && !b->tuned[prec]) {
+        const int rt = nek_batch_tune(b, prec, 20, nullptr);
+        if (rt) return rt;
+    }
     int rc = prec == NEK_PREC_FP64 ? batch_fp64(b, f, x0, tol, maxit, x, st, graph)
                                    : batch_mixed(b, f, x0, tol, maxit, x, st, graph);
     if (hipStreamSynchronize(b->stream) != hipSuccess && rc >= 0) rc = NEK_E_HIP;

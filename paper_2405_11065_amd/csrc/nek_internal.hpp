@@ -99,6 +99,9 @@ struct nek_ctx {
     nek_opts opts{};
     int prec = NEK_PREC_FP64;
     int variant[3] = {0, 0, 0};   // CG kernel configuration per precision (nek_tune)
+    bool tuned[3] = {false, false, false};   // configuration fixed (else the next solve autotunes)
+    int max_wg = 0;               // cap on persistent / reduction workgroups (0: default)
+    bool batch_member = false;    // owned by a batch, which lays out its grid once
 
     std::vector<double> xi, w, D, vtx;
 
@@ -108,7 +111,7 @@ struct nek_ctx {
     double *g64 = nullptr;
     float *g32 = nullptr;
     uint16_t *g16 = nullptr;
-    // NEK_GEOM_TRILINEAR: the operator kernels recompute the factors from
+    // NEK_GSRC_TRILINEAR: the operator kernels recompute the factors from
     // per-element trilinear coefficients (header + [E][24], FP64 and FP32)
     int geom = 0;
     double *tri64 = nullptr;
@@ -132,8 +135,8 @@ struct nek_ctx {
     long hist_cap = 0;
     // work vectors
     double *b = nullptr, *r64 = nullptr, *p64 = nullptr, *w64 = nullptr;
-    double *d64 = nullptr;   // iterate of FP64 autotuning runs
-    float *d32 = nullptr;    // correction of an inner (FP32 / BF16-g) solve
+    double *d64 = nullptr;   // iterate of FP64 autotuning runs; FP64 correction of inner solves
+    float *d32 = nullptr;    // FP32 correction of inner solves (opts.corr_fp32)
     float *r32 = nullptr, *p32 = nullptr, *w32 = nullptr;
     int *hflags = nullptr;   // pinned; [0] mirrors the run's done flag (written by its kernels)
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -168,7 +171,7 @@ namespace nek {
 inline unsigned red_grid(const nek_ctx *c)
 {
     long want = (c->nl + UPD_BS - 1) / UPD_BS;
-    long cap = std::min<long>(MAXB / 2, 4L * num_cu());
+    long cap = std::min<long>(MAXB / 2, c->max_wg > 0 ? (long)c->max_wg : 4L * num_cu());
     return (unsigned)std::max<long>(1, std::min(want, cap));
 }
 
@@ -186,8 +189,8 @@ inline unsigned ax_grid(const nek_ctx *c, int epw, int vbytes)
     long want = ax_groups(c, epw);
     // FP64 with in-kernel factors: half the workgroups, each with twice the
     // groups (16^3 N=9 CG: 105 -> 95 us per iteration; FP32 is slower so)
-    const bool half = c->geom == NEK_GEOM_TRILINEAR && vbytes == 8;
-    long cap = std::min<long>(MAXB, (half ? 4L : 8L) * num_cu());
+    const bool half = c->geom == NEK_GSRC_TRILINEAR && vbytes == 8;
+    long cap = std::min<long>(MAXB, c->max_wg > 0 ? (long)c->max_wg : (half ? 4L : 8L) * num_cu());
     return (unsigned)std::max<long>(1, std::min(want, cap));
 }
 
@@ -202,9 +205,10 @@ struct NpOps {
     // iterate x has the type of the vectors
     int (*cg_iter64)(nek_ctx *, int variant, int it, bool final, double *x, double *r, double *p, double *w,
                      const double *g, const double *D);
-    int (*cg_iter32)(nek_ctx *, int variant, int it, bool final, float *x, float *r, float *p, float *w,
+    // 4-byte vectors: x is the inner correction, FP64 (x64) or FP32
+    int (*cg_iter32)(nek_ctx *, int variant, int it, bool final, void *x, bool x64, float *r, float *p, float *w,
                      const float *g, const float *D);
-    int (*cg_iter16)(nek_ctx *, int variant, int it, bool final, float *x, float *r, float *p, float *w,
+    int (*cg_iter16)(nek_ctx *, int variant, int it, bool final, void *x, bool x64, float *r, float *p, float *w,
                      const uint16_t *g, const float *D);
     // w = A_L u
     int (*ax64)(nek_ctx *, const double *u, double *w);
@@ -228,15 +232,16 @@ struct NpOps {
     // with step set, as the third kernel of CG iteration it
     int (*pc_fdm64)(nek_ctx *, const double *r, double *z, double *P, unsigned grid, bool step, int it);
     int (*pc_fdm32)(nek_ctx *, const float *r, float *z, double *P, unsigned grid, bool step, int it);
-    // r32 = (float) r64, d = 0, partials of glsc3(r32, c, r32)
-    int (*inner_start)(nek_ctx *, const double *r64, float *r32, float *d);
+    // r32 = (float) r64, d = 0 (FP64 when d64, else FP32), partials of glsc3(r32, c, r32)
+    int (*inner_start)(nek_ctx *, const double *r64, float *r32, void *d, bool d64);
     // elements per workgroup of a CG variant
     int (*variant_epw)(int variant);
     // Batched CG iteration base + it_local of every active problem in tab
     // (operator, then gather/update unless final) on stream s; with prepare
     // set, only configures the kernels (call before any graph capture).
-    int (*batch_iter)(hipStream_t s, int prec, int variant, const BatchProb *tab, const int *owner, unsigned grid,
-                      const void *D, int it_local, const int *base, bool final, bool prepare);
+    // x64: the iterates of 4-byte runs are FP64 corrections.
+    int (*batch_iter)(hipStream_t s, int prec, int variant, bool x64, const BatchProb *tab, const int *owner,
+                      unsigned grid, const void *D, int it_local, const int *base, bool final, bool prepare);
 };
 
 const NpOps *np_ops(int NP);
@@ -263,6 +268,14 @@ int pc_start32(nek_ctx *c, float *r, int *rtz_slot);
 int ensure_diag(nek_ctx *c);
 int ensure_fdm(nek_ctx *c);
 int ensure_tri(nek_ctx *c);
+// the inner correction of a mixed solve (FP64 unless opts.corr_fp32)
+inline void *inner_x(nek_ctx *c) { return c->opts.corr_fp32 ? (void *)c->d32 : (void *)c->d64; }
+// configuration of the CG pair for opts.elts_per_wg > 0 (-1 if none)
+int variant_for_epw(int NP, int epw);
+// opts.elts_per_wg == 0 and no configuration fixed yet at prec: autotune
+int autotune_if_needed(nek_ctx *c, int prec);
+// true relative residual of x (FP64 operator and gather); red[1] = its r.r
+int true_residual(nek_ctx *c, const double *x, double bb, double *rho);
 int cg_prologue(nek_ctx *c, const double *f, const double *x0, double *x, double *r);
 int ax_local_launch(nek_ctx *c, const void *u, void *w, int dtype, int prec);
 int resid_launch(nek_ctx *c, const double *b, const double *w, double *r, int slot);
@@ -275,7 +288,7 @@ int fill_i32(hipStream_t s, int *p, int v, unsigned long n);
 // Control state of one mixed-precision (iterative refinement) solve; the
 // solo and batched solvers drive it through the same steps.
 struct IrCtl {
-    double bb = 0, rho = 0, rho_prev = 0, tau = 0, rtz_last = 0;
+    double bb = 0, rho = 0, rho_prev = 0, tau = 0, rtz_last = 0, last_rec = 0;
     int total = 0, outer = 0, fp64_iters = 0, status = NEK_OK, inner_cap = 0, max_outer = 0;
     bool keep_p = false, finished = false;
 };

@@ -1152,7 +1152,7 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_cg_update(T *__restrict__ r, co
 struct BatchProb {
     void *r, *p, *w;       // residual, search direction, A_L p (T)
     const void *g;         // geometric factors (GT)
-    void *x;               // FP64 iterate (FP64 solve) or FP32 inner correction (T)
+    void *x;               // FP64 iterate (FP64 solve) or inner correction (FP64, or FP32)
     Scal *sc;
     double *partials;      // pAp by parity, then rtr by parity (MAXB each)
     double *hist;
@@ -1167,7 +1167,7 @@ __device__ __forceinline__ int batch_it(const int *__restrict__ base, int it_loc
 
 // The operator kernel of every problem of one order in one launch: workgroup
 // b runs the solo body as workgroup b - blk0 of its problem.
-template <int NP, int EPW, int PD, typename T, typename GT>
+template <int NP, int EPW, int PD, typename T, typename GT, typename XT>
 __global__ __launch_bounds__(EPW *NP *NP) void k_ax_batch(const BatchProb *__restrict__ tab,
                                                           const int *__restrict__ owner, const T *__restrict__ D,
                                                           int it_local, const int *__restrict__ base)
@@ -1177,8 +1177,8 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_ax_batch(const BatchProb *__res
     const BatchProb P = tab[q];
     if (!P.active) return;
     const int it = batch_it(base, it_local);
-    ax_body<NP, EPW, PD, T, GT, true, T>(
-        (const T *)P.r, (T *)P.p, (T *)P.w, (const GT *)P.g, D, (T *)P.x, P.sc, P.partials + (it & 1) * MAXB,
+    ax_body<NP, EPW, PD, T, GT, true, XT>(
+        (const T *)P.r, (T *)P.p, (T *)P.w, (const GT *)P.g, D, (XT *)P.x, P.sc, P.partials + (it & 1) * MAXB,
         P.partials + ((it - 1) & 1) * MAXB, P.partials + (2 + ((it - 1) & 1)) * MAXB, P.nblk, it, P.hist, P.E,
         P.ngroups, blockIdx.x - P.blk0, P.nblk);
 }
@@ -1252,10 +1252,11 @@ __global__ __launch_bounds__(UPD_BS) void k_glsc3(const TA *__restrict__ a, cons
 }
 
 // r32 = (float) r64, d = 0, and partials of glsc3(r32, c, r32): start of an
-// inner (FP32-operator) solve of the refinement loop.
-template <int NP>
+// inner (FP32-operator) solve of the refinement loop; the correction d is
+// FP64 or FP32.
+template <int NP, typename DT>
 __global__ __launch_bounds__(UPD_BS) void k_inner_start(const double *__restrict__ r64, float *__restrict__ r32,
-                                                        float *__restrict__ d, double *__restrict__ P, Box box,
+                                                        DT *__restrict__ d, double *__restrict__ P, Box box,
                                                         unsigned nl)
 {
     __shared__ double sbuf[UPD_BS];
@@ -1267,7 +1268,7 @@ __global__ __launch_bounds__(UPD_BS) void k_inner_start(const double *__restrict
         const PointInfo<NP> Pt = locate<NP>(t, box);
         const float v = (float)r64[t];
         r32[t] = v;
-        d[t] = 0.0f;
+        d[t] = (DT)0;
         part += ((double)v * (double)v) * inv_mult(Pt.mult);
     }
     const double s = block_sum<UPD_BS>(part, sbuf);

@@ -115,8 +115,9 @@ __global__ __launch_bounds__(256) void k_batch_alldone(Scal *const *__restrict__
     if (threadIdx.x == 0) set_host_flag(out, !pending);
 }
 
-// x += d: FP64 iterate, FP32 correction of an inner solve.
-__global__ void k_axpy1(double *__restrict__ x, const float *__restrict__ d, unsigned long n)
+// x += d: FP64 iterate, FP64 or FP32 correction of an inner solve.
+template <typename DT>
+__global__ void k_axpy1(double *__restrict__ x, const DT *__restrict__ d, unsigned long n)
 {
     for (unsigned long t = blockIdx.x * (unsigned long)blockDim.x + threadIdx.x; t < n; t += (unsigned long)gridDim.x * blockDim.x)
         x[t] += (double)d[t];

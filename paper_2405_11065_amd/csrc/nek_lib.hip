@@ -290,14 +290,42 @@ int pc_start32(nek_ctx *c, float *r, int *rtz_slot)
 }
 
 // one CG iteration of the context at precision prec on its work vectors;
-// x is FP64 at FP64, else FP32 (the correction of an inner solve)
+// x is FP64 at FP64, else the correction of an inner solve (FP64 unless
+// opts.corr_fp32)
 int cg_iter(nek_ctx *c, int prec, int variant, int it, bool final, void *x)
 {
     if (prec == NEK_PREC_FP64)
         return ops(c)->cg_iter64(c, variant, it, final, (double *)x, c->r64, c->p64, c->w64, c->g64, c->D64);
+    const bool x64 = !c->opts.corr_fp32;
     if (prec == NEK_PREC_BF16G)
-        return ops(c)->cg_iter16(c, variant, it, final, (float *)x, c->r32, c->p32, c->w32, c->g16, c->D32);
-    return ops(c)->cg_iter32(c, variant, it, final, (float *)x, c->r32, c->p32, c->w32, c->g32, c->D32);
+        return ops(c)->cg_iter16(c, variant, it, final, x, x64, c->r32, c->p32, c->w32, c->g16, c->D32);
+    return ops(c)->cg_iter32(c, variant, it, final, x, x64, c->r32, c->p32, c->w32, c->g32, c->D32);
+}
+
+int true_residual(nek_ctx *c, const double *x, double bb, double *rho)
+{
+    int rc;
+    if ((rc = ax_local_launch(c, x, c->w64, NEK_F64, NEK_PREC_FP64)) || (rc = resid_launch(c, c->b, c->w64, c->r64, 1)))
+        return rc;
+    Scal h;
+    if ((rc = read_scal(c, h))) return rc;
+    *rho = bb > 0 ? std::sqrt(h.red[1]) / std::sqrt(bb) : 0.0;
+    return NEK_OK;
+}
+
+int variant_for_epw(int NP, int epw)
+{
+    const NpOps *o = np_ops(NP);
+    if (!o) return -1;
+    for (int v = 0; v < o->nvariants; v += 2)   // even variants: the default prefetch depth
+        if (o->variant_epw(v) == epw) return v;
+    return -1;
+}
+
+int autotune_if_needed(nek_ctx *c, int prec)
+{
+    if (c->tuned[prec] || c->opts.elts_per_wg != 0) return NEK_OK;
+    return nek_tune(c, prec, 20, nullptr, nullptr);
 }
 
 int start_launch(nek_ctx *c, int rslot, int hist_off, double stop_tol, int maxit, int stop_on_initial,
@@ -397,23 +425,26 @@ int solve_fp64(nek_ctx *c, const double *f, const double *x0, double tol, int ma
     Scal h;
     if ((rc = read_scal(c, h))) return rc;
     st->iters = h.fin.iter;
-    st->rel_res = h.hist_den > 0 ? std::sqrt(h.fin.rtr / h.hist_den) : 0.0;
-    return finish_status(h.fin, tol);
+    st->last_rec_res = h.hist_den > 0 ? std::sqrt(h.fin.rtr / h.hist_den) : 0.0;
+    const int status = finish_status(h.fin, tol);
+    if (status >= 0 && (rc = true_residual(c, x, h.hist_den, &st->true_rel_res))) return rc;
+    return status;
 }
 
 int ensure_mixed_work(nek_ctx *c)
 {
     int rc;
     if ((rc = ensure_fp64_work(c)) || (rc = ensure_g(c, c->prec))) return rc;
-    if (dalloc(c->d32, c->nl) || dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) || dalloc(c->w32, c->nl))
+    if ((c->opts.corr_fp32 ? dalloc(c->d32, c->nl) : dalloc(c->d64, c->nl)) || dalloc(c->r32, c->nl) ||
+        dalloc(c->p32, c->nl) || dalloc(c->w32, c->nl))
         return NEK_E_OOM;
     return NEK_OK;
 }
 
 // Iterative refinement: FP64 outer residual with FP64 g; inner CG with an
-// FP32 operator (FP32 or BF16 g), FP64 reductions/scalars and an FP32
-// correction d (each update d += alpha p formed in FP64, rounded once), added
-// to the FP64 x after the inner solve.
+// FP32 operator (FP32 or BF16 g), FP64 reductions/scalars and a correction d
+// accumulated in FP64 (or stored in FP32, each update d += alpha p formed in
+// FP64 and rounded once), added to the FP64 x after the inner solve.
 // The control below is shared by the solo and the batched solver.
 void ir_init(const nek_ctx *c, IrCtl &s)
 {
@@ -472,6 +503,7 @@ int ir_fallback(nek_ctx *c, IrCtl &s, double tol, int maxit, double *x)
     if ((rc = read_scal(c, h))) return rc;
     s.fp64_iters = h.fin.iter;
     s.total += h.fin.iter;
+    s.last_rec = h.hist_den > 0 ? std::sqrt(h.fin.rtr / h.hist_den) : 0.0;
     if ((rc = ax_local_launch(c, x, c->w64, NEK_F64, NEK_PREC_FP64))) return rc;
     if ((rc = resid_launch(c, c->b, c->w64, c->r64, 1))) return rc;
     if ((rc = read_scal(c, h))) return rc;
@@ -486,7 +518,7 @@ int ir_fallback(nek_ctx *c, IrCtl &s, double tol, int maxit, double *x)
 int ir_inner_launch(nek_ctx *c, IrCtl &s, double tol, int maxit, int *cap)
 {
     int rc;
-    if ((rc = ops(c)->inner_start(c, c->r64, c->r32, c->d32))) return rc;
+    if ((rc = ops(c)->inner_start(c, c->r64, c->r32, inner_x(c), !c->opts.corr_fp32))) return rc;
     if ((rc = red_final(c, 1))) return rc;
     int rs = 1;
     if ((rc = pc_start32(c, c->r32, &rs))) return rc;
@@ -501,12 +533,16 @@ int ir_inner_done(nek_ctx *c, IrCtl &s, const Scal &h, double *x)
 {
     s.total += h.fin.iter;
     s.rtz_last = h.fin.rtz;
+    s.last_rec = h.hist_den > 0 ? std::sqrt(h.fin.rtr / h.hist_den) : 0.0;
     if (h.fin.status) {
         s.status = h.fin.status;
         s.finished = true;
         return NEK_OK;
     }
-    hipLaunchKernelGGL(k_axpy1, dim3(4 * num_cu()), dim3(256), 0, c->stream, x, c->d32, (unsigned long)c->nl);
+    if (c->opts.corr_fp32)
+        hipLaunchKernelGGL(k_axpy1<float>, dim3(4 * num_cu()), dim3(256), 0, c->stream, x, c->d32, (unsigned long)c->nl);
+    else
+        hipLaunchKernelGGL(k_axpy1<double>, dim3(4 * num_cu()), dim3(256), 0, c->stream, x, c->d64, (unsigned long)c->nl);
     HIP_TRY(hipGetLastError());
     int rc;
     if ((rc = ax_local_launch(c, x, c->w64, NEK_F64, NEK_PREC_FP64))) return rc;
@@ -530,7 +566,8 @@ void ir_stats(const IrCtl &s, nek_stats *st)
     st->iters = s.total;
     st->outer_iters = s.outer;
     st->fp64_iters = s.fp64_iters;
-    st->rel_res = s.rho;
+    st->true_rel_res = s.rho;
+    st->last_rec_res = s.last_rec;
 }
 
 int solve_mixed(nek_ctx *c, const double *f, const double *x0, double tol, int maxit, double *x, nek_stats *st)
@@ -553,7 +590,7 @@ int solve_mixed(nek_ctx *c, const double *f, const double *x0, double tol, int m
         int cap = 0;
         if ((rc = ir_inner_launch(c, s, tol, maxit, &cap))) return rc;
         rc = run_cg(c, cap, [&](int it, bool final) -> int {
-            return cg_iter(c, c->prec, c->variant[c->prec], it, final, c->d32);
+            return cg_iter(c, c->prec, c->variant[c->prec], it, final, inner_x(c));
         });
         if (rc) return rc;
         if ((rc = read_scal(c, h))) return rc;
@@ -628,9 +665,12 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
     const long NP = N + 1, n3 = NP * NP * NP;
     const long E = (long)mesh->nel[0] * mesh->nel[1] * mesh->nel[2];
     if (E * n3 >= (1L << 31)) return NEK_E_ARG;
-    if (opts && (opts->prec < NEK_PREC_FP64 || opts->prec > NEK_PREC_BF16G || opts->elts_per_wg != 0 ||
-                 opts->precond < NEK_PC_NONE || opts->precond > NEK_PC_FDM))
+    if (opts && (opts->prec < NEK_PREC_FP64 || opts->prec > NEK_PREC_BF16G || opts->elts_per_wg < -1 ||
+                 opts->precond < NEK_PC_NONE || opts->precond > NEK_PC_FDM || opts->corr_fp32 < 0 ||
+                 opts->corr_fp32 > 1))
         return NEK_E_ARG;
+    int v_epw = 0;
+    if (opts && opts->elts_per_wg > 0 && (v_epw = variant_for_epw(N + 1, opts->elts_per_wg)) < 0) return NEK_E_ARG;
     nek_ctx *c = new (std::nothrow) nek_ctx;
     if (!c) return NEK_E_OOM;
     c->N = N;
@@ -643,6 +683,11 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
     c->stream = (hipStream_t)stream;
     if (opts) c->opts = *opts;
     c->prec = c->opts.prec;
+    if (c->opts.elts_per_wg != 0)
+        for (int q = 0; q < 3; ++q) {
+            c->variant[q] = v_epw;
+            c->tuned[q] = true;
+        }
 
     gll_rule(N, c->xi, c->w);
     deriv_matrix(c->xi, c->D);
@@ -775,12 +820,19 @@ int nek_set_precond(nek_ctx *c, int precond)
 
 int nek_set_geometry(nek_ctx *c, int geom)
 {
-    if (!c || geom < NEK_GEOM_STORED || geom > NEK_GEOM_TRILINEAR) return NEK_E_ARG;
-    if (geom == NEK_GEOM_TRILINEAR) {
+    if (!c || geom < NEK_GSRC_STORED || geom > NEK_GSRC_TRILINEAR) return NEK_E_ARG;
+    if (geom == NEK_GSRC_TRILINEAR) {
         const int rc = ensure_tri(c);
         if (rc) return rc;
     }
     c->geom = geom;
+    return NEK_OK;
+}
+
+int nek_set_max_workgroups(nek_ctx *c, int n)
+{
+    if (!c || n < 0 || n > MAXB || c->batch_member) return NEK_E_ARG;
+    c->max_wg = n;
     return NEK_OK;
 }
 
@@ -884,6 +936,7 @@ int nek_set_variant(nek_ctx *c, int prec, int variant)
     const int nv = nek_num_variants(c);
     if (variant < 0 || variant >= nv) return NEK_E_ARG;
     c->variant[prec] = variant;
+    c->tuned[prec] = true;
     return NEK_OK;
 }
 
@@ -900,10 +953,10 @@ int nek_tune(nek_ctx *c, int prec, int iters, double *us_per_iter, int *best)
     int rc;
     if ((rc = ensure_fp64_work(c)) || (rc = ensure_g(c, prec)) || (rc = ensure_hist(c, iters + 1))) return rc;
     if (prec == NEK_PREC_FP64 ? dalloc(c->d64, c->nl)
-                              : (dalloc(c->d32, c->nl) || dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) ||
-                                 dalloc(c->w32, c->nl)))
+                              : ((c->opts.corr_fp32 ? dalloc(c->d32, c->nl) : dalloc(c->d64, c->nl)) ||
+                                 dalloc(c->r32, c->nl) || dalloc(c->p32, c->nl) || dalloc(c->w32, c->nl)))
         return NEK_E_OOM;
-    void *xt = prec == NEK_PREC_FP64 ? (void *)c->d64 : (void *)c->d32;
+    void *xt = prec == NEK_PREC_FP64 ? (void *)c->d64 : inner_x(c);
     // synthetic SPD system: b = M dssum(1), x0 = 0
     if ((rc = fill<double>(c, c->w64, 1.0, c->nl)) || (rc = gather_launch(c, c->w64, c->b, false)) ||
         (rc = glsc3_to_slot(c, c->b, c->b, NEK_F64, 0)))
@@ -927,7 +980,7 @@ int nek_tune(nek_ctx *c, int prec, int iters, double *us_per_iter, int *best)
                     (rc = pc_start64(c, c->r64, &rs)))
                     break;
             } else {
-                if ((rc = ops(c)->inner_start(c, c->b, c->r32, c->d32))) break;
+                if ((rc = ops(c)->inner_start(c, c->b, c->r32, xt, !c->opts.corr_fp32))) break;
                 if ((rc = red_final(c, 1)) || (rc = pc_start32(c, c->r32, &rs))) break;
             }
             if ((rc = start_launch(c, rs, 0, 0.0, iters, 0, 0.0, 1))) break;
@@ -949,6 +1002,7 @@ int nek_tune(nek_ctx *c, int prec, int iters, double *us_per_iter, int *best)
     c->prof_every = saved_prof;
     if (rc) return rc;
     c->variant[prec] = best_v;
+    c->tuned[prec] = true;
     if (best) *best = best_v;
     return NEK_OK;
 }
@@ -961,6 +1015,7 @@ int nek_cg_solve(nek_ctx *c, const double *f, const double *x0, double tol, int 
     int rc = ensure_hist(c, (long)maxit + 1);
     if (rc) return rc;
     auto t0 = std::chrono::steady_clock::now();
+    if ((rc = autotune_if_needed(c, c->prec))) return rc;
     if (c->prec == NEK_PREC_FP64)
         rc = solve_fp64(c, f, x0, tol, maxit, x, &st);
     else

@@ -34,19 +34,19 @@ template <int NP> struct OpsImpl {
     // the operator kernel runs: it applies the last x update and publishes
     // the final state.  Sampled timing brackets every prof_every-th
     // iteration with events.
-    template <typename T, typename GT, bool PC>
-    static int cg_iter_pc(nek_ctx *c, int variant, int it, bool final, T *x, T *r, T *p, T *w, const GT *g,
+    template <typename T, typename GT, bool PC, typename XT>
+    static int cg_iter_pc(nek_ctx *c, int variant, int it, bool final, XT *x, T *r, T *p, T *w, const GT *g,
                           const T *D, const T *dg)
     {
         return with_variant<NP, GT>(variant, [&](auto epw_c, auto pd_c) -> int {
             constexpr int EPW = decltype(epw_c)::value, PD = decltype(pd_c)::value;
-            if (final) return launch_ax<EPW, PD, T, GT, true, T, PC>(c, r, p, w, g, D, it, x);
+            if (final) return launch_ax<EPW, PD, T, GT, true, XT, PC>(c, r, p, w, g, D, it, x);
             int slot = -1;
             if (c->prof_every > 0 && (c->prof_tick++ % c->prof_every) == 0) {
                 if ((slot = prof_take(c)) < 0) return NEK_E_HIP;
                 HIP_TRY(hipEventRecord(c->prof_pool[3 * slot], c->stream));
             }
-            int rc = launch_ax<EPW, PD, T, GT, true, T, PC>(c, r, p, w, g, D, it, x);
+            int rc = launch_ax<EPW, PD, T, GT, true, XT, PC>(c, r, p, w, g, D, it, x);
             if (rc) return rc;
             if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 1], c->stream));
             const unsigned grid = ax_grid(c, EPW, (int)sizeof(T));
@@ -92,8 +92,8 @@ template <int NP> struct OpsImpl {
     // r.r partials to P4, the block-solve kernel forms z = M^-1 r and writes
     // the r.z partials to P2 (the prologue of the next operator kernel sums
     // both, as for the diagonal preconditioner).
-    template <typename T, typename GT>
-    static int cg_iter_fdm(nek_ctx *c, int variant, int it, bool final, T *x, T *r, T *p, T *w, const GT *g,
+    template <typename T, typename GT, typename XT>
+    static int cg_iter_fdm(nek_ctx *c, int variant, int it, bool final, XT *x, T *r, T *p, T *w, const GT *g,
                            const T *D)
     {
         T *zb;
@@ -102,13 +102,13 @@ template <int NP> struct OpsImpl {
         if (!zb) return NEK_E_ARG;
         return with_variant<NP, GT>(variant, [&](auto epw_c, auto pd_c) -> int {
             constexpr int EPW = decltype(epw_c)::value, PD = decltype(pd_c)::value;
-            if (final) return launch_ax<EPW, PD, T, GT, true, T, true>(c, zb, p, w, g, D, it, x);
+            if (final) return launch_ax<EPW, PD, T, GT, true, XT, true>(c, zb, p, w, g, D, it, x);
             int slot = -1;
             if (c->prof_every > 0 && (c->prof_tick++ % c->prof_every) == 0) {
                 if ((slot = prof_take(c)) < 0) return NEK_E_HIP;
                 HIP_TRY(hipEventRecord(c->prof_pool[3 * slot], c->stream));
             }
-            int rc = launch_ax<EPW, PD, T, GT, true, T, true>(c, zb, p, w, g, D, it, x);
+            int rc = launch_ax<EPW, PD, T, GT, true, XT, true>(c, zb, p, w, g, D, it, x);
             if (rc) return rc;
             if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 1], c->stream));
             const unsigned grid = ax_grid(c, EPW, (int)sizeof(T));
@@ -123,19 +123,28 @@ template <int NP> struct OpsImpl {
 
     // With the diagonal preconditioner on, r holds z = M^-1 r and the update
     // kernel reads the diagonal of the vectors' precision.
-    template <typename T, typename GT>
-    static int cg_iter(nek_ctx *c, int variant, int it, bool final, T *x, T *r, T *p, T *w, const GT *g,
+    template <typename T, typename GT, typename XT>
+    static int cg_iter(nek_ctx *c, int variant, int it, bool final, XT *x, T *r, T *p, T *w, const GT *g,
                        const T *D)
     {
-        if (c->precond == NEK_PC_FDM) return cg_iter_fdm<T, GT>(c, variant, it, final, x, r, p, w, g, D);
+        if (c->precond == NEK_PC_FDM) return cg_iter_fdm<T, GT, XT>(c, variant, it, final, x, r, p, w, g, D);
         if (c->precond) {
             const T *dg;
             if constexpr (sizeof(T) == 8) dg = c->dg64;
             else dg = c->dg32;
             if (!dg) return NEK_E_ARG;
-            return cg_iter_pc<T, GT, true>(c, variant, it, final, x, r, p, w, g, D, dg);
+            return cg_iter_pc<T, GT, true, XT>(c, variant, it, final, x, r, p, w, g, D, dg);
         }
-        return cg_iter_pc<T, GT, false>(c, variant, it, final, x, r, p, w, g, D, nullptr);
+        return cg_iter_pc<T, GT, false, XT>(c, variant, it, final, x, r, p, w, g, D, nullptr);
+    }
+
+    // 4-byte vectors with an FP64 (x64) or FP32 inner correction x
+    template <typename GT>
+    static int cg_iter4(nek_ctx *c, int v, int it, bool final, void *x, bool x64, float *r, float *p, float *w,
+                        const GT *g, const float *D)
+    {
+        if (x64) return cg_iter<float, GT, double>(c, v, it, final, (double *)x, r, p, w, g, D);
+        return cg_iter<float, GT, float>(c, v, it, final, (float *)x, r, p, w, g, D);
     }
 
     // FP64 and FP32 operators read the stored factors, or recompute them in
@@ -143,33 +152,33 @@ template <int NP> struct OpsImpl {
     static int cg_iter64(nek_ctx *c, int v, int it, bool final, double *x, double *r, double *p, double *w,
                          const double *g, const double *D)
     {
-        if (c->geom == NEK_GEOM_TRILINEAR)
-            return cg_iter<double, TriG<double>>(c, v, it, final, x, r, p, w, tri_ptr<double>(c), D);
-        return cg_iter<double, double>(c, v, it, final, x, r, p, w, g, D);
+        if (c->geom == NEK_GSRC_TRILINEAR)
+            return cg_iter<double, TriG<double>, double>(c, v, it, final, x, r, p, w, tri_ptr<double>(c), D);
+        return cg_iter<double, double, double>(c, v, it, final, x, r, p, w, g, D);
     }
-    static int cg_iter32(nek_ctx *c, int v, int it, bool final, float *x, float *r, float *p, float *w,
+    static int cg_iter32(nek_ctx *c, int v, int it, bool final, void *x, bool x64, float *r, float *p, float *w,
                          const float *g, const float *D)
     {
-        if (c->geom == NEK_GEOM_TRILINEAR)
-            return cg_iter<float, TriG<float>>(c, v, it, final, x, r, p, w, tri_ptr<float>(c), D);
-        return cg_iter<float, float>(c, v, it, final, x, r, p, w, g, D);
+        if (c->geom == NEK_GSRC_TRILINEAR)
+            return cg_iter4<TriG<float>>(c, v, it, final, x, x64, r, p, w, tri_ptr<float>(c), D);
+        return cg_iter4<float>(c, v, it, final, x, x64, r, p, w, g, D);
     }
-    static int cg_iter16(nek_ctx *c, int v, int it, bool final, float *x, float *r, float *p, float *w,
+    static int cg_iter16(nek_ctx *c, int v, int it, bool final, void *x, bool x64, float *r, float *p, float *w,
                          const uint16_t *g, const float *D)
     {
-        return cg_iter<float, uint16_t>(c, v, it, final, x, r, p, w, g, D);
+        return cg_iter4<uint16_t>(c, v, it, final, x, x64, r, p, w, g, D);
     }
 
     static int ax64(nek_ctx *c, const double *u, double *w)
     {
-        if (c->geom == NEK_GEOM_TRILINEAR)
+        if (c->geom == NEK_GSRC_TRILINEAR)
             return launch_ax<epw_for(NP), pd_for<double>(), double, TriG<double>, false>(c, u, nullptr, w,
                                                                                          tri_ptr<double>(c), c->D64, 0);
         return launch_ax<epw_for(NP), pd_for<double>(), double, double, false>(c, u, nullptr, w, c->g64, c->D64, 0);
     }
     static int ax32(nek_ctx *c, const float *u, float *w)
     {
-        if (c->geom == NEK_GEOM_TRILINEAR)
+        if (c->geom == NEK_GSRC_TRILINEAR)
             return launch_ax<epw_for(NP), pd_for<float>(), float, TriG<float>, false>(c, u, nullptr, w,
                                                                                       tri_ptr<float>(c), c->D32, 0);
         return launch_ax<epw_for(NP), pd_for<float>(), float, float, false>(c, u, nullptr, w, c->g32, c->D32, 0);
@@ -197,13 +206,13 @@ template <int NP> struct OpsImpl {
     }
     static int axa64(nek_ctx *c, int v, const double *u, double *scratch, double *w)
     {
-        if (c->geom == NEK_GEOM_TRILINEAR)
+        if (c->geom == NEK_GSRC_TRILINEAR)
             return ax_assembled<double, TriG<double>>(c, v, u, scratch, w, tri_ptr<double>(c), c->D64);
         return ax_assembled<double, double>(c, v, u, scratch, w, c->g64, c->D64);
     }
     static int axa32(nek_ctx *c, int v, const float *u, float *scratch, float *w)
     {
-        if (c->geom == NEK_GEOM_TRILINEAR)
+        if (c->geom == NEK_GSRC_TRILINEAR)
             return ax_assembled<float, TriG<float>>(c, v, u, scratch, w, tri_ptr<float>(c), c->D32);
         return ax_assembled<float, float>(c, v, u, scratch, w, c->g32, c->D32);
     }
@@ -257,10 +266,14 @@ template <int NP> struct OpsImpl {
     static int pc_start64(nek_ctx *c, double *r, const double *m) { return pc_start<double>(c, r, m); }
     static int pc_start32(nek_ctx *c, float *r, const float *m) { return pc_start<float>(c, r, m); }
 
-    static int inner_start(nek_ctx *c, const double *r64, float *r32, float *d)
+    static int inner_start(nek_ctx *c, const double *r64, float *r32, void *d, bool d64)
     {
-        hipLaunchKernelGGL((k_inner_start<NP>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, r64, r32, d, c->P3(),
-                           c->box, (unsigned)c->nl);
+        if (d64)
+            hipLaunchKernelGGL((k_inner_start<NP, double>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, r64, r32,
+                               (double *)d, c->P3(), c->box, (unsigned)c->nl);
+        else
+            hipLaunchKernelGGL((k_inner_start<NP, float>), dim3(red_grid(c)), dim3(UPD_BS), 0, c->stream, r64, r32,
+                               (float *)d, c->P3(), c->box, (unsigned)c->nl);
         HIP_TRY(hipGetLastError());
         return NEK_OK;
     }
@@ -270,7 +283,7 @@ template <int NP> struct OpsImpl {
         return with_variant<NP, double>(v, [](auto epw_c, auto) -> int { return decltype(epw_c)::value; });
     }
 
-    template <typename T, typename GT>
+    template <typename T, typename GT, typename XT>
     static int batch_iter_t(hipStream_t s, int v, const BatchProb *tab, const int *owner, unsigned grid, const T *D,
                             int it_local, const int *base, bool final, bool prepare)
     {
@@ -279,12 +292,12 @@ template <int NP> struct OpsImpl {
             const size_t shm = ax_lds_bytes<NP, EPW, T>();
             if (prepare) {
                 if (shm > 65536)
-                    HIP_TRY(hipFuncSetAttribute((const void *)k_ax_batch<NP, EPW, PD, T, GT>,
+                    HIP_TRY(hipFuncSetAttribute((const void *)k_ax_batch<NP, EPW, PD, T, GT, XT>,
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
                 return NEK_OK;
             }
-            hipLaunchKernelGGL((k_ax_batch<NP, EPW, PD, T, GT>), dim3(grid), dim3(BS), shm, s, tab, owner, D, it_local,
-                               base);
+            hipLaunchKernelGGL((k_ax_batch<NP, EPW, PD, T, GT, XT>), dim3(grid), dim3(BS), shm, s, tab, owner, D,
+                               it_local, base);
             HIP_TRY(hipGetLastError());
             if (!final) {
                 hipLaunchKernelGGL((k_cg_update_batch<NP, EPW, T>), dim3(grid), dim3(BS), 0, s, tab, owner, it_local,
@@ -295,16 +308,20 @@ template <int NP> struct OpsImpl {
         });
     }
 
-    static int batch_iter(hipStream_t s, int prec, int v, const BatchProb *tab, const int *owner, unsigned grid,
-                          const void *D, int it_local, const int *base, bool final, bool prepare)
+    static int batch_iter(hipStream_t s, int prec, int v, bool x64, const BatchProb *tab, const int *owner,
+                          unsigned grid, const void *D, int it_local, const int *base, bool final, bool prepare)
     {
+        const float *D32 = (const float *)D;
         if (prec == NEK_PREC_FP64)
-            return batch_iter_t<double, double>(s, v, tab, owner, grid, (const double *)D, it_local, base, final,
-                                                prepare);
+            return batch_iter_t<double, double, double>(s, v, tab, owner, grid, (const double *)D, it_local, base,
+                                                        final, prepare);
         if (prec == NEK_PREC_BF16G)
-            return batch_iter_t<float, uint16_t>(s, v, tab, owner, grid, (const float *)D, it_local, base, final,
-                                                 prepare);
-        return batch_iter_t<float, float>(s, v, tab, owner, grid, (const float *)D, it_local, base, final, prepare);
+            return x64 ? batch_iter_t<float, uint16_t, double>(s, v, tab, owner, grid, D32, it_local, base, final,
+                                                               prepare)
+                       : batch_iter_t<float, uint16_t, float>(s, v, tab, owner, grid, D32, it_local, base, final,
+                                                              prepare);
+        return x64 ? batch_iter_t<float, float, double>(s, v, tab, owner, grid, D32, it_local, base, final, prepare)
+                   : batch_iter_t<float, float, float>(s, v, tab, owner, grid, D32, it_local, base, final, prepare);
     }
 };
 

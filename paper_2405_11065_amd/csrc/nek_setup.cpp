@@ -1,7 +1,7 @@
 // Host-side FP64 initialisation for libnek: GLL rule, differentiation
 // matrix, trilinear geometry and the sorted-segment gather-scatter maps.
 // The paper's mixed build leaves all of this set-up in double precision and
-// lowers only the CG loop (Sect. 5).
+// lowers only the CG loop (Sect. 6).
 #include "nek_setup.hpp"
 
 #include <algorithm>

@@ -27,15 +27,16 @@ PC_NAMES = {"none": NEK_PC_NONE, "jacobi": NEK_PC_JACOBI, "fdm": NEK_PC_FDM}
 (NEK_SIZE_NLOCAL, NEK_SIZE_NGLOBAL, NEK_SIZE_E, NEK_SIZE_NPERM, NEK_SIZE_NSEG, NEK_SIZE_N) = range(6)
 
 PREC_NAMES = {"fp64": NEK_PREC_FP64, "fp32": NEK_PREC_FP32, "bf16g": NEK_PREC_BF16G}
-NEK_GEOM_STORED, NEK_GEOM_TRILINEAR = 0, 1
-GEOM_NAMES = {"stored": NEK_GEOM_STORED, "trilinear": NEK_GEOM_TRILINEAR}
+NEK_GSRC_STORED, NEK_GSRC_TRILINEAR = 0, 1
+GEOM_NAMES = {"stored": NEK_GSRC_STORED, "trilinear": NEK_GSRC_TRILINEAR}
 
 # every entry point declared in include/nek.h
-EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_set_precond", "nek_set_geometry", "nek_precond_apply", "nek_ax_local", "nek_ax",
+EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_set_precond", "nek_set_geometry",
+           "nek_set_max_workgroups", "nek_precond_apply", "nek_ax_local", "nek_ax",
            "nek_dssum", "nek_glsc3", "nek_cg_solve", "nek_prof_enable", "nek_prof_read", "nek_num_variants",
-           "nek_tune", "nek_set_variant", "nek_get_variant", "nek_batch_setup", "nek_batch_free",
+           "nek_tune", "nek_set_variant", "nek_get_variant", "nek_setup_batch", "nek_batch_free",
            "nek_batch_size", "nek_batch_ctx", "nek_batch_orders", "nek_batch_tune", "nek_batch_set_variant",
-           "nek_batch_get_variant", "nek_batch_solve", "nek_batch_counters", "nek_strerror",
+           "nek_batch_get_variant", "nek_cg_solve_batch", "nek_batch_counters", "nek_strerror",
            "nek_mlp_create", "nek_mlp_free", "nek_mlp_num_params", "nek_mlp_get_params", "nek_mlp_set_params",
            "nek_mlp_forward", "nek_mlp_loss_grad", "nek_mlp_adam", "nek_mlp_train", "nek_x0_features",
            "nek_x0_targets", "nek_x0_predict", "nek_grf")
@@ -52,12 +53,13 @@ class nek_mesh(ctypes.Structure):
 class nek_opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("fp64_fallback", ctypes.c_int), ("elts_per_wg", ctypes.c_int),
-                ("refine_mode", ctypes.c_int), ("precond", ctypes.c_int)]
+                ("refine_mode", ctypes.c_int), ("precond", ctypes.c_int), ("corr_fp32", ctypes.c_int)]
 
 
 class nek_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("fp64_iters", ctypes.c_int),
-                ("status", ctypes.c_int), ("rel_res", ctypes.c_double), ("t_solve_s", ctypes.c_double)]
+                ("status", ctypes.c_int), ("true_rel_res", ctypes.c_double), ("last_rec_res", ctypes.c_double),
+                ("t_solve_s", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -90,6 +92,7 @@ def load(path: str = LIB_PATH):
     lib.nek_set_prec.argtypes = [vp, ctypes.c_int]
     lib.nek_set_precond.argtypes = [vp, ctypes.c_int]
     lib.nek_set_geometry.argtypes = [vp, ctypes.c_int]
+    lib.nek_set_max_workgroups.argtypes = [vp, ctypes.c_int]
     lib.nek_precond_apply.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_ax_local.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_ax.argtypes = [vp, vp, vp, ctypes.c_int]
@@ -103,7 +106,7 @@ def load(path: str = LIB_PATH):
                              ctypes.POINTER(ctypes.c_int)]
     lib.nek_set_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.nek_get_variant.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
-    lib.nek_batch_setup.argtypes = [ctypes.c_int, ctypes.POINTER(nek_mesh), ctypes.POINTER(ctypes.c_int),
+    lib.nek_setup_batch.argtypes = [ctypes.c_int, ctypes.POINTER(nek_mesh), ctypes.POINTER(ctypes.c_int),
                                     ctypes.POINTER(nek_opts), vp, ctypes.POINTER(vp)]
     lib.nek_batch_free.argtypes = [vp]
     lib.nek_batch_free.restype = None
@@ -113,7 +116,7 @@ def load(path: str = LIB_PATH):
     lib.nek_batch_tune.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     lib.nek_batch_set_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.nek_batch_get_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
-    lib.nek_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double, ctypes.c_int,
+    lib.nek_cg_solve_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double, ctypes.c_int,
                                     ctypes.POINTER(vp), ctypes.POINTER(nek_stats), ctypes.c_int]
     lib.nek_batch_counters.argtypes = [vp, i64p, i64p]
     dp, fp = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)
@@ -177,7 +180,8 @@ def _mesh(nel, vtx=None, lo=(0.0, 0.0, 0.0), hi=None):
     return m, nel, keep
 
 
-def _opts(prec="fp64", inner_tol=0.0, inner_maxit=0, max_outer=0, fp64_fallback=1, refine_mode=0, precond="none"):
+def _opts(prec="fp64", inner_tol=0.0, inner_maxit=0, max_outer=0, fp64_fallback=1, refine_mode=0, precond="none",
+          elts_per_wg=0, corr_fp32=0):
     o = nek_opts()
     o.prec = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
     o.inner_tol = float(inner_tol)
@@ -186,6 +190,8 @@ def _opts(prec="fp64", inner_tol=0.0, inner_maxit=0, max_outer=0, fp64_fallback=
     o.fp64_fallback = int(fp64_fallback)
     o.refine_mode = int(refine_mode)
     o.precond = PC_NAMES[precond] if isinstance(precond, str) else int(precond)
+    o.elts_per_wg = int(elts_per_wg)
+    o.corr_fp32 = int(corr_fp32)
     return o
 
 
@@ -193,12 +199,14 @@ class Context:
     """One box mesh of order N on the current GPU (nek_setup / nek_free)."""
 
     def __init__(self, nel, N, vtx=None, lo=(0.0, 0.0, 0.0), hi=None, prec="fp64", inner_tol=0.0,
-                 inner_maxit=0, max_outer=0, fp64_fallback=1, refine_mode=0, precond="none", stream=None):
+                 inner_maxit=0, max_outer=0, fp64_fallback=1, refine_mode=0, precond="none", stream=None,
+                 elts_per_wg=0, corr_fp32=0):
         torch = _torch()
         self._lib = load()
         self.N = int(N)
         m, self.nel, self._vtx = _mesh(nel, vtx, lo, hi)
-        o = _opts(prec, inner_tol, inner_maxit, max_outer, fp64_fallback, refine_mode, precond)
+        o = _opts(prec, inner_tol, inner_maxit, max_outer, fp64_fallback, refine_mode, precond, elts_per_wg,
+                  corr_fp32)
         self.stream = torch.cuda.current_stream() if stream is None else stream
         h = ctypes.c_void_p()
         _check(self._lib.nek_setup(ctypes.byref(m), self.N, ctypes.byref(o), ctypes.c_void_p(self.stream.cuda_stream),
@@ -282,6 +290,10 @@ class Context:
         recompute them in the kernel from each element's trilinear map)."""
         _check(self._lib.nek_set_geometry(self._h, GEOM_NAMES[geom] if isinstance(geom, str) else int(geom)),
                "nek_set_geometry")
+
+    def set_max_workgroups(self, n: int):
+        """Cap the persistent / reduction grid at n workgroups (0 = default)."""
+        _check(self._lib.nek_set_max_workgroups(self._h, int(n)), "nek_set_max_workgroups")
 
     def precond_apply(self, r, z=None):
         """z = M^-1 r with the context's preconditioner."""
@@ -392,14 +404,14 @@ class Context:
 
 
 class Batch:
-    """Many box problems solved together (nek_batch_*).
+    """Many box problems solved together (nek_setup_batch, nek_cg_solve_batch, nek_batch_*).
 
     problems: sequence of dicts with keys nel, N and optionally vtx, lo, hi.
     The options (prec, inner_tol, ...) are common to all problems.
     """
 
     def __init__(self, problems, prec="fp64", inner_tol=0.0, inner_maxit=0, max_outer=0, fp64_fallback=1,
-                 refine_mode=0, stream=None):
+                 refine_mode=0, stream=None, elts_per_wg=0, corr_fp32=0):
         torch = _torch()
         self._lib = load()
         n = len(problems)
@@ -413,11 +425,12 @@ class Batch:
             Ns[i] = int(p["N"])
             self._keep.append(keep)
             self.specs.append((nel, int(p["N"])))
-        o = _opts(prec, inner_tol, inner_maxit, max_outer, fp64_fallback, refine_mode)
+        o = _opts(prec, inner_tol, inner_maxit, max_outer, fp64_fallback, refine_mode, elts_per_wg=elts_per_wg,
+                  corr_fp32=corr_fp32)
         self.stream = torch.cuda.current_stream() if stream is None else stream
         h = ctypes.c_void_p()
-        _check(self._lib.nek_batch_setup(n, meshes, Ns, ctypes.byref(o), ctypes.c_void_p(self.stream.cuda_stream),
-                                         ctypes.byref(h)), "nek_batch_setup")
+        _check(self._lib.nek_setup_batch(n, meshes, Ns, ctypes.byref(o), ctypes.c_void_p(self.stream.cuda_stream),
+                                         ctypes.byref(h)), "nek_setup_batch")
         self._h = h
         self._keep = None
         self.n = n
@@ -491,15 +504,15 @@ class Batch:
         for i in range(self.n):
             for t, nm in ((fs[i], "f"), (xs[i], "x")) + (((x0s[i], "x0"),) if x0s is not None else ()):
                 if t is not None and self.ctx[i]._vec(t, f"{nm}[{i}]") != NEK_F64:
-                    raise TypeError(f"{nm}[{i}]: nek_batch_solve takes float64 vectors")
+                    raise TypeError(f"{nm}[{i}]: nek_cg_solve_batch takes float64 vectors")
         P = ctypes.c_void_p * self.n
         fa = P(*[t.data_ptr() for t in fs])
         xa = P(*[t.data_ptr() for t in xs])
         x0a = P(*[(t.data_ptr() if t is not None else None) for t in x0s]) if x0s is not None else None
         st = (nek_stats * self.n)()
-        rc = self._lib.nek_batch_solve(self._h, fa, x0a, float(tol), int(maxit), xa, st,
-                                       0 if graph else NEK_BATCH_NO_GRAPH)
-        _check(rc, "nek_batch_solve", ok=(NEK_OK,) if raise_on_noconv else (NEK_OK, NEK_NOCONV))
+        rc = self._lib.nek_cg_solve_batch(self._h, fa, x0a, float(tol), int(maxit), xa, st,
+                                          0 if graph else NEK_BATCH_NO_GRAPH)
+        _check(rc, "nek_cg_solve_batch", ok=(NEK_OK,) if raise_on_noconv else (NEK_OK, NEK_NOCONV))
         return xs, [s.as_dict() for s in st], rc
 
 

@@ -1,9 +1,9 @@
 """GPU parity of the in-kernel geometric factors (nek_set_geometry with
-NEK_GEOM_TRILINEAR) against the FP64 CPU oracle, through the C ABI.
+NEK_GSRC_TRILINEAR) against the FP64 CPU oracle, through the C ABI.
 
 The kernels recompute G = w det(J) J^-1 J^-T per point from each element's
 trilinear map; the oracle forms J by GLL differentiation of the mapped nodes
-(Sect. 2, Fig. 2: g1..g6 of ax_e).  Both are exact for trilinear elements,
+(Sect. 4.1, Fig. 2: g1..g6 of ax_e).  Both are exact for trilinear elements,
 so the operators agree to rounding: FP64 within the stored-factor bound
 (1e-12, max-norm relative), FP32 within 2e-6, as for the stored FP32 copy.
 Solves are checked as the stored-factor ones: the oracle's true FP64

@@ -318,6 +318,20 @@ def test_full_size_16cubed_N9():
     dx = np.linalg.norm(res["fp32"][0] - res["fp64"][0]) / np.linalg.norm(res["fp64"][0])
     print(f"  |x_mixed - x_fp64| / |x_fp64| = {dx:.2e}")
     assert dx <= 1e-6
+    # factors recomputed in the kernels from the trilinear maps: 1366 element
+    # groups over at most 1024 FP64 workgroups, so some walk two
+    ctx.set_geometry("trilinear")
+    for prec in ("fp64", "fp32"):
+        ctx.set_prec(prec)
+        ctx.tune(prec, iters=10)
+        _case(f"cg 16^3 N=9 {prec} trilinear")
+        x, st, _ = ctx.cg_solve(fd, tol=1e-8, maxit=20000)
+        xh = host(x)
+        rho = P.true_residual(xh, f)
+        dx = np.linalg.norm(xh - res[prec][0]) / np.linalg.norm(res[prec][0])
+        print(f"  {prec} trilinear: iters {st['iters']} rho* {rho:.2e} |x - x_stored|/|x_stored| {dx:.2e}")
+        assert st["status"] == 0 and rho <= 1e-8 and dx <= 1e-6
+    ctx.set_geometry("stored")
     # both preconditioners on the benchmarked workload, FP64 and mixed
     for pc in ("jacobi", "fdm"):
         ctx.set_precond(pc)
@@ -350,6 +364,20 @@ def test_full_size_32cubed_N9_bf16g():
     print(f"  bf16g: iters {st['iters']} outer {st['outer_iters']} fp64 {st['fp64_iters']} "
           f"t {st['t_solve_s']:.3f}s rho* {rho:.2e}")
     assert st["status"] == 0 and rho <= 1e-8
+    # FP64 CG on the same mesh: 16384 element groups over the persistent grid,
+    # every workgroup walking several; stored and in-kernel factors
+    ctx.set_prec("fp64")
+    for geom in ("stored", "trilinear"):
+        ctx.set_geometry(geom)
+        ctx.tune("fp64", iters=10)
+        _case(f"cg 32^3 N=9 fp64 {geom}")
+        x64, s64, _ = ctx.cg_solve(dev(f_gpu), tol=1e-8, maxit=20000)
+        rho = P.true_residual(host(x64), f_or)
+        print(f"  fp64 {geom}: iters {s64['iters']} t {s64['t_solve_s']:.3f}s rho* {rho:.2e} "
+              f"reported {s64['true_rel_res']:.2e}")
+        assert s64["status"] == 0 and rho <= 1e-8
+    ctx.set_geometry("stored")
+    ctx.set_prec("bf16g")
     # the same solve with each preconditioner, as the benchmark times it
     for pc in ("jacobi", "fdm"):
         ctx.set_precond(pc)

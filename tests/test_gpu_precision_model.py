@@ -9,8 +9,12 @@ its refinement; with a single refinement step and the inner tolerance set
 to the outer one, its returned true residual must show the same stall, at
 the level the emulation predicts (within a factor of 5: the GPU fuses
 multiply-adds and sums copies in FP64 before rounding, so the two agree
-in magnitude, not bit for bit).  With refinement allowed the same solve
-must reach the tolerance.
+in magnitude, not bit for bit).  The emulation rounds every vector update,
+the iterate's included, so the GPU runs with its FP32-stored correction
+(corr_fp32), the layout the emulation models.  Each check also runs with
+the persistent grid capped at 3 workgroups, so that every workgroup walks
+several element groups, the path the kernels take at full size.  With
+refinement allowed the same solve must reach the tolerance.
 """
 import numpy as np
 import pytest
@@ -29,7 +33,8 @@ def _gpu():
     nek.load()
 
 
-def test_fp32_inner_cg_stall_matches_emulation():
+@pytest.mark.parametrize("cap", [0, 3])
+def test_fp32_inner_cg_stall_matches_emulation(cap):
     nel, N, tol = (4, 4, 4), 7, 1e-8
     vtx = synth.box_vertices(nel)
     P = oracle.Problem(N, nel, vtx)
@@ -41,18 +46,20 @@ def test_fp32_inner_cg_stall_matches_emulation():
     assert he[-1] <= tol and emu > 100 * tol
 
     fd = torch.from_numpy(f).cuda()
-    one = nek.Context(nel, N, vtx=vtx, prec="fp32", inner_tol=tol, max_outer=1)
+    one = nek.Context(nel, N, vtx=vtx, prec="fp32", inner_tol=tol, max_outer=1, corr_fp32=1)
+    one.set_max_workgroups(cap)
     x, st, _ = one.cg_solve(fd, tol=tol, maxit=3000)
     torch.cuda.synchronize()
     gpu = P.true_residual(x.cpu().numpy(), f)
-    print(f"GPU one refinement step: {st['iters']} inner its, returned {st['rel_res']:.3e}, oracle {gpu:.3e}",
+    print(f"GPU one refinement step: {st['iters']} inner its, returned {st['true_rel_res']:.3e}, oracle {gpu:.3e}",
           flush=True)
     assert st["outer_iters"] == 1
-    assert gpu == pytest.approx(st["rel_res"], rel=1e-6)
+    assert gpu == pytest.approx(st["true_rel_res"], rel=1e-6)
     assert emu / 5 <= gpu <= emu * 5
     assert abs(st["iters"] - ite) <= 0.1 * ite
 
     full = nek.Context(nel, N, vtx=vtx, prec="fp32")
+    full.set_max_workgroups(cap)
     x, st, _ = full.cg_solve(fd, tol=tol, maxit=3000, raise_on_noconv=True)
     res = P.true_residual(x.cpu().numpy(), f)
     print(f"GPU refinement: {st['outer_iters']} steps, {st['iters']} its, oracle true residual {res:.3e}", flush=True)
@@ -61,7 +68,8 @@ def test_fp32_inner_cg_stall_matches_emulation():
     full.close()
 
 
-def test_fp32_inner_pcg_stall_matches_emulation():
+@pytest.mark.parametrize("cap", [0, 3])
+def test_fp32_inner_pcg_stall_matches_emulation(cap):
     """The same with the diagonal (Jacobi) preconditioner: the 23-bit
     preconditioned loop stalls too, the GPU's FP32 inner PCG at the level the
     emulation predicts (factor 5), and refinement removes the stall."""
@@ -77,16 +85,18 @@ def test_fp32_inner_pcg_stall_matches_emulation():
     assert he[-1] <= tol and emu > 100 * tol
 
     fd = torch.from_numpy(f).cuda()
-    one = nek.Context(nel, N, vtx=vtx, prec="fp32", inner_tol=tol, max_outer=1, precond="jacobi")
+    one = nek.Context(nel, N, vtx=vtx, prec="fp32", inner_tol=tol, max_outer=1, precond="jacobi", corr_fp32=1)
+    one.set_max_workgroups(cap)
     x, st, _ = one.cg_solve(fd, tol=tol, maxit=3000)
     gpu = P.true_residual(x.cpu().numpy(), f)
-    print(f"GPU one refinement step: {st['iters']} inner its, returned {st['rel_res']:.3e}, oracle {gpu:.3e}",
+    print(f"GPU one refinement step: {st['iters']} inner its, returned {st['true_rel_res']:.3e}, oracle {gpu:.3e}",
           flush=True)
     assert st["outer_iters"] == 1
     assert emu / 5 <= gpu <= emu * 5
     assert abs(st["iters"] - ite) <= 0.1 * ite
 
     full = nek.Context(nel, N, vtx=vtx, prec="fp32", precond="jacobi")
+    full.set_max_workgroups(cap)
     x, st, _ = full.cg_solve(fd, tol=tol, maxit=3000, raise_on_noconv=True)
     res = P.true_residual(x.cpu().numpy(), f)
     print(f"GPU refinement: {st['outer_iters']} steps, {st['iters']} its, oracle true residual {res:.3e}", flush=True)
