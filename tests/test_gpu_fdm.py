@@ -117,7 +117,9 @@ def test_switching_to_fdm_and_back():
     vtx = synth.box_vertices(nel, perturb=0.1, seed=10)
     f = torch.from_numpy(synth.uniform_load(3 * 2 * 2 * 216, 34)).cuda()
     for prec in ("fp64", "fp32"):
-        ctx = nek.Context(nel, N, vtx=vtx, prec=prec)
+        # one fixed kernel configuration for both contexts (no autotuning), so
+        # their results can be compared bit for bit
+        ctx = nek.Context(nel, N, vtx=vtx, prec=prec, elts_per_wg=-1)
         a, sa, _ = ctx.cg_solve(f, tol=1e-8, maxit=3000)
         a = a.clone()
         ctx.set_precond("fdm")
@@ -125,7 +127,7 @@ def test_switching_to_fdm_and_back():
         b = b.clone()
         ctx.set_precond("none")
         c, sc, _ = ctx.cg_solve(f, tol=1e-8, maxit=3000)
-        fresh = nek.Context(nel, N, vtx=vtx, prec=prec, precond="fdm")
+        fresh = nek.Context(nel, N, vtx=vtx, prec=prec, precond="fdm", elts_per_wg=-1)
         d, sd, _ = fresh.cg_solve(f, tol=1e-8, maxit=3000)
         print(f"  {prec}: none {sa['iters']} its, fdm {sb['iters']}, none again {sc['iters']}")
         assert torch.equal(a, c) and torch.equal(b, d) and sb["iters"] < sa["iters"]

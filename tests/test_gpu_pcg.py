@@ -139,7 +139,9 @@ def test_switching_preconditioner_on_one_context():
     vtx = synth.box_vertices(nel, perturb=0.1, seed=10)
     f = torch.from_numpy(synth.uniform_load(3 * 2 * 2 * 216, 34)).cuda()
     for prec in ("fp64", "fp32"):
-        ctx = nek.Context(nel, N, vtx=vtx, prec=prec)
+        # one fixed kernel configuration for both contexts (no autotuning), so
+        # their results can be compared bit for bit
+        ctx = nek.Context(nel, N, vtx=vtx, prec=prec, elts_per_wg=-1)
         a, sa, _ = ctx.cg_solve(f, tol=1e-8, maxit=3000)
         a = a.clone()
         ctx.set_precond("jacobi")
@@ -147,7 +149,7 @@ def test_switching_preconditioner_on_one_context():
         b = b.clone()
         ctx.set_precond("none")
         c, sc, _ = ctx.cg_solve(f, tol=1e-8, maxit=3000)
-        fresh = nek.Context(nel, N, vtx=vtx, prec=prec, precond="jacobi")
+        fresh = nek.Context(nel, N, vtx=vtx, prec=prec, precond="jacobi", elts_per_wg=-1)
         d, sd, _ = fresh.cg_solve(f, tol=1e-8, maxit=3000)
         print(f"{prec}: none {sa['iters']} its, jacobi {sb['iters']}, none again {sc['iters']}")
         assert torch.equal(a, c) and sa["iters"] == sc["iters"]
