@@ -51,8 +51,10 @@ typedef enum {
     NEK_E_JACOBIAN = -4,     /* det J <= 0 somewhere: inverted element      */
     NEK_E_BREAKDOWN = -5,    /* CG breakdown: p.Ap <= 0                     */
     NEK_E_NONFINITE = -6,    /* a NaN or Inf reached a reduction            */
-    NEK_E_STAGNATION = -7    /* mixed refinement stopped reducing and the
+    NEK_E_STAGNATION = -7,   /* mixed refinement stopped reducing and the
                                 FP64 fallback was disabled                  */
+    NEK_E_SCRATCH = -8       /* nek_ax_noalloc: the vector exceeds the static
+                                scratch (NEK_NOALLOC_SCRATCH_BYTES)          */
 } nek_status;
 
 /* Operator precision of a context's solves. */
@@ -262,6 +264,28 @@ int nek_ax_local(nek_ctx *ctx, const void *u, void *w, int dtype);
  * dtype.  Runs in the context's CG kernel configuration for the precision.
  */
 int nek_ax(nek_ctx *ctx, const void *u, void *w, int dtype);
+
+/*
+ * nek_ax_noalloc -- nek_ax that allocates nothing, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments and result as nek_ax, the
+ * same kernels and configuration (bit-identical output), but the
+ * unassembled A_L u goes to a static device array of the library instead of
+ * a work vector of the context (which nek_ax allocates on its first call).
+ * The array holds NEK_NOALLOC_SCRATCH_BYTES (32 MiB: n_local up to 4,194,304
+ * for NEK_F64, 8,388,608 for NEK_F32); a larger vector returns
+ * NEK_E_SCRATCH.  Each GPU the library runs on holds one such array until
+ * the process ends, shared by every call on that GPU: calls that overlap on
+ * one GPU (on different streams, or from different host threads) race on
+ * it, so serialise them.  Every entry it reads is written earlier in the
+ * same call, so nothing needs clearing between calls.  The factor copy the
+ * dtype needs must already exist (NEK_E_ARG otherwise): FP64 always; for
+ * NEK_F32 the FP32 or BF16 copy that nek_setup (opts->prec) or
+ * nek_set_prec built.  No hipMalloc, hipFree or allocating library call is
+ * made; asynchronous on the context's stream.
+ */
+#define NEK_NOALLOC_SCRATCH_BYTES (32u << 20)
+int nek_ax_noalloc(nek_ctx *ctx, const void *u, void *w, int dtype);
 
 /*
  * nek_dssum -- in place: every local copy of a global node receives the sum

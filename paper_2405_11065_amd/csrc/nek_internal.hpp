@@ -102,6 +102,7 @@ struct nek_ctx {
     bool tuned[3] = {false, false, false};   // configuration fixed (else the next solve autotunes)
     int max_wg = 0;               // cap on persistent / reduction workgroups (0: default)
     bool batch_member = false;    // owned by a batch, which lays out its grid once
+    void *noalloc_scratch = nullptr;   // this device's static scratch of nek_ax_noalloc
 
     std::vector<double> xi, w, D, vtx;
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -18,9 +19,37 @@
 
 using namespace nek;
 
+// Static device scratch of nek_ax_noalloc (the unassembled A_L u of one call).
+// In host code `scratch` names a host-side stand-in, not device memory: host
+// code reaches the array only through the per-device address that
+// hipGetSymbolAddress returns (noalloc_scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[NEK_NOALLOC_SCRATCH_BYTES];
+
 namespace nek {
 
 int g_num_cu = 0;
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device (with the device current) and kept.
+int noalloc_scratch_ptr(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return NEK_E_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NEK_E_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NEK_OK;
+}
 
 int num_cu()
 {
@@ -634,6 +663,7 @@ const char *nek_strerror(int s)
     case NEK_E_BREAKDOWN: return "CG breakdown (pAp <= 0)";
     case NEK_E_NONFINITE: return "non-finite value in a reduction";
     case NEK_E_STAGNATION: return "mixed-precision refinement stagnated";
+    case NEK_E_SCRATCH: return "vector larger than the static scratch of nek_ax_noalloc (32 MiB)";
     default: return "unknown status";
     }
 }
@@ -734,6 +764,7 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
         hipMemcpy(&c->sc->host_done, &hflag_dev, sizeof(int *), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->partials, 0, 7 * MAXB * sizeof(double)) != hipSuccess)
         return fail(NEK_E_HIP);
+    if ((rc = noalloc_scratch_ptr(&c->noalloc_scratch))) return fail(rc);
     if ((rc = ensure_g(c, c->prec))) return fail(rc);
     if (c->opts.precond != NEK_PC_NONE) {
         if ((rc = c->opts.precond == NEK_PC_FDM ? ensure_fdm(c) : ensure_diag(c))) return fail(rc);
@@ -888,6 +919,22 @@ int nek_ax(nek_ctx *c, const void *u, void *w, int dtype)
     if (dalloc(c->w32, c->nl)) return NEK_E_OOM;
     if (prec == NEK_PREC_BF16G) return ops(c)->axa16(c, c->variant[prec], (const float *)u, c->w32, (float *)w);
     return ops(c)->axa32(c, c->variant[prec], (const float *)u, c->w32, (float *)w);
+}
+
+int nek_ax_noalloc(nek_ctx *c, const void *u, void *w, int dtype)
+{
+    if (!c || !u || !w || u == w || (dtype != NEK_F64 && dtype != NEK_F32) || !c->noalloc_scratch) return NEK_E_ARG;
+    const size_t bytes = (size_t)c->nl * (dtype == NEK_F64 ? sizeof(double) : sizeof(float));
+    if (bytes > NEK_NOALLOC_SCRATCH_BYTES) return NEK_E_SCRATCH;
+    if (dtype == NEK_F64) return ops(c)->axa64(c, c->variant[NEK_PREC_FP64], (const double *)u, (double *)c->noalloc_scratch,
+                                               (double *)w);
+    const int prec = c->prec == NEK_PREC_BF16G ? NEK_PREC_BF16G : NEK_PREC_FP32;
+    const bool have = prec == NEK_PREC_BF16G ? c->g16 != nullptr
+                    : c->geom == NEK_GSRC_TRILINEAR ? c->tri32 != nullptr : c->g32 != nullptr;
+    if (!have) return NEK_E_ARG;   // the factor copy would have to be allocated
+    float *sp = (float *)c->noalloc_scratch;
+    if (prec == NEK_PREC_BF16G) return ops(c)->axa16(c, c->variant[prec], (const float *)u, sp, (float *)w);
+    return ops(c)->axa32(c, c->variant[prec], (const float *)u, sp, (float *)w);
 }
 
 int nek_glsc3(nek_ctx *c, const void *a, const void *b, int dtype, double *out)

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_PKG, "libnek.so")
 
 NEK_OK, NEK_NOCONV = 0, 1
 NEK_E_ARG, NEK_E_HIP, NEK_E_OOM, NEK_E_JACOBIAN = -1, -2, -3, -4
-NEK_E_BREAKDOWN, NEK_E_NONFINITE, NEK_E_STAGNATION = -5, -6, -7
+NEK_E_BREAKDOWN, NEK_E_NONFINITE, NEK_E_STAGNATION, NEK_E_SCRATCH = -5, -6, -7, -8
+NEK_NOALLOC_SCRATCH_BYTES = 32 << 20
 NEK_PREC_FP64, NEK_PREC_FP32, NEK_PREC_BF16G = 0, 1, 2
 NEK_F64, NEK_F32 = 0, 1
 (NEK_GET_GLL, NEK_GET_W, NEK_GET_D, NEK_GET_G, NEK_GET_B, NEK_GET_GID, NEK_GET_MULT, NEK_GET_MASK,
@@ -32,7 +33,7 @@ GEOM_NAMES = {"stored": NEK_GSRC_STORED, "trilinear": NEK_GSRC_TRILINEAR}
 
 # every entry point declared in include/nek.h
 EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_set_precond", "nek_set_geometry",
-           "nek_set_max_workgroups", "nek_precond_apply", "nek_ax_local", "nek_ax",
+           "nek_set_max_workgroups", "nek_precond_apply", "nek_ax_local", "nek_ax", "nek_ax_noalloc",
            "nek_dssum", "nek_glsc3", "nek_cg_solve", "nek_prof_enable", "nek_prof_read", "nek_num_variants",
            "nek_tune", "nek_set_variant", "nek_get_variant", "nek_setup_batch", "nek_batch_free",
            "nek_batch_size", "nek_batch_ctx", "nek_batch_orders", "nek_batch_tune", "nek_batch_set_variant",
@@ -96,6 +97,7 @@ def load(path: str = LIB_PATH):
     lib.nek_precond_apply.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_ax_local.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_ax.argtypes = [vp, vp, vp, ctypes.c_int]
+    lib.nek_ax_noalloc.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_dssum.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int]
     lib.nek_glsc3.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     lib.nek_cg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, vp, ctypes.POINTER(nek_stats), vp]
@@ -334,6 +336,14 @@ class Context:
         if self._vec(w, "w") != dt or w.data_ptr() == u.data_ptr():
             raise ValueError("w must match u's dtype and not alias it")
         _check(self._lib.nek_ax(self._h, u.data_ptr(), w.data_ptr(), dt), "nek_ax")
+        return w
+
+    def ax_noalloc(self, u, w):
+        """nek_ax through the library's static scratch: no device allocation (w must be given)."""
+        dt = self._vec(u, "u")
+        if self._vec(w, "w") != dt or w.data_ptr() == u.data_ptr():
+            raise ValueError("w must match u's dtype and not alias it")
+        _check(self._lib.nek_ax_noalloc(self._h, u.data_ptr(), w.data_ptr(), dt), "nek_ax_noalloc")
         return w
 
     def dssum(self, w, mask=True):
