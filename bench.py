@@ -152,10 +152,14 @@ def big_case(torch, nek, synth, steps=2, energy=True, jacobi=True):
     del X, B, noise
     x = ctx.new_vector()
     out = {"local_points": ctx.nl}
-    for prec in ("bf16g", "fp64"):
+    roof = {}
+    for prec in ("bf16g", "fp32", "fp64"):
         ctx.set_prec(prec)
         ctx.tune(prec, iters=10)
         ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+        ctx.prof_read(0, reset=True)
+        ctx.prof_read(1, reset=True)
+        ctx.prof_enable(16)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         its = 0
@@ -164,12 +168,35 @@ def big_case(torch, nek, synth, steps=2, energy=True, jacobi=True):
             its += st["iters"]
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
+        ctx.prof_enable(0)
         out[prec] = {"ms_per_solve": round(dt * 1e3, 2), "iters": its / steps, "outer": st["outer_iters"],
                      "GDOF_iter_per_s": round(ctx.nl * its / steps / dt / 1e9, 3),
-                     "true_rel_res": st["true_rel_res"], "last_rec_res": st["last_rec_res"]}
-    out["speedup_vs_fp64"] = round(out["fp64"]["ms_per_solve"] / out["bf16g"]["ms_per_solve"], 3)
+                     "true_rel_res": st["true_rel_res"], "last_rec_res": st["last_rec_res"],
+                     "tuned_variant": ctx.get_variant(prec)}
+        roof[prec] = kernel_roofline(ctx, prec)
+    out["cg_kernel_roofline"] = roof
+    # FP64 CG with the factors recomputed in the kernels (every element is trilinear)
+    ctx.set_geometry("trilinear")
+    ctx.set_prec("fp64")
+    ctx.tune("fp64", iters=10)
+    ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st, _ = ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    out["fp64_trilinear"] = {"ms_per_solve": round(dt * 1e3, 2), "iters": st["iters"],
+                             "true_rel_res": st["true_rel_res"], "tuned_variant": ctx.get_variant("fp64")}
+    ctx.set_geometry("stored")
+    best64 = min(out["fp64"]["ms_per_solve"], out["fp64_trilinear"]["ms_per_solve"])
+    out["fastest_fp64"] = "trilinear" if out["fp64_trilinear"]["ms_per_solve"] < out["fp64"]["ms_per_solve"] else "stored"
+    out["speedup_vs_fp64"] = round(best64 / out["bf16g"]["ms_per_solve"], 3)
+    out["speedup_vs_fp64_stored"] = round(out["fp64"]["ms_per_solve"] / out["bf16g"]["ms_per_solve"], 3)
+    out["fp32_speedup_vs_fp64"] = round(best64 / out["fp32"]["ms_per_solve"], 3)
     if energy:
-        out["energy"] = big_energy(torch, ctx, f, x, {p: out[p]["ms_per_solve"] for p in ("bf16g", "fp64")})
+        out["energy"] = big_energy(torch, ctx, f, x, {"bf16g": out["bf16g"]["ms_per_solve"], "fp64": best64},
+                                   out["fastest_fp64"])
     for pc in (("jacobi", "fdm") if jacobi else ()):
         # the same solves with a preconditioner (kernels autotuned for it)
         saved = {p: ctx.get_variant(p) for p in ("bf16g", "fp64")}
@@ -200,8 +227,9 @@ def big_case(torch, nek, synth, steps=2, energy=True, jacobi=True):
     return out
 
 
-def big_energy(torch, ctx, f, x, ms_per_solve):
-    """Energy per solve of the 32^3 case, BF16-g mixed against FP64."""
+def big_energy(torch, ctx, f, x, ms_per_solve, fp64_geometry="stored"):
+    """Energy per solve of the 32^3 case, BF16-g mixed against FP64 (in its
+    fastest factor source)."""
     try:
         meter = EnergyCounter(torch)
     except Exception as ex:
@@ -210,17 +238,41 @@ def big_energy(torch, ctx, f, x, ms_per_solve):
     try:
         for prec in ("bf16g", "fp64"):
             ctx.set_prec(prec)
+            ctx.set_geometry(fp64_geometry if prec == "fp64" else "stored")
             watts, window, calls = steady_power(
                 meter.read, lambda: ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True),
                 min_window_s=4.0, max_run_s=30.0)
             out[prec] = {"W": round(watts, 1), "window_s": round(window, 2), "solves_in_run": calls,
                          "J_per_solve": round(watts * ms_per_solve[prec] / 1e3, 2)}
         out["energy_reduction_pct"] = round(100 * (1 - out["bf16g"]["J_per_solve"] / out["fp64"]["J_per_solve"]), 2)
+        out["fp64_geometry"] = fp64_geometry
     except Exception as ex:
         out["error"] = repr(ex)
     finally:
+        ctx.set_geometry("stored")
         meter.close()
     return out
+
+
+def kernel_roofline(ctx, prec):
+    """Sampled mean durations of the two CG kernels (HIP events on the
+    solver's stream, every 16th iteration) against their algorithmic bytes:
+    the operator kernel moves 4 s_v + 6 s_g + 2 s_x per point (r, p in; p,
+    w out; six factors; the deferred iterate / correction update, FP64),
+    the gather/update kernel 3 s_v (w, r in; r out)."""
+    sv, sg = {"fp64": (8, 8), "fp32": (4, 4), "bf16g": (4, 2)}[prec]
+    ops = {"operator": (0, cg_operator_bytes_per_point(sv, sg, 8)), "update": (1, 3 * sv)}
+    res = {}
+    for name, (k, bpp) in ops.items():
+        ms, n = ctx.prof_read(k)
+        if not n:
+            res[name] = None
+            continue
+        t = ms / n / 1e3
+        gbs = bpp * ctx.nl / t / 1e9
+        res[name] = {"avg_us": round(t * 1e6, 2), "bytes_per_point": bpp, "GBps": round(gbs, 1),
+                     "frac_hbm": round(gbs / PEAK_HBM_GBS, 3), "sampled_launches": n}
+    return res
 
 
 def precond_case(torch, ctx, f, steps, base, pc="jacobi"):
@@ -263,6 +315,32 @@ def precond_case(torch, ctx, f, steps, base, pc="jacobi"):
         ctx.set_precond("none")
         for p, v in saved.items():
             ctx.set_variant(p, v)
+    return out
+
+
+def refinement_case(torch, nek, f, steps, base_ms):
+    """The same mixed solve under the other refinement layouts, each on its
+    own context (the layout is a set-up option) and autotuned: restarted
+    refinement (CG restarted after every true-residual update, inner
+    reduction 1e-4) and the correction d stored in FP32 instead of FP64."""
+    out = {}
+    for label, kw in (("restarted", {"refine_mode": 1}), ("corr_fp32", {"corr_fp32": 1})):
+        c = nek.Context(NEL, N, prec="fp32", **kw)
+        c.tune("fp32", iters=30)
+        xr = c.new_vector()
+        c.cg_solve(f, tol=TOL, maxit=20000, x=xr, raise_on_noconv=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = 0
+        for _ in range(steps):
+            _, st, _ = c.cg_solve(f, tol=TOL, maxit=20000, x=xr, raise_on_noconv=True)
+            its += st["iters"]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[label] = {"ms_per_solve": round(dt * 1e3, 3), "iters": its / steps, "outer": st["outer_iters"],
+                      "true_rel_res": st["true_rel_res"], "GDOF_iter_per_s": round(c.nl * its / steps / dt / 1e9, 3),
+                      "default_ms_over_this": round(base_ms / (dt * 1e3), 3)}
+        c.close()
     return out
 
 
@@ -366,11 +444,12 @@ def steady_power(read, work, min_window_s=3.0, max_run_s=20.0, clock=time.perf_c
     return (e1 - e0) / (s1 - s0), s1 - s0, calls
 
 
-def energy_to_solution(torch, ctx, solve, ms_per_solve):
+def energy_to_solution(torch, ctx, solve, ms_per_solve, fp64_geometry="stored"):
     """Energy per solve at each precision (the paper's energy-to-solution,
     Table 6, here for the GPU package): mean package power while the solve
     repeats back to back, times the solve's time from the timed steps.
-    Idle power is measured beside it so the dynamic part can be separated."""
+    Idle power is measured beside it so the dynamic part can be separated.
+    FP64 runs in its fastest factor source (fp64_geometry)."""
     try:
         meter = EnergyCounter(torch)
     except Exception as ex:   # no amdsmi or no permission: report, do not fail the bench
@@ -381,6 +460,7 @@ def energy_to_solution(torch, ctx, solve, ms_per_solve):
         out["idle_W"] = round(steady_power(meter.read, lambda: time.sleep(0.05), min_window_s=2.0)[0], 1)
         for prec in ("fp32", "fp64"):
             ctx.set_prec(prec)
+            ctx.set_geometry(fp64_geometry if prec == "fp64" else "stored")
             watts, window, calls = steady_power(meter.read, solve, min_window_s=4.0)
             ms = ms_per_solve[prec]
             out[prec] = {"W": round(watts, 1), "window_s": round(window, 2), "solves_in_run": calls,
@@ -389,9 +469,11 @@ def energy_to_solution(torch, ctx, solve, ms_per_solve):
         out["energy_reduction_pct"] = round(100 * (1 - out["fp32"]["J_per_solve"] / out["fp64"]["J_per_solve"]), 2)
         out["paper_context"] = ("47.14 % energy-to-solution reduction at 128 MPI ranks on a 2x EPYC 7763 node "
                                 "(Table 6); a CPU node, not comparable hardware")
+        out["fp64_geometry"] = fp64_geometry
     except Exception as ex:
         out["error"] = repr(ex)
     finally:
+        ctx.set_geometry("stored")
         meter.close()
     return out
 
@@ -632,7 +714,8 @@ def main():
     t0 = time.perf_counter()
     it64 = 0
     for _ in range(args.steps):
-        it64 += solve()["iters"]
+        st64 = solve()
+        it64 += st64["iters"]
     torch.cuda.synchronize()
     t_fp64 = time.perf_counter() - t0
 
@@ -642,12 +725,18 @@ def main():
     log(f"jacobi: {jac}")
     fdmc = None if args.no_jacobi else precond_case(torch, ctx, f, args.steps, base, "fdm")
     log(f"fdm: {fdmc}")
-    geo = None if args.no_jacobi else geometry_case(torch, ctx, f, args.steps, base)
+    geo = geometry_case(torch, ctx, f, args.steps, base)
     log(f"trilinear geometry: {geo}")
+    # the GPU's fastest FP64 CG: stored or in-kernel factors
+    ms64_stored = t_fp64 / args.steps * 1e3
+    fast64 = "trilinear" if geo["fp64"]["ms_per_solve"] < ms64_stored else "stored"
+    ms64_best = min(ms64_stored, geo["fp64"]["ms_per_solve"])
+    refine = refinement_case(torch, nek, f, args.steps, ms_per_step)
+    log(f"refinement layouts: {refine}")
 
-    # ---- energy-to-solution, mixed vs FP64, same solve
+    # ---- energy-to-solution, mixed vs FP64 (fastest factor source), same solve
     energy = None if args.no_energy else energy_to_solution(
-        torch, ctx, solve, {"fp32": ms_per_step, "fp64": t_fp64 / args.steps * 1e3})
+        torch, ctx, solve, {"fp32": ms_per_step, "fp64": ms64_best}, fast64)
     log(f"energy: {energy}")
 
     # ---- ax + dssum bandwidth at each precision (nek_ax), and a plain copy beside it
@@ -660,7 +749,7 @@ def main():
     batch = None if args.no_batch else batch_case(torch, nek, synth)
     learned = None if args.no_learned else learned_case(torch)
 
-    bpp = cg_operator_bytes_per_point(4, 4, 4)   # FP32 vectors, g and inner correction
+    bpp = cg_operator_bytes_per_point(4, 4, 8)   # FP32 vectors and g, FP64 inner correction
     ax_avg_s = ax_ms / max(ax_n, 1) / 1e3
     achieved = bpp * nl / ax_avg_s / 1e9 if ax_n else None
     cpu = None if args.no_cpu else cpu_baseline(f_host)
@@ -679,19 +768,25 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "box 16x16x16 unit-cube hexahedra, N=9, f~U[0,1) seed 2, tol 1e-8 relative",
-                   "local_points": nl, "precision": "FP32 operator/dssum, FP64 glsc3/scalars/x/refinement"},
+                   "local_points": nl, "precision": "FP32 operator/dssum/p/r/w, FP64 glsc3/scalars/correction/x/"
+                                                    "refinement residual; reliable-update refinement"},
         "mixed": {"iters_per_solve": iters / args.steps, "outer_per_solve": stats[-1]["outer_iters"],
-                  "true_rel_res": stats[-1]["true_rel_res"], "ms_per_solve": round(ms_per_step, 3)},
+                  "true_rel_res": stats[-1]["true_rel_res"], "last_rec_res": stats[-1]["last_rec_res"],
+                  "ms_per_solve": round(ms_per_step, 3), "inner_over_fp64_iters": round(iters / max(it64, 1), 4)},
         "fp64": {"value": round(nl * it64 / t_fp64 / 1e9, 3), "iters_per_solve": it64 / args.steps,
-                 "ms_per_solve": round(t_fp64 / args.steps * 1e3, 3)},
-        "speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
+                 "ms_per_solve": round(ms64_stored, 3), "true_rel_res": st64["true_rel_res"],
+                 "fastest": fast64, "fastest_ms_per_solve": round(ms64_best, 3)},
+        "speedup_vs_fp64": round(ms64_best / ms_per_step, 3),
+        "speedup_vs_fp64_stored": round(ms64_stored / ms_per_step, 3),
+        "refinement_layouts": refine,
         "tuned_variant": {k: {"best": v[0], "us_per_iter": [round(u, 1) for u in v[1]]} for k, v in tuned.items()},
         "ax_dssum": axd,
         "energy": energy,
         "jacobi": jac,
         "fdm": fdmc,
         "geometry_trilinear": geo,
-        "roofline": {"bound": "hbm", "kernel": f"k_ax<NP=10,f32,f32,CG> variant {tuned['fp32'][0]} (add2s1 + ax_e + correction update)",
+        "roofline": {"bound": "hbm", "kernel": f"k_ax<NP=10,f32,f32,CG,x=f64> variant {tuned['fp32'][0]} "
+                                               f"(add2s1 + ax_e + FP64 correction update)",
                      "achieved": round(achieved, 1) if achieved else None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4) if achieved else None,
                      "traffic": counter_traffic(tuned["fp32"][0]), "traffic_unit": "bytes per launch",

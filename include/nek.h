@@ -79,8 +79,9 @@ typedef struct {
 typedef struct {
     int prec;                /* nek_prec of nek_cg_solve                                */
     double inner_tol;        /* mixed: residual reduction of each inner run before the
-                                next FP64 true-residual update; 0 = 1e-4 (FP32 g,
-                                restarted) or 1e-2 (BF16 g, or reliable update)      */
+                                next FP64 true-residual update; 0 = the default of
+                                the refinement mode: reliable update 1e-2 (FP32 g) or
+                                0.3 (BF16 g); restarted 1e-4 (FP32 g) or 1e-2 (BF16 g) */
     int inner_maxit;         /* mixed: inner iteration cap per refinement step; 0 = 4000 */
     int max_outer;           /* mixed: refinement steps cap; 0 = 30                      */
     int fp64_fallback;       /* mixed: 1 = when a refinement step fails to halve the
@@ -94,10 +95,12 @@ typedef struct {
                                      (NEK_E_ARG when the order has none);
                                 -1 = the order's default configuration, untuned.
                                 nek_tune and nek_set_variant override it.              */
-    int refine_mode;         /* mixed: 0 = default (1);
+    int refine_mode;         /* mixed: 0 = default (2);
                                 1 = restart CG after each true-residual update;
                                 2 = reliable update: replace r by the FP64 true
-                                    residual and continue the search direction   */
+                                    residual and continue the search direction
+                                    (beta from the replaced residual and the one
+                                    before the run's last)                      */
     int precond;             /* solveM of Table 1: NEK_PC_NONE (z = r), NEK_PC_JACOBI or
                                 NEK_PC_FDM                                              */
     int corr_fp32;           /* mixed: 0 = the inner correction d is FP64 (each

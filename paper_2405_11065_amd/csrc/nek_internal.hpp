@@ -289,6 +289,8 @@ int fill_i32(hipStream_t s, int *p, int v, unsigned long n);
 // Control state of one mixed-precision (iterative refinement) solve; the
 // solo and batched solvers drive it through the same steps.
 struct IrCtl {
+    // rtz_last: rtz of the residual before the last one of the previous inner
+    // run (denominator of the resumed beta in reliable-update mode)
     double bb = 0, rho = 0, rho_prev = 0, tau = 0, rtz_last = 0, last_rec = 0;
     int total = 0, outer = 0, fp64_iters = 0, status = NEK_OK, inner_cap = 0, max_outer = 0;
     bool keep_p = false, finished = false;

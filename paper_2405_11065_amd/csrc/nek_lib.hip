@@ -478,14 +478,15 @@ int ensure_mixed_work(nek_ctx *c)
 void ir_init(const nek_ctx *c, IrCtl &s)
 {
     s = IrCtl{};
-    // Restarted refinement by default: on the benchmarked meshes it needs
-    // fewer FP32 iterations than reliable updates (which keep p across
-    // true-residual replacements and so inherit FP32 CG's loss of
-    // orthogonality), and BF16 g's ~2^-8 operator error would spoil kept
-    // directions altogether.
+    // Reliable updates by default: the inner CG keeps its search direction
+    // when its residual is replaced by the FP64 true residual, so the solve
+    // keeps the Krylov space that a restart would discard (16^3 N=9: 875
+    // FP32-operator iterations against 1020 restarted and 861 in FP64).  The
+    // replacement threshold is a residual reduction of 1e-2 with FP32 g; BF16
+    // g's ~2^-9 operator error needs replacements every 0.3.
     const bool bf16 = c->prec == NEK_PREC_BF16G;
-    s.keep_p = c->opts.refine_mode == 2;
-    s.tau = c->opts.inner_tol > 0 ? c->opts.inner_tol : (bf16 || s.keep_p ? 1e-2 : 1e-4);
+    s.keep_p = c->opts.refine_mode != 1;
+    s.tau = c->opts.inner_tol > 0 ? c->opts.inner_tol : s.keep_p ? (bf16 ? 0.3 : 1e-2) : (bf16 ? 1e-2 : 1e-4);
     s.inner_cap = c->opts.inner_maxit > 0 ? c->opts.inner_maxit : 4000;
     s.max_outer = c->opts.max_outer > 0 ? c->opts.max_outer : 30;
 }
@@ -561,7 +562,12 @@ int ir_inner_launch(nek_ctx *c, IrCtl &s, double tol, int maxit, int *cap)
 int ir_inner_done(nek_ctx *c, IrCtl &s, const Scal &h, double *x)
 {
     s.total += h.fin.iter;
-    s.rtz_last = h.fin.rtz;
+    // A resumed run continues the search direction with beta = rtz(r_new) /
+    // rtz(r_{K-1}), r_{K-1} the residual before the run's last one (the one
+    // the true residual replaces); the stopping iteration's beta is
+    // rtz(r_K) / rtz(r_{K-1}), so rtz(r_{K-1}) = rtz(r_K) / beta.  A run
+    // that stopped at its start has no such residual and restarts.
+    s.rtz_last = h.fin.beta > 0 ? h.fin.rtz / h.fin.beta : 0.0;
     s.last_rec = h.hist_den > 0 ? std::sqrt(h.fin.rtr / h.hist_den) : 0.0;
     if (h.fin.status) {
         s.status = h.fin.status;
