@@ -101,8 +101,8 @@ typedef struct {
                                     residual and continue the search direction
                                     (beta from the replaced residual and the one
                                     before the run's last)                      */
-    int precond;             /* solveM of Table 1: NEK_PC_NONE (z = r), NEK_PC_JACOBI or
-                                NEK_PC_FDM                                              */
+    int precond;             /* solveM of Table 1: NEK_PC_NONE (z = r), NEK_PC_JACOBI,
+                                NEK_PC_FDM or NEK_PC_SCHWARZ                            */
     int corr_fp32;           /* mixed: 0 = the inner correction d is FP64 (each
                                 d += alpha p in FP64); 1 = d stored in FP32 (each
                                 update formed in FP64 and rounded once: 8 B per point
@@ -115,11 +115,22 @@ typedef enum {
     NEK_PC_JACOBI = 1,       /* z = r / m, m = diagonal of the assembled masked operator
                                 (FP64 in FP64 solves, its FP32 rounding in the inner
                                 solves of mixed ones); 1 on Dirichlet nodes             */
-    NEK_PC_FDM = 2           /* element-interior block solve by fast diagonalization on
+    NEK_PC_FDM = 2,          /* element-interior block solve by fast diagonalization on
                                 each element's (N-1)^3 interior nodes (the element's
                                 separable stiffness block with factors from its mean
                                 edge lengths: exact for axis-aligned boxes), z = r / m
                                 on the other nodes: the non-overlapping Schwarz stage  */
+    NEK_PC_SCHWARZ = 3       /* two-level overlapping Schwarz (N >= 2): z = sum_e R_e^T
+                                A~_e^-1 R_e r + P A~_c^-1 P^T r.  Each element's
+                                subdomain is extruded one GLL node into every face
+                                neighbour ((N+3)^3 window, clipped at Dirichlet faces)
+                                and solved by fast diagonalization of the separable
+                                operator with the element's mean edge lengths; the
+                                coarse space is the trilinear functions on the vertex
+                                lattice, solved by fast diagonalization of the
+                                separable Q1 operator of the slab-mean lattice (FP64).
+                                Exact subdomain and coarse solves on uniform box
+                                meshes; symmetric positive definite on any mesh       */
 } nek_pc;
 
 /* Source of the geometric factors g1..g6 in the operator kernels. */
@@ -200,15 +211,18 @@ int nek_set_prec(nek_ctx *ctx, int prec);
 /*
  * nek_set_precond -- preconditioner (nek_pc) of later nek_cg_solve calls.
  * NEK_PC_JACOBI builds the diagonal on first use (host FP64, from the
- * geometric factors; then an FP32 copy); NEK_PC_FDM builds the diagonal and
- * the 1-D interior modes and element factors, and runs each iteration as the
- * operator kernel, the gather/update kernel and the block-solve kernel, with
- * z in its own vector.  Solves follow Table 1 with solveM
- * z = r / m; the stopping test and the reported residuals stay those of r.
- * The work vector of the loop then holds z, updated as z -= alpha S / m, and
- * the gather/update kernel reduces both r.z and r.r (r = m z).  Batches
- * (nek_batch_*) run unpreconditioned and refuse members with a
- * preconditioner (NEK_E_ARG).
+ * geometric factors; then an FP32 copy); the loop's work vector then holds
+ * z = r / m, updated as z -= alpha S / m, and the gather/update kernel
+ * reduces both r.z and r.r (r = m z).  NEK_PC_FDM builds the diagonal, the
+ * 1-D interior modes and the element factors; NEK_PC_SCHWARZ (N >= 2) the
+ * window and coarse modes and the window-solution buffer (E (N+3)^3 entries
+ * per precision); both run each iteration as the operator kernel, the
+ * gather/update kernel and the preconditioner kernels (one block-solve
+ * kernel; or the window solves, the one-workgroup coarse solve and the
+ * gather of z), with z in its own vector.  Solves follow Table 1 with
+ * solveM; the stopping test and the reported residuals stay those of r.
+ * Batches (nek_batch_*) run unpreconditioned and refuse members with a
+ * preconditioner (NEK_E_ARG).  NEK_E_ARG for NEK_PC_SCHWARZ at N = 1.
  */
 int nek_set_precond(nek_ctx *ctx, int precond);
 

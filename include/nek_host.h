@@ -45,6 +45,26 @@ int nek_host_segments(int N, const int nel[3], int32_t *perm, int32_t *seg_ptr, 
  * N >= 2. */
 int nek_host_fdm(int N, const int nel[3], const double *vtx, double *S, double *lam, double *cf);
 
+/*
+ * nek_host_schwarz -- set-up data of the two-level overlapping Schwarz
+ * preconditioner (NEK_PC_SCHWARZ; solveM of Table 1, the Schwarz smoother by
+ * fast diagonalization of the Fig. 3 call graph), N >= 2.
+ * Sw [4][N+3][N+3], lamw [4][N+3]: per clipping variant v = lo + 2 hi (lo:
+ * the element's left face is on the Dirichlet boundary, hi: its right face),
+ * the 1-D modes of the window (the left neighbour's node N-1, the element's
+ * nodes 0..N, the right neighbour's node 1; the two nodes past a Dirichlet
+ * face dropped): K S = W S Lambda, S^T W S = I, with K, W the GLL stiffness
+ * and mass of three reference elements assembled and restricted to the
+ * window; S padded with zero rows (dropped nodes) and columns (missing
+ * modes, lambda 1).  Sc, lamc: the coarse modes per direction d = x, y, z in
+ * turn, (nel[d]-1)^2 and nel[d]-1 entries, of the Q1 stiffness and
+ * GLL-integrated mass on the slab-mean lattice restricted to the interior
+ * vertices (S^T M S = I).  Host pointers sized by the caller.  0, or -1 for
+ * bad arguments.
+ */
+int nek_host_schwarz(int N, const int nel[3], const double *vtx, double *Sw, double *lamw, double *Sc,
+                     double *lamc);
+
 /* Trilinear map of every element, the input of the in-kernel geometric
  * factors (nek_set_geometry): coef[E][3][8] = (a0..a7) of
  * x_d(r,s,t) = a0 + a1 r + a2 s + a3 t + a4 rs + a5 rt + a6 st + a7 rst on

@@ -132,6 +132,16 @@ struct nek_ctx {
     float *fdmS32 = nullptr, *fdmL32 = nullptr, *fdmC32 = nullptr;
     double *z64 = nullptr;
     float *z32 = nullptr;
+    // two-level overlapping Schwarz: padded window modes [4][NW][NW], their
+    // lambda [4][NW] (FP64 and FP32), GLL interpolation weights [2][NP], the
+    // coarse modes per direction (FP64: S at asmCoff[d], lambda at asmCloff[d]),
+    // the window solutions [E][NW^3], element moments [E][8], the coarse
+    // correction on the vertex lattice and two coarse scratch vectors
+    double *asmS64 = nullptr, *asmL64 = nullptr, *asmEll = nullptr, *asmCS = nullptr, *asmCL = nullptr;
+    float *asmS32 = nullptr, *asmL32 = nullptr;
+    int asmCoff[3] = {0, 0, 0}, asmCloff[3] = {0, 0, 0};
+    double *asmU64 = nullptr, *asmMom = nullptr, *asmEc = nullptr, *asmTmp = nullptr;
+    float *asmU32 = nullptr;
     double *hist = nullptr;
     long hist_cap = 0;
     // work vectors
@@ -233,6 +243,10 @@ struct NpOps {
     // with step set, as the third kernel of CG iteration it
     int (*pc_fdm64)(nek_ctx *, const double *r, double *z, double *P, unsigned grid, bool step, int it);
     int (*pc_fdm32)(nek_ctx *, const float *r, float *z, double *P, unsigned grid, bool step, int it);
+    // z = M^-1 r (two-level overlapping Schwarz), partials of glsc3(r, c, z)
+    // in P over `grid` workgroups; with step set, as a CG step of iteration it
+    int (*pc_asm64)(nek_ctx *, const double *r, double *z, double *P, unsigned grid, bool step, int it);
+    int (*pc_asm32)(nek_ctx *, const float *r, float *z, double *P, unsigned grid, bool step, int it);
     // r32 = (float) r64, d = 0 (FP64 when d64, else FP32), partials of glsc3(r32, c, r32)
     int (*inner_start)(nek_ctx *, const double *r64, float *r32, void *d, bool d64);
     // elements per workgroup of a CG variant
@@ -268,6 +282,10 @@ int pc_start64(nek_ctx *c, double *r, int *rtz_slot);
 int pc_start32(nek_ctx *c, float *r, int *rtz_slot);
 int ensure_diag(nek_ctx *c);
 int ensure_fdm(nek_ctx *c);
+int ensure_schwarz(nek_ctx *c);
+// the coarse solve of the Schwarz preconditioner (one workgroup), from the
+// element moments to the correction on the vertex lattice
+int asm_coarse_launch(nek_ctx *c, const Scal *sc, int it);
 int ensure_tri(nek_ctx *c);
 // the inner correction of a mixed solve (FP64 unless opts.corr_fp32)
 inline void *inner_x(nek_ctx *c) { return c->opts.corr_fp32 ? (void *)c->d32 : (void *)c->d64; }

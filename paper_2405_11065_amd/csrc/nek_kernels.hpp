@@ -1407,6 +1407,269 @@ __global__ __launch_bounds__(NP *NP) void k_pc_fdm(const T *__restrict__ r, T *_
     if (tid == 0) P[blockIdx.x] = sum;
 }
 
+// ------------------------------------- two-level overlapping Schwarz (solveM)
+//
+// M^-1 r = sum_e R_e^T A~_e^-1 R_e r + P A~_c^-1 P^T r  (see nek.h,
+// NEK_PC_SCHWARZ).  The window of element e along x is the global lattice
+// line gi = ex N - 1 .. ex N + N + 1 (NW = N + 3 nodes, window index
+// a = gi - ex N + 1); nodes on or past the Dirichlet boundary carry no
+// unknown (zero rows of the padded modes S, zero values).
+
+// Window node a of element coordinate ed (of nd) along one direction: the
+// element and local index holding a copy of it, or false when the node is
+// not an unknown (a Dirichlet node or past the boundary).
+template <int NP>
+__device__ __forceinline__ bool win_node(int a, int ed, int nd, int &eo, int &io)
+{
+    constexpr int N = NP - 1;
+    const int g = ed * N - 1 + a, G = nd * N + 1;
+    if (g <= 0 || g >= G - 1) return false;
+    eo = a == 0 ? ed - 1 : a == N + 2 ? ed + 1 : ed;
+    io = a == 0 ? N - 1 : a == N + 2 ? 1 : a - 1;
+    return true;
+}
+
+// Local solves: one workgroup of NW^2 threads per element.  The window of r
+// is staged in LDS (rows of pitch NW + 1); six passes apply S^T along x, y, z,
+// the scaling 2 / (cx l_a + cy l_b + cz l_c), and S back along z, y, x, each
+// pass one line per thread held in registers (the z passes share a thread's
+// column).  Writes the window solution u[e][c][b][a] and the element's eight
+// coarse moments mom[e][v] = sum over its nodes of c_l l_v(x) r_l, v = vx +
+// 2 vy + 4 vz (c_l = 1 / multiplicity, separable; l_0 = (1-x)/2, l_1 =
+// (1+x)/2).  With sc set, a CG step of iteration it (nothing after the run
+// has ended).
+template <int NP, typename T>
+__global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
+    const T *__restrict__ r, T *__restrict__ u, double *__restrict__ mom, const T *__restrict__ Sw,
+    const T *__restrict__ lamw, const T *__restrict__ cf, const double *__restrict__ ell, Box box,
+    const Scal *__restrict__ sc, int it)
+{
+    constexpr int N = NP - 1, NW = NP + 2, PW = NW + 1, NW2 = NW * NW, NP2 = NP * NP, NP3 = NP2 * NP;
+    __shared__ T buf[NW * NW * PW];
+    __shared__ T sS[3][NW2];
+    __shared__ T sl[3][NW];
+    __shared__ double mx[2][NP2];
+    __shared__ double my[4][NP];
+    if (sc && sc->st[it & 1].done) return;
+    const int tid = threadIdx.x;
+    const int e = blockIdx.x;
+    const int ex = e % box.nx, eyz = e / box.nx, ey = eyz % box.ny, ez = eyz / box.ny;
+    const int ed[3] = {ex, ey, ez}, nd[3] = {box.nx, box.ny, box.nz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int v = (ed[d] == 0 ? 1 : 0) + (ed[d] == nd[d] - 1 ? 2 : 0);
+        for (int q = tid; q < NW2; q += NW2) sS[d][q] = Sw[v * NW2 + q];
+        if (tid < NW) sl[d][tid] = lamw[v * NW + tid];
+    }
+    // the window of r
+    for (int q = tid; q < NW2 * NW; q += NW2) {
+        const int a = q % NW, b = (q / NW) % NW, c = q / NW2;
+        int e0, i0, e1, i1, e2, i2;
+        T v = (T)0;
+        if (win_node<NP>(a, ex, box.nx, e0, i0) && win_node<NP>(b, ey, box.ny, e1, i1) &&
+            win_node<NP>(c, ez, box.nz, e2, i2))
+            v = r[(long)(e0 + box.nx * (e1 + box.ny * e2)) * NP3 + i0 + NP * (i1 + NP * i2)];
+        buf[a + PW * (b + NW * c)] = v;
+    }
+    __syncthreads();
+    // coarse moments: along x per (j, k) line of the element's own nodes, then y, then z
+    auto cw = [&](int i, int edd, int ndd, int side) -> double {
+        const double l = ell[side * NP + i];
+        const bool shared = (i == 0 && edd > 0) || (i == N && edd < ndd - 1);
+        return shared ? 0.5 * l : l;
+    };
+    if (tid < NP2) {
+        const int j = tid % NP, k = tid / NP;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const double v = (double)buf[(i + 1) + PW * ((j + 1) + NW * (k + 1))];
+            s0 += cw(i, ex, box.nx, 0) * v;
+            s1 += cw(i, ex, box.nx, 1) * v;
+        }
+        mx[0][k * NP + j] = s0;
+        mx[1][k * NP + j] = s1;
+    }
+    __syncthreads();
+    if (tid < 2 * NP) {
+        const int xa = tid & 1, k = tid >> 1;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            s0 += cw(j, ey, box.ny, 0) * mx[xa][k * NP + j];
+            s1 += cw(j, ey, box.ny, 1) * mx[xa][k * NP + j];
+        }
+        my[xa][k] = s0;
+        my[2 + xa][k] = s1;
+    }
+    __syncthreads();
+    if (tid < 8) {
+        const int xa = tid & 1, yb = (tid >> 1) & 1, zc = tid >> 2;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) s += cw(k, ez, box.nz, zc) * my[2 * yb + xa][k];
+        mom[(long)e * 8 + tid] = s;
+    }
+    // fast diagonalization; thread t takes line (t % NW, t / NW) of each pass
+    const int p0 = tid % NW, p1 = tid / NW;
+    T in[NW], out[NW];
+    // S^T along x: line (b, c) = (p0, p1)
+#pragma unroll
+    for (int a = 0; a < NW; ++a) in[a] = buf[a + PW * (p0 + NW * p1)];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) {
+        T acc = 0;
+#pragma unroll
+        for (int a = 0; a < NW; ++a) acc += sS[0][a * NW + m] * in[a];
+        out[m] = acc;
+    }
+#pragma unroll
+    for (int m = 0; m < NW; ++m) buf[m + PW * (p0 + NW * p1)] = out[m];
+    __syncthreads();
+    // S^T along y: line (a, c) = (p0, p1)
+#pragma unroll
+    for (int b = 0; b < NW; ++b) in[b] = buf[p0 + PW * (b + NW * p1)];
+#pragma unroll
+    for (int m = 0; m < NW; ++m) {
+        T acc = 0;
+#pragma unroll
+        for (int b = 0; b < NW; ++b) acc += sS[1][b * NW + m] * in[b];
+        out[m] = acc;
+    }
+#pragma unroll
+    for (int m = 0; m < NW; ++m) buf[p0 + PW * (m + NW * p1)] = out[m];
+    __syncthreads();
+    // along z: line (a, b) = (p0, p1) = modes (ma, mb); S^T, scale, S
+    {
+        const T cx = cf[3 * e], cy = cf[3 * e + 1], cz = cf[3 * e + 2];
+        const T lxy = cx * sl[0][p0] + cy * sl[1][p1];
+#pragma unroll
+        for (int c = 0; c < NW; ++c) in[c] = buf[p0 + PW * (p1 + NW * c)];
+#pragma unroll
+        for (int m = 0; m < NW; ++m) {
+            T acc = 0;
+#pragma unroll
+            for (int c = 0; c < NW; ++c) acc += sS[2][c * NW + m] * in[c];
+            out[m] = (T)2 * acc / (lxy + cz * sl[2][m]);
+        }
+#pragma unroll
+        for (int c = 0; c < NW; ++c) {
+            T acc = 0;
+#pragma unroll
+            for (int m = 0; m < NW; ++m) acc += sS[2][c * NW + m] * out[m];
+            in[c] = acc;
+        }
+#pragma unroll
+        for (int c = 0; c < NW; ++c) buf[p0 + PW * (p1 + NW * c)] = in[c];
+    }
+    __syncthreads();
+    // S along y: line (a, c)
+#pragma unroll
+    for (int m = 0; m < NW; ++m) in[m] = buf[p0 + PW * (m + NW * p1)];
+#pragma unroll
+    for (int b = 0; b < NW; ++b) {
+        T acc = 0;
+#pragma unroll
+        for (int m = 0; m < NW; ++m) acc += sS[1][b * NW + m] * in[m];
+        out[b] = acc;
+    }
+#pragma unroll
+    for (int b = 0; b < NW; ++b) buf[p0 + PW * (b + NW * p1)] = out[b];
+    __syncthreads();
+    // S along x: line (b, c); to memory
+#pragma unroll
+    for (int m = 0; m < NW; ++m) in[m] = buf[m + PW * (p0 + NW * p1)];
+    T *ue = u + (long)e * NW2 * NW + NW * (p0 + NW * p1);
+#pragma unroll
+    for (int a = 0; a < NW; ++a) {
+        T acc = 0;
+#pragma unroll
+        for (int m = 0; m < NW; ++m) acc += sS[0][a * NW + m] * in[m];
+        ue[a] = acc;
+    }
+}
+
+// Subdomains of one direction holding global lattice node ed N + i: the
+// element coordinates (ascending) and the node's window index in each.
+template <int NP>
+__device__ __forceinline__ int win_cands(int i, int ed, int nd, int eo[3], int ao[3])
+{
+    constexpr int N = NP - 1;
+    int n = 0;
+    if (i <= 1 && ed > 0) { eo[n] = ed - 1; ao[n++] = i + N + 1; }
+    eo[n] = ed; ao[n++] = i + 1;
+    if (i >= N - 1 && ed < nd - 1) { eo[n] = ed + 1; ao[n++] = i - N + 1; }
+    return n;
+}
+
+// z = sum over the subdomains holding each node of their window solutions
+// (ascending element order: every copy of a node forms the identical sum)
+// + the trilinear interpolation of the coarse correction ec (vertex lattice,
+// 0 on the boundary; weights by reference coordinate, so copies agree bit
+// for bit), 0 on Dirichlet nodes; partials of glsc3(r, c, z) to P.  With sc
+// set, a CG step of iteration it.
+template <int NP, typename T>
+__global__ __launch_bounds__(UPD_BS) void k_asm_gather(const T *__restrict__ r, T *__restrict__ z,
+                                                       const T *__restrict__ u, const double *__restrict__ ec,
+                                                       const double *__restrict__ ell, double *__restrict__ P,
+                                                       Box box, unsigned nl, const Scal *__restrict__ sc, int it)
+{
+    constexpr int NW = NP + 2, NW2 = NW * NW;
+    __shared__ double sbuf[UPD_BS];
+    if (sc && sc->st[it & 1].done) return;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned t0 = (unsigned)(((unsigned long)lb * nl) / gridDim.x);
+    const unsigned t1 = (unsigned)(((unsigned long)(lb + 1) * nl) / gridDim.x);
+    const long vx = box.nx + 1, vy = box.ny + 1;
+    double part = 0.0;
+    for (unsigned t = t0 + threadIdx.x; t < t1; t += UPD_BS) {
+        const PointInfo<NP> Pt = locate<NP>(t, box);
+        double zv = 0.0;
+        if (!Pt.masked) {
+            int exo[3], axo[3], eyo[3], ayo[3], ezo[3], azo[3];
+            const int nx = win_cands<NP>(Pt.i, Pt.ex, box.nx, exo, axo);
+            const int ny = win_cands<NP>(Pt.j, Pt.ey, box.ny, eyo, ayo);
+            const int nz = win_cands<NP>(Pt.k, Pt.ez, box.nz, ezo, azo);
+            double s = 0.0;
+#pragma unroll
+            for (int qz = 0; qz < 3; ++qz) {
+                if (qz >= nz) break;
+#pragma unroll
+                for (int qy = 0; qy < 3; ++qy) {
+                    if (qy >= ny) break;
+#pragma unroll
+                    for (int qx = 0; qx < 3; ++qx) {
+                        if (qx >= nx) break;
+                        const long eo = exo[qx] + (long)box.nx * (eyo[qy] + (long)box.ny * ezo[qz]);
+                        s += (double)u[eo * NW2 * NW + axo[qx] + NW * (ayo[qy] + NW * azo[qz])];
+                    }
+                }
+            }
+            // coarse correction: along x, then y, then z
+            const double lx0 = ell[Pt.i], lx1 = ell[NP + Pt.i];
+            const double ly0 = ell[Pt.j], ly1 = ell[NP + Pt.j];
+            const double lz0 = ell[Pt.k], lz1 = ell[NP + Pt.k];
+            double tz[2];
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz) {
+                double ty[2];
+#pragma unroll
+                for (int dy = 0; dy < 2; ++dy) {
+                    const double *row = ec + Pt.ex + vx * ((Pt.ey + dy) + vy * (Pt.ez + dz));
+                    ty[dy] = lx0 * row[0] + lx1 * row[1];
+                }
+                tz[dz] = ly0 * ty[0] + ly1 * ty[1];
+            }
+            zv = s + (lz0 * tz[0] + lz1 * tz[1]);
+        }
+        const T zt = (T)zv;
+        z[t] = zt;
+        part += ((double)r[t] * (double)zt) * inv_mult(Pt.mult);
+    }
+    const double sum = block_sum<UPD_BS>(part, sbuf);
+    if (threadIdx.x == 0) P[blockIdx.x] = sum;
+}
+
 // Start of a preconditioned run: r -> z = r / m in place (m the diagonal,
 // 1 on Dirichlet nodes), each quotient formed in FP64 and rounded once, and
 // partials of glsc3(r, c, z).

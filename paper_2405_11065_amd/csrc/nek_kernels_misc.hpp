@@ -115,6 +115,74 @@ __global__ __launch_bounds__(256) void k_batch_alldone(Scal *const *__restrict__
     if (threadIdx.x == 0) set_host_flag(out, !pending);
 }
 
+// Coarse solve of the two-level Schwarz preconditioner, one workgroup: the
+// coarse right-hand side P^T r of the interior vertices from the elements'
+// moments (the up to eight elements around a vertex in ascending order),
+// then S^T along x, y, z, the scaling 1 / (lx + ly + lz), and S back along
+// z, y, x (per-direction modes S [vertex][mode] of n_d - 1 interior
+// vertices), through the two scratch buffers a and b (interior vertices,
+// x fastest).  ec receives the result on the whole vertex lattice, 0 on the
+// boundary.  With sc set, a CG step of iteration it.
+__global__ __launch_bounds__(1024) void k_asm_coarse(const double *__restrict__ mom, const double *__restrict__ Sx,
+                                                     const double *__restrict__ Sy, const double *__restrict__ Sz,
+                                                     const double *__restrict__ lx, const double *__restrict__ ly,
+                                                     const double *__restrict__ lz, double *__restrict__ a,
+                                                     double *__restrict__ b, double *__restrict__ ec, Box box,
+                                                     const Scal *__restrict__ sc, int it)
+{
+    if (sc && sc->st[it & 1].done) return;
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int mx = box.nx - 1, my = box.ny - 1, mz = box.nz - 1;
+    const long vx = box.nx + 1, vy = box.ny + 1, nv = vx * vy * (box.nz + 1);
+    const long nc = (long)mx * my * mz;
+    for (long q = tid; q < nv; q += bs) ec[q] = 0.0;
+    for (long q = tid; q < nc; q += bs) {
+        const int ix = (int)(q % mx) + 1, iy = (int)((q / mx) % my) + 1, iz = (int)(q / ((long)mx * my)) + 1;
+        double s = 0.0;
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    const long e = (ix - 1 + dx) + (long)box.nx * ((iy - 1 + dy) + (long)box.ny * (iz - 1 + dz));
+                    s += mom[e * 8 + (1 - dx) + 2 * (1 - dy) + 4 * (1 - dz)];
+                }
+        a[q] = s;
+    }
+    __syncthreads();
+    if (nc == 0) return;
+    // one line per thread: in (stride st, n entries) -> out, out[m] = sum_k S[k][m] in[k] (fwd) or
+    // out[k] = sum_m S[k][m] in[m] (back)
+    auto pass = [&](const double *in, double *out, const double *S, int n, long st, long nlines, auto base_of,
+                    bool fwd) {
+        for (long l = tid; l < nlines; l += bs) {
+            const long o = base_of(l);
+            for (int m = 0; m < n; ++m) {
+                double acc = 0.0;
+                for (int k = 0; k < n; ++k) acc += (fwd ? S[k * n + m] : S[m * n + k]) * in[o + k * st];
+                out[o + m * st] = acc;
+            }
+        }
+        __syncthreads();
+    };
+    auto bx = [&](long l) { return l * mx; };                                       // lines along x: (y, z)
+    auto by = [&](long l) { return (l % mx) + (long)mx * my * (l / mx); };          // along y: (x, z)
+    auto bz = [&](long l) { return l; };                                            // along z: (x, y)
+    pass(a, b, Sx, mx, 1, (long)my * mz, bx, true);
+    pass(b, a, Sy, my, mx, (long)mx * mz, by, true);
+    pass(a, b, Sz, mz, (long)mx * my, (long)mx * my, bz, true);
+    for (long q = tid; q < nc; q += bs) {
+        const int ix = (int)(q % mx), iy = (int)((q / mx) % my), iz = (int)(q / ((long)mx * my));
+        b[q] = b[q] / (lx[ix] + ly[iy] + lz[iz]);
+    }
+    __syncthreads();
+    pass(b, a, Sz, mz, (long)mx * my, (long)mx * my, bz, false);
+    pass(a, b, Sy, my, mx, (long)mx * mz, by, false);
+    pass(b, a, Sx, mx, 1, (long)my * mz, bx, false);
+    for (long q = tid; q < nc; q += bs) {
+        const int ix = (int)(q % mx) + 1, iy = (int)((q / mx) % my) + 1, iz = (int)(q / ((long)mx * my)) + 1;
+        ec[ix + vx * (iy + vy * iz)] = a[q];
+    }
+}
+
 // x += d: FP64 iterate, FP64 or FP32 correction of an inner solve.
 template <typename DT>
 __global__ void k_axpy1(double *__restrict__ x, const DT *__restrict__ d, unsigned long n)

@@ -284,14 +284,70 @@ int ensure_fdm(nek_ctx *c)
     return NEK_OK;
 }
 
+int ensure_schwarz(nek_ctx *c)
+{
+    if (c->N < 2) return NEK_E_ARG;
+    if (c->asmS64 && c->asmU64 && c->z64 && c->z32) return NEK_OK;
+    const int NP = c->NP, NW = NP + 2;
+    std::vector<double> S, L, CS, CL, ell((size_t)2 * NP), C((size_t)3 * c->E);
+    schwarz_windows(c->N, c->w, c->D, S, L);
+    schwarz_coarse(c->N, c->nel, c->vtx, c->xi, c->w, CS, CL, c->asmCoff, c->asmCloff);
+    for (int i = 0; i < NP; ++i) {
+        ell[i] = (1.0 - c->xi[i]) / 2.0;
+        ell[NP + i] = (1.0 + c->xi[i]) / 2.0;
+    }
+    fdm_scales(c->nel, c->vtx, C.data());
+    std::vector<float> S32(S.begin(), S.end()), L32(L.begin(), L.end()), C32(C.begin(), C.end());
+    const long nv = (long)(c->nel[0] + 1) * (c->nel[1] + 1) * (c->nel[2] + 1);
+    const long ncv = (long)(c->nel[0] - 1) * (c->nel[1] - 1) * (c->nel[2] - 1);
+    const size_t nu = (size_t)c->E * NW * NW * NW;
+    if (dalloc(c->asmS64, S.size()) || dalloc(c->asmL64, L.size()) || dalloc(c->asmS32, S.size()) ||
+        dalloc(c->asmL32, L.size()) || dalloc(c->asmEll, ell.size()) || dalloc(c->asmCS, CS.size()) ||
+        dalloc(c->asmCL, CL.size()) || dalloc(c->fdmC64, C.size()) || dalloc(c->fdmC32, C.size()) ||
+        dalloc(c->asmU64, nu) || dalloc(c->asmU32, nu) || dalloc(c->asmMom, (size_t)8 * c->E) ||
+        dalloc(c->asmEc, nv) || dalloc(c->asmTmp, 2 * ncv) || dalloc(c->z64, c->nl) || dalloc(c->z32, c->nl))
+        return NEK_E_OOM;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(c->asmS64, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->asmL64, L.data(), L.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->asmS32, S32.data(), S32.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->asmL32, L32.data(), L32.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->asmEll, ell.data(), ell.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (!CS.empty()) {
+        HIP_TRY(hipMemcpy(c->asmCS, CS.data(), CS.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->asmCL, CL.data(), CL.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    HIP_TRY(hipMemcpy(c->fdmC64, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->fdmC32, C32.data(), C32.size() * sizeof(float), hipMemcpyHostToDevice));
+    return NEK_OK;
+}
+
+int asm_coarse_launch(nek_ctx *c, const Scal *sc, int it)
+{
+    const long ncv = (long)(c->box.nx - 1) * (c->box.ny - 1) * (c->box.nz - 1);
+    hipLaunchKernelGGL(k_asm_coarse, dim3(1), dim3(1024), 0, c->stream, c->asmMom, c->asmCS + c->asmCoff[0],
+                       c->asmCS + c->asmCoff[1], c->asmCS + c->asmCoff[2], c->asmCL + c->asmCloff[0],
+                       c->asmCL + c->asmCloff[1], c->asmCL + c->asmCloff[2], c->asmTmp, c->asmTmp + ncv, c->asmEc,
+                       c->box, sc, it);
+    HIP_TRY(hipGetLastError());
+    return NEK_OK;
+}
+
+int ensure_precond(nek_ctx *c, int pc)
+{
+    return pc == NEK_PC_FDM ? ensure_fdm(c) : pc == NEK_PC_SCHWARZ ? ensure_schwarz(c)
+         : pc == NEK_PC_JACOBI ? ensure_diag(c) : NEK_OK;
+}
+
 int pc_start64(nek_ctx *c, double *r, int *rtz_slot)
 {
     *rtz_slot = 1;
     if (!c->precond) return NEK_OK;
     int rc;
-    if (c->precond == NEK_PC_FDM) {
+    if (c->precond == NEK_PC_FDM || c->precond == NEK_PC_SCHWARZ) {
         if (!c->z64) return NEK_E_ARG;
-        rc = ops(c)->pc_fdm64(c, r, c->z64, c->P3(), red_grid(c), false, 0);
+        rc = c->precond == NEK_PC_FDM ? ops(c)->pc_fdm64(c, r, c->z64, c->P3(), red_grid(c), false, 0)
+                                      : ops(c)->pc_asm64(c, r, c->z64, c->P3(), red_grid(c), false, 0);
     } else {
         if (!c->dg64) return NEK_E_ARG;
         rc = ops(c)->pc_start64(c, r, c->dg64);
@@ -306,9 +362,10 @@ int pc_start32(nek_ctx *c, float *r, int *rtz_slot)
     *rtz_slot = 1;
     if (!c->precond) return NEK_OK;
     int rc;
-    if (c->precond == NEK_PC_FDM) {
+    if (c->precond == NEK_PC_FDM || c->precond == NEK_PC_SCHWARZ) {
         if (!c->z32) return NEK_E_ARG;
-        rc = ops(c)->pc_fdm32(c, r, c->z32, c->P3(), red_grid(c), false, 0);
+        rc = c->precond == NEK_PC_FDM ? ops(c)->pc_fdm32(c, r, c->z32, c->P3(), red_grid(c), false, 0)
+                                      : ops(c)->pc_asm32(c, r, c->z32, c->P3(), red_grid(c), false, 0);
     } else {
         if (!c->dg32) return NEK_E_ARG;
         rc = ops(c)->pc_start32(c, r, c->dg32);
@@ -684,6 +741,8 @@ void nek_free(nek_ctx *c)
     dfree(c->r32); dfree(c->p32); dfree(c->w32); dfree(c->dg64); dfree(c->dg32);
     dfree(c->fdmS64); dfree(c->fdmL64); dfree(c->fdmC64); dfree(c->fdmS32); dfree(c->fdmL32); dfree(c->fdmC32);
     dfree(c->z64); dfree(c->z32);
+    dfree(c->asmS64); dfree(c->asmL64); dfree(c->asmEll); dfree(c->asmCS); dfree(c->asmCL); dfree(c->asmS32);
+    dfree(c->asmL32); dfree(c->asmU64); dfree(c->asmMom); dfree(c->asmEc); dfree(c->asmTmp); dfree(c->asmU32);
     dfree(c->xyz); dfree(c->gfeat); dfree(c->x0_X); dfree(c->x0_Y); dfree(c->x0_s);
     if (c->hflags) (void)hipHostFree(c->hflags);
     for (auto &e : c->ev)
@@ -702,7 +761,7 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
     const long E = (long)mesh->nel[0] * mesh->nel[1] * mesh->nel[2];
     if (E * n3 >= (1L << 31)) return NEK_E_ARG;
     if (opts && (opts->prec < NEK_PREC_FP64 || opts->prec > NEK_PREC_BF16G || opts->elts_per_wg < -1 ||
-                 opts->precond < NEK_PC_NONE || opts->precond > NEK_PC_FDM || opts->corr_fp32 < 0 ||
+                 opts->precond < NEK_PC_NONE || opts->precond > NEK_PC_SCHWARZ || opts->corr_fp32 < 0 ||
                  opts->corr_fp32 > 1))
         return NEK_E_ARG;
     int v_epw = 0;
@@ -773,7 +832,7 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
     if ((rc = noalloc_scratch_ptr(&c->noalloc_scratch))) return fail(rc);
     if ((rc = ensure_g(c, c->prec))) return fail(rc);
     if (c->opts.precond != NEK_PC_NONE) {
-        if ((rc = c->opts.precond == NEK_PC_FDM ? ensure_fdm(c) : ensure_diag(c))) return fail(rc);
+        if ((rc = ensure_precond(c, c->opts.precond))) return fail(rc);
         c->precond = c->opts.precond;
     }
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(NEK_E_HIP);
@@ -845,9 +904,9 @@ int nek_set_prec(nek_ctx *c, int prec)
 
 int nek_set_precond(nek_ctx *c, int precond)
 {
-    if (!c || precond < NEK_PC_NONE || precond > NEK_PC_FDM) return NEK_E_ARG;
+    if (!c || precond < NEK_PC_NONE || precond > NEK_PC_SCHWARZ) return NEK_E_ARG;
     if (precond != NEK_PC_NONE) {
-        const int rc = precond == NEK_PC_FDM ? ensure_fdm(c) : ensure_diag(c);
+        const int rc = ensure_precond(c, precond);
         if (rc) return rc;
     }
     c->precond = precond;
@@ -880,6 +939,10 @@ int nek_precond_apply(nek_ctx *c, const void *r, void *z, int dtype)
     if (c->precond == NEK_PC_FDM) {
         if (dtype == NEK_F64) return ops(c)->pc_fdm64(c, (const double *)r, (double *)z, c->P3(), red_grid(c), false, 0);
         return ops(c)->pc_fdm32(c, (const float *)r, (float *)z, c->P3(), red_grid(c), false, 0);
+    }
+    if (c->precond == NEK_PC_SCHWARZ) {
+        if (dtype == NEK_F64) return ops(c)->pc_asm64(c, (const double *)r, (double *)z, c->P3(), red_grid(c), false, 0);
+        return ops(c)->pc_asm32(c, (const float *)r, (float *)z, c->P3(), red_grid(c), false, 0);
     }
     HIP_TRY(hipMemcpyAsync(z, r, bytes, hipMemcpyDeviceToDevice, c->stream));
     if (c->precond == NEK_PC_JACOBI) {

@@ -87,6 +87,49 @@ template <int NP> struct OpsImpl {
         return pc_fdm<float>(c, r, z, P, grid, step, it);
     }
 
+    // Two-level overlapping Schwarz: local window solves and element moments,
+    // the coarse solve (one workgroup), then the gather of z with the
+    // partials of glsc3(r, c, z) over `grid` workgroups.
+    template <typename T>
+    static int pc_asm(nek_ctx *c, const T *r, T *z, double *P, unsigned grid, bool step, int it)
+    {
+        constexpr int NW = NP + 2;
+        const T *S, *L, *C;
+        T *U;
+        if constexpr (sizeof(T) == 8) {
+            S = c->asmS64; L = c->asmL64; C = c->fdmC64; U = c->asmU64;
+        } else {
+            S = c->asmS32; L = c->asmL32; C = c->fdmC32; U = c->asmU32;
+        }
+        if (NP < 3 || !S || !L || !C || !U || !c->asmMom || !c->asmEc || !c->asmTmp) return NEK_E_ARG;
+        const Scal *scp = step ? c->sc : nullptr;
+        hipLaunchKernelGGL((k_asm_local<NP, T>), dim3((unsigned)c->E), dim3(NW * NW), 0, c->stream, r, U, c->asmMom,
+                           S, L, C, c->asmEll, c->box, scp, it);
+        HIP_TRY(hipGetLastError());
+        int rc = asm_coarse_launch(c, scp, it);
+        if (rc) return rc;
+        hipLaunchKernelGGL((k_asm_gather<NP, T>), dim3(grid), dim3(UPD_BS), 0, c->stream, r, z, U, c->asmEc,
+                           c->asmEll, P, c->box, (unsigned)c->nl, scp, it);
+        HIP_TRY(hipGetLastError());
+        return NEK_OK;
+    }
+    static int pc_asm64(nek_ctx *c, const double *r, double *z, double *P, unsigned grid, bool step, int it)
+    {
+        return pc_asm<double>(c, r, z, P, grid, step, it);
+    }
+    static int pc_asm32(nek_ctx *c, const float *r, float *z, double *P, unsigned grid, bool step, int it)
+    {
+        return pc_asm<float>(c, r, z, P, grid, step, it);
+    }
+
+    // block preconditioner of the three-kernel iteration
+    template <typename T>
+    static int pc_block(nek_ctx *c, const T *r, T *z, double *P, unsigned grid, bool step, int it)
+    {
+        if (c->precond == NEK_PC_SCHWARZ) return pc_asm<T>(c, r, z, P, grid, step, it);
+        return pc_fdm<T>(c, r, z, P, grid, step, it);
+    }
+
     // Fast-diagonalization iteration: the operator kernel forms p = z + beta p
     // from the z vector, the gather/update kernel updates r and writes the
     // r.r partials to P4, the block-solve kernel forms z = M^-1 r and writes
@@ -115,7 +158,7 @@ template <int NP> struct OpsImpl {
             hipLaunchKernelGGL((k_cg_update<NP, EPW, T>), dim3(grid), dim3(EPW * NP * NP), 0, c->stream, r, w, c->sc,
                                c->P1(it), (int)grid, c->P4(it), it, c->box, (int)c->E, ax_groups(c, EPW));
             HIP_TRY(hipGetLastError());
-            if ((rc = pc_fdm<T>(c, r, zb, c->P2(it), grid, true, it))) return rc;
+            if ((rc = pc_block<T>(c, r, zb, c->P2(it), grid, true, it))) return rc;
             if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 2], c->stream));
             return NEK_OK;
         });
@@ -127,7 +170,8 @@ template <int NP> struct OpsImpl {
     static int cg_iter(nek_ctx *c, int variant, int it, bool final, XT *x, T *r, T *p, T *w, const GT *g,
                        const T *D)
     {
-        if (c->precond == NEK_PC_FDM) return cg_iter_fdm<T, GT, XT>(c, variant, it, final, x, r, p, w, g, D);
+        if (c->precond == NEK_PC_FDM || c->precond == NEK_PC_SCHWARZ)
+            return cg_iter_fdm<T, GT, XT>(c, variant, it, final, x, r, p, w, g, D);
         if (c->precond) {
             const T *dg;
             if constexpr (sizeof(T) == 8) dg = c->dg64;
@@ -329,7 +373,7 @@ template <int NP> const NpOps *make_np_ops()
 {
     using I = OpsImpl<NP>;
     static const NpOps ops{n_variants<NP>(), &I::cg_iter64, &I::cg_iter32, &I::cg_iter16, &I::ax64, &I::ax32,
-                           &I::ax16, &I::axa64, &I::axa32, &I::axa16, &I::gather64, &I::glsc3_64, &I::glsc3_32, &I::resid, &I::pc_start64, &I::pc_start32, &I::pc_fdm64, &I::pc_fdm32,
+                           &I::ax16, &I::axa64, &I::axa32, &I::axa16, &I::gather64, &I::glsc3_64, &I::glsc3_32, &I::resid, &I::pc_start64, &I::pc_start32, &I::pc_fdm64, &I::pc_fdm32, &I::pc_asm64, &I::pc_asm32,
                            &I::inner_start,
                            &I::variant_epw, &I::batch_iter};
     return &ops;

@@ -361,21 +361,12 @@ void numbering(int N, const int nel[3], int64_t *gid, int32_t *mult, int8_t *mas
 // the symmetric eigenproblem of C = W_I^-1/2 K_I W_I^-1/2, solved by cyclic
 // Jacobi rotations; S = W_I^-1/2 V.  S is row-major S[i * (N-1) + a] (node i,
 // mode a).
-void fdm_modes(int N, const std::vector<double> &w, const std::vector<double> &D, std::vector<double> &S,
-               std::vector<double> &lam)
+// Eigen-decomposition of the symmetric m x m matrix C (row-major, destroyed)
+// by cyclic Jacobi rotations: C = V diag(lam) V^T, V row-major [row][mode].
+void sym_eig(int m, std::vector<double> &C, std::vector<double> &V, std::vector<double> &lam)
 {
-    const int n = N + 1, m = N - 1;
-    S.assign((size_t)std::max(m, 0) * std::max(m, 0), 0.0);
-    lam.assign(std::max(m, 0), 0.0);
-    if (m <= 0) return;
-    std::vector<double> C((size_t)m * m), V((size_t)m * m, 0.0), s(m);
-    for (int a = 0; a < m; ++a) s[a] = 1.0 / std::sqrt(w[a + 1]);
-    for (int a = 0; a < m; ++a)
-        for (int b = 0; b < m; ++b) {
-            double k = 0.0;   // K[a+1][b+1] = sum_l D[l][a+1] w[l] D[l][b+1]
-            for (int l = 0; l < n; ++l) k += D[l * n + a + 1] * w[l] * D[l * n + b + 1];
-            C[a * m + b] = s[a] * k * s[b];
-        }
+    V.assign((size_t)m * m, 0.0);
+    lam.assign(m, 0.0);
     for (int a = 0; a < m; ++a) V[a * m + a] = 1.0;
     for (int sweep = 0; sweep < 100; ++sweep) {
         double off = 0.0, diag = 0.0;
@@ -406,9 +397,181 @@ void fdm_modes(int N, const std::vector<double> &w, const std::vector<double> &D
                 }
             }
     }
-    for (int a = 0; a < m; ++a) {
-        lam[a] = C[a * m + a];
+    for (int a = 0; a < m; ++a) lam[a] = C[a * m + a];
+}
+
+void fdm_modes(int N, const std::vector<double> &w, const std::vector<double> &D, std::vector<double> &S,
+               std::vector<double> &lam)
+{
+    const int n = N + 1, m = N - 1;
+    S.assign((size_t)std::max(m, 0) * std::max(m, 0), 0.0);
+    lam.assign(std::max(m, 0), 0.0);
+    if (m <= 0) return;
+    std::vector<double> C((size_t)m * m), V, s(m);
+    for (int a = 0; a < m; ++a) s[a] = 1.0 / std::sqrt(w[a + 1]);
+    for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+            double k = 0.0;   // K[a+1][b+1] = sum_l D[l][a+1] w[l] D[l][b+1]
+            for (int l = 0; l < n; ++l) k += D[l * n + a + 1] * w[l] * D[l * n + b + 1];
+            C[a * m + b] = s[a] * k * s[b];
+        }
+    sym_eig(m, C, V, lam);
+    for (int a = 0; a < m; ++a)
         for (int i = 0; i < m; ++i) S[i * m + a] = s[i] * V[i * m + a];
+}
+
+// Overlapping Schwarz windows.  The window of an element along one direction
+// holds NW = N + 3 nodes: the left neighbour's node N-1, the element's nodes
+// 0..N and the right neighbour's node 1.  Kw, Ww: the 1-D GLL stiffness
+// D^T W D and the mass W of three reference elements assembled along the line
+// and restricted to the window.  Variant v = lo + 2 hi drops the two nodes on
+// the left (lo: the element's left face is the Dirichlet boundary, the node
+// beyond it does not exist) and / or the two on the right.  For each variant
+// K S = W S Lambda (S^T W S = I) on the kept nodes; S is stored padded to
+// NW x NW (row = window node, column = mode; rows of dropped nodes and
+// columns past the kept count are 0, their lambda 1).  S[v][a][m] =
+// S[(v * NW + a) * NW + m], lam[v * NW + m].
+void schwarz_windows(int N, const std::vector<double> &w, const std::vector<double> &D, std::vector<double> &S,
+                     std::vector<double> &lam)
+{
+    const int n = N + 1, NW = N + 3, L = 3 * N + 1;
+    std::vector<double> K((size_t)n * n, 0.0);
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b)
+            for (int l = 0; l < n; ++l) K[a * n + b] += D[l * n + a] * w[l] * D[l * n + b];
+    std::vector<double> Ka((size_t)L * L, 0.0), Wa(L, 0.0);
+    for (int q = 0; q < 3; ++q)
+        for (int a = 0; a < n; ++a) {
+            Wa[q * N + a] += w[a];
+            for (int b = 0; b < n; ++b) Ka[(q * N + a) * L + q * N + b] += K[a * n + b];
+        }
+    S.assign((size_t)4 * NW * NW, 0.0);
+    lam.assign((size_t)4 * NW, 1.0);
+    for (int v = 0; v < 4; ++v) {
+        const int a0 = (v & 1) ? 2 : 0, a1 = (v & 2) ? N + 1 : N + 3;   // kept window nodes [a0, a1)
+        const int m = a1 - a0;
+        std::vector<double> C((size_t)m * m), V, l, s(m);
+        for (int a = 0; a < m; ++a) s[a] = 1.0 / std::sqrt(Wa[N - 1 + a0 + a]);
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) C[a * m + b] = s[a] * Ka[(N - 1 + a0 + a) * L + N - 1 + a0 + b] * s[b];
+        sym_eig(m, C, V, l);
+        for (int md = 0; md < m; ++md) {
+            lam[v * NW + md] = l[md];
+            for (int a = 0; a < m; ++a) S[((size_t)v * NW + a0 + a) * NW + md] = s[a] * V[a * m + md];
+        }
+    }
+}
+
+// Coarse level of the Schwarz preconditioner along each direction d: the
+// trilinear (Q1) functions on the vertex lattice, on the rectilinear
+// lattice whose spacing in slab q is the mean of the element lengths h_d
+// over the slab (h_d per element: mean of its four edges along d).  The 1-D
+// stiffness is assembled from (1/h) [[1,-1],[-1,1]] and the mass from
+// (h/2) [sum_q w_q l_a(x_q) l_b(x_q)] (the GLL rule of order N; l_0 = (1-x)/2,
+// l_1 = (1+x)/2), both restricted to the n_d - 1 interior vertices; then
+// K S = M S Lambda with S^T M S = I (Cholesky M = L L^T, C = L^-1 K L^-T =
+// V Lambda V^T, S = L^-T V).  Out: per direction, S row-major [vertex][mode]
+// at offset off[d] of S (size (n_d - 1)^2) and lambda at offset loff[d].
+void schwarz_coarse(int N, const int nel[3], const std::vector<double> &vtx, const std::vector<double> &x,
+                    const std::vector<double> &w, std::vector<double> &S, std::vector<double> &lam, int off[3],
+                    int loff[3])
+{
+    // element mean lengths: the mean of each element's four edges along d
+    const long vx = nel[0] + 1, vy = nel[1] + 1;
+    auto V = [&](long a, long b, long c, int d) { return vtx[3 * (a + vx * (b + vy * c)) + d]; };
+    auto len = [&](long a0, long b0, long c0, long a1, long b1, long c1) {
+        double s2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double t = V(a1, b1, c1, d) - V(a0, b0, c0, d);
+            s2 += t * t;
+        }
+        return std::sqrt(s2);
+    };
+    std::vector<double> slab[3];
+    for (int d = 0; d < 3; ++d) slab[d].assign(nel[d], 0.0);
+    for (long ez = 0; ez < nel[2]; ++ez)
+        for (long ey = 0; ey < nel[1]; ++ey)
+            for (long ex = 0; ex < nel[0]; ++ex) {
+                double h[3] = {0.0, 0.0, 0.0};
+                for (int u = 0; u < 2; ++u)
+                    for (int v = 0; v < 2; ++v) {
+                        h[0] += len(ex, ey + u, ez + v, ex + 1, ey + u, ez + v);
+                        h[1] += len(ex + u, ey, ez + v, ex + u, ey + 1, ez + v);
+                        h[2] += len(ex + u, ey + v, ez, ex + u, ey + v, ez + 1);
+                    }
+                slab[0][ex] += 0.25 * h[0];
+                slab[1][ey] += 0.25 * h[1];
+                slab[2][ez] += 0.25 * h[2];
+            }
+    const double cnt[3] = {(double)nel[1] * nel[2], (double)nel[0] * nel[2], (double)nel[0] * nel[1]};
+    double me[2][2] = {{0, 0}, {0, 0}};
+    for (size_t q = 0; q < x.size(); ++q) {
+        const double l[2] = {(1.0 - x[q]) / 2.0, (1.0 + x[q]) / 2.0};
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) me[a][b] += w[q] * l[a] * l[b];
+    }
+    S.clear();
+    lam.clear();
+    for (int d = 0; d < 3; ++d) {
+        const int n = nel[d], m = n - 1;
+        off[d] = (int)S.size();
+        loff[d] = (int)lam.size();
+        if (m <= 0) continue;
+        std::vector<double> Kf((size_t)(n + 1) * (n + 1), 0.0), Mf((size_t)(n + 1) * (n + 1), 0.0);
+        for (int e = 0; e < n; ++e) {
+            const double h = slab[d][e] / cnt[d];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    Kf[(e + a) * (n + 1) + e + b] += (a == b ? 1.0 : -1.0) / h;
+                    Mf[(e + a) * (n + 1) + e + b] += me[a][b] * h / 2.0;
+                }
+        }
+        // interior block, Cholesky of M
+        std::vector<double> K((size_t)m * m), M((size_t)m * m), Lc((size_t)m * m, 0.0);
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) {
+                K[a * m + b] = Kf[(a + 1) * (n + 1) + b + 1];
+                M[a * m + b] = Mf[(a + 1) * (n + 1) + b + 1];
+            }
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b <= a; ++b) {
+                double t = M[a * m + b];
+                for (int q = 0; q < b; ++q) t -= Lc[a * m + q] * Lc[b * m + q];
+                Lc[a * m + b] = a == b ? std::sqrt(t) : t / Lc[b * m + b];
+            }
+        // Li = L^-1 (lower triangular)
+        std::vector<double> Li((size_t)m * m, 0.0);
+        for (int col = 0; col < m; ++col)
+            for (int a = col; a < m; ++a) {
+                double t = a == col ? 1.0 : 0.0;
+                for (int q = col; q < a; ++q) t -= Lc[a * m + q] * Li[q * m + col];
+                Li[a * m + col] = t / Lc[a * m + a];
+            }
+        std::vector<double> T((size_t)m * m, 0.0), C((size_t)m * m, 0.0), Vv, l;
+        for (int a = 0; a < m; ++a)   // T = Li K
+            for (int b = 0; b < m; ++b) {
+                double t = 0.0;
+                for (int q = 0; q <= a; ++q) t += Li[a * m + q] * K[q * m + b];
+                T[a * m + b] = t;
+            }
+        for (int a = 0; a < m; ++a)   // C = T Li^T, symmetrised
+            for (int b = 0; b < m; ++b) {
+                double t = 0.0;
+                for (int q = 0; q <= b; ++q) t += T[a * m + q] * Li[b * m + q];
+                C[a * m + b] = t;
+            }
+        for (int a = 0; a < m; ++a)
+            for (int b = a + 1; b < m; ++b) C[a * m + b] = C[b * m + a] = 0.5 * (C[a * m + b] + C[b * m + a]);
+        sym_eig(m, C, Vv, l);
+        const size_t base = S.size();
+        S.resize(base + (size_t)m * m, 0.0);
+        for (int a = 0; a < m; ++a)   // S = Li^T V
+            for (int md = 0; md < m; ++md) {
+                double t = 0.0;
+                for (int q = a; q < m; ++q) t += Li[q * m + a] * Vv[q * m + md];
+                S[base + (size_t)a * m + md] = t;
+            }
+        lam.insert(lam.end(), l.begin(), l.end());
     }
 }
 
@@ -579,6 +742,25 @@ int nek_host_fdm(int N, const int nel[3], const double *vtx, double *S, double *
     const size_t nv = 3 * (size_t)(nel[0] + 1) * (nel[1] + 1) * (nel[2] + 1);
     std::vector<double> v(vtx, vtx + nv);
     nek::fdm_scales(nel, v, cf);
+    return 0;
+}
+
+int nek_host_schwarz(int N, const int nel[3], const double *vtx, double *Sw, double *lamw, double *Sc,
+                     double *lamc)
+{
+    if (!host_args_ok(N, nel) || N < 2 || !vtx || !Sw || !lamw || !Sc || !lamc) return -1;
+    std::vector<double> x, w, d, s, l;
+    nek::gll_rule(N, x, w);
+    nek::deriv_matrix(x, d);
+    nek::schwarz_windows(N, w, d, s, l);
+    std::memcpy(Sw, s.data(), s.size() * sizeof(double));
+    std::memcpy(lamw, l.data(), l.size() * sizeof(double));
+    const size_t nv = 3 * (size_t)(nel[0] + 1) * (nel[1] + 1) * (nel[2] + 1);
+    std::vector<double> v(vtx, vtx + nv), sc, lc;
+    int off[3], loff[3];
+    nek::schwarz_coarse(N, nel, v, x, w, sc, lc, off, loff);
+    if (!sc.empty()) std::memcpy(Sc, sc.data(), sc.size() * sizeof(double));
+    if (!lc.empty()) std::memcpy(lamc, lc.data(), lc.size() * sizeof(double));
     return 0;
 }
 

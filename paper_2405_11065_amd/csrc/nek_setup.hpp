@@ -34,6 +34,20 @@ void fdm_modes(int N, const std::vector<double> &w, const std::vector<double> &D
                std::vector<double> &lam);
 void fdm_scales(const int nel[3], const std::vector<double> &vtx, double *cf);
 
+// Symmetric eigen-decomposition by cyclic Jacobi rotations (C destroyed):
+// C = V diag(lam) V^T, V row-major [row][mode].
+void sym_eig(int m, std::vector<double> &C, std::vector<double> &V, std::vector<double> &lam);
+
+// Two-level overlapping Schwarz preconditioner: the window modes of the four
+// clipping variants, padded to (N+3) x (N+3) (S[v][node][mode], lam[v][mode]),
+// and the coarse modes per direction (S at off[d], (n_d-1)^2 entries
+// [vertex][mode]; lambda at loff[d]).
+void schwarz_windows(int N, const std::vector<double> &w, const std::vector<double> &D, std::vector<double> &S,
+                     std::vector<double> &lam);
+void schwarz_coarse(int N, const int nel[3], const std::vector<double> &vtx, const std::vector<double> &x,
+                    const std::vector<double> &w, std::vector<double> &S, std::vector<double> &lam, int off[3],
+                    int loff[3]);
+
 // Coefficients of every element's trilinear map for the in-kernel factors:
 // out = [hdr entries: x[0..N], w[0..N], zeros] then per element, per
 // coordinate d, (a1..a7, 0) of x_d(r,s,t) = a0 + a1 r + a2 s + a3 t + a4 rs

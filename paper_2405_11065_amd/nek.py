@@ -23,8 +23,8 @@ NEK_PREC_FP64, NEK_PREC_FP32, NEK_PREC_BF16G = 0, 1, 2
 NEK_F64, NEK_F32 = 0, 1
 (NEK_GET_GLL, NEK_GET_W, NEK_GET_D, NEK_GET_G, NEK_GET_B, NEK_GET_GID, NEK_GET_MULT, NEK_GET_MASK,
  NEK_GET_PERM, NEK_GET_SEGPTR, NEK_GET_SEGFLAG, NEK_GET_XYZ, NEK_GET_DIAG) = range(13)
-NEK_PC_NONE, NEK_PC_JACOBI, NEK_PC_FDM = 0, 1, 2
-PC_NAMES = {"none": NEK_PC_NONE, "jacobi": NEK_PC_JACOBI, "fdm": NEK_PC_FDM}
+NEK_PC_NONE, NEK_PC_JACOBI, NEK_PC_FDM, NEK_PC_SCHWARZ = 0, 1, 2, 3
+PC_NAMES = {"none": NEK_PC_NONE, "jacobi": NEK_PC_JACOBI, "fdm": NEK_PC_FDM, "schwarz": NEK_PC_SCHWARZ}
 (NEK_SIZE_NLOCAL, NEK_SIZE_NGLOBAL, NEK_SIZE_E, NEK_SIZE_NPERM, NEK_SIZE_NSEG, NEK_SIZE_N) = range(6)
 
 PREC_NAMES = {"fp64": NEK_PREC_FP64, "fp32": NEK_PREC_FP32, "bf16g": NEK_PREC_BF16G}

@@ -41,8 +41,8 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_strerror_covers_statuses(lib):
     lib.nek_strerror.restype = ctypes.c_char_p
-    msgs = {s: lib.nek_strerror(s).decode() for s in range(-7, 2)}
-    assert len(set(msgs.values())) == 9
+    msgs = {s: lib.nek_strerror(s).decode() for s in range(-8, 2)}
+    assert len(set(msgs.values())) == 10
     assert lib.nek_strerror(42).decode() == "unknown status"
 
 
@@ -204,3 +204,49 @@ def test_host_trilinear_inverted_element(lib):
     coef = np.empty(2 * 24)
     assert lib.nek_host_trilinear(3, _i3(nel), _ptr(V.ravel()), _ptr(coef)) == nek.NEK_E_JACOBIAN
     assert lib.nek_host_trilinear(0, _i3(nel), _ptr(vtx), _ptr(coef)) == nek.NEK_E_ARG
+
+
+@pytest.mark.parametrize("N,nel,perturb", [(2, (3, 2, 4), 0.1), (5, (4, 3, 2), 0.1), (9, (3, 3, 3), 0.0),
+                                           (15, (2, 1, 3), 0.1)])
+def test_host_schwarz_matches_oracle(lib, N, nel, perturb):
+    """Window and coarse modes by the library's Cholesky and Jacobi rotations
+    against the oracle's NumPy ones: for every window variant and coarse
+    direction, S Lambda^-1 S^T (the inverse of the 1-D operator, independent
+    of the order and signs of the modes) and S^T W S = I."""
+    from oracle import schwarz
+    vtx = synth.box_vertices(nel, perturb=perturb, seed=12)
+    NW = N + 3
+    Sw, lw = np.empty(4 * NW * NW), np.empty(4 * NW)
+    nc = sum((n - 1) ** 2 for n in nel)
+    Sc, lc = np.empty(max(nc, 1)), np.empty(max(sum(n - 1 for n in nel), 1))
+    assert lib.nek_host_schwarz(N, _i3(nel), _ptr(vtx), _ptr(Sw), _ptr(lw), _ptr(Sc), _ptr(lc)) == 0
+    xi, w = oracle.gll(N)
+    D = oracle.deriv(N)
+    Kw, Ww = schwarz.window_operators(N, D, w)
+    for (lo, hi), (keep, So, lo_) in schwarz.window_variants(N, D, w).items():
+        v = lo + 2 * hi
+        S = Sw[v * NW * NW:(v + 1) * NW * NW].reshape(NW, NW)
+        lam = lw[v * NW:(v + 1) * NW]
+        m = len(keep)
+        drop = np.setdiff1d(np.arange(NW), keep)
+        assert not S[drop].any() and not S[:, m:].any() and np.all(lam[m:] == 1.0)
+        Sk = S[keep][:, :m]
+        np.testing.assert_allclose(np.sort(lam[:m]), np.sort(lo_), rtol=1e-11)
+        ref = So @ np.diag(1 / lo_) @ So.T
+        np.testing.assert_allclose(Sk @ np.diag(1 / lam[:m]) @ Sk.T, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+        np.testing.assert_allclose(Sk.T @ np.diag(Ww[keep]) @ Sk, np.eye(m), atol=1e-11)
+    P = oracle.Problem(N, nel, vtx)
+    M = schwarz.Schwarz(P, vtx)
+    so = lo2 = 0
+    for d, n in enumerate(nel):
+        m = n - 1
+        if m == 0:
+            continue
+        S = Sc[so:so + m * m].reshape(m, m)
+        lam = lc[lo2:lo2 + m]
+        So, lo_ = M.coarse[d]
+        np.testing.assert_allclose(np.sort(lam), np.sort(lo_), rtol=1e-11)
+        ref = So @ np.diag(1 / lo_) @ So.T
+        np.testing.assert_allclose(S @ np.diag(1 / lam) @ S.T, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+        so += m * m
+        lo2 += m
