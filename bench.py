@@ -197,7 +197,7 @@ def big_case(torch, nek, synth, steps=2, energy=True, jacobi=True):
     if energy:
         out["energy"] = big_energy(torch, ctx, f, x, {"bf16g": out["bf16g"]["ms_per_solve"], "fp64": best64},
                                    out["fastest_fp64"])
-    for pc in (("jacobi", "fdm") if jacobi else ()):
+    for pc in (("jacobi", "fdm", "schwarz") if jacobi else ()):
         # the same solves with a preconditioner (kernels autotuned for it)
         saved = {p: ctx.get_variant(p) for p in ("bf16g", "fp64")}
         ctx.set_precond(pc)
@@ -276,10 +276,11 @@ def kernel_roofline(ctx, prec):
 
 
 def precond_case(torch, ctx, f, steps, base, pc="jacobi"):
-    """A preconditioner (pc: 'jacobi' diagonal, or 'fdm' element-interior fast
-    diagonalization with the diagonal elsewhere) on the same solve:
-    iterations, time and per-kernel sampled durations (for 'fdm' the second
-    figure brackets the update and block-solve kernels together) for FP64 CG
+    """A preconditioner (pc: 'jacobi' diagonal, 'fdm' element-interior fast
+    diagonalization with the diagonal elsewhere, or 'schwarz' two-level
+    overlapping Schwarz) on the same solve: iterations, time and per-kernel
+    sampled durations (for 'fdm' and 'schwarz' the second figure brackets the
+    update and preconditioner kernels together) for FP64 CG
     and the mixed solve, against the unpreconditioned runs in `base`
     (prec -> (ms, iters))."""
     out = {}
@@ -725,6 +726,8 @@ def main():
     log(f"jacobi: {jac}")
     fdmc = None if args.no_jacobi else precond_case(torch, ctx, f, args.steps, base, "fdm")
     log(f"fdm: {fdmc}")
+    asm = None if args.no_jacobi else precond_case(torch, ctx, f, args.steps, base, "schwarz")
+    log(f"schwarz: {asm}")
     geo = geometry_case(torch, ctx, f, args.steps, base)
     log(f"trilinear geometry: {geo}")
     # the GPU's fastest FP64 CG: stored or in-kernel factors
@@ -784,6 +787,7 @@ def main():
         "energy": energy,
         "jacobi": jac,
         "fdm": fdmc,
+        "schwarz": asm,
         "geometry_trilinear": geo,
         "roofline": {"bound": "hbm", "kernel": f"k_ax<NP=10,f32,f32,CG,x=f64> variant {tuned['fp32'][0]} "
                                                f"(add2s1 + ax_e + FP64 correction update)",

@@ -1446,7 +1446,6 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
 {
     constexpr int N = NP - 1, NW = NP + 2, PW = NW + 1, NW2 = NW * NW, NP2 = NP * NP, NP3 = NP2 * NP;
     __shared__ T buf[NW * NW * PW];
-    __shared__ T sS[3][NW2];
     __shared__ T sl[3][NW];
     __shared__ double mx[2][NP2];
     __shared__ double my[4][NP];
@@ -1454,22 +1453,33 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
     const int tid = threadIdx.x;
     const int e = blockIdx.x;
     const int ex = e % box.nx, eyz = e / box.nx, ey = eyz % box.ny, ez = eyz / box.ny;
-    const int ed[3] = {ex, ey, ez}, nd[3] = {box.nx, box.ny, box.nz};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const int v = (ed[d] == 0 ? 1 : 0) + (ed[d] == nd[d] - 1 ? 2 : 0);
-        for (int q = tid; q < NW2; q += NW2) sS[d][q] = Sw[v * NW2 + q];
-        if (tid < NW) sl[d][tid] = lamw[v * NW + tid];
+    // the modes of each direction's clipping variant: element-uniform, so the
+    // compiler reads them through the scalar cache
+    const int vx = (ex == 0 ? 1 : 0) + (ex == box.nx - 1 ? 2 : 0);
+    const int vy = (ey == 0 ? 1 : 0) + (ey == box.ny - 1 ? 2 : 0);
+    const int vz = (ez == 0 ? 1 : 0) + (ez == box.nz - 1 ? 2 : 0);
+    const T *__restrict__ Sx = Sw + vx * NW2, *__restrict__ Sy = Sw + vy * NW2, *__restrict__ Sz = Sw + vz * NW2;
+    if (tid < NW) {
+        sl[0][tid] = lamw[vx * NW + tid];
+        sl[1][tid] = lamw[vy * NW + tid];
+        sl[2][tid] = lamw[vz * NW + tid];
     }
-    // the window of r
-    for (int q = tid; q < NW2 * NW; q += NW2) {
-        const int a = q % NW, b = (q / NW) % NW, c = q / NW2;
-        int e0, i0, e1, i1, e2, i2;
-        T v = (T)0;
-        if (win_node<NP>(a, ex, box.nx, e0, i0) && win_node<NP>(b, ey, box.ny, e1, i1) &&
-            win_node<NP>(c, ez, box.nz, e2, i2))
-            v = r[(long)(e0 + box.nx * (e1 + box.ny * e2)) * NP3 + i0 + NP * (i1 + NP * i2)];
-        buf[a + PW * (b + NW * c)] = v;
+    // the window of r: thread (a, b) loads its column along z
+    {
+        const int a = tid % NW, b = tid / NW;
+        int e0 = 0, i0 = 0, e1 = 0, i1 = 0;
+        const bool hxy = win_node<NP>(a, ex, box.nx, e0, i0) && win_node<NP>(b, ey, box.ny, e1, i1);
+        const long col = (long)(e0 + box.nx * e1) * NP3 + i0 + NP * i1;
+        T v[NW];
+#pragma unroll
+        for (int c = 0; c < NW; ++c) {
+            int e2, i2;
+            v[c] = (T)0;
+            if (hxy && win_node<NP>(c, ez, box.nz, e2, i2))
+                v[c] = r[col + (long)box.nx * box.ny * e2 * NP3 + NP2 * i2];
+        }
+#pragma unroll
+        for (int c = 0; c < NW; ++c) buf[a + PW * (b + NW * c)] = v[c];
     }
     __syncthreads();
     // coarse moments: along x per (j, k) line of the element's own nodes, then y, then z
@@ -1520,7 +1530,7 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
     for (int m = 0; m < NW; ++m) {
         T acc = 0;
 #pragma unroll
-        for (int a = 0; a < NW; ++a) acc += sS[0][a * NW + m] * in[a];
+        for (int a = 0; a < NW; ++a) acc += Sx[a * NW + m] * in[a];
         out[m] = acc;
     }
 #pragma unroll
@@ -1533,7 +1543,7 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
     for (int m = 0; m < NW; ++m) {
         T acc = 0;
 #pragma unroll
-        for (int b = 0; b < NW; ++b) acc += sS[1][b * NW + m] * in[b];
+        for (int b = 0; b < NW; ++b) acc += Sy[b * NW + m] * in[b];
         out[m] = acc;
     }
 #pragma unroll
@@ -1549,14 +1559,14 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
         for (int m = 0; m < NW; ++m) {
             T acc = 0;
 #pragma unroll
-            for (int c = 0; c < NW; ++c) acc += sS[2][c * NW + m] * in[c];
+            for (int c = 0; c < NW; ++c) acc += Sz[c * NW + m] * in[c];
             out[m] = (T)2 * acc / (lxy + cz * sl[2][m]);
         }
 #pragma unroll
         for (int c = 0; c < NW; ++c) {
             T acc = 0;
 #pragma unroll
-            for (int m = 0; m < NW; ++m) acc += sS[2][c * NW + m] * out[m];
+            for (int m = 0; m < NW; ++m) acc += Sz[c * NW + m] * out[m];
             in[c] = acc;
         }
 #pragma unroll
@@ -1570,7 +1580,7 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
     for (int b = 0; b < NW; ++b) {
         T acc = 0;
 #pragma unroll
-        for (int m = 0; m < NW; ++m) acc += sS[1][b * NW + m] * in[m];
+        for (int m = 0; m < NW; ++m) acc += Sy[b * NW + m] * in[m];
         out[b] = acc;
     }
 #pragma unroll
@@ -1584,7 +1594,7 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
     for (int a = 0; a < NW; ++a) {
         T acc = 0;
 #pragma unroll
-        for (int m = 0; m < NW; ++m) acc += sS[0][a * NW + m] * in[m];
+        for (int m = 0; m < NW; ++m) acc += Sx[a * NW + m] * in[m];
         ue[a] = acc;
     }
 }
@@ -1606,68 +1616,81 @@ __device__ __forceinline__ int win_cands(int i, int ed, int nd, int eo[3], int a
 // (ascending element order: every copy of a node forms the identical sum)
 // + the trilinear interpolation of the coarse correction ec (vertex lattice,
 // 0 on the boundary; weights by reference coordinate, so copies agree bit
-// for bit), 0 on Dirichlet nodes; partials of glsc3(r, c, z) to P.  With sc
-// set, a CG step of iteration it.
+// for bit), 0 on Dirichlet nodes; partials of glsc3(r, c, z) to P.  A
+// workgroup of NP^2 threads walks a contiguous range of elements, thread
+// (i, j) its k-column: the x and y subdomains and the coarse weights along x
+// and y are the column's, only the z part changes along it.  With sc set, a
+// CG step of iteration it.
 template <int NP, typename T>
-__global__ __launch_bounds__(UPD_BS) void k_asm_gather(const T *__restrict__ r, T *__restrict__ z,
+__global__ __launch_bounds__(NP *NP) void k_asm_gather(const T *__restrict__ r, T *__restrict__ z,
                                                        const T *__restrict__ u, const double *__restrict__ ec,
                                                        const double *__restrict__ ell, double *__restrict__ P,
-                                                       Box box, unsigned nl, const Scal *__restrict__ sc, int it)
+                                                       Box box, int E, const Scal *__restrict__ sc, int it)
 {
-    constexpr int NW = NP + 2, NW2 = NW * NW;
-    __shared__ double sbuf[UPD_BS];
+    constexpr int N = NP - 1, NW = NP + 2, NW3 = NW * NW * NW, NP2 = NP * NP, NP3 = NP2 * NP, BS = NP2;
+    __shared__ double sbuf[BS];
     if (sc && sc->st[it & 1].done) return;
+    const int tid = threadIdx.x, i = tid % NP, j = tid / NP;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
-    const unsigned t0 = (unsigned)(((unsigned long)lb * nl) / gridDim.x);
-    const unsigned t1 = (unsigned)(((unsigned long)(lb + 1) * nl) / gridDim.x);
+    const int e0 = (int)(((long)lb * E) / gridDim.x), e1 = (int)(((long)(lb + 1) * E) / gridDim.x);
     const long vx = box.nx + 1, vy = box.ny + 1;
+    const double lx0 = ell[i], lx1 = ell[NP + i], ly0 = ell[j], ly1 = ell[NP + j];
     double part = 0.0;
-    for (unsigned t = t0 + threadIdx.x; t < t1; t += UPD_BS) {
-        const PointInfo<NP> Pt = locate<NP>(t, box);
-        double zv = 0.0;
-        if (!Pt.masked) {
-            int exo[3], axo[3], eyo[3], ayo[3], ezo[3], azo[3];
-            const int nx = win_cands<NP>(Pt.i, Pt.ex, box.nx, exo, axo);
-            const int ny = win_cands<NP>(Pt.j, Pt.ey, box.ny, eyo, ayo);
-            const int nz = win_cands<NP>(Pt.k, Pt.ez, box.nz, ezo, azo);
-            double s = 0.0;
+    for (int e = e0; e < e1; ++e) {
+        const int ex = e % box.nx, eyz = e / box.nx, ey = eyz % box.ny, ez = eyz / box.ny;
+        const bool dir_xy = (i == 0 && ex == 0) || (i == N && ex == box.nx - 1) || (j == 0 && ey == 0) ||
+                            (j == N && ey == box.ny - 1);
+        int exo[3], axo[3], eyo[3], ayo[3];
+        const int nx = win_cands<NP>(i, ex, box.nx, exo, axo);
+        const int ny = win_cands<NP>(j, ey, box.ny, eyo, ayo);
+        // coarse correction of the column: along x, then y, per z-layer of vertices
+        double tz[2];
 #pragma unroll
-            for (int qz = 0; qz < 3; ++qz) {
-                if (qz >= nz) break;
+        for (int dz = 0; dz < 2; ++dz) {
+            double ty[2];
 #pragma unroll
-                for (int qy = 0; qy < 3; ++qy) {
-                    if (qy >= ny) break;
+            for (int dy = 0; dy < 2; ++dy) {
+                const double *row = ec + ex + vx * ((ey + dy) + vy * (ez + dz));
+                ty[dy] = lx0 * row[0] + lx1 * row[1];
+            }
+            tz[dz] = ly0 * ty[0] + ly1 * ty[1];
+        }
+        const T *re = r + (long)e * NP3 + tid;
+        T *ze = z + (long)e * NP3 + tid;
 #pragma unroll
-                    for (int qx = 0; qx < 3; ++qx) {
-                        if (qx >= nx) break;
-                        const long eo = exo[qx] + (long)box.nx * (eyo[qy] + (long)box.ny * ezo[qz]);
-                        s += (double)u[eo * NW2 * NW + axo[qx] + NW * (ayo[qy] + NW * azo[qz])];
+        for (int k = 0; k < NP; ++k) {
+            double zv = 0.0;
+            const bool dir = dir_xy || (k == 0 && ez == 0) || (k == N && ez == box.nz - 1);
+            if (!dir) {
+                int ezo[3], azo[3];
+                const int nz = win_cands<NP>(k, ez, box.nz, ezo, azo);
+                double sm = 0.0;
+#pragma unroll
+                for (int qz = 0; qz < 3; ++qz) {
+                    if (qz >= nz) break;
+#pragma unroll
+                    for (int qy = 0; qy < 3; ++qy) {
+                        if (qy >= ny) break;
+#pragma unroll
+                        for (int qx = 0; qx < 3; ++qx) {
+                            if (qx >= nx) break;
+                            const long eo = exo[qx] + (long)box.nx * (eyo[qy] + (long)box.ny * ezo[qz]);
+                            sm += (double)u[eo * NW3 + axo[qx] + NW * (ayo[qy] + NW * azo[qz])];
+                        }
                     }
                 }
+                zv = sm + (ell[k] * tz[0] + ell[NP + k] * tz[1]);
             }
-            // coarse correction: along x, then y, then z
-            const double lx0 = ell[Pt.i], lx1 = ell[NP + Pt.i];
-            const double ly0 = ell[Pt.j], ly1 = ell[NP + Pt.j];
-            const double lz0 = ell[Pt.k], lz1 = ell[NP + Pt.k];
-            double tz[2];
-#pragma unroll
-            for (int dz = 0; dz < 2; ++dz) {
-                double ty[2];
-#pragma unroll
-                for (int dy = 0; dy < 2; ++dy) {
-                    const double *row = ec + Pt.ex + vx * ((Pt.ey + dy) + vy * (Pt.ez + dz));
-                    ty[dy] = lx0 * row[0] + lx1 * row[1];
-                }
-                tz[dz] = ly0 * ty[0] + ly1 * ty[1];
-            }
-            zv = s + (lz0 * tz[0] + lz1 * tz[1]);
+            const T zt = (T)zv;
+            ze[k * NP2] = zt;
+            const int mx = ((i == 0 && ex > 0) || (i == N && ex < box.nx - 1)) ? 2 : 1;
+            const int my = ((j == 0 && ey > 0) || (j == N && ey < box.ny - 1)) ? 2 : 1;
+            const int mz = ((k == 0 && ez > 0) || (k == N && ez < box.nz - 1)) ? 2 : 1;
+            part += ((double)re[k * NP2] * (double)zt) * inv_mult(mx * my * mz);
         }
-        const T zt = (T)zv;
-        z[t] = zt;
-        part += ((double)r[t] * (double)zt) * inv_mult(Pt.mult);
     }
-    const double sum = block_sum<UPD_BS>(part, sbuf);
-    if (threadIdx.x == 0) P[blockIdx.x] = sum;
+    const double sum = block_sum<BS>(part, sbuf);
+    if (tid == 0) P[blockIdx.x] = sum;
 }
 
 // Start of a preconditioned run: r -> z = r / m in place (m the diagonal,

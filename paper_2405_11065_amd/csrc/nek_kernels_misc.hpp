@@ -115,71 +115,109 @@ __global__ __launch_bounds__(256) void k_batch_alldone(Scal *const *__restrict__
     if (threadIdx.x == 0) set_host_flag(out, !pending);
 }
 
-// Coarse solve of the two-level Schwarz preconditioner, one workgroup: the
-// coarse right-hand side P^T r of the interior vertices from the elements'
-// moments (the up to eight elements around a vertex in ascending order),
-// then S^T along x, y, z, the scaling 1 / (lx + ly + lz), and S back along
-// z, y, x (per-direction modes S [vertex][mode] of n_d - 1 interior
-// vertices), through the two scratch buffers a and b (interior vertices,
-// x fastest).  ec receives the result on the whole vertex lattice, 0 on the
-// boundary.  With sc set, a CG step of iteration it.
-__global__ __launch_bounds__(1024) void k_asm_coarse(const double *__restrict__ mom, const double *__restrict__ Sx,
-                                                     const double *__restrict__ Sy, const double *__restrict__ Sz,
-                                                     const double *__restrict__ lx, const double *__restrict__ ly,
-                                                     const double *__restrict__ lz, double *__restrict__ a,
-                                                     double *__restrict__ b, double *__restrict__ ec, Box box,
-                                                     const Scal *__restrict__ sc, int it)
+// Coarse solve of the two-level Schwarz preconditioner in three launches on
+// the interior vertices (mx x my x mz = n_d - 1 per direction, x fastest),
+// each workgroup staging its slab or plane in LDS (dynamic: the slab, then
+// the modes it applies):
+//   k_coarse_xy<true>  one workgroup per z-slab: the coarse right-hand side
+//                      P^T r of the slab's vertices from the elements'
+//                      moments (the eight elements around a vertex in
+//                      ascending order), then S^T along x and along y -> a;
+//   k_coarse_z         one workgroup per y-plane: S^T along z, the scaling
+//                      1 / (lx + ly + lz), S along z -> b;
+//   k_coarse_xy<false> one workgroup per z-slab: S along y and along x, into
+//                      the vertex lattice ec (its boundary stays 0).
+// Modes S are [vertex][mode] per direction.  With sc set, a CG step of
+// iteration it (nothing after the run has ended).
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_coarse_xy(const double *__restrict__ src, const double *__restrict__ Sx,
+                                                   const double *__restrict__ Sy, double *__restrict__ dst, Box box,
+                                                   const Scal *__restrict__ sc, int it)
 {
+    extern __shared__ double cl[];
     if (sc && sc->st[it & 1].done) return;
-    const int tid = threadIdx.x, bs = blockDim.x;
-    const int mx = box.nx - 1, my = box.ny - 1, mz = box.nz - 1;
-    const long vx = box.nx + 1, vy = box.ny + 1, nv = vx * vy * (box.nz + 1);
-    const long nc = (long)mx * my * mz;
-    for (long q = tid; q < nv; q += bs) ec[q] = 0.0;
-    for (long q = tid; q < nc; q += bs) {
-        const int ix = (int)(q % mx) + 1, iy = (int)((q / mx) % my) + 1, iz = (int)(q / ((long)mx * my)) + 1;
-        double s = 0.0;
-        for (int dz = 0; dz < 2; ++dz)
-            for (int dy = 0; dy < 2; ++dy)
-                for (int dx = 0; dx < 2; ++dx) {
-                    const long e = (ix - 1 + dx) + (long)box.nx * ((iy - 1 + dy) + (long)box.ny * (iz - 1 + dz));
-                    s += mom[e * 8 + (1 - dx) + 2 * (1 - dy) + 4 * (1 - dz)];
-                }
-        a[q] = s;
+    const int mx = box.nx - 1, my = box.ny - 1;
+    const int vz = blockIdx.x;   // interior z-index, vertex vz + 1
+    const int tid = threadIdx.x, bs = blockDim.x, ns = mx * my;
+    double *sl = cl, *t = cl + ns, *sx = t + ns, *sy = sx + mx * mx;
+    for (int q = tid; q < mx * mx; q += bs) sx[q] = Sx[q];
+    for (int q = tid; q < my * my; q += bs) sy[q] = Sy[q];
+    if constexpr (FWD) {
+        for (int q = tid; q < ns; q += bs) {
+            const int ix = q % mx + 1, iy = q / mx + 1, iz = vz + 1;
+            double s = 0.0;
+            for (int dz = 0; dz < 2; ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const long e = (ix - 1 + dx) + (long)box.nx * ((iy - 1 + dy) + (long)box.ny * (iz - 1 + dz));
+                        s += src[e * 8 + (1 - dx) + 2 * (1 - dy) + 4 * (1 - dz)];
+                    }
+            sl[q] = s;
+        }
+    } else {
+        for (int q = tid; q < ns; q += bs) sl[q] = src[(long)vz * ns + q];
     }
     __syncthreads();
-    if (nc == 0) return;
-    // one line per thread: in (stride st, n entries) -> out, out[m] = sum_k S[k][m] in[k] (fwd) or
-    // out[k] = sum_m S[k][m] in[m] (back)
-    auto pass = [&](const double *in, double *out, const double *S, int n, long st, long nlines, auto base_of,
-                    bool fwd) {
-        for (long l = tid; l < nlines; l += bs) {
-            const long o = base_of(l);
-            for (int m = 0; m < n; ++m) {
-                double acc = 0.0;
-                for (int k = 0; k < n; ++k) acc += (fwd ? S[k * n + m] : S[m * n + k]) * in[o + k * st];
-                out[o + m * st] = acc;
-            }
+    if constexpr (FWD) {
+        for (int q = tid; q < ns; q += bs) {   // along x: t[y][m] = sum_k Sx[k][m] sl[y][k]
+            const int m = q % mx, y = q / mx;
+            double acc = 0.0;
+            for (int k = 0; k < mx; ++k) acc += sx[k * mx + m] * sl[y * mx + k];
+            t[q] = acc;
         }
         __syncthreads();
-    };
-    auto bx = [&](long l) { return l * mx; };                                       // lines along x: (y, z)
-    auto by = [&](long l) { return (l % mx) + (long)mx * my * (l / mx); };          // along y: (x, z)
-    auto bz = [&](long l) { return l; };                                            // along z: (x, y)
-    pass(a, b, Sx, mx, 1, (long)my * mz, bx, true);
-    pass(b, a, Sy, my, mx, (long)mx * mz, by, true);
-    pass(a, b, Sz, mz, (long)mx * my, (long)mx * my, bz, true);
-    for (long q = tid; q < nc; q += bs) {
-        const int ix = (int)(q % mx), iy = (int)((q / mx) % my), iz = (int)(q / ((long)mx * my));
-        b[q] = b[q] / (lx[ix] + ly[iy] + lz[iz]);
+        for (int q = tid; q < ns; q += bs) {   // along y: out[m][x] = sum_k Sy[k][m] t[k][x]
+            const int x = q % mx, m = q / mx;
+            double acc = 0.0;
+            for (int k = 0; k < my; ++k) acc += sy[k * my + m] * t[k * mx + x];
+            dst[(long)vz * ns + q] = acc;
+        }
+    } else {
+        for (int q = tid; q < ns; q += bs) {   // along y: t[y][x] = sum_m Sy[y][m] sl[m][x]
+            const int x = q % mx, y = q / mx;
+            double acc = 0.0;
+            for (int m = 0; m < my; ++m) acc += sy[y * my + m] * sl[m * mx + x];
+            t[q] = acc;
+        }
+        __syncthreads();
+        const long vx = box.nx + 1, vy = box.ny + 1;
+        for (int q = tid; q < ns; q += bs) {   // along x: ec[x][y] = sum_m Sx[x][m] t[y][m]
+            const int x = q % mx, y = q / mx;
+            double acc = 0.0;
+            for (int m = 0; m < mx; ++m) acc += sx[x * mx + m] * t[y * mx + m];
+            dst[(x + 1) + vx * ((y + 1) + vy * (vz + 1))] = acc;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_coarse_z(const double *__restrict__ a, const double *__restrict__ Sz,
+                                                  const double *__restrict__ lx, const double *__restrict__ ly,
+                                                  const double *__restrict__ lz, double *__restrict__ b, Box box,
+                                                  const Scal *__restrict__ sc, int it)
+{
+    extern __shared__ double cl[];
+    if (sc && sc->st[it & 1].done) return;
+    const int mx = box.nx - 1, my = box.ny - 1, mz = box.nz - 1;
+    const int y = blockIdx.x, tid = threadIdx.x, bs = blockDim.x, np = mx * mz;
+    double *pl = cl, *t = cl + np, *sz = t + np;
+    for (int q = tid; q < mz * mz; q += bs) sz[q] = Sz[q];
+    for (int q = tid; q < np; q += bs) {   // plane [z][x]
+        const int x = q % mx, z = q / mx;
+        pl[q] = a[(long)z * mx * my + (long)y * mx + x];
     }
     __syncthreads();
-    pass(b, a, Sz, mz, (long)mx * my, (long)mx * my, bz, false);
-    pass(a, b, Sy, my, mx, (long)mx * mz, by, false);
-    pass(b, a, Sx, mx, 1, (long)my * mz, bx, false);
-    for (long q = tid; q < nc; q += bs) {
-        const int ix = (int)(q % mx) + 1, iy = (int)((q / mx) % my) + 1, iz = (int)(q / ((long)mx * my)) + 1;
-        ec[ix + vx * (iy + vy * iz)] = a[q];
+    for (int q = tid; q < np; q += bs) {   // t[m][x] = sum_k Sz[k][m] pl[k][x] / (lx + ly + lz)
+        const int x = q % mx, m = q / mx;
+        double acc = 0.0;
+        for (int k = 0; k < mz; ++k) acc += sz[k * mz + m] * pl[k * mx + x];
+        t[q] = acc / (lx[x] + ly[y] + lz[m]);
+    }
+    __syncthreads();
+    for (int q = tid; q < np; q += bs) {   // back along z
+        const int x = q % mx, z = q / mx;
+        double acc = 0.0;
+        for (int m = 0; m < mz; ++m) acc += sz[z * mz + m] * t[m * mx + x];
+        b[(long)z * mx * my + (long)y * mx + x] = acc;
     }
 }
 

@@ -286,7 +286,9 @@ int ensure_fdm(nek_ctx *c)
 
 int ensure_schwarz(nek_ctx *c)
 {
-    if (c->N < 2) return NEK_E_ARG;
+    // the coarse slabs and planes are staged in LDS: at most 64 interior
+    // vertices per direction (meshes of up to 65 elements along each)
+    if (c->N < 2 || c->nel[0] > 65 || c->nel[1] > 65 || c->nel[2] > 65) return NEK_E_ARG;
     if (c->asmS64 && c->asmU64 && c->z64 && c->z32) return NEK_OK;
     const int NP = c->NP, NW = NP + 2;
     std::vector<double> S, L, CS, CL, ell((size_t)2 * NP), C((size_t)3 * c->E);
@@ -319,16 +321,38 @@ int ensure_schwarz(nek_ctx *c)
     }
     HIP_TRY(hipMemcpy(c->fdmC64, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->fdmC32, C32.data(), C32.size() * sizeof(float), hipMemcpyHostToDevice));
+    // the coarse correction's boundary vertices are never written: zero once
+    const int rc = fill_f64(c, c->asmEc, 0.0, (unsigned long)nv);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(c->stream));
     return NEK_OK;
 }
 
 int asm_coarse_launch(nek_ctx *c, const Scal *sc, int it)
 {
-    const long ncv = (long)(c->box.nx - 1) * (c->box.ny - 1) * (c->box.nz - 1);
-    hipLaunchKernelGGL(k_asm_coarse, dim3(1), dim3(1024), 0, c->stream, c->asmMom, c->asmCS + c->asmCoff[0],
-                       c->asmCS + c->asmCoff[1], c->asmCS + c->asmCoff[2], c->asmCL + c->asmCloff[0],
-                       c->asmCL + c->asmCloff[1], c->asmCL + c->asmCloff[2], c->asmTmp, c->asmTmp + ncv, c->asmEc,
-                       c->box, sc, it);
+    const int mx = c->box.nx - 1, my = c->box.ny - 1, mz = c->box.nz - 1;
+    if (mx <= 0 || my <= 0 || mz <= 0) return NEK_OK;   // no interior vertex: ec stays 0
+    const long ncv = (long)mx * my * mz;
+    const double *S = c->asmCS, *L = c->asmCL;
+    double *a = c->asmTmp, *b = c->asmTmp + ncv;
+    const size_t lxy = (size_t)(2 * mx * my + mx * mx + my * my) * sizeof(double);
+    const size_t lz = (size_t)(2 * mx * mz + mz * mz) * sizeof(double);
+    static bool attr_done = false;   // up to 128 KB of LDS at 64 interior vertices per direction
+    if (!attr_done) {
+        const int big = 160 * 1024;
+        HIP_TRY(hipFuncSetAttribute((const void *)k_coarse_xy<true>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+        HIP_TRY(hipFuncSetAttribute((const void *)k_coarse_xy<false>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+        HIP_TRY(hipFuncSetAttribute((const void *)k_coarse_z, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+        attr_done = true;
+    }
+    hipLaunchKernelGGL(k_coarse_xy<true>, dim3(mz), dim3(256), lxy, c->stream, c->asmMom, S + c->asmCoff[0],
+                       S + c->asmCoff[1], a, c->box, sc, it);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_coarse_z, dim3(my), dim3(256), lz, c->stream, a, S + c->asmCoff[2], L + c->asmCloff[0],
+                       L + c->asmCloff[1], L + c->asmCloff[2], b, c->box, sc, it);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_coarse_xy<false>, dim3(mz), dim3(256), lxy, c->stream, b, S + c->asmCoff[0],
+                       S + c->asmCoff[1], c->asmEc, c->box, sc, it);
     HIP_TRY(hipGetLastError());
     return NEK_OK;
 }

@@ -108,8 +108,8 @@ template <int NP> struct OpsImpl {
         HIP_TRY(hipGetLastError());
         int rc = asm_coarse_launch(c, scp, it);
         if (rc) return rc;
-        hipLaunchKernelGGL((k_asm_gather<NP, T>), dim3(grid), dim3(UPD_BS), 0, c->stream, r, z, U, c->asmEc,
-                           c->asmEll, P, c->box, (unsigned)c->nl, scp, it);
+        hipLaunchKernelGGL((k_asm_gather<NP, T>), dim3(grid), dim3(NP * NP), 0, c->stream, r, z, U, c->asmEc,
+                           c->asmEll, P, c->box, (int)c->E, scp, it);
         HIP_TRY(hipGetLastError());
         return NEK_OK;
     }

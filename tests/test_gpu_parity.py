@@ -332,8 +332,8 @@ def test_full_size_16cubed_N9():
         print(f"  {prec} trilinear: iters {st['iters']} rho* {rho:.2e} |x - x_stored|/|x_stored| {dx:.2e}")
         assert st["status"] == 0 and rho <= 1e-8 and dx <= 1e-6
     ctx.set_geometry("stored")
-    # both preconditioners on the benchmarked workload, FP64 and mixed
-    for pc in ("jacobi", "fdm"):
+    # the preconditioners on the benchmarked workload, FP64 and mixed
+    for pc in ("jacobi", "fdm", "schwarz"):
         ctx.set_precond(pc)
         for prec in ("fp64", "fp32"):
             ctx.set_prec(prec)
@@ -379,7 +379,7 @@ def test_full_size_32cubed_N9_bf16g():
     ctx.set_geometry("stored")
     ctx.set_prec("bf16g")
     # the same solve with each preconditioner, as the benchmark times it
-    for pc in ("jacobi", "fdm"):
+    for pc in ("jacobi", "fdm", "schwarz"):
         ctx.set_precond(pc)
         ctx.tune("bf16g", iters=10)
         _case(f"cg 32^3 N=9 bf16g {pc}")

@@ -155,3 +155,28 @@ def test_converged_solves_against_oracle(prec):
             assert abs(st["iters"] - ito) <= 1
         assert st["iters"] < itc / 3
     ctx.close()
+
+
+def test_refinement_removes_the_mixed_precision_stall():
+    """The paper's mixed build stagnated with its multigrid preconditioner;
+    here the FP32-operator loop with the Schwarz preconditioner, limited to
+    one refinement step, stalls far above the tolerance in its true residual
+    while its recursive residual reaches it, and FP64 refinement removes the
+    stall (true residual by the oracle)."""
+    N, nel, tol = 7, (6, 6, 6), 1e-8
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=42)
+    P = oracle.Problem(N, nel, vtx)
+    f = synth.uniform_load(P.nl, 8)
+    fd = dev(f)
+    one = nek.Context(nel, N, vtx=vtx, prec="fp32", precond="schwarz", inner_tol=tol, max_outer=1, corr_fp32=1)
+    x, st, _ = one.cg_solve(fd, tol=tol, maxit=2000)
+    stall = P.true_residual(host(x), f)
+    print(f"  one FP32 step: {st['iters']} its, recursive {st['last_rec_res']:.2e}, true {stall:.2e}")
+    assert st["last_rec_res"] <= 2 * tol and stall > 10 * tol
+    one.close()
+    full = nek.Context(nel, N, vtx=vtx, prec="fp32", precond="schwarz")
+    x, st, _ = full.cg_solve(fd, tol=tol, maxit=2000, raise_on_noconv=True)
+    rho = P.true_residual(host(x), f)
+    print(f"  refined: {st['iters']} its in {st['outer_iters']} steps, true {rho:.2e}")
+    assert rho <= tol
+    full.close()
