@@ -35,7 +35,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nek_oracle.c")
 _SRCS = [_SRC, os.path.join(_HERE, "nek_vprec.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 _lib = None
+_lib_omp = None
 
 _d = ctypes.POINTER(ctypes.c_double)
 _i64 = ctypes.POINTER(ctypes.c_int64)
@@ -45,46 +47,70 @@ _int3 = ctypes.c_int * 3
 
 
 def build(force: bool = False) -> str:
-    """Compile nek_oracle.c into liboracle.so (plain gcc, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(map(os.path.getmtime, _SRCS)):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                               "-shared", "-o", tmp] + _SRCS + ["-lm"])
-        os.replace(tmp, _LIB)
+    """Compile nek_oracle.c into liboracle.so (plain gcc, no FMA contraction)
+    and, from the same sources, liboracle_omp.so: -O3 with OpenMP for the
+    all-core timing of the CPU baseline (bit-identical results; x86-64-v3,
+    so the object built here also runs on the GPU machine's host)."""
+    stale = lambda lib: force or not os.path.exists(lib) or os.path.getmtime(lib) < max(map(os.path.getmtime, _SRCS))
+    for lib, flags in ((_LIB, ["-O2"]), (_LIB_OMP, ["-O3", "-march=x86-64-v3", "-fopenmp"])):
+        if stale(lib):
+            tmp = lib + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", *flags, "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                                   "-shared", "-o", tmp] + _SRCS + ["-lm"])
+            os.replace(tmp, lib)
     return _LIB
 
 
-def _get():
-    global _lib
+def _get(omp: bool = False):
+    global _lib, _lib_omp
+    if omp:
+        if _lib_omp is None:
+            build()
+            _lib_omp = _bind(ctypes.CDLL(_LIB_OMP))
+        return _lib_omp
     if _lib is None:
         build()
-        lib = ctypes.CDLL(_LIB)
-        lib.or_gll.argtypes = [ctypes.c_int, _d, _d]
-        lib.or_deriv.argtypes = [ctypes.c_int, _d, _d]
-        lib.or_numbering.argtypes = [ctypes.c_int, _int3, _i64, _i32, _i8]
-        lib.or_segments.argtypes = [ctypes.c_int, _int3, _i64, _i8, _i32, _i32, _i8, _i64, _i64]
-        lib.or_geometry.argtypes = [ctypes.c_int, _int3, _d, _d, _d, _d]
-        lib.or_ax_local.argtypes = [ctypes.c_int, ctypes.c_int64, _d, _d, _d, _d]
-        lib.or_dssum.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64, _d, _d]
-        lib.or_mask.argtypes = [ctypes.c_int64, _i8, _d]
-        lib.or_glsc3.argtypes = [ctypes.c_int64, _d, _d, _d]
-        lib.or_glsc3.restype = ctypes.c_double
-        lib.or_glsc3_plain.argtypes = [ctypes.c_int64, _d, _d, _d]
-        lib.or_glsc3_plain.restype = ctypes.c_double
-        lib.or_apply_A.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i8, _d, _d]
-        lib.or_cg.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i32, _i8, _d, _d,
-                              ctypes.c_double, ctypes.c_int, _d, _d]
-        lib.or_diag.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i8, _d]
-        lib.or_pcg.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i32, _i8, _d, _d, _d,
-                               ctypes.c_double, ctypes.c_int, _d, _d]
-        lib.vp_round.argtypes = [ctypes.c_double, ctypes.c_int]
-        lib.vp_round.restype = ctypes.c_double
-        lib.vp_perturb.argtypes = [ctypes.c_double, ctypes.c_int]
-        lib.vp_perturb.restype = ctypes.c_double
-        lib.vp_cg.argtypes = [ctypes.c_int, _int3, _d, _d, _i32, ctypes.c_int, ctypes.c_uint64,
-                              ctypes.c_double, ctypes.c_int, _d, _d, _d, _d]
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
+
+
+def _bind(lib):
+    """Argument types of the oracle's entry points."""
+    lib.or_gll.argtypes = [ctypes.c_int, _d, _d]
+    lib.or_deriv.argtypes = [ctypes.c_int, _d, _d]
+    lib.or_numbering.argtypes = [ctypes.c_int, _int3, _i64, _i32, _i8]
+    lib.or_segments.argtypes = [ctypes.c_int, _int3, _i64, _i8, _i32, _i32, _i8, _i64, _i64]
+    lib.or_geometry.argtypes = [ctypes.c_int, _int3, _d, _d, _d, _d]
+    lib.or_ax_local.argtypes = [ctypes.c_int, ctypes.c_int64, _d, _d, _d, _d]
+    lib.or_dssum.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64, _d, _d]
+    lib.or_mask.argtypes = [ctypes.c_int64, _i8, _d]
+    lib.or_glsc3.argtypes = [ctypes.c_int64, _d, _d, _d]
+    lib.or_glsc3.restype = ctypes.c_double
+    lib.or_glsc3_plain.argtypes = [ctypes.c_int64, _d, _d, _d]
+    lib.or_glsc3_plain.restype = ctypes.c_double
+    lib.or_apply_A.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i8, _d, _d]
+    lib.or_cg.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i32, _i8, _d, _d,
+                          ctypes.c_double, ctypes.c_int, _d, _d]
+    lib.or_diag.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i8, _d]
+    lib.or_pcg.argtypes = [ctypes.c_int, _int3, _d, _d, _i64, _i32, _i8, _d, _d, _d,
+                           ctypes.c_double, ctypes.c_int, _d, _d]
+    lib.vp_round.argtypes = [ctypes.c_double, ctypes.c_int]
+    lib.vp_round.restype = ctypes.c_double
+    lib.vp_perturb.argtypes = [ctypes.c_double, ctypes.c_int]
+    lib.vp_perturb.restype = ctypes.c_double
+    lib.vp_cg.argtypes = [ctypes.c_int, _int3, _d, _d, _i32, ctypes.c_int, ctypes.c_uint64,
+                          ctypes.c_double, ctypes.c_int, _d, _d, _d, _d]
+    lib.or_num_threads.restype = ctypes.c_int
+    lib.or_set_threads.argtypes = [ctypes.c_int]
+    return lib
+
+
+def omp_threads(n: int | None = None) -> int:
+    """Threads of the OpenMP build (setting them when n is given)."""
+    lib = _get(omp=True)
+    if n is not None:
+        lib.or_set_threads(int(n))
+    return lib.or_num_threads()
 
 
 def _p(a, t):
@@ -242,11 +268,12 @@ class Problem:
     def segments(self):
         return segments(self.N, self.nel, self.gid, self.mask)
 
-    def cg(self, f, x0=None, tol: float = 1e-8, maxit: int = 1000):
-        """Table-1 CG.  Returns (x, iterations, residual history)."""
+    def cg(self, f, x0=None, tol: float = 1e-8, maxit: int = 1000, omp: bool = False):
+        """Table-1 CG (omp: the OpenMP build, bit-identical).  Returns (x,
+        iterations, residual history)."""
         x = np.empty(self.nl)
         hist = np.zeros(maxit + 1)
-        it = _get().or_cg(self.N, _int3(*self.nel), _p(self.D, _d), _p(self.g, _d),
+        it = _get(omp).or_cg(self.N, _int3(*self.nel), _p(self.D, _d), _p(self.g, _d),
                           _p(self.gid, _i64), _p(self.mult, _i32), _p(self.mask, _i8),
                           _p(_f64(f), _d), _p(None if x0 is None else _f64(x0), _d),
                           float(tol), int(maxit), _p(x, _d), _p(hist, _d))

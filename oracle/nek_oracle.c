@@ -24,7 +24,16 @@
  * Gauss-Lobatto-Legendre points), with homogeneous Dirichlet conditions on the
  * outer faces of a box of hexahedra.  Parity is pinned by closed forms and
  * invariants in the CPU tests, not by the paper.
+ *
+ * The same file also builds with OpenMP (the all-core timing of the CPU
+ * baseline): the element loop of or_ax_local and the element-wise vector
+ * updates of or_cg then run on several threads.  Every reduction and the
+ * gather-scatter stay serial in their fixed order, so that build returns
+ * results bit-identical to the serial one.
  */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -299,8 +308,13 @@ int or_geometry(int N, const int *nel, const double *vtx, double *g, double *B, 
 void or_ax_local(int N, int64_t E, const double *D, const double *g, const double *u, double *w)
 {
     int n = N + 1, n3 = n * n * n;
+    /* elements are independent: an OpenMP build splits them over threads
+       (each with its own scratch); the arithmetic per element is unchanged */
+#pragma omp parallel
+    {
     double *wr = (double *)malloc(sizeof(double) * 3 * n3);
     double *ws = wr + n3, *wt = wr + 2 * n3;
+#pragma omp for schedule(static)
     for (int64_t e = 0; e < E; ++e) {
         const double *ue = u + e * n3;
         const double *ge = g + e * 6 * n3;
@@ -332,6 +346,27 @@ void or_ax_local(int N, int64_t E, const double *D, const double *g, const doubl
                 }
     }
     free(wr);
+    }
+}
+
+/* Threads an OpenMP build runs the element loop on (1 without OpenMP);
+   or_set_threads(n) changes it (no effect without OpenMP). */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 /*
@@ -484,14 +519,18 @@ int or_cg(int N, const int *nel, const double *D, const double *g, const int64_t
             rtz1 = or_glsc3(nl, r, c, r);
             if (rtz1 == 0.0) { --it; break; }   /* exact solution reached */
             double beta = it == 1 ? 0.0 : rtz1 / rtz2;
+#pragma omp parallel for schedule(static)
             for (int64_t l = 0; l < nl; ++l) p[l] = beta * p[l] + r[l];
             or_apply(&op, p, w);
             double pap = or_glsc3(nl, w, c, p);
             if (!isfinite(pap) || !isfinite(rtz1)) { status = -6; break; }
             if (!(pap > 0)) { status = -5; break; }
             double alpha = rtz1 / pap;
-            for (int64_t l = 0; l < nl; ++l) x[l] = x[l] + alpha * p[l];
-            for (int64_t l = 0; l < nl; ++l) r[l] = r[l] + (-alpha) * w[l];
+#pragma omp parallel for schedule(static)
+            for (int64_t l = 0; l < nl; ++l) {
+                x[l] = x[l] + alpha * p[l];
+                r[l] = r[l] + (-alpha) * w[l];
+            }
             double rtr = or_glsc3(nl, r, c, r);
             double res = sqrt(rtr) / sqrt(bb);
             if (res_hist) res_hist[it] = res;
@@ -611,8 +650,11 @@ int or_pcg(int N, const int *nel, const double *D, const double *g, const int64_
             if (!isfinite(pap) || !isfinite(rtz1)) { status = -6; break; }
             if (!(pap > 0)) { status = -5; break; }
             double alpha = rtz1 / pap;
-            for (int64_t l = 0; l < nl; ++l) x[l] = x[l] + alpha * p[l];
-            for (int64_t l = 0; l < nl; ++l) r[l] = r[l] + (-alpha) * w[l];
+#pragma omp parallel for schedule(static)
+            for (int64_t l = 0; l < nl; ++l) {
+                x[l] = x[l] + alpha * p[l];
+                r[l] = r[l] + (-alpha) * w[l];
+            }
             double rtr = or_glsc3(nl, r, c, r);
             double res = sqrt(rtr) / sqrt(bb);
             if (res_hist) res_hist[it] = res;

@@ -467,3 +467,17 @@ def test_pcg_matches_dense_solve_and_saves_iterations():
     xp, it_pcg, _ = P.pcg(f, P.diag(), tol=1e-8, maxit=2000)
     assert it_pcg < 0.92 * it_cg
     assert P.true_residual(xp, f) <= 1e-8
+
+
+def test_openmp_build_is_bit_identical():
+    """The all-core build of the oracle (OpenMP over elements and element-wise
+    updates, serial fixed-order reductions and gather-scatter) returns the
+    serial build's iterates and history bit for bit."""
+    nel, N = (3, 4, 2), 6
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=13)
+    P = oracle.Problem(N, nel, vtx)
+    f = synth.uniform_load(P.nl, 14)
+    oracle.omp_threads(3)
+    a = P.cg(f, tol=0.0, maxit=40)
+    b = P.cg(f, tol=0.0, maxit=40, omp=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
