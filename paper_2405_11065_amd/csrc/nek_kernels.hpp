@@ -1415,6 +1415,23 @@ __global__ __launch_bounds__(NP *NP) void k_pc_fdm(const T *__restrict__ r, T *_
 // a = gi - ex N + 1); nodes on or past the Dirichlet boundary carry no
 // unknown (zero rows of the padded modes S, zero values).
 
+// A row of RP (a multiple of 16 / sizeof(T)) entries from 16-byte aligned LDS.
+template <int RP, typename T> __device__ __forceinline__ void lds_row(const T *__restrict__ src, T out[RP])
+{
+    constexpr int V = 16 / sizeof(T);
+    static_assert(RP % V == 0, "row pitch a multiple of the 16-byte vector");
+#pragma unroll
+    for (int q = 0; q < RP / V; ++q) {
+        const uint4 v = reinterpret_cast<const uint4 *>(src)[q];
+        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int t = 0; t < V; ++t) {
+            if constexpr (sizeof(T) == 4) out[V * q + t] = __builtin_bit_cast(T, w[t]);
+            else out[V * q + t] = __builtin_bit_cast(T, (unsigned long long)w[2 * t] | ((unsigned long long)w[2 * t + 1] << 32));
+        }
+    }
+}
+
 // Window node a of element coordinate ed (of nd) along one direction: the
 // element and local index holding a copy of it, or false when the node is
 // not an unknown (a Dirichlet node or past the boundary).
@@ -1429,7 +1446,8 @@ __device__ __forceinline__ bool win_node(int a, int ed, int nd, int &eo, int &io
     return true;
 }
 
-// Local solves: one workgroup of NW^2 threads per element.  The window of r
+// Local solves: a workgroup of NW^2 threads walks a contiguous range of
+// elements (persistent grid).  The window of r
 // is staged in LDS (rows of pitch NW + 1); six passes apply S^T along x, y, z,
 // the scaling 2 / (cx l_a + cy l_b + cz l_c), and S back along z, y, x, each
 // pass one line per thread held in registers (the z passes share a thread's
@@ -1441,45 +1459,64 @@ __device__ __forceinline__ bool win_node(int a, int ed, int nd, int &eo, int &io
 template <int NP, typename T>
 __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
     const T *__restrict__ r, T *__restrict__ u, double *__restrict__ mom, const T *__restrict__ Sw,
-    const T *__restrict__ lamw, const T *__restrict__ cf, const double *__restrict__ ell, Box box,
+    const T *__restrict__ lamw, const T *__restrict__ cf, const double *__restrict__ ell, Box box, int E,
     const Scal *__restrict__ sc, int it)
 {
     constexpr int N = NP - 1, NW = NP + 2, PW = NW + 1, NW2 = NW * NW, NP2 = NP * NP, NP3 = NP2 * NP;
+    constexpr int VS = 16 / sizeof(T), SP = (NW + VS - 1) / VS * VS;   // mode rows padded to 16 bytes
     __shared__ T buf[NW * NW * PW];
+    __shared__ __align__(16) T sS[3][NW][SP];
     __shared__ T sl[3][NW];
     __shared__ double mx[2][NP2];
     __shared__ double my[4][NP];
     if (sc && sc->st[it & 1].done) return;
     const int tid = threadIdx.x;
-    const int e = blockIdx.x;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int eb = (int)(((long)lb * E) / gridDim.x), ee = (int)(((long)(lb + 1) * E) / gridDim.x);
+    for (int e = eb; e < ee; ++e) {
+    __syncthreads();   // the previous element's LDS reads are done
     const int ex = e % box.nx, eyz = e / box.nx, ey = eyz % box.ny, ez = eyz / box.ny;
-    // the modes of each direction's clipping variant: element-uniform, so the
-    // compiler reads them through the scalar cache
+    // the modes of each direction's clipping variant, as 16-byte aligned rows
+    // in LDS (a thread's pass reads one row per output or input entry)
     const int vx = (ex == 0 ? 1 : 0) + (ex == box.nx - 1 ? 2 : 0);
     const int vy = (ey == 0 ? 1 : 0) + (ey == box.ny - 1 ? 2 : 0);
     const int vz = (ez == 0 ? 1 : 0) + (ez == box.nz - 1 ? 2 : 0);
-    const T *__restrict__ Sx = Sw + vx * NW2, *__restrict__ Sy = Sw + vy * NW2, *__restrict__ Sz = Sw + vz * NW2;
+    {
+        const int a = tid % NW, m = tid / NW;   // NW^2 threads: one entry per direction each
+        sS[0][a][m] = Sw[vx * NW2 + a * NW + m];
+        sS[1][a][m] = Sw[vy * NW2 + a * NW + m];
+        sS[2][a][m] = Sw[vz * NW2 + a * NW + m];
+        if (m < SP - NW) {   // padding of the rows
+            sS[0][a][NW + m] = sS[1][a][NW + m] = sS[2][a][NW + m] = (T)0;
+        }
+    }
     if (tid < NW) {
         sl[0][tid] = lamw[vx * NW + tid];
         sl[1][tid] = lamw[vy * NW + tid];
         sl[2][tid] = lamw[vz * NW + tid];
     }
-    // the window of r: thread (a, b) loads its column along z
+    // the window of r: thread (a, b) loads its column along z, every load
+    // issued without a branch (a node that is not an unknown reads a valid
+    // address, the element's own node 0, and its value is replaced by 0)
     {
         const int a = tid % NW, b = tid / NW;
-        int e0 = 0, i0 = 0, e1 = 0, i1 = 0;
-        const bool hxy = win_node<NP>(a, ex, box.nx, e0, i0) && win_node<NP>(b, ey, box.ny, e1, i1);
+        int e0 = ex, i0 = 0, e1 = ey, i1 = 0;
+        const bool hx = win_node<NP>(a, ex, box.nx, e0, i0), hy = win_node<NP>(b, ey, box.ny, e1, i1);
+        if (!hx) { e0 = ex; i0 = 0; }
+        if (!hy) { e1 = ey; i1 = 0; }
         const long col = (long)(e0 + box.nx * e1) * NP3 + i0 + NP * i1;
+        const long zst = (long)box.nx * box.ny * NP3;
         T v[NW];
+        bool ok[NW];
 #pragma unroll
         for (int c = 0; c < NW; ++c) {
-            int e2, i2;
-            v[c] = (T)0;
-            if (hxy && win_node<NP>(c, ez, box.nz, e2, i2))
-                v[c] = r[col + (long)box.nx * box.ny * e2 * NP3 + NP2 * i2];
+            int e2 = ez, i2 = 0;
+            ok[c] = hx && hy && win_node<NP>(c, ez, box.nz, e2, i2);
+            if (!ok[c]) { e2 = ez; i2 = 0; }
+            v[c] = r[col + zst * e2 + NP2 * i2];
         }
 #pragma unroll
-        for (int c = 0; c < NW; ++c) buf[a + PW * (b + NW * c)] = v[c];
+        for (int c = 0; c < NW; ++c) buf[a + PW * (b + NW * c)] = ok[c] ? v[c] : (T)0;
     }
     __syncthreads();
     // coarse moments: along x per (j, k) line of the element's own nodes, then y, then z
@@ -1527,11 +1564,14 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
 #pragma unroll
     for (int a = 0; a < NW; ++a) in[a] = buf[a + PW * (p0 + NW * p1)];
 #pragma unroll
-    for (int m = 0; m < NW; ++m) {
-        T acc = 0;
+    for (int m = 0; m < NW; ++m) out[m] = 0;
 #pragma unroll
-        for (int a = 0; a < NW; ++a) acc += Sx[a * NW + m] * in[a];
-        out[m] = acc;
+    for (int a = 0; a < NW; ++a) {
+        __builtin_amdgcn_sched_barrier(0);   // one mode row in flight at a time
+        T row[SP];
+        lds_row<SP>(&sS[0][a][0], row);
+#pragma unroll
+        for (int m = 0; m < NW; ++m) out[m] += row[m] * in[a];
     }
 #pragma unroll
     for (int m = 0; m < NW; ++m) buf[m + PW * (p0 + NW * p1)] = out[m];
@@ -1540,11 +1580,14 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
 #pragma unroll
     for (int b = 0; b < NW; ++b) in[b] = buf[p0 + PW * (b + NW * p1)];
 #pragma unroll
-    for (int m = 0; m < NW; ++m) {
-        T acc = 0;
+    for (int m = 0; m < NW; ++m) out[m] = 0;
 #pragma unroll
-        for (int b = 0; b < NW; ++b) acc += Sy[b * NW + m] * in[b];
-        out[m] = acc;
+    for (int b = 0; b < NW; ++b) {
+        __builtin_amdgcn_sched_barrier(0);   // one mode row in flight at a time
+        T row[SP];
+        lds_row<SP>(&sS[1][b][0], row);
+#pragma unroll
+        for (int m = 0; m < NW; ++m) out[m] += row[m] * in[b];
     }
 #pragma unroll
     for (int m = 0; m < NW; ++m) buf[p0 + PW * (m + NW * p1)] = out[m];
@@ -1556,17 +1599,25 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
 #pragma unroll
         for (int c = 0; c < NW; ++c) in[c] = buf[p0 + PW * (p1 + NW * c)];
 #pragma unroll
-        for (int m = 0; m < NW; ++m) {
-            T acc = 0;
-#pragma unroll
-            for (int c = 0; c < NW; ++c) acc += Sz[c * NW + m] * in[c];
-            out[m] = (T)2 * acc / (lxy + cz * sl[2][m]);
-        }
+        for (int m = 0; m < NW; ++m) out[m] = 0;
 #pragma unroll
         for (int c = 0; c < NW; ++c) {
+            __builtin_amdgcn_sched_barrier(0);
+            T row[SP];
+            lds_row<SP>(&sS[2][c][0], row);
+#pragma unroll
+            for (int m = 0; m < NW; ++m) out[m] += row[m] * in[c];
+        }
+#pragma unroll
+        for (int m = 0; m < NW; ++m) out[m] = (T)2 * out[m] / (lxy + cz * sl[2][m]);
+#pragma unroll
+        for (int c = 0; c < NW; ++c) {
+            __builtin_amdgcn_sched_barrier(0);
+            T row[SP];
+            lds_row<SP>(&sS[2][c][0], row);
             T acc = 0;
 #pragma unroll
-            for (int m = 0; m < NW; ++m) acc += Sz[c * NW + m] * out[m];
+            for (int m = 0; m < NW; ++m) acc += row[m] * out[m];
             in[c] = acc;
         }
 #pragma unroll
@@ -1578,9 +1629,12 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
     for (int m = 0; m < NW; ++m) in[m] = buf[p0 + PW * (m + NW * p1)];
 #pragma unroll
     for (int b = 0; b < NW; ++b) {
+        __builtin_amdgcn_sched_barrier(0);   // one mode row in flight at a time
+        T row[SP];
+        lds_row<SP>(&sS[1][b][0], row);
         T acc = 0;
 #pragma unroll
-        for (int m = 0; m < NW; ++m) acc += Sy[b * NW + m] * in[m];
+        for (int m = 0; m < NW; ++m) acc += row[m] * in[m];
         out[b] = acc;
     }
 #pragma unroll
@@ -1592,10 +1646,14 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
     T *ue = u + (long)e * NW2 * NW + NW * (p0 + NW * p1);
 #pragma unroll
     for (int a = 0; a < NW; ++a) {
+        __builtin_amdgcn_sched_barrier(0);   // one mode row in flight at a time
+        T row[SP];
+        lds_row<SP>(&sS[0][a][0], row);
         T acc = 0;
 #pragma unroll
-        for (int m = 0; m < NW; ++m) acc += Sx[a * NW + m] * in[m];
+        for (int m = 0; m < NW; ++m) acc += row[m] * in[m];
         ue[a] = acc;
+    }
     }
 }
 
@@ -1640,7 +1698,7 @@ __global__ __launch_bounds__(NP *NP) void k_asm_gather(const T *__restrict__ r, 
         const int ex = e % box.nx, eyz = e / box.nx, ey = eyz % box.ny, ez = eyz / box.ny;
         const bool dir_xy = (i == 0 && ex == 0) || (i == N && ex == box.nx - 1) || (j == 0 && ey == 0) ||
                             (j == N && ey == box.ny - 1);
-        int exo[3], axo[3], eyo[3], ayo[3];
+        int exo[3] = {ex, ex, ex}, axo[3] = {1, 1, 1}, eyo[3] = {ey, ey, ey}, ayo[3] = {1, 1, 1};
         const int nx = win_cands<NP>(i, ex, box.nx, exo, axo);
         const int ny = win_cands<NP>(j, ey, box.ny, eyo, ayo);
         // coarse correction of the column: along x, then y, per z-layer of vertices
@@ -1657,36 +1715,67 @@ __global__ __launch_bounds__(NP *NP) void k_asm_gather(const T *__restrict__ r, 
         }
         const T *re = r + (long)e * NP3 + tid;
         T *ze = z + (long)e * NP3 + tid;
+        // every load of the column first: r, then for each (y, x) subdomain
+        // pair its column in the own z-layer and the two end nodes that the
+        // layers below and above contribute (pairs and layers that do not
+        // exist read the element's own window and are not added)
+        constexpr int CX = NP >= 4 ? 2 : 3;   // subdomains per direction holding a node
+        const bool zlo = ez > 0, zhi = ez < box.nz - 1;
+        const long zs = (long)box.nx * box.ny;
+        T rv[NP], own[CX * CX][NP], zl[CX * CX][2], zh[CX * CX][2];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) rv[k] = re[k * NP2];
+#pragma unroll
+        for (int qy = 0; qy < CX; ++qy)
+#pragma unroll
+            for (int qx = 0; qx < CX; ++qx) {
+                const bool ok = qy < ny && qx < nx;
+                const long eo = ok ? exo[qx] + (long)box.nx * (eyo[qy] + (long)box.ny * ez) : (long)e;
+                const T *uo = u + eo * NW3 + (ok ? axo[qx] + NW * ayo[qy] : 1 + NW);
+                const T *ul = zlo && ok ? uo - zs * NW3 : uo;
+                const T *uh = zhi && ok ? uo + zs * NW3 : uo;
+#pragma unroll
+                for (int k = 0; k < NP; ++k) own[qy * CX + qx][k] = uo[NW * NW * (k + 1)];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    zl[qy * CX + qx][q] = ul[NW * NW * (q + N + 1)];
+                    zh[qy * CX + qx][q] = uh[NW * NW * q];
+                }
+            }
+        const int mx = ((i == 0 && ex > 0) || (i == N && ex < box.nx - 1)) ? 2 : 1;
+        const int my = ((j == 0 && ey > 0) || (j == N && ey < box.ny - 1)) ? 2 : 1;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             double zv = 0.0;
             const bool dir = dir_xy || (k == 0 && ez == 0) || (k == N && ez == box.nz - 1);
             if (!dir) {
-                int ezo[3], azo[3];
-                const int nz = win_cands<NP>(k, ez, box.nz, ezo, azo);
+                // ascending element order: the layer below, the own layer, the layer above
                 double sm = 0.0;
+                if (k <= 1 && zlo) {
 #pragma unroll
-                for (int qz = 0; qz < 3; ++qz) {
-                    if (qz >= nz) break;
+                    for (int qy = 0; qy < CX; ++qy)
 #pragma unroll
-                    for (int qy = 0; qy < 3; ++qy) {
-                        if (qy >= ny) break;
+                        for (int qx = 0; qx < CX; ++qx)
+                            if (qy < ny && qx < nx) sm += (double)zl[qy * CX + qx][k];
+                }
 #pragma unroll
-                        for (int qx = 0; qx < 3; ++qx) {
-                            if (qx >= nx) break;
-                            const long eo = exo[qx] + (long)box.nx * (eyo[qy] + (long)box.ny * ezo[qz]);
-                            sm += (double)u[eo * NW3 + axo[qx] + NW * (ayo[qy] + NW * azo[qz])];
-                        }
-                    }
+                for (int qy = 0; qy < CX; ++qy)
+#pragma unroll
+                    for (int qx = 0; qx < CX; ++qx)
+                        if (qy < ny && qx < nx) sm += (double)own[qy * CX + qx][k];
+                if (k >= N - 1 && zhi) {
+#pragma unroll
+                    for (int qy = 0; qy < CX; ++qy)
+#pragma unroll
+                        for (int qx = 0; qx < CX; ++qx)
+                            if (qy < ny && qx < nx) sm += (double)zh[qy * CX + qx][k - (N - 1)];
                 }
                 zv = sm + (ell[k] * tz[0] + ell[NP + k] * tz[1]);
             }
             const T zt = (T)zv;
             ze[k * NP2] = zt;
-            const int mx = ((i == 0 && ex > 0) || (i == N && ex < box.nx - 1)) ? 2 : 1;
-            const int my = ((j == 0 && ey > 0) || (j == N && ey < box.ny - 1)) ? 2 : 1;
             const int mz = ((k == 0 && ez > 0) || (k == N && ez < box.nz - 1)) ? 2 : 1;
-            part += ((double)re[k * NP2] * (double)zt) * inv_mult(mx * my * mz);
+            part += ((double)rv[k] * (double)zt) * inv_mult(mx * my * mz);
         }
     }
     const double sum = block_sum<BS>(part, sbuf);

@@ -461,8 +461,11 @@ int read_scal(nek_ctx *c, Scal &h)
 template <typename IterFn> int run_cg(nek_ctx *c, int maxit, IterFn iter)
 {
     int launched = 0, pend = -1, slot = 0;
+    // Schwarz-preconditioned runs take a few iterations per refinement step:
+    // shorter chunks enqueue fewer iterations past the end of a run
+    const int chunk = c->precond == NEK_PC_SCHWARZ ? 4 : CHUNK_ITERS;
     while (launched < maxit) {
-        const int n = std::min(CHUNK_ITERS, maxit - launched);
+        const int n = std::min(chunk, maxit - launched);
         for (int q = 0; q < n; ++q) {
             int rc = iter(launched + q + 1, false);
             if (rc) return rc;

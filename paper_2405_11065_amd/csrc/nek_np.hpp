@@ -103,8 +103,9 @@ template <int NP> struct OpsImpl {
         }
         if (NP < 3 || !S || !L || !C || !U || !c->asmMom || !c->asmEc || !c->asmTmp) return NEK_E_ARG;
         const Scal *scp = step ? c->sc : nullptr;
-        hipLaunchKernelGGL((k_asm_local<NP, T>), dim3((unsigned)c->E), dim3(NW * NW), 0, c->stream, r, U, c->asmMom,
-                           S, L, C, c->asmEll, c->box, scp, it);
+        const unsigned lgrid = (unsigned)std::min<long>(c->E, 8L * num_cu());   // persistent
+        hipLaunchKernelGGL((k_asm_local<NP, T>), dim3(lgrid), dim3(NW * NW), 0, c->stream, r, U, c->asmMom, S, L, C,
+                           c->asmEll, c->box, (int)c->E, scp, it);
         HIP_TRY(hipGetLastError());
         int rc = asm_coarse_launch(c, scp, it);
         if (rc) return rc;
