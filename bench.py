@@ -582,10 +582,18 @@ def learned_case(torch, nsolves=10000, steps=2500, neval=16, data_tol=1e-10):
             "eval_per_problem": ev["per_problem"]}
 
 
-def profile_sequence(torch, nek, synth, variants="", geometry="stored"):
-    """A short sequence for counter collection (few dispatches); geometry
-    'trilinear' runs it with the factors recomputed in the kernels."""
-    ctx = nek.Context(NEL, N, prec="fp32")
+def profile_sequence(torch, nek, synth, variants="", geometry="stored", ne=16, precond="none"):
+    """A short sequence for counter collection (few dispatches): 40 mixed and
+    40 FP64 CG iterations (BF16-g mixed as well on the deformed mesh), then 5
+    nek_ax per precision and a 256 MiB copy for calibration.  ne = 16: the
+    16^3 N=9 box; ne = 32: the 32^3 N=9 deformed mesh.  geometry 'trilinear'
+    runs it with the factors recomputed in the kernels; precond selects the
+    solves' preconditioner (20 iterations each with 'schwarz')."""
+    nel = (ne, ne, ne)
+    vtx = None
+    if ne != 16:
+        vtx = synth.box_vertices(nel, hi=(1.0, 1.0, 1.0), perturb=0.1, seed=synth.SEED_C3_VERTICES)
+    ctx = nek.Context(nel, N, vtx=vtx, prec="fp32", precond=precond)
     ctx.set_geometry(geometry)
     chosen = dict(kv.split("=") for kv in variants.split(",") if kv)
     for prec in ("fp32", "fp64", "bf16g"):
@@ -596,9 +604,10 @@ def profile_sequence(torch, nek, synth, variants="", geometry="stored"):
     f = torch.from_numpy(synth.uniform_load(ctx.nl, SEED)).cuda()
     x = ctx.new_vector()
     out = {}
-    for prec in ("fp32", "fp64"):
+    its = 20 if precond == "schwarz" else 40
+    for prec in ("fp32", "fp64") + (("bf16g",) if ne != 16 else ()):
         ctx.set_prec(prec)
-        _, st, _ = ctx.cg_solve(f, tol=TOL, maxit=40, x=x)
+        _, st, _ = ctx.cg_solve(f, tol=TOL, maxit=its, x=x)
         out[prec] = st["iters"]
     for prec, dt in (("fp64", torch.float64), ("fp32", torch.float32), ("bf16g", torch.float32)):
         ctx.set_prec(prec)
@@ -612,7 +621,8 @@ def profile_sequence(torch, nek, synth, variants="", geometry="stored"):
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"profile_sequence": out, "geometry": geometry, "copy_bytes": a.numel() * 8,
+    print(json.dumps({"profile_sequence": out, "nel": ne, "local_points": ctx.nl, "geometry": geometry,
+                      "precond": precond, "copy_bytes": a.numel() * 8,
                       "variants": {p: ctx.get_variant(p) for p in ("fp32", "fp64", "bf16g")}}), flush=True)
     ctx.close()
 
@@ -665,6 +675,10 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short fixed sequence for hardware-counter runs: 40 mixed and 40 FP64 CG iterations, "
                          "5 nek_ax per precision and a 256 MiB copy for calibration")
+    ap.add_argument("--profile-ne", type=int, default=16, choices=(16, 32),
+                    help="with --profile: the 16^3 box or the 32^3 deformed mesh (N=9)")
+    ap.add_argument("--precond", default="none", choices=("none", "jacobi", "fdm", "schwarz"),
+                    help="with --profile: preconditioner of the profiled solves")
     ap.add_argument("--profile-ax", type=int, default=0, metavar="NE",
                     help="short nek_ax sequence on the NE^3 deformed N=9 mesh (5 calls per precision) and a "
                          "256 MiB copy, for counter runs of the operator and assembly passes")
@@ -684,7 +698,7 @@ def main():
     torch.cuda.set_device(0)
 
     if args.profile:
-        return profile_sequence(torch, nek, synth, args.variants, args.geometry)
+        return profile_sequence(torch, nek, synth, args.variants, args.geometry, args.profile_ne, args.precond)
     if args.profile_ax:
         return profile_ax(torch, nek, synth, args.profile_ax, args.variants)
 
