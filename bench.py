@@ -554,6 +554,59 @@ def batch_case(torch, nek, synth, nprob=64, steps=1):
     return out
 
 
+def multi_rhs_case(torch, nek, synth, nrhs=(4, 8), steps=2):
+    """Many right-hand sides on the headline mesh (16^3 box, N=9): K problems
+    with f ~ U[0,1) seeds 2, 3, ... on one mesh form a batch whose members
+    share the set-up data and the persistent grid and run interleaved
+    (nek_setup_batch); one batched mixed solve per step, against the K solves
+    one after another on a standalone context.  Each member's own solve (on
+    its share of the grid) must reproduce its batched x bit for bit."""
+    out = {}
+    for K in nrhs:
+        b = nek.Batch([{"nel": NEL, "N": N}] * K, prec="fp32")
+        assert all(b.mesh_of(i) == 0 for i in range(K))
+        tuned = b.tune("fp32", iters=10)
+        fs = [torch.from_numpy(synth.uniform_load(b.nl[i], SEED + i)).cuda() for i in range(K)]
+        xs = [torch.empty(b.nl[i], dtype=torch.float64, device="cuda") for i in range(K)]
+        b.solve(fs, tol=TOL, maxit=20000, xs=xs, raise_on_noconv=True)   # warm-up (records the graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st, _ = b.solve(fs, tol=TOL, maxit=20000, xs=xs, raise_on_noconv=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        work = sum(b.nl[i] * st[i]["iters"] for i in range(K))
+        x1 = torch.empty(b.nl[0], dtype=torch.float64, device="cuda")
+        # bit-identity: each member's own solve (on its share of the grid)
+        same = True
+        for i in range(K):
+            _, s1, _ = b.ctx[i].cg_solve(fs[i], tol=TOL, maxit=20000, x=x1, raise_on_noconv=True)
+            same &= s1["iters"] == st[i]["iters"] and bool(torch.equal(x1, xs[i]))
+        # baseline: the K solves one after another on a standalone context
+        # (full persistent grid, autotuned at its first solve)
+        solo = nek.Context(NEL, N, prec="fp32")
+        solo.cg_solve(fs[0], tol=TOL, maxit=20000, x=x1, raise_on_noconv=True)   # tunes, warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(K):
+            solo.cg_solve(fs[i], tol=TOL, maxit=20000, x=x1, raise_on_noconv=True)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        solo.close()
+        out[f"K{K}"] = {"ms_per_batch": round(dt * 1e3, 2), "ms_per_rhs": round(dt * 1e3 / K, 2),
+                        "GDOF_iter_per_s": round(work / dt / 1e9, 3), "ms_sequential": round(t_seq * 1e3, 2),
+                        "speedup_vs_sequential": round(t_seq / dt, 3), "bit_identical_to_solo": same,
+                        "iters": [s["iters"] for s in st], "max_true_rel_res": max(s["true_rel_res"] for s in st),
+                        "tuned_variant": tuned[N][0]}
+        log(f"multi-rhs K={K}: {out[f'K{K}']}")
+        for c in b.ctx:
+            c.close()
+        b.close()
+        del fs, xs, x1
+        torch.cuda.empty_cache()
+    return out
+
+
 def learned_case(torch, nsolves=10000, steps=2500, neval=16, data_tol=1e-10):
     """Learned initial guess: 10,000 FP64 solves (to 1e-10) on 8^3-element
     N=7 meshes of [0,1]^3 (+-10 % interior vertex moves, 64 distinct meshes)
@@ -665,7 +718,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-big", action="store_true", help="skip the 32^3 deformed-mesh BF16 measurement")
-    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched solve")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-problem batched solve and the many-right-hand-side batches")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned initial guess (data, training, eval)")
     ap.add_argument("--no-energy", action="store_true", help="skip the energy-to-solution measurement")
     ap.add_argument("--no-jacobi", action="store_true",
@@ -781,6 +835,7 @@ def main():
     big = None if args.no_big else big_case(torch, nek, synth, energy=not args.no_energy, jacobi=not args.no_jacobi)
     log("32^3 case done")
     batch = None if args.no_batch else batch_case(torch, nek, synth)
+    multi = None if args.no_batch else multi_rhs_case(torch, nek, synth)
     learned = None if args.no_learned else learned_case(torch)
 
     bpp = cg_operator_bytes_per_point(4, 4, 8)   # FP32 vectors and g, FP64 inner correction
@@ -831,6 +886,7 @@ def main():
         "cpu_baseline": cpu,
         "deformed_32x32x32_N9": big,
         "batch_64": batch,
+        "multi_rhs_16x16x16_N9": multi,
         "learned_x0": learned,
     }
     ctx.close()

@@ -406,6 +406,16 @@ typedef struct nek_batch nek_batch;
  * configuration), -1 keeps the defaults.  Member contexts take the batch's
  * configuration and do not tune on their own.  Errors as nek_setup (nothing
  * is left allocated).
+ *
+ * Many right-hand sides on one mesh: a problem whose order and mesh repeat
+ * an earlier problem's (equal nel and, with vtx NULL, equal lo and hi, else
+ * identical vertex values) shares that problem's set-up data on the device
+ * (geometric factors in every precision, D, mass, maps) instead of holding
+ * a copy, and its context reads them from there.  In the batched solve the
+ * workgroups of the problems on one mesh are interleaved block by block on
+ * the same XCD, so that their reads of the shared factors are served by
+ * that XCD's L2 after the first.  Results are bit-identical to separate
+ * meshes (the kernels and their summation order do not change).
  */
 int nek_setup_batch(int nprob, const nek_mesh *meshes, const int *N, const nek_opts *opts, void *stream,
                     nek_batch **out);
@@ -424,6 +434,13 @@ int nek_batch_size(const nek_batch *batch);
  * stream reads their output.
  */
 int nek_batch_ctx(nek_batch *batch, int i, nek_ctx **out);
+
+/*
+ * nek_batch_mesh_of -- index of the problem whose set-up data problem i
+ * uses (i itself when it holds its own; an earlier problem on the same mesh
+ * and order otherwise), or NEK_E_ARG.
+ */
+int nek_batch_mesh_of(const nek_batch *batch, int i);
 
 /*
  * nek_batch_orders -- number of distinct orders in the batch; N_out (may be

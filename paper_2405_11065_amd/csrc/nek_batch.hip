@@ -1,9 +1,13 @@
 // libnek batches: many independent box problems (each its own mesh and
-// order) solved together.  Every problem keeps a full context; a device
-// table per order lets one launch of the operator kernel and one of the
-// gather/update kernel advance every problem of that order by one CG
-// iteration, each workgroup running the solo kernel body on its problem's
-// share.  A chunk of iterations for all orders (one stream per order, forked
+// order, or many right-hand sides on one mesh) solved together.  Every
+// problem keeps a context of its own; problems whose mesh and order repeat
+// an earlier problem's share its set-up data (geometric factors, D, mass,
+// maps) instead of holding a copy.  A device table per order lets one
+// launch of the operator kernel and one of the gather/update kernel advance
+// every problem of that order by one CG iteration, each workgroup running
+// the solo kernel body on its problem's share; the shares of problems on
+// one mesh are interleaved block by block on the same XCD, so that the
+// factors one of them streams are still in that XCD's L2 for the others.  A chunk of iterations for all orders (one stream per order, forked
 // and joined by events) is recorded once as a HIP graph and replayed; the
 // iteration number comes from a device counter the graph advances, so the
 // same graph serves every chunk of every run.
@@ -12,7 +16,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "nek.h"
@@ -29,12 +35,12 @@ struct Group {
     int variant[3] = {0, 0, 0};        // per nek_prec
     BatchProb *dtab = nullptr;         // device table, one entry per member
     BatchProb *htab = nullptr;         // pinned staging of the table
-    int *downer = nullptr;             // device map workgroup -> member (-1: none)
+    int2 *downer = nullptr;            // device map workgroup -> (member, block); member -1: none
     long owner_cap = 0;
     int layout_v = -1;                 // variant and members the layout below was built for
     std::vector<char> layout_act;
     unsigned grid = 0;
-    std::vector<int> blk0, nblk, ngroups;
+    std::vector<int> nblk, ngroups;
     bool active = false;               // some member takes part in the current run
     hipStream_t s = nullptr;
     hipEvent_t join = nullptr;
@@ -45,6 +51,7 @@ struct Group {
 
 struct nek_batch {
     std::vector<nek_ctx *> ctx;
+    std::vector<int> root;             // problem whose set-up data problem i uses (i itself if its own)
     std::vector<int> group_of;
     std::vector<Group> groups;
     hipStream_t stream = nullptr;      // owned; every member context runs on it
@@ -68,9 +75,30 @@ namespace {
 
 int nprob(const nek_batch *b) { return (int)b->ctx.size(); }
 
-// Workgroup ranges of the group's members taking part in a run (act) under
-// variant v: each gets exactly the grid of its solo launch, starting at a
-// multiple of 8; the others get none.
+// The same mesh: equal element counts and, for a uniform lattice, equal box
+// corners, else the same vertex values (an identical pointer or content).
+bool same_mesh(const nek_mesh &a, const nek_mesh &b)
+{
+    for (int d = 0; d < 3; ++d)
+        if (a.nel[d] != b.nel[d]) return false;
+    if (!a.vtx || !b.vtx) {
+        if (a.vtx || b.vtx) return false;
+        for (int d = 0; d < 3; ++d)
+            if (a.lo[d] != b.lo[d] || a.hi[d] != b.hi[d]) return false;
+        return true;
+    }
+    const size_t nv = 3 * (size_t)(a.nel[0] + 1) * (a.nel[1] + 1) * (a.nel[2] + 1);
+    return a.vtx == b.vtx || std::memcmp(a.vtx, b.vtx, nv * sizeof(double)) == 0;
+}
+
+// Workgroups of the group's members taking part in a run (act) under
+// variant v: each gets exactly the grid of its solo launch; the others get
+// none.  The active members on one mesh form a set of K, laid out from a
+// multiple of 8: block j of the set's i-th member at
+//     8 K floor(j / 8) + 8 i + (j mod 8),
+// so block j of every member lands on XCD j mod 8, as in a solo launch, and
+// the K blocks that walk the same elements are dispatched together.  Sets
+// follow one another in the order of their first member.
 int layout(nek_batch *b, Group &G, int v, const std::vector<char> &act)
 {
     const size_t n = G.members.size();
@@ -79,31 +107,46 @@ int layout(nek_batch *b, Group &G, int v, const std::vector<char> &act)
     if (G.layout_v == v && G.layout_act == ga) return NEK_OK;
     const int epw = np_ops(G.NP)->variant_epw(v);
     if (epw <= 0) return NEK_E_ARG;
-    G.blk0.assign(n, 0);
     G.nblk.assign(n, 0);
     G.ngroups.assign(n, 0);
-    long blk = 0;
+    std::vector<std::vector<int>> sets;   // member positions q, by mesh
+    std::vector<int> set_root;
     for (size_t q = 0; q < n; ++q) {
         const nek_ctx *c = b->ctx[G.members[q]];
-        blk = (blk + 7) / 8 * 8;
-        G.blk0[q] = (int)blk;
         G.ngroups[q] = ax_groups(c, epw);
-        G.nblk[q] = ga[q] ? (int)ax_grid(c, epw, 0) : 0;   // batches read stored factors
-        blk += G.nblk[q];
+        if (!ga[q]) continue;
+        G.nblk[q] = (int)ax_grid(c, epw, 0);   // batches read stored factors
+        const int r = b->root[G.members[q]];
+        size_t k = 0;
+        while (k < sets.size() && set_root[k] != r) ++k;
+        if (k == sets.size()) {
+            sets.emplace_back();
+            set_root.push_back(r);
+        }
+        sets[k].push_back((int)q);
+    }
+    long blk = 0;
+    std::vector<std::pair<long, int2>> place;
+    for (const auto &S : sets) {
+        const long K = (long)S.size(), nb = G.nblk[S[0]];   // one mesh: one grid size
+        blk = (blk + 7) / 8 * 8;
+        for (long i = 0; i < K; ++i)
+            for (long j = 0; j < nb; ++j)
+                place.push_back({blk + 8 * K * (j / 8) + 8 * i + (j % 8), make_int2(S[i], (int)j)});
+        blk += 8 * K * ((nb + 7) / 8);
     }
     if (blk >= (1L << 31)) return NEK_E_ARG;
     blk = std::max(blk, 1L);
     G.grid = (unsigned)blk;
-    std::vector<int> owner(blk, -1);
-    for (size_t q = 0; q < n; ++q)
-        for (int k = 0; k < G.nblk[q]; ++k) owner[G.blk0[q] + k] = (int)q;
+    std::vector<int2> owner(blk, make_int2(-1, 0));
+    for (const auto &pl : place) owner[pl.first] = pl.second;
     if (blk > G.owner_cap) {
         dfree(G.downer);
         if (dalloc(G.downer, blk)) return NEK_E_OOM;
         G.owner_cap = blk;
     }
     HIP_TRY(hipStreamSynchronize(b->stream));
-    HIP_TRY(hipMemcpy(G.downer, owner.data(), blk * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(G.downer, owner.data(), blk * sizeof(int2), hipMemcpyHostToDevice));
     G.layout_v = v;
     G.layout_act = ga;
     return NEK_OK;
@@ -211,7 +254,6 @@ int run_batch(nek_batch *b, int prec, const std::vector<char> &act, const std::v
             P.box = c->box;
             P.E = (int)c->E;
             P.ngroups = G.ngroups[q];
-            P.blk0 = G.blk0[q];
             P.nblk = G.nblk[q];
             P.active = act[m] ? 1 : 0;
             if (act[m] && (!P.r || !P.p || !P.w || !P.g || !P.x)) return NEK_E_ARG;
@@ -378,7 +420,8 @@ void nek_batch_free(nek_batch *b)
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
-    for (nek_ctx *c : b->ctx) nek_free(c);
+    // sharers before the owners of their set-up data
+    for (size_t m = b->ctx.size(); m-- > 0;) nek_free(b->ctx[m]);
     for (auto &G : b->groups) {
         dfree(G.dtab);
         dfree(G.downer);
@@ -414,13 +457,29 @@ int nek_setup_batch(int n, const nek_mesh *meshes, const int *N, const nek_opts 
         hipStreamWaitEvent(b->stream, b->entry, 0) != hipSuccess)
         return fail(NEK_E_HIP);
     b->ctx.assign(n, nullptr);
+    b->root.assign(n, 0);
     b->epw_opt = opts ? opts->elts_per_wg : 0;
     for (int m = 0; m < n; ++m) {
-        const int rc = nek_setup(&meshes[m], N[m], opts, b->stream, &b->ctx[m]);
+        int k = 0;
+        while (k < m && !(b->root[k] == k && N[k] == N[m] && same_mesh(meshes[k], meshes[m]))) ++k;
+        b->root[m] = k;
+        const int rc = k < m ? setup_shared(b->ctx[k], opts, b->stream, &b->ctx[m])
+                             : nek_setup(&meshes[m], N[m], opts, b->stream, &b->ctx[m]);
         if (rc) return fail(rc);
         // members follow the batch's configuration and never tune alone
         b->ctx[m]->batch_member = true;
         for (int q = 0; q < 3; ++q) b->ctx[m]->tuned[q] = true;
+    }
+    // The K problems on one mesh share the persistent grid of one solo
+    // launch: each gets 1/K of it (never less than its element groups allow),
+    // so their K blocks per XCD slot run in one round, with the factors of an
+    // element group read from HBM once and from L2 by the others.  Each
+    // member context keeps that grid for its own solves too, which therefore
+    // reproduce its batched result bit for bit.
+    for (int m = 0; m < n; ++m) {
+        int K = 0;
+        for (int k = 0; k < n; ++k) K += b->root[k] == b->root[m];
+        if (K > 1) b->ctx[m]->ax_wg = (int)((8L * num_cu() + K - 1) / K);
     }
     b->group_of.assign(n, -1);
     for (int NP = 2; NP <= MAX_NP; ++NP) {
@@ -467,6 +526,12 @@ int nek_batch_ctx(nek_batch *b, int i, nek_ctx **out)
     if (!b || !out || i < 0 || i >= nprob(b)) return NEK_E_ARG;
     *out = b->ctx[i];
     return NEK_OK;
+}
+
+int nek_batch_mesh_of(const nek_batch *b, int i)
+{
+    if (!b || i < 0 || i >= nprob(b)) return NEK_E_ARG;
+    return b->root[i];
 }
 
 int nek_batch_set_variant(nek_batch *b, int prec, int N, int variant)

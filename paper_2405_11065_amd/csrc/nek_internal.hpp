@@ -101,7 +101,13 @@ struct nek_ctx {
     int variant[3] = {0, 0, 0};   // CG kernel configuration per precision (nek_tune)
     bool tuned[3] = {false, false, false};   // configuration fixed (else the next solve autotunes)
     int max_wg = 0;               // cap on persistent / reduction workgroups (0: default)
+    int ax_wg = 0;                // cap on the CG kernels' persistent grid alone (0: none): a batch
+                                  // divides the grid among the problems on one mesh
     bool batch_member = false;    // owned by a batch, which lays out its grid once
+    // set-up data borrowed from another context of the same mesh and order
+    // (batch members with identical meshes): D*, g*, B and the segment maps
+    // point into mesh_owner's buffers, which outlive this context
+    nek_ctx *mesh_owner = nullptr;
     void *noalloc_scratch = nullptr;   // this device's static scratch of nek_ax_noalloc
 
     std::vector<double> xi, w, D, vtx;
@@ -202,6 +208,7 @@ inline unsigned ax_grid(const nek_ctx *c, int epw, int vbytes)
     // groups (16^3 N=9 CG: 105 -> 95 us per iteration; FP32 is slower so)
     const bool half = c->geom == NEK_GSRC_TRILINEAR && vbytes == 8;
     long cap = std::min<long>(MAXB, c->max_wg > 0 ? (long)c->max_wg : (half ? 4L : 8L) * num_cu());
+    if (c->ax_wg > 0) cap = std::min<long>(cap, c->ax_wg);
     return (unsigned)std::max<long>(1, std::min(want, cap));
 }
 
@@ -255,7 +262,7 @@ struct NpOps {
     // (operator, then gather/update unless final) on stream s; with prepare
     // set, only configures the kernels (call before any graph capture).
     // x64: the iterates of 4-byte runs are FP64 corrections.
-    int (*batch_iter)(hipStream_t s, int prec, int variant, bool x64, const BatchProb *tab, const int *owner,
+    int (*batch_iter)(hipStream_t s, int prec, int variant, bool x64, const BatchProb *tab, const int2 *owner,
                       unsigned grid, const void *D, int it_local, const int *base, bool final, bool prepare);
 };
 
@@ -266,6 +273,9 @@ const NpOps *ops(const nek_ctx *c);
 
 int ensure_hist(nek_ctx *c, long need);
 int ensure_g(nek_ctx *c, int prec);
+// A context on owner's mesh and order that shares its read-only set-up data
+// (the options validated as nek_setup does); its own CG state and vectors.
+int setup_shared(nek_ctx *owner, const nek_opts *opts, void *stream, nek_ctx **out);
 int ensure_fp64_work(nek_ctx *c);
 int ensure_mixed_work(nek_ctx *c);
 int fill_f64(nek_ctx *c, double *p, double v, unsigned long n);

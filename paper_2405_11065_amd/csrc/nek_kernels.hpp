@@ -1146,9 +1146,12 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_cg_update(T *__restrict__ r, co
 // ------------------------------------------------------------- batched CG
 
 // One problem of a batch: its vectors (element type fixed by the launch), its
-// factors, CG state and partials, and the range [blk0, blk0 + nblk) of the
-// batched grid that works on it.  blk0 is a multiple of 8, so each workgroup
-// runs on the same XCD as the workgroup of the same index in a solo launch.
+// factors, CG state and partials, and the size nblk of its share of the
+// batched grid.  The launch's owner map gives each workgroup its problem and
+// its block index within that share; block j sits at a grid index congruent
+// to j mod 8, so it runs on the same XCD as block j of a solo launch, and
+// the blocks j of problems that share one mesh sit next to each other, so
+// their reads of the same factors meet in that XCD's L2.
 struct BatchProb {
     void *r, *p, *w;       // residual, search direction, A_L p (T)
     const void *g;         // geometric factors (GT)
@@ -1157,7 +1160,7 @@ struct BatchProb {
     double *partials;      // pAp by parity, then rtr by parity (MAXB each)
     double *hist;
     Box box;
-    int E, ngroups, blk0, nblk, active;
+    int E, ngroups, nblk, active;
 };
 
 // Iteration number of a batched launch: the chunk base kept on the device
@@ -1166,35 +1169,36 @@ struct BatchProb {
 __device__ __forceinline__ int batch_it(const int *__restrict__ base, int it_local) { return *base + it_local; }
 
 // The operator kernel of every problem of one order in one launch: workgroup
-// b runs the solo body as workgroup b - blk0 of its problem.
+// b runs the solo body as block owner[b].y of problem owner[b].x (none if
+// owner[b].x < 0).
 template <int NP, int EPW, int PD, typename T, typename GT, typename XT>
 __global__ __launch_bounds__(EPW *NP *NP) void k_ax_batch(const BatchProb *__restrict__ tab,
-                                                          const int *__restrict__ owner, const T *__restrict__ D,
+                                                          const int2 *__restrict__ owner, const T *__restrict__ D,
                                                           int it_local, const int *__restrict__ base)
 {
-    const int q = owner[blockIdx.x];
-    if (q < 0) return;
-    const BatchProb P = tab[q];
+    const int2 o = owner[blockIdx.x];
+    if (o.x < 0) return;
+    const BatchProb P = tab[o.x];
     if (!P.active) return;
     const int it = batch_it(base, it_local);
     ax_body<NP, EPW, PD, T, GT, true, XT>(
         (const T *)P.r, (T *)P.p, (T *)P.w, (const GT *)P.g, D, (XT *)P.x, P.sc, P.partials + (it & 1) * MAXB,
         P.partials + ((it - 1) & 1) * MAXB, P.partials + (2 + ((it - 1) & 1)) * MAXB, P.nblk, it, P.hist, P.E,
-        P.ngroups, blockIdx.x - P.blk0, P.nblk);
+        P.ngroups, (unsigned)o.y, P.nblk);
 }
 
 template <int NP, int EPW, typename T>
 __global__ __launch_bounds__(EPW *NP *NP) void k_cg_update_batch(const BatchProb *__restrict__ tab,
-                                                                 const int *__restrict__ owner, int it_local,
+                                                                 const int2 *__restrict__ owner, int it_local,
                                                                  const int *__restrict__ base)
 {
-    const int q = owner[blockIdx.x];
-    if (q < 0) return;
-    const BatchProb P = tab[q];
+    const int2 o = owner[blockIdx.x];
+    if (o.x < 0) return;
+    const BatchProb P = tab[o.x];
     if (!P.active) return;
     const int it = batch_it(base, it_local);
     upd_body<NP, EPW, T>((T *)P.r, (const T *)P.w, P.sc, P.partials + (it & 1) * MAXB, P.nblk,
-                         P.partials + (2 + (it & 1)) * MAXB, it, P.box, P.E, P.ngroups, blockIdx.x - P.blk0, P.nblk);
+                         P.partials + (2 + (it & 1)) * MAXB, it, P.box, P.E, P.ngroups, (unsigned)o.y, P.nblk);
 }
 
 // out = M o sum over copies of (c o) in: the right-hand side b = M dssum(f)

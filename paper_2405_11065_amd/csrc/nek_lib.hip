@@ -151,6 +151,12 @@ int ensure_hist(nek_ctx *c, long need)
 
 int ensure_g(nek_ctx *c, int prec)
 {
+    if (nek_ctx *o = c->mesh_owner) {
+        const int rc = ensure_g(o, prec);
+        c->g32 = o->g32;
+        c->g16 = o->g16;
+        return rc;
+    }
     const unsigned long n = (unsigned long)c->E * 6 * c->NP * c->NP * c->NP;
     const int grid = 4 * num_cu();
     if (prec == NEK_PREC_FP32 && !c->g32) {
@@ -737,6 +743,102 @@ void points_to_planes(const double *src, double *dst, long E, long n3)
             for (int f = 0; f < 6; ++f) dst[(e * 6 + f) * n3 + q] = src[(e * n3 + q) * 6 + f];
 }
 
+namespace {
+
+// Options check shared by nek_setup and setup_shared; *v_epw receives the
+// kernel configuration that opts->elts_per_wg selects (0 if none).
+int check_opts(int N, const nek_opts *opts, int *v_epw)
+{
+    *v_epw = 0;
+    if (opts && (opts->prec < NEK_PREC_FP64 || opts->prec > NEK_PREC_BF16G || opts->elts_per_wg < -1 ||
+                 opts->precond < NEK_PC_NONE || opts->precond > NEK_PC_SCHWARZ || opts->corr_fp32 < 0 ||
+                 opts->corr_fp32 > 1))
+        return NEK_E_ARG;
+    if (opts && opts->elts_per_wg > 0 && (*v_epw = variant_for_epw(N + 1, opts->elts_per_wg)) < 0) return NEK_E_ARG;
+    return NEK_OK;
+}
+
+void set_opts(nek_ctx *c, const nek_opts *opts, int v_epw)
+{
+    if (opts) c->opts = *opts;
+    c->prec = c->opts.prec;
+    if (c->opts.elts_per_wg != 0)
+        for (int q = 0; q < 3; ++q) {
+            c->variant[q] = v_epw;
+            c->tuned[q] = true;
+        }
+}
+
+// Per-context CG state: scalars, partials, the pinned done flag and its
+// events, the static scratch address, g in the solve precision and the
+// preconditioner.  Synchronises.
+int setup_state(nek_ctx *c)
+{
+    int rc;
+    if (dalloc(c->sc, 1) || dalloc(c->partials, 7 * MAXB)) return NEK_E_OOM;
+    if (hipHostMalloc((void **)&c->hflags, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) return NEK_E_OOM;
+    c->hflags[0] = c->hflags[1] = 0;
+    int *hflag_dev = nullptr;
+    if (hipHostGetDevicePointer((void **)&hflag_dev, c->hflags, 0) != hipSuccess) return NEK_E_HIP;
+    for (auto &e : c->ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return NEK_E_HIP;
+    if (hipMemset(c->sc, 0, sizeof(Scal)) != hipSuccess ||
+        hipMemcpy(&c->sc->host_done, &hflag_dev, sizeof(int *), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(c->partials, 0, 7 * MAXB * sizeof(double)) != hipSuccess)
+        return NEK_E_HIP;
+    if ((rc = noalloc_scratch_ptr(&c->noalloc_scratch))) return rc;
+    if ((rc = ensure_g(c, c->prec))) return rc;
+    if (c->opts.precond != NEK_PC_NONE) {
+        if ((rc = ensure_precond(c, c->opts.precond))) return rc;
+        c->precond = c->opts.precond;
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return NEK_E_HIP;
+    return NEK_OK;
+}
+
+}  // namespace
+
+int setup_shared(nek_ctx *owner, const nek_opts *opts, void *stream, nek_ctx **out)
+{
+    if (!owner || !out || owner->mesh_owner) return NEK_E_ARG;
+    *out = nullptr;
+    int v_epw = 0, rc;
+    if ((rc = check_opts(owner->N, opts, &v_epw))) return rc;
+    nek_ctx *c = new (std::nothrow) nek_ctx;
+    if (!c) return NEK_E_OOM;
+    c->N = owner->N;
+    c->NP = owner->NP;
+    for (int d = 0; d < 3; ++d) c->nel[d] = owner->nel[d];
+    c->box = owner->box;
+    c->E = owner->E;
+    c->nl = owner->nl;
+    c->ng = owner->ng;
+    c->nperm = owner->nperm;
+    c->nseg = owner->nseg;
+    c->stream = (hipStream_t)stream;
+    set_opts(c, opts, v_epw);
+    c->xi = owner->xi;
+    c->w = owner->w;
+    c->D = owner->D;
+    c->vtx = owner->vtx;
+    c->mesh_owner = owner;
+    c->D64 = owner->D64;
+    c->D32 = owner->D32;
+    c->g64 = owner->g64;
+    c->g32 = owner->g32;
+    c->g16 = owner->g16;
+    c->B = owner->B;
+    c->perm = owner->perm;
+    c->segptr = owner->segptr;
+    c->segflag = owner->segflag;
+    if ((rc = setup_state(c))) {
+        nek_free(c);
+        return rc;
+    }
+    *out = c;
+    return NEK_OK;
+}
+
 }  // namespace nek
 
 extern "C" {
@@ -762,6 +864,10 @@ void nek_free(nek_ctx *c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->mesh_owner) {   // borrowed set-up data stays with its owner
+        c->D64 = nullptr; c->D32 = nullptr; c->g64 = nullptr; c->g32 = nullptr; c->g16 = nullptr;
+        c->B = nullptr; c->perm = nullptr; c->segptr = nullptr; c->segflag = nullptr;
+    }
     dfree(c->D64); dfree(c->D32); dfree(c->g64); dfree(c->g32); dfree(c->g16); dfree(c->tri64); dfree(c->tri32); dfree(c->B);
     dfree(c->perm); dfree(c->segptr); dfree(c->segflag); dfree(c->sc); dfree(c->partials); dfree(c->hist);
     dfree(c->b); dfree(c->r64); dfree(c->p64); dfree(c->w64); dfree(c->d64); dfree(c->d32);
@@ -778,6 +884,7 @@ void nek_free(nek_ctx *c)
     delete c;
 }
 
+
 int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, nek_ctx **out)
 {
     if (!mesh || !out || N < 1 || N + 1 > MAX_NP) return NEK_E_ARG;
@@ -787,12 +894,8 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
     const long NP = N + 1, n3 = NP * NP * NP;
     const long E = (long)mesh->nel[0] * mesh->nel[1] * mesh->nel[2];
     if (E * n3 >= (1L << 31)) return NEK_E_ARG;
-    if (opts && (opts->prec < NEK_PREC_FP64 || opts->prec > NEK_PREC_BF16G || opts->elts_per_wg < -1 ||
-                 opts->precond < NEK_PC_NONE || opts->precond > NEK_PC_SCHWARZ || opts->corr_fp32 < 0 ||
-                 opts->corr_fp32 > 1))
-        return NEK_E_ARG;
     int v_epw = 0;
-    if (opts && opts->elts_per_wg > 0 && (v_epw = variant_for_epw(N + 1, opts->elts_per_wg)) < 0) return NEK_E_ARG;
+    if (const int rc0 = check_opts(N, opts, &v_epw)) return rc0;
     nek_ctx *c = new (std::nothrow) nek_ctx;
     if (!c) return NEK_E_OOM;
     c->N = N;
@@ -803,13 +906,7 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
     c->nl = E * n3;
     c->ng = ((long)mesh->nel[0] * N + 1) * ((long)mesh->nel[1] * N + 1) * ((long)mesh->nel[2] * N + 1);
     c->stream = (hipStream_t)stream;
-    if (opts) c->opts = *opts;
-    c->prec = c->opts.prec;
-    if (c->opts.elts_per_wg != 0)
-        for (int q = 0; q < 3; ++q) {
-            c->variant[q] = v_epw;
-            c->tuned[q] = true;
-        }
+    set_opts(c, opts, v_epw);
 
     gll_rule(N, c->xi, c->w);
     deriv_matrix(c->xi, c->D);
@@ -835,15 +932,8 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
     std::vector<float> D32(c->D.begin(), c->D.end());
 
     if (dalloc(c->D64, NP * NP) || dalloc(c->D32, NP * NP) || dalloc(c->g64, hg.size()) || dalloc(c->B, hB.size()) ||
-        dalloc(c->perm, perm.size()) || dalloc(c->segptr, segptr.size()) || dalloc(c->segflag, segflag.size()) ||
-        dalloc(c->sc, 1) || dalloc(c->partials, 7 * MAXB))
+        dalloc(c->perm, perm.size()) || dalloc(c->segptr, segptr.size()) || dalloc(c->segflag, segflag.size()))
         return fail(NEK_E_OOM);
-    if (hipHostMalloc((void **)&c->hflags, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) return fail(NEK_E_OOM);
-    c->hflags[0] = c->hflags[1] = 0;
-    int *hflag_dev = nullptr;
-    if (hipHostGetDevicePointer((void **)&hflag_dev, c->hflags, 0) != hipSuccess) return fail(NEK_E_HIP);
-    for (auto &e : c->ev)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(NEK_E_HIP);
     // synchronous uploads: the host staging vectors die at return
     if (hipMemcpy(c->D64, c->D.data(), NP * NP * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->D32, D32.data(), NP * NP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
@@ -851,18 +941,9 @@ int nek_setup(const nek_mesh *mesh, int N, const nek_opts *opts, void *stream, n
         hipMemcpy(c->B, hB.data(), hB.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->perm, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->segptr, segptr.data(), segptr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->segflag, segflag.data(), segflag.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(c->sc, 0, sizeof(Scal)) != hipSuccess ||
-        hipMemcpy(&c->sc->host_done, &hflag_dev, sizeof(int *), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(c->partials, 0, 7 * MAXB * sizeof(double)) != hipSuccess)
+        hipMemcpy(c->segflag, segflag.data(), segflag.size(), hipMemcpyHostToDevice) != hipSuccess)
         return fail(NEK_E_HIP);
-    if ((rc = noalloc_scratch_ptr(&c->noalloc_scratch))) return fail(rc);
-    if ((rc = ensure_g(c, c->prec))) return fail(rc);
-    if (c->opts.precond != NEK_PC_NONE) {
-        if ((rc = ensure_precond(c, c->opts.precond))) return fail(rc);
-        c->precond = c->opts.precond;
-    }
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(NEK_E_HIP);
+    if ((rc = setup_state(c))) return fail(rc);
     *out = c;
     return NEK_OK;
 }

@@ -329,7 +329,7 @@ template <int NP> struct OpsImpl {
     }
 
     template <typename T, typename GT, typename XT>
-    static int batch_iter_t(hipStream_t s, int v, const BatchProb *tab, const int *owner, unsigned grid, const T *D,
+    static int batch_iter_t(hipStream_t s, int v, const BatchProb *tab, const int2 *owner, unsigned grid, const T *D,
                             int it_local, const int *base, bool final, bool prepare)
     {
         return with_variant<NP, GT>(v, [&](auto epw_c, auto pd_c) -> int {
@@ -353,7 +353,7 @@ template <int NP> struct OpsImpl {
         });
     }
 
-    static int batch_iter(hipStream_t s, int prec, int v, bool x64, const BatchProb *tab, const int *owner,
+    static int batch_iter(hipStream_t s, int prec, int v, bool x64, const BatchProb *tab, const int2 *owner,
                           unsigned grid, const void *D, int it_local, const int *base, bool final, bool prepare)
     {
         const float *D32 = (const float *)D;

@@ -36,7 +36,7 @@ EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_
            "nek_set_max_workgroups", "nek_precond_apply", "nek_ax_local", "nek_ax", "nek_ax_noalloc",
            "nek_dssum", "nek_glsc3", "nek_cg_solve", "nek_prof_enable", "nek_prof_read", "nek_num_variants",
            "nek_tune", "nek_set_variant", "nek_get_variant", "nek_setup_batch", "nek_batch_free",
-           "nek_batch_size", "nek_batch_ctx", "nek_batch_orders", "nek_batch_tune", "nek_batch_set_variant",
+           "nek_batch_size", "nek_batch_ctx", "nek_batch_mesh_of", "nek_batch_orders", "nek_batch_tune", "nek_batch_set_variant",
            "nek_batch_get_variant", "nek_cg_solve_batch", "nek_batch_counters", "nek_strerror",
            "nek_mlp_create", "nek_mlp_free", "nek_mlp_num_params", "nek_mlp_get_params", "nek_mlp_set_params",
            "nek_mlp_forward", "nek_mlp_loss_grad", "nek_mlp_adam", "nek_mlp_train", "nek_x0_features",
@@ -114,6 +114,7 @@ def load(path: str = LIB_PATH):
     lib.nek_batch_free.restype = None
     lib.nek_batch_size.argtypes = [vp]
     lib.nek_batch_ctx.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp)]
+    lib.nek_batch_mesh_of.argtypes = [vp, ctypes.c_int]
     lib.nek_batch_orders.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.nek_batch_tune.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     lib.nek_batch_set_variant.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
@@ -469,6 +470,12 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+    def mesh_of(self, i):
+        """Index of the problem whose set-up data problem i shares (i if its own)."""
+        k = self._lib.nek_batch_mesh_of(self._h, int(i))
+        _check(min(k, 0), "nek_batch_mesh_of")
+        return k
 
     def orders(self):
         out = (ctypes.c_int * 16)()

@@ -220,3 +220,69 @@ def test_full_64_problem_draw_judged_by_oracle():
         assert st[i]["status"] == nek.NEK_OK and rho <= TOL
         del P
     print(f"  worst oracle rho* over the draw {worst:.2e}")
+
+
+def test_many_right_hand_sides_share_the_mesh():
+    """Problems that repeat an earlier problem's mesh and order share its
+    set-up data (nek_batch_mesh_of names the owner) and run interleaved on the
+    owner's XCDs; every x and statistic is still bit-identical to a solo
+    solve on a context of its own, and judged by the oracle."""
+    nel, N = (4, 3, 3), 7
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=71)
+    sp = [{"nel": nel, "N": N, "vtx": vtx},                              # 0: owner
+          {"nel": nel, "N": N, "vtx": vtx},                              # 1: same array
+          {"nel": nel, "N": N, "vtx": vtx.copy()},                       # 2: same values
+          {"nel": nel, "N": N, "vtx": synth.box_vertices(nel, perturb=0.1, seed=72)},   # 3: another mesh
+          {"nel": nel, "N": 5, "vtx": vtx},                              # 4: another order
+          {"nel": (2, 3, 2), "N": N},                                    # 5: uniform lattice
+          {"nel": (2, 3, 2), "N": N},                                    # 6: the same uniform lattice
+          {"nel": nel, "N": N, "vtx": vtx}]                              # 7: owner's mesh again
+    roots = [0, 0, 0, 3, 4, 5, 5, 0]
+    for prec in ("fp64", "fp32", "bf16g"):
+        _case(f"many right-hand sides prec={prec}")
+        b = nek.Batch(sp, prec=prec)
+        assert [b.mesh_of(i) for i in range(b.n)] == roots
+        fs = loads(b, seed=23)
+        xs, st, rc = b.solve(fs, tol=TOL, maxit=20000)
+        assert rc == nek.NEK_OK
+        for i, spec in enumerate(sp):
+            v = b.get_variant(prec, i)
+            if "vtx" not in spec:
+                spec = dict(spec, vtx=synth.box_vertices(spec["nel"]))
+            xs_solo, st_solo = solo_solve(spec, prec, fs[i], v)
+            x = host(xs[i])
+            rho = oracle_rho(spec, fs[i], x)
+            print(f"  [{i}] shares {roots[i]} iters {st[i]['iters']} outer {st[i]['outer_iters']} rho* {rho:.2e}")
+            assert st[i]["iters"] == st_solo["iters"] and st[i]["true_rel_res"] == st_solo["true_rel_res"]
+            assert np.array_equal(x, xs_solo), f"problem {i}"
+            assert rho <= TOL
+        # a sharing member's context works on its own as well
+        x1, st1, _ = b.ctx[1].cg_solve(fs[1], tol=TOL, maxit=20000)
+        assert np.array_equal(host(x1), host(xs[1])) and st1["iters"] == st[1]["iters"]
+        b.close()
+
+
+def test_many_right_hand_sides_divide_the_grid():
+    """Four right-hand sides on a mesh with more element groups than a
+    quarter of the solo persistent grid: each problem runs on a quarter of it
+    (every workgroup walks several element groups); the batched x equals the
+    member context's own solve bit for bit and the oracle's true residual is
+    within tol, in every precision."""
+    nel, N, K = (10, 10, 9), 5, 4
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=73)
+    sp = [{"nel": nel, "N": N, "vtx": vtx}] * K
+    for prec in ("fp64", "fp32", "bf16g"):
+        _case(f"{K} right-hand sides on 10x10x9 N=5, prec={prec}")
+        b = nek.Batch(sp, prec=prec)
+        assert [b.mesh_of(i) for i in range(K)] == [0] * K
+        fs = loads(b, seed=29)
+        xs, st, rc = b.solve(fs, tol=TOL, maxit=20000)
+        assert rc == nek.NEK_OK
+        for i in range(K):
+            x = host(xs[i])
+            xi, sti, _ = b.ctx[i].cg_solve(fs[i], tol=TOL, maxit=20000)
+            rho = oracle_rho(sp[i], fs[i], x)
+            print(f"  [{i}] iters {st[i]['iters']} outer {st[i]['outer_iters']} rho* {rho:.2e}")
+            assert np.array_equal(x, host(xi)) and sti["iters"] == st[i]["iters"]
+            assert rho <= TOL
+        b.close()
