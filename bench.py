@@ -232,6 +232,8 @@ def big_case(torch, nek, synth, steps=2, energy=True, jacobi=True):
             jac[prec] = {"ms_per_solve": round(dt * 1e3, 2), "iters": st["iters"], "outer": st["outer_iters"],
                          "true_rel_res": st["true_rel_res"], "speedup_vs_unpreconditioned":
                          round(out[prec]["ms_per_solve"] / (dt * 1e3), 3)}
+        if pc == "schwarz":
+            jac["window_kernels"] = schwarz_kernels(torch, ctx, f, x, ("bf16g", "fp64"), steps)
         ctx.set_precond("none")
         for p, v in saved.items():
             ctx.set_variant(p, v)
@@ -292,6 +294,41 @@ def kernel_roofline(ctx, prec):
     return res
 
 
+def schwarz_kernels(torch, ctx, f, x, precs, steps, napply=20):
+    """The Schwarz window solves on the matrix cores against the vector-ALU
+    form (the default takes the matrix cores for FP64 vectors only), on a context already set up for the Schwarz-preconditioned
+    solve: mean time of one preconditioner application z = M^-1 r (window
+    solves, coarse solve, gather) per vector type, and of the whole solve per
+    precision, with each kernel."""
+    out = {}
+    r = {dt: torch.rand(ctx.nl, dtype=dt, device="cuda") for dt in (torch.float32, torch.float64)}
+    for kind in ("mfma", "valu"):
+        ctx.set_schwarz_kernel(kind)
+        res = {}
+        for name, dt in (("apply_fp32_us", torch.float32), ("apply_fp64_us", torch.float64)):
+            z = ctx.precond_apply(r[dt])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(napply):
+                ctx.precond_apply(r[dt], z)
+            torch.cuda.synchronize()
+            res[name] = round((time.perf_counter() - t0) / napply * 1e6, 1)
+        for prec in precs:
+            ctx.set_prec(prec)
+            ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, st, _ = ctx.cg_solve(f, tol=TOL, maxit=20000, x=x, raise_on_noconv=True)
+            torch.cuda.synchronize()
+            res[f"{prec}_ms_per_solve"] = round((time.perf_counter() - t0) / steps * 1e3, 2)
+            res[f"{prec}_iters"] = st["iters"]
+        out[kind] = res
+    ctx.set_schwarz_kernel("auto")
+    out["mfma_speedup"] = {k: round(out["valu"][k] / out["mfma"][k], 3) for k in out["mfma"] if not k.endswith("iters")}
+    return out
+
+
 def precond_case(torch, ctx, f, steps, base, pc="jacobi"):
     """A preconditioner (pc: 'jacobi' diagonal, 'fdm' element-interior fast
     diagonalization with the diagonal elsewhere, or 'schwarz' two-level
@@ -329,6 +366,8 @@ def precond_case(torch, ctx, f, steps, base, pc="jacobi"):
                          "operator_us": round(k0 / max(n0, 1) * 1e3, 2), "update_us": round(k1 / max(n1, 1) * 1e3, 2),
                          "unpreconditioned_ms": round(ms0, 3), "unpreconditioned_iters": it0,
                          "speedup": round(ms0 / (dt * 1e3), 3)}
+        if pc == "schwarz":
+            out["window_kernels"] = schwarz_kernels(torch, ctx, f, x, ("fp32", "fp64"), steps)
     finally:
         ctx.set_precond("none")
         for p, v in saved.items():

@@ -255,6 +255,25 @@ int nek_set_geometry(nek_ctx *ctx, int geom);
  */
 int nek_set_max_workgroups(nek_ctx *ctx, int n);
 
+/* Kernel of the Schwarz window solves (NEK_PC_SCHWARZ). */
+typedef enum {
+    NEK_SCHWARZ_AUTO = 0,    /* the faster of the two on MI355X per vector type:
+                                matrix cores for FP64, vector ALUs for FP32 (the
+                                default)                                          */
+    NEK_SCHWARZ_MFMA = 1,    /* each fast-diagonalization pass as 16x16x4 matrix-core
+                                products (v_mfma_f32 / v_mfma_f64)               */
+    NEK_SCHWARZ_VALU = 2     /* one window line per thread on the vector ALUs    */
+} nek_schwarz_kernel;
+
+/*
+ * nek_set_schwarz_kernel -- choose the kernel of the overlapping Schwarz
+ * window solves (the local solves of solveM in Table 1, Fig. 3's
+ * fast-diagonalization smoother); both compute the same products in a
+ * different summation order, so results agree to rounding.  Takes effect at
+ * the next preconditioner application.  NEK_E_ARG for an unknown kind.
+ */
+int nek_set_schwarz_kernel(nek_ctx *ctx, int kind);
+
 /*
  * nek_precond_apply -- z = M^-1 r with the context's preconditioner (a copy
  * without one); r and z are device vectors of n_local entries of dtype

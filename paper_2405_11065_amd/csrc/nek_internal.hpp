@@ -129,6 +129,7 @@ struct nek_ctx {
     nek::Scal *sc = nullptr;
     double *partials = nullptr;   // 7 regions of MAXB doubles
     int precond = 0;              // 1: diagonal (Jacobi) preconditioner in the CG loop
+    int asm_kernel = NEK_SCHWARZ_AUTO;   // Schwarz window solves: matrix cores or vector ALUs
     double *dg64 = nullptr;       // assembled diagonal, 1 on Dirichlet nodes
     float *dg32 = nullptr;        // its FP32 rounding (mixed inner solves)
     // fast-diagonalization preconditioner: 1-D interior modes S [(N-1)^2],
@@ -193,6 +194,15 @@ inline unsigned red_grid(const nek_ctx *c)
 }
 
 inline int ax_groups(const nek_ctx *c, int epw) { return (int)((c->E + epw - 1) / epw); }
+
+// Workgroups of `kernel` (block threads, static LDS only) resident on one
+// compute unit at once, at least 1.
+inline int resident_per_cu(const void *kernel, int threads)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n < 1) n = 1;
+    return n;
+}
 
 // Trilinear-coefficient buffer of the vectors' type, as the operator's tag type.
 template <typename T> inline const TriG<T> *tri_ptr(const nek_ctx *c)

@@ -1661,6 +1661,218 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
     }
 }
 
+// ---- the same local solves on the matrix cores
+//
+// Each pass of the fast diagonalization is a product of the NW^2 lines of the
+// window (one of the three directions running along the line) with an NW x NW
+// matrix of 1-D modes: (NW^2 x NW) x (NW x NW).  v_mfma_*_16x16x4 multiplies a
+// 16 x 4 block of lines by a 4 x 16 block of modes into a 16 x 16 block held
+// by one wave; lane l supplies line l mod 16 at contracted index l / 16 and
+// mode (l mod 16) at the same contracted index, and receives four outputs of
+// column l mod 16 (rows 4 (l / 16) + q for FP32, l / 16 + 4 q for FP64: the
+// two instructions order their outputs differently).  Lines and modes past NW
+// are zero-padded; the modes stay in LDS and each lane reads its few operands
+// once per pass, so the per-thread row reads of the VALU form disappear.
+template <typename T> struct Mfma16;
+template <> struct Mfma16<float> {
+    typedef float V __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ V mma(float a, float b, V c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+};
+template <> struct Mfma16<double> {
+    typedef double V __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ V mma(double a, double b, V c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int q) { return (lane >> 4) + 4 * q; }
+};
+
+// One pass: out(L, m) = sum_k A(L, k) B(k, m) over the NW^2 lines L and the
+// NW outputs m; wave w of NWV takes the line tiles w, w + NWV, ...  a_at(L, k)
+// and b_at(k, m) read the operands, put(L, m, v) stores a result.
+template <int NW, int NWV, typename T, typename FA, typename FB, typename FO>
+__device__ __forceinline__ void mfma_pass(int wave, int lane, FA a_at, FB b_at, FO put)
+{
+    using M = Mfma16<T>;
+    constexpr int NL = NW * NW, MT = (NL + 15) / 16, NT = (NW + 15) / 16, KT = (NW + 3) / 4;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        T bop[KT];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+            const int k = 4 * kt + lk, m = 16 * nt + lr;
+            bop[kt] = (k < NW && m < NW) ? b_at(k, m) : (T)0;
+        }
+        for (int mt = wave; mt < MT; mt += NWV) {
+            typename M::V acc = {0, 0, 0, 0};
+            const int L = 16 * mt + lr;
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) {
+                const int k = 4 * kt + lk;
+                const T a = (L < NL && k < NW) ? a_at(L, k) : (T)0;
+                acc = M::mma(a, bop[kt], acc);
+            }
+            const int m = 16 * nt + lr;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int Lo = 16 * mt + M::row(lane, q);
+                if (Lo < NL && m < NW) put(Lo, m, acc[q]);
+            }
+        }
+    }
+}
+
+// The local solves of k_asm_local (same window, moments, outputs and order of
+// the fast-diagonalization steps) with every pass on the matrix cores: a
+// workgroup of 4 waves walks a contiguous range of elements; the passes
+// ping-pong between two LDS copies of the window.
+template <int NP, typename T>
+__global__ __launch_bounds__(256) void k_asm_local_mfma(
+    const T *__restrict__ r, T *__restrict__ u, double *__restrict__ mom, const T *__restrict__ Sw,
+    const T *__restrict__ lamw, const T *__restrict__ cf, const double *__restrict__ ell, Box box, int E,
+    const Scal *__restrict__ sc, int it)
+{
+    constexpr int N = NP - 1, NW = NP + 2, PW = NW + 1, NW2 = NW * NW, NP2 = NP * NP, NP3 = NP2 * NP;
+    constexpr int BS = 256, NWV = BS / 64;
+    __shared__ T b0[NW * NW * PW], b1[NW * NW * PW];
+    __shared__ T sS[3][NW][NW];
+    __shared__ T sl[3][NW];
+    __shared__ double mx[2][NP2];
+    __shared__ double my[4][NP];
+    if (sc && sc->st[it & 1].done) return;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int eb = (int)(((long)lb * E) / gridDim.x), ee = (int)(((long)(lb + 1) * E) / gridDim.x);
+    auto ix = [](int a, int b, int c) { return a + PW * (b + NW * c); };
+    for (int e = eb; e < ee; ++e) {
+        __syncthreads();   // the previous element's LDS reads are done
+        const int ex = e % box.nx, eyz = e / box.nx, ey = eyz % box.ny, ez = eyz / box.ny;
+        const int vx = (ex == 0 ? 1 : 0) + (ex == box.nx - 1 ? 2 : 0);
+        const int vy = (ey == 0 ? 1 : 0) + (ey == box.ny - 1 ? 2 : 0);
+        const int vz = (ez == 0 ? 1 : 0) + (ez == box.nz - 1 ? 2 : 0);
+        for (int q = tid; q < NW2; q += BS) {
+            const int a = q / NW, m = q % NW;
+            sS[0][a][m] = Sw[vx * NW2 + q];
+            sS[1][a][m] = Sw[vy * NW2 + q];
+            sS[2][a][m] = Sw[vz * NW2 + q];
+        }
+        if (tid < NW) {
+            sl[0][tid] = lamw[vx * NW + tid];
+            sl[1][tid] = lamw[vy * NW + tid];
+            sl[2][tid] = lamw[vz * NW + tid];
+        }
+        // the window of r by columns along z, every load issued without a
+        // branch (a node that is not an unknown reads the element's own node
+        // 0 and its value is replaced by 0)
+        for (int col = tid; col < NW2; col += BS) {
+            const int a = col % NW, b = col / NW;
+            int e0 = ex, i0 = 0, e1 = ey, i1 = 0;
+            const bool hx = win_node<NP>(a, ex, box.nx, e0, i0), hy = win_node<NP>(b, ey, box.ny, e1, i1);
+            if (!hx) { e0 = ex; i0 = 0; }
+            if (!hy) { e1 = ey; i1 = 0; }
+            const long cb = (long)(e0 + box.nx * e1) * NP3 + i0 + NP * i1;
+            const long zst = (long)box.nx * box.ny * NP3;
+            T v[NW];
+            bool ok[NW];
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                int e2 = ez, i2 = 0;
+                ok[c] = hx && hy && win_node<NP>(c, ez, box.nz, e2, i2);
+                if (!ok[c]) { e2 = ez; i2 = 0; }
+                v[c] = r[cb + zst * e2 + NP2 * i2];
+            }
+#pragma unroll
+            for (int c = 0; c < NW; ++c) b0[ix(a, b, c)] = ok[c] ? v[c] : (T)0;
+        }
+        __syncthreads();
+        // coarse moments, as in k_asm_local
+        auto cw = [&](int i, int edd, int ndd, int side) -> double {
+            const double l = ell[side * NP + i];
+            const bool shared = (i == 0 && edd > 0) || (i == N && edd < ndd - 1);
+            return shared ? 0.5 * l : l;
+        };
+        if (tid < NP2) {
+            const int j = tid % NP, k = tid / NP;
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                const double v = (double)b0[ix(i + 1, j + 1, k + 1)];
+                s0 += cw(i, ex, box.nx, 0) * v;
+                s1 += cw(i, ex, box.nx, 1) * v;
+            }
+            mx[0][k * NP + j] = s0;
+            mx[1][k * NP + j] = s1;
+        }
+        __syncthreads();
+        if (tid < 2 * NP) {
+            const int xa = tid & 1, k = tid >> 1;
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                s0 += cw(j, ey, box.ny, 0) * mx[xa][k * NP + j];
+                s1 += cw(j, ey, box.ny, 1) * mx[xa][k * NP + j];
+            }
+            my[xa][k] = s0;
+            my[2 + xa][k] = s1;
+        }
+        __syncthreads();
+        if (tid < 8) {
+            const int xa = tid & 1, yb = (tid >> 1) & 1, zc = tid >> 2;
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) s += cw(k, ez, box.nz, zc) * my[2 * yb + xa][k];
+            mom[(long)e * 8 + tid] = s;
+        }
+        // S^T along x: lines (b, c)
+        mfma_pass<NW, NWV, T>(
+            wave, lane, [&](int L, int k) { return b0[ix(k, L % NW, L / NW)]; },
+            [&](int k, int m) { return sS[0][k][m]; },
+            [&](int L, int m, T v) { b1[ix(m, L % NW, L / NW)] = v; });
+        __syncthreads();
+        // S^T along y: lines (a, c)
+        mfma_pass<NW, NWV, T>(
+            wave, lane, [&](int L, int k) { return b1[ix(L % NW, k, L / NW)]; },
+            [&](int k, int m) { return sS[1][k][m]; },
+            [&](int L, int m, T v) { b0[ix(L % NW, m, L / NW)] = v; });
+        __syncthreads();
+        // S^T along z: lines (a, b) of modes; scaled by 2 / (cx l_a + cy l_b + cz l_c)
+        {
+            const T cx = cf[3 * e], cy = cf[3 * e + 1], cz = cf[3 * e + 2];
+            mfma_pass<NW, NWV, T>(
+                wave, lane, [&](int L, int k) { return b0[ix(L % NW, L / NW, k)]; },
+                [&](int k, int m) { return sS[2][k][m]; },
+                [&](int L, int m, T v) {
+                    const int a = L % NW, b = L / NW;
+                    b1[ix(a, b, m)] = (T)2 * v / (cx * sl[0][a] + cy * sl[1][b] + cz * sl[2][m]);
+                });
+        }
+        __syncthreads();
+        // S along z
+        mfma_pass<NW, NWV, T>(
+            wave, lane, [&](int L, int k) { return b1[ix(L % NW, L / NW, k)]; },
+            [&](int k, int m) { return sS[2][m][k]; },
+            [&](int L, int m, T v) { b0[ix(L % NW, L / NW, m)] = v; });
+        __syncthreads();
+        // S along y
+        mfma_pass<NW, NWV, T>(
+            wave, lane, [&](int L, int k) { return b0[ix(L % NW, k, L / NW)]; },
+            [&](int k, int m) { return sS[1][m][k]; },
+            [&](int L, int m, T v) { b1[ix(L % NW, m, L / NW)] = v; });
+        __syncthreads();
+        // S along x, to the window solution u[e][c][b][a]
+        T *ue = u + (long)e * NW2 * NW;
+        mfma_pass<NW, NWV, T>(
+            wave, lane, [&](int L, int k) { return b1[ix(k, L % NW, L / NW)]; },
+            [&](int k, int m) { return sS[0][m][k]; },
+            [&](int L, int m, T v) { ue[m + NW * L] = v; });
+    }
+}
+
 // Subdomains of one direction holding global lattice node ed N + i: the
 // element coordinates (ascending) and the node's window index in each.
 template <int NP>

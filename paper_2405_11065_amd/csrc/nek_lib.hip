@@ -1040,6 +1040,13 @@ int nek_set_max_workgroups(nek_ctx *c, int n)
     return NEK_OK;
 }
 
+int nek_set_schwarz_kernel(nek_ctx *c, int kind)
+{
+    if (!c || kind < NEK_SCHWARZ_AUTO || kind > NEK_SCHWARZ_VALU) return NEK_E_ARG;
+    c->asm_kernel = kind;
+    return NEK_OK;
+}
+
 int nek_precond_apply(nek_ctx *c, const void *r, void *z, int dtype)
 {
     if (!c || !r || !z || r == z || (dtype != NEK_F64 && dtype != NEK_F32)) return NEK_E_ARG;

@@ -12,6 +12,9 @@ FP64 oracle (oracle/schwarz.py), through the C ABI.
   * converged FP64, FP32-operator and BF16-g solves judged by the oracle's
     true residual, FP64 iteration counts within one of the oracle's;
   * a single element converges in one iteration; N = 1 is refused.
+Every check of the application and of the fixed-iteration loop runs with
+both kernels of the window solves (matrix cores, the default, and the
+vector-ALU form), which differ only in summation order.
 """
 import numpy as np
 import pytest
@@ -59,19 +62,21 @@ def copies_equal(P, z):
                                         (15, (2, 2, 1), 0.0), (4, (1, 1, 1), 0.0)])
 def test_apply_matches_oracle(N, nel, pert):
     vtx = synth.box_vertices(nel, perturb=pert, seed=20 + N)
-    _case(f"schwarz apply N={N} nel={nel} perturb={pert}")
     P = oracle.Problem(N, nel, vtx)
     M = schwarz.Schwarz(P, vtx)
     ctx = nek.Context(nel, N, vtx=vtx, precond="schwarz")
     r = P.rhs(synth.uniform_load(P.nl, 3) - 0.5)     # continuous, zero on the boundary
     ref = M.apply(r)
-    z64 = host(ctx.precond_apply(dev(r)))
-    e64 = relmax(z64, ref)
-    z32 = host(ctx.precond_apply(dev(r, torch.float32))).astype(np.float64)
-    e32 = relmax(z32, ref)
-    print(f"  fp64 {e64:.2e}  fp32 {e32:.2e}", flush=True)
-    assert e64 <= 1e-12 and e32 <= 2e-5
-    assert copies_equal(P, z64) and copies_equal(P, z32)
+    for kind in ("mfma", "valu"):
+        _case(f"schwarz apply N={N} nel={nel} perturb={pert} kernel={kind}")
+        ctx.set_schwarz_kernel(kind)
+        z64 = host(ctx.precond_apply(dev(r)))
+        e64 = relmax(z64, ref)
+        z32 = host(ctx.precond_apply(dev(r, torch.float32))).astype(np.float64)
+        e32 = relmax(z32, ref)
+        print(f"  fp64 {e64:.2e}  fp32 {e32:.2e}", flush=True)
+        assert e64 <= 1e-12 and e32 <= 2e-5
+        assert copies_equal(P, z64) and copies_equal(P, z32)
     ctx.close()
 
 
@@ -121,16 +126,17 @@ def test_pcg_fixed_iterations_match_oracle(N, nel, pert, cap, its):
     assert ito == its and sens <= 1e-14
     ctx = nek.Context(nel, N, vtx=vtx, precond="schwarz", elts_per_wg=-1)
     fd = dev(f)
-    for v in range(ctx.num_variants()):
-        for c in (0, cap):
-            _case(f"schwarz pcg N={N} nel={nel} variant={v} cap={c}")
-            ctx.set_variant("fp64", v)
-            ctx.set_max_workgroups(c)
-            x, st, hist = ctx.cg_solve(fd, tol=0.0, maxit=its, history=True)
-            err = relmax(host(x), xo)
-            herr = float(np.abs(hist - ho).max() / ho[0])
-            print(f"  x err {err:.2e} history err {herr:.2e}", flush=True)
-            assert st["iters"] == its and err <= 1e-12 and herr <= 1e-12
+    runs = [(v, c, "mfma") for v in range(ctx.num_variants()) for c in (0, cap)] + [(0, 0, "valu"), (0, cap, "valu")]
+    for v, c, kind in runs:
+        _case(f"schwarz pcg N={N} nel={nel} variant={v} cap={c} kernel={kind}")
+        ctx.set_schwarz_kernel(kind)
+        ctx.set_variant("fp64", v)
+        ctx.set_max_workgroups(c)
+        x, st, hist = ctx.cg_solve(fd, tol=0.0, maxit=its, history=True)
+        err = relmax(host(x), xo)
+        herr = float(np.abs(hist - ho).max() / ho[0])
+        print(f"  x err {err:.2e} history err {herr:.2e}", flush=True)
+        assert st["iters"] == its and err <= 1e-12 and herr <= 1e-12
     ctx.close()
 
 
