@@ -294,6 +294,40 @@ def kernel_roofline(ctx, prec):
     return res
 
 
+def operator_kernels(torch, nek, synth, orders=(7, 9, 11), ne=16, reps=20):
+    """The plain operator pass (nek_ax_local) with its D contractions on the
+    vector ALUs (the kernel form of every CG iteration) and on the matrix
+    cores, on the ne^3 box at N + 1 = 8, 10, 12, FP32 and FP64: mean time per
+    call and algorithmic bandwidth (u read, w written, six factors read)."""
+    out = {}
+    for N in orders:
+        ctx = nek.Context((ne, ne, ne), N, prec="fp64")
+        for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+            ctx.set_prec(prec)
+            ctx.tune(prec, iters=5)
+            u = torch.rand(ctx.nl, dtype=dt, device="cuda")
+            w = torch.empty_like(u)
+            res = {}
+            for kind in ("valu", "mfma"):
+                ctx.set_operator_kernel(kind)
+                ctx.ax_local(u, w)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    ctx.ax_local(u, w)
+                torch.cuda.synchronize()
+                t = (time.perf_counter() - t0) / reps
+                gbs = ctx.nl * 8 * u.element_size() / t / 1e9
+                res[kind] = {"us": round(t * 1e6, 1), "GBps": round(gbs, 1)}
+            ctx.set_operator_kernel("valu")
+            res["mfma_over_valu_time"] = round(res["mfma"]["us"] / res["valu"]["us"], 3)
+            out[f"NP{N + 1}_{prec}"] = res
+            log(f"operator kernels N={N} {prec}: {res}")
+        ctx.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def schwarz_kernels(torch, ctx, f, x, precs, steps, napply=20):
     """The Schwarz window solves on the matrix cores against the vector-ALU
     form (the default takes the matrix cores for FP64 vectors only), on a context already set up for the Schwarz-preconditioned
@@ -772,6 +806,9 @@ def main():
                     help="with --profile: the 16^3 box or the 32^3 deformed mesh (N=9)")
     ap.add_argument("--precond", default="none", choices=("none", "jacobi", "fdm", "schwarz"),
                     help="with --profile: preconditioner of the profiled solves")
+    ap.add_argument("--profile-operators", action="store_true",
+                    help="only the plain operator pass with vector-ALU and matrix-core D contractions (16^3 box, "
+                         "N + 1 = 8, 10, 12, FP32 and FP64), for kernel traces")
     ap.add_argument("--profile-ax", type=int, default=0, metavar="NE",
                     help="short nek_ax sequence on the NE^3 deformed N=9 mesh (5 calls per precision) and a "
                          "256 MiB copy, for counter runs of the operator and assembly passes")
@@ -792,6 +829,9 @@ def main():
 
     if args.profile:
         return profile_sequence(torch, nek, synth, args.variants, args.geometry, args.profile_ne, args.precond)
+    if args.profile_operators:
+        print(json.dumps({"operator_kernels_16x16x16": operator_kernels(torch, nek, synth)}), flush=True)
+        return None
     if args.profile_ax:
         return profile_ax(torch, nek, synth, args.profile_ax, args.variants)
 
@@ -875,6 +915,7 @@ def main():
     log("32^3 case done")
     batch = None if args.no_batch else batch_case(torch, nek, synth)
     multi = None if args.no_batch else multi_rhs_case(torch, nek, synth)
+    opk = None if args.no_jacobi else operator_kernels(torch, nek, synth)
     learned = None if args.no_learned else learned_case(torch)
 
     bpp = cg_operator_bytes_per_point(4, 4, 8)   # FP32 vectors and g, FP64 inner correction
@@ -926,6 +967,7 @@ def main():
         "deformed_32x32x32_N9": big,
         "batch_64": batch,
         "multi_rhs_16x16x16_N9": multi,
+        "operator_kernels_16x16x16": opk,
         "learned_x0": learned,
     }
     ctx.close()

@@ -255,6 +255,25 @@ int nek_set_geometry(nek_ctx *ctx, int geom);
  */
 int nek_set_max_workgroups(nek_ctx *ctx, int n);
 
+/* Kernel of the plain operator pass (nek_ax_local, nek_ax). */
+typedef enum {
+    NEK_OPERATOR_VALU = 0,   /* D contractions on the vector ALUs, u staged in LDS
+                                (the kernel of every CG iteration; the default)   */
+    NEK_OPERATOR_MFMA = 1    /* each D contraction as 16x16x4 matrix-core products
+                                (v_mfma_f32 / v_mfma_f64), N + 1 <= 12            */
+} nek_operator_kernel;
+
+/*
+ * nek_set_operator_kernel -- choose how the plain local operator A_L u of
+ * nek_ax_local and nek_ax computes the D contractions of local_grad3 and
+ * local_grad3_t (Fig. 2).  Both apply the same factors and products in a
+ * different summation order (results agree to rounding); the CG kernels
+ * always use the vector-ALU form, which measured faster on MI355X at
+ * N + 1 = 10 and 12 in both precisions (NEK_OPERATOR_MFMA is the measured
+ * alternative).  NEK_E_ARG for an unknown kind, or MFMA with N + 1 > 12.
+ */
+int nek_set_operator_kernel(nek_ctx *ctx, int kind);
+
 /* Kernel of the Schwarz window solves (NEK_PC_SCHWARZ). */
 typedef enum {
     NEK_SCHWARZ_AUTO = 0,    /* the faster of the two on MI355X per vector type:

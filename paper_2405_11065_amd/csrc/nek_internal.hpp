@@ -130,6 +130,7 @@ struct nek_ctx {
     double *partials = nullptr;   // 7 regions of MAXB doubles
     int precond = 0;              // 1: diagonal (Jacobi) preconditioner in the CG loop
     int asm_kernel = NEK_SCHWARZ_AUTO;   // Schwarz window solves: matrix cores or vector ALUs
+    int op_kernel = NEK_OPERATOR_VALU;   // plain operator pass (nek_ax_local, nek_ax): D contractions
     double *dg64 = nullptr;       // assembled diagonal, 1 on Dirichlet nodes
     float *dg32 = nullptr;        // its FP32 rounding (mixed inner solves)
     // fast-diagonalization preconditioner: 1-D interior modes S [(N-1)^2],

@@ -1873,6 +1873,71 @@ __global__ __launch_bounds__(256) void k_asm_local_mfma(
     }
 }
 
+// The plain local operator w = A_L u (local_grad3, the six factors,
+// local_grad3_t; Fig. 2) with its six D contractions on the matrix cores:
+// each is the product of the NP^2 lines of the element along one direction
+// with D or D^T (mfma_pass with NW = NP); the factors are applied per point
+// on the vector ALUs between the two halves.  A workgroup of 4 waves walks a
+// contiguous range of elements.  The measured alternative to ax_body's
+// vector-ALU contractions (nek_set_operator_kernel); NP <= 12 (four LDS
+// copies of the element).
+template <int NP, typename T, typename GT>
+__global__ __launch_bounds__(256) void k_ax_mfma(const T *__restrict__ u, T *__restrict__ w,
+                                                 const GT *__restrict__ g, const T *__restrict__ D, int E)
+{
+    constexpr int NP2 = NP * NP, NP3 = NP2 * NP, PWn = NP + 1, NWV = 4, SZ = NP * NP * PWn;
+    using GL = GLoad<GT>;
+    __shared__ T su[SZ], sr[SZ], ss[SZ], st[SZ];
+    __shared__ T sD[NP * NP];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int q = tid; q < NP * NP; q += 256) sD[q] = D[q];
+    auto ix = [](int i, int j, int k) { return i + PWn * (j + NP * k); };
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int eb = (int)(((long)lb * E) / gridDim.x), ee = (int)(((long)(lb + 1) * E) / gridDim.x);
+    for (int e = eb; e < ee; ++e) {
+        __syncthreads();   // the previous element's LDS reads are done (and sD written)
+        for (int p = tid; p < NP3; p += 256) su[ix(p % NP, (p / NP) % NP, p / NP2)] = u[(long)e * NP3 + p];
+        __syncthreads();
+        // ur = D u along r, us along s, ut along t
+        mfma_pass<NP, NWV, T>(
+            wave, lane, [&](int L, int l) { return su[ix(l, L % NP, L / NP)]; },
+            [&](int l, int m) { return sD[m * NP + l]; }, [&](int L, int m, T v) { sr[ix(m, L % NP, L / NP)] = v; });
+        mfma_pass<NP, NWV, T>(
+            wave, lane, [&](int L, int l) { return su[ix(L % NP, l, L / NP)]; },
+            [&](int l, int m) { return sD[m * NP + l]; }, [&](int L, int m, T v) { ss[ix(L % NP, m, L / NP)] = v; });
+        mfma_pass<NP, NWV, T>(
+            wave, lane, [&](int L, int l) { return su[ix(L % NP, L / NP, l)]; },
+            [&](int l, int m) { return sD[m * NP + l]; }, [&](int L, int m, T v) { st[ix(L % NP, L / NP, m)] = v; });
+        __syncthreads();
+        for (int p = tid; p < NP3; p += 256) {
+            const int a = ix(p % NP, (p / NP) % NP, p / NP2);
+            T gk[6];
+            GL::unpack(GL::load(g + ((long)e * NP3 + p) * 6), gk);
+            const T ur = sr[a], us = ss[a], ut = st[a];
+            sr[a] = gk[0] * ur + gk[3] * us + gk[4] * ut;
+            ss[a] = gk[3] * ur + gk[1] * us + gk[5] * ut;
+            st[a] = gk[4] * ur + gk[5] * us + gk[2] * ut;
+        }
+        __syncthreads();
+        // w = D^T wr + D^T ws + D^T wt, accumulated in su
+        mfma_pass<NP, NWV, T>(
+            wave, lane, [&](int L, int l) { return sr[ix(l, L % NP, L / NP)]; },
+            [&](int l, int m) { return sD[l * NP + m]; }, [&](int L, int m, T v) { su[ix(m, L % NP, L / NP)] = v; });
+        __syncthreads();
+        mfma_pass<NP, NWV, T>(
+            wave, lane, [&](int L, int l) { return ss[ix(L % NP, l, L / NP)]; },
+            [&](int l, int m) { return sD[l * NP + m]; }, [&](int L, int m, T v) { su[ix(L % NP, m, L / NP)] += v; });
+        __syncthreads();
+        mfma_pass<NP, NWV, T>(
+            wave, lane, [&](int L, int l) { return st[ix(L % NP, L / NP, l)]; },
+            [&](int l, int m) { return sD[l * NP + m]; },
+            [&](int L, int m, T v) {
+                const int i = L % NP, j = L / NP;
+                w[(long)e * NP3 + i + NP * (j + NP * m)] = su[ix(i, j, m)] + v;
+            });
+    }
+}
+
 // Subdomains of one direction holding global lattice node ed N + i: the
 // element coordinates (ascending) and the node's window index in each.
 template <int NP>

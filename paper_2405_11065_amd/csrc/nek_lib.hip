@@ -1040,6 +1040,14 @@ int nek_set_max_workgroups(nek_ctx *c, int n)
     return NEK_OK;
 }
 
+int nek_set_operator_kernel(nek_ctx *c, int kind)
+{
+    if (!c || (kind != NEK_OPERATOR_VALU && kind != NEK_OPERATOR_MFMA)) return NEK_E_ARG;
+    if (kind == NEK_OPERATOR_MFMA && c->NP > 12) return NEK_E_ARG;
+    c->op_kernel = kind;
+    return NEK_OK;
+}
+
 int nek_set_schwarz_kernel(nek_ctx *c, int kind)
 {
     if (!c || kind < NEK_SCHWARZ_AUTO || kind > NEK_SCHWARZ_VALU) return NEK_E_ARG;

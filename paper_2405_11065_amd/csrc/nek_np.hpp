@@ -9,6 +9,15 @@ template <int NP> struct OpsImpl {
     template <int EPW, int PD, typename T, typename GT, bool CG, typename XT = T, bool PC = false>
     static int launch_ax(nek_ctx *c, const T *src, T *p, T *w, const GT *g, const T *D, int it, XT *x = nullptr)
     {
+        if constexpr (!CG && !TriOf<GT>::value && NP <= 12)
+            if (c->op_kernel == NEK_OPERATOR_MFMA) {   // the D contractions on the matrix cores
+                static const int occ = resident_per_cu((const void *)k_ax_mfma<NP, T, GT>, 256);
+                const unsigned grid = (unsigned)std::min<long>(c->E, (long)occ * num_cu());
+                hipLaunchKernelGGL((k_ax_mfma<NP, T, GT>), dim3(grid), dim3(256), 0, c->stream, src, w, g, D,
+                                   (int)c->E);
+                HIP_TRY(hipGetLastError());
+                return NEK_OK;
+            }
         constexpr int BS = EPW * NP * NP;
         const size_t shm = ax_lds_bytes<NP, EPW, T>();
         static bool attr_done = false;

@@ -33,7 +33,7 @@ GEOM_NAMES = {"stored": NEK_GSRC_STORED, "trilinear": NEK_GSRC_TRILINEAR}
 
 # every entry point declared in include/nek.h
 EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_set_precond", "nek_set_geometry",
-           "nek_set_max_workgroups", "nek_set_schwarz_kernel", "nek_precond_apply", "nek_ax_local", "nek_ax", "nek_ax_noalloc",
+           "nek_set_max_workgroups", "nek_set_operator_kernel", "nek_set_schwarz_kernel", "nek_precond_apply", "nek_ax_local", "nek_ax", "nek_ax_noalloc",
            "nek_dssum", "nek_glsc3", "nek_cg_solve", "nek_prof_enable", "nek_prof_read", "nek_num_variants",
            "nek_tune", "nek_set_variant", "nek_get_variant", "nek_setup_batch", "nek_batch_free",
            "nek_batch_size", "nek_batch_ctx", "nek_batch_mesh_of", "nek_batch_orders", "nek_batch_tune", "nek_batch_set_variant",
@@ -44,6 +44,7 @@ EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_
 
 NEK_MAX_VARIANTS = 6
 SCHWARZ_KERNELS = {"auto": 0, "mfma": 1, "valu": 2}
+OPERATOR_KERNELS = {"valu": 0, "mfma": 1}
 NEK_BATCH_NO_GRAPH = 1
 
 
@@ -96,6 +97,7 @@ def load(path: str = LIB_PATH):
     lib.nek_set_geometry.argtypes = [vp, ctypes.c_int]
     lib.nek_set_max_workgroups.argtypes = [vp, ctypes.c_int]
     lib.nek_set_schwarz_kernel.argtypes = [vp, ctypes.c_int]
+    lib.nek_set_operator_kernel.argtypes = [vp, ctypes.c_int]
     lib.nek_precond_apply.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_ax_local.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_ax.argtypes = [vp, vp, vp, ctypes.c_int]
@@ -299,6 +301,10 @@ class Context:
     def set_max_workgroups(self, n: int):
         """Cap the persistent / reduction grid at n workgroups (0 = default)."""
         _check(self._lib.nek_set_max_workgroups(self._h, int(n)), "nek_set_max_workgroups")
+
+    def set_operator_kernel(self, kind: str):
+        """D contractions of the plain operator pass (ax_local, ax): "valu" (default) or "mfma"."""
+        _check(self._lib.nek_set_operator_kernel(self._h, OPERATOR_KERNELS[kind]), "nek_set_operator_kernel")
 
     def set_schwarz_kernel(self, kind: str):
         """Kernel of the Schwarz window solves: "auto" (default: matrix cores for FP64
