@@ -708,7 +708,7 @@ def learned_case(torch, nsolves=10000, steps=2500, neval=16, data_tol=1e-10):
             "eval_per_problem": ev["per_problem"]}
 
 
-def profile_sequence(torch, nek, synth, variants="", geometry="stored", ne=16, precond="none"):
+def profile_sequence(torch, nek, synth, variants="", geometry="stored", ne=16, precond="none", schwarz_kernel="auto"):
     """A short sequence for counter collection (few dispatches): 40 mixed and
     40 FP64 CG iterations (BF16-g mixed as well on the deformed mesh), then 5
     nek_ax per precision and a 256 MiB copy for calibration.  ne = 16: the
@@ -721,6 +721,7 @@ def profile_sequence(torch, nek, synth, variants="", geometry="stored", ne=16, p
         vtx = synth.box_vertices(nel, hi=(1.0, 1.0, 1.0), perturb=0.1, seed=synth.SEED_C3_VERTICES)
     ctx = nek.Context(nel, N, vtx=vtx, prec="fp32", precond=precond)
     ctx.set_geometry(geometry)
+    ctx.set_schwarz_kernel(schwarz_kernel)
     chosen = dict(kv.split("=") for kv in variants.split(",") if kv)
     for prec in ("fp32", "fp64", "bf16g"):
         if prec in chosen:
@@ -806,6 +807,8 @@ def main():
                     help="with --profile: the 16^3 box or the 32^3 deformed mesh (N=9)")
     ap.add_argument("--precond", default="none", choices=("none", "jacobi", "fdm", "schwarz"),
                     help="with --profile: preconditioner of the profiled solves")
+    ap.add_argument("--schwarz-kernel", default="auto", choices=("auto", "mfma", "valu"),
+                    help="with --profile --precond schwarz: kernel of the window solves")
     ap.add_argument("--profile-operators", action="store_true",
                     help="only the plain operator pass with vector-ALU and matrix-core D contractions (16^3 box, "
                          "N + 1 = 8, 10, 12, FP32 and FP64), for kernel traces")
@@ -828,7 +831,8 @@ def main():
     torch.cuda.set_device(0)
 
     if args.profile:
-        return profile_sequence(torch, nek, synth, args.variants, args.geometry, args.profile_ne, args.precond)
+        return profile_sequence(torch, nek, synth, args.variants, args.geometry, args.profile_ne, args.precond,
+                                args.schwarz_kernel)
     if args.profile_operators:
         print(json.dumps({"operator_kernels_16x16x16": operator_kernels(torch, nek, synth)}), flush=True)
         return None
