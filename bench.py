@@ -98,6 +98,31 @@ def ax_dssum_all(ctx, torch):
     return axd
 
 
+def dssum_seg(ctx, torch, reps=20):
+    """The standalone sorted-segment direct-stiffness summation (nek_dssum,
+    masked) per vector type: mean time per call and algorithmic bandwidth.
+    Algorithmic bytes: every surface copy read and written once, its int32
+    permutation entry, and per segment its int32 offset and int8 flag."""
+    from paper_2405_11065_amd import nek
+    nperm, nseg = ctx.size(nek.NEK_SIZE_NPERM), ctx.size(nek.NEK_SIZE_NSEG)
+    out = {}
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        w = torch.rand(ctx.nl, dtype=dt, device="cuda")
+        ctx.dssum(w)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            ctx.dssum(w)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) / reps / 1e3
+        b = nperm * (2 * w.element_size() + 4) + nseg * 5
+        out[name] = {"us": round(t * 1e6, 2), "GBps": round(b / t / 1e9, 1), "frac_hbm": round(b / t / 1e9 / PEAK_HBM_GBS, 3),
+                     "segments": nseg, "surface_copies": nperm}
+    return out
+
+
 def copy_bandwidth(torch, mib=512, reps=10):
     """Device-to-device copy of `mib` MiB (read + write counted), beyond the
     256 MB memory-side cache: the practical streaming ceiling that the
@@ -241,6 +266,7 @@ def big_case(torch, nek, synth, steps=2, energy=True, jacobi=True):
     # ax + dssum at this size: the working set exceeds the 256 MB memory-side cache
     ctx.tune("fp32", iters=10)
     out["ax_dssum"] = ax_dssum_all(ctx, torch)
+    out["dssum_seg"] = dssum_seg(ctx, torch)
     ctx.close()
     torch.cuda.empty_cache()
     return out
@@ -913,6 +939,8 @@ def main():
     # ---- ax + dssum bandwidth at each precision (nek_ax), and a plain copy beside it
     axd = ax_dssum_all(ctx, torch)
     axd["copy_512MiB"] = copy_bandwidth(torch)
+    axd["dssum_seg"] = dssum_seg(ctx, torch)
+    log(f"sorted-segment dssum: {axd['dssum_seg']}")
 
     # ---- secondary: 32^3 deformed mesh, N=9, manufactured forcing, BF16 g vs FP64
     big = None if args.no_big else big_case(torch, nek, synth, energy=not args.no_energy, jacobi=not args.no_jacobi)

@@ -68,14 +68,35 @@ __global__ __launch_bounds__(UPD_BS) void k_dssum_seg(T *__restrict__ w, const i
     const unsigned s = blockIdx.x * UPD_BS + threadIdx.x;
     if (s >= nseg) return;
     const int b = seg_ptr[s], e = seg_ptr[s + 1];
+    // A node of a hexahedral mesh has at most 8 copies: their indices, then
+    // their values, are requested together (predicated), so a segment costs
+    // two dependent loads instead of two per copy; longer segments of
+    // general maps finish in the loop after.  Sum in ascending copy order.
+    constexpr int K = 8;
+    const int n = e - b;
+    int idx[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) idx[q] = q < n ? perm[b + q] : 0;
     if (apply_mask && flag[s]) {
-        for (int q = b; q < e; ++q) w[perm[q]] = (T)0;
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+            if (q < n) w[idx[q]] = (T)0;
+        for (int q = b + K; q < e; ++q) w[perm[q]] = (T)0;
         return;
     }
+    T v[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = q < n ? w[idx[q]] : (T)0;
     double acc = 0.0;
-    for (int q = b; q < e; ++q) acc += (double)w[perm[q]];
-    const T v = (T)acc;
-    for (int q = b; q < e; ++q) w[perm[q]] = v;
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+        if (q < n) acc += (double)v[q];
+    for (int q = b + K; q < e; ++q) acc += (double)w[perm[q]];
+    const T r = (T)acc;
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+        if (q < n) w[idx[q]] = r;
+    for (int q = b + K; q < e; ++q) w[perm[q]] = r;
 }
 
 // Rounding of the FP64 geometric factors to the storage precision.
