@@ -706,32 +706,54 @@ def multi_rhs_case(torch, nek, synth, nrhs=(4, 8), steps=2):
     return out
 
 
-def learned_case(torch, nsolves=10000, steps=2500, neval=16, data_tol=1e-10):
+def learned_case(torch, nsolves=10000, steps=(2500, 10000, 40000), neval=16, data_tol=1e-10, holdout=0.05):
     """Learned initial guess: 10,000 FP64 solves (to 1e-10) on 8^3-element
     N=7 meshes of [0,1]^3 (+-10 % interior vertex moves, 64 distinct meshes)
     forced by Gaussian random fields (length scale 0.2) give 5.12 M element
-    rows; the 518 -> 256 -> 256 -> 512 network trains for `steps` Adam steps
-    of 4096 rows on the GPU; then `neval` fresh 16^3-element N=7 problems
-    are solved to 1e-8 by FP64 CG from zero and from the network's guess
-    (prediction time included)."""
+    rows; the rows of the last 5 % of the solves are held out.  The
+    518 -> 256 -> 256 -> 512 network trains on the rest with Adam steps of
+    4096 rows on the GPU, continued to each length in `steps`; at each length
+    the training loss (mean of the last 50 steps), the held-out loss and the
+    evaluation: `neval` fresh 16^3-element N=7 problems solved to 1e-8 by
+    FP64 CG from zero and from the network's guess (prediction time
+    included)."""
     from paper_2405_11065_amd import learned_x0 as lx
     X, T, info = lx.make_dataset(torch, nsolves, tol=data_tol, log=log)
-    net, hist, t_train = lx.train(torch, X, T, steps)
     rows = X.shape[0]
-    del X, T
-    torch.cuda.empty_cache()
-    log(f"learned x0: trained {steps} steps in {t_train:.1f} s")
-    ev = lx.evaluate(torch, net, neval=neval)
+    per_solve = rows // nsolves
+    n_train = (nsolves - int(round(holdout * nsolves))) * per_solve
+    Xv, Tv = X[n_train:], T[n_train:]
+    from paper_2405_11065_amd import nek, synth
+    n3 = T.shape[1]
+    net = nek.Mlp(n3 + 6, lx.HIDDEN, n3, synth.mlp_init((n3 + 6, lx.HIDDEN, lx.HIDDEN, n3), synth.SEED_C5))
+    sweep, done, t_train, hist_all = [], 0, 0.0, []
+    for k, total in enumerate(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = net.train(X, T, n_train, 4096, total - done, lr=1e-3, seed=synth.SEED_C5 + k)
+        torch.cuda.synchronize()
+        t_train += time.perf_counter() - t0
+        done = total
+        hist_all.append(hist)
+        val, _ = net.loss_grad(Xv, Tv)
+        ev = lx.evaluate(torch, net, neval=neval)
+        sweep.append({"steps": total, "train_loss": float(hist[-50:].mean()), "heldout_loss": float(val),
+                      "train_s": round(t_train, 2),
+                      "eval": {kk: v for kk, v in ev.items() if kk != "per_problem"}})
+        log(f"learned x0: {total} steps, train loss {sweep[-1]['train_loss']:.4f}, held-out {val:.4f}, "
+            f"iters saved {ev['iters_saved_frac']:.3f} / energy {ev['energy_iters_saved_frac']:.3f}")
     net.close()
+    del X, T, Xv, Tv
+    torch.cuda.empty_cache()
     # GEMM work of one training step: forward 3 products, backward 5 (2 m n k flops each)
     n_in, h, n_out, bsz = 518, lx.HIDDEN, 512, 4096
     fl = 2 * bsz * (n_in * h + h * h + h * n_out) * 3 - 2 * bsz * n_in * h
-    return {"data": info, "feature_mode": lx.MODE, "train_steps": steps, "train_rows": rows, "batch": bsz,
-            "train_s": round(t_train, 2), "ms_per_step": round(t_train / steps * 1e3, 3),
-            "train_TFLOPs_bf16": round(fl * steps / t_train / 1e12, 2),
-            "loss_first_last": [float(hist[:50].mean()), float(hist[-50:].mean())],
-            "eval": {k: v for k, v in ev.items() if k != "per_problem"},
-            "eval_per_problem": ev["per_problem"]}
+    first = hist_all[0]
+    return {"data": info, "feature_mode": lx.MODE, "train_rows": n_train, "heldout_rows": rows - n_train,
+            "batch": bsz, "train_steps": done, "train_s": round(t_train, 2),
+            "ms_per_step": round(t_train / done * 1e3, 3), "train_TFLOPs_bf16": round(fl * done / t_train / 1e12, 2),
+            "loss_first_last": [float(first[:50].mean()), sweep[-1]["train_loss"]],
+            "sweep": sweep, "eval": sweep[-1]["eval"], "eval_per_problem": ev["per_problem"]}
 
 
 def profile_sequence(torch, nek, synth, variants="", geometry="stored", ne=16, precond="none", schwarz_kernel="auto"):

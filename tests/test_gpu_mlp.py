@@ -5,7 +5,10 @@ oracle is run with the same bfloat16 rounding points (oracle.mlp, bf16=True)
 and FP64 accumulation, so the two differ by accumulation rounding (~1e-6
 relative) and the rare bfloat16 rounding decisions that it moves (each one a
 2^-9 relative change of one operand).  Outputs must agree to 1e-4 in norm
-(relative), parameter gradients to 2e-3 in norm per tensor, the loss to 1e-5;
+(relative), parameter gradients to 2e-3 in norm per tensor, the loss to 1e-5,
+and every element of the outputs and gradients within its own bound derived
+from those two effects (elementwise_bounds: FP32 accumulation of each sum and
+one moved bfloat16 rounding per stored value, propagated to first order);
 against the pure FP64 oracle (no bfloat16 anywhere) gradients stay within
 5e-2.  Adam (FP32) must agree with the FP64 update of the same gradient to
 1e-6 relative.  Features: bfloat16 inputs bit-equal to the oracle's FP64
@@ -68,6 +71,79 @@ def nrel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
+U32 = 2.0 ** -24   # FP32 unit roundoff
+
+
+def stored_err(v, ev):
+    """Bound on |bf16(v') - bf16(v)| for |v' - v| <= ev: zero where no
+    bfloat16 rounding boundary (a midpoint between neighbours) lies within
+    ev of v, else ev plus one spacing."""
+    v = np.asarray(v, dtype=np.float64)
+    rv = om.bf16(v)
+    _, e = np.frexp(np.where(rv == 0, 1.0, rv))
+    spacing = np.ldexp(1.0, e - 8)            # 8 significant bits
+    nearest_mid = np.minimum(np.abs(v - (rv + spacing / 2)), np.abs(v - (rv - spacing / 2)))
+    flip = (nearest_mid <= ev) | (rv == 0)
+    return np.where(flip, ev + spacing, 0.0)
+
+
+def elementwise_bounds(params, X, T=None):
+    """Per-element bounds on |GPU - bf16 oracle| for Y and, with T, for every
+    parameter gradient, propagated to first order from the two differences
+    the arithmetic allows: FP32 accumulation of a K-term sum (at most
+    K u sum |terms|) and, at a bfloat16 storage point, a rounding decision
+    moved by that error (stored_err: only where a rounding boundary lies
+    within the propagated error).  Activation derivatives enter through
+    |silu'| <= 1.1 and |silu''| <= 0.5."""
+    W1, b1, W2, b2, W3, b3 = [np.asarray(p, dtype=np.float64) for p in params]
+    r = om.bf16
+    A0 = r(X)
+    W1r, W2r, W3r = r(W1), r(W2), r(W3)
+    Z1 = A0 @ W1r.T + b1
+    H1 = r(om.silu(Z1))
+    Z2 = H1 @ W2r.T + b2
+    H2 = r(om.silu(Z2))
+    Y = H2 @ W3r.T + b3
+    eZ1 = A0.shape[1] * U32 * (np.abs(A0) @ np.abs(W1r).T + np.abs(b1))
+    eH1 = stored_err(om.silu(Z1), 1.1 * eZ1)
+    eZ2 = H1.shape[1] * U32 * (np.abs(H1) @ np.abs(W2r).T + np.abs(b2)) + eH1 @ np.abs(W2r).T
+    eH2 = stored_err(om.silu(Z2), 1.1 * eZ2)
+    eY = H2.shape[1] * U32 * (np.abs(H2) @ np.abs(W3r).T + np.abs(b3)) + eH2 @ np.abs(W3r).T
+    if T is None:
+        return eY
+    R, n = X.shape[0], Y.size
+    dY = 2.0 * (Y - np.asarray(T, dtype=np.float64)) / n
+    e_dY = 2.0 * eY / n
+    dYr = r(dY)
+    e_dYr = stored_err(dY, e_dY)
+    g = []
+    e_gW3 = R * U32 * (np.abs(dYr).T @ np.abs(H2)) + e_dYr.T @ np.abs(H2) + np.abs(dYr).T @ eH2
+    e_gb3 = R * U32 * np.abs(dY).sum(axis=0) + e_dY.sum(axis=0)
+    P2 = dYr @ W3r
+    dZ2 = P2 * om.dsilu(Z2)
+    e_dZ2 = (W3r.shape[0] * U32 * (np.abs(dYr) @ np.abs(W3r)) + e_dYr @ np.abs(W3r)) * 1.1 + 0.5 * np.abs(P2) * eZ2
+    dZ2r = r(dZ2)
+    e_dZ2r = stored_err(dZ2, e_dZ2)
+    e_gW2 = R * U32 * (np.abs(dZ2r).T @ np.abs(H1)) + e_dZ2r.T @ np.abs(H1) + np.abs(dZ2r).T @ eH1
+    e_gb2 = R * U32 * np.abs(dZ2).sum(axis=0) + e_dZ2.sum(axis=0)
+    P1 = dZ2r @ W2r
+    dZ1 = P1 * om.dsilu(Z1)
+    e_dZ1 = (W2r.shape[0] * U32 * (np.abs(dZ2r) @ np.abs(W2r)) + e_dZ2r @ np.abs(W2r)) * 1.1 + 0.5 * np.abs(P1) * eZ1
+    dZ1r = r(dZ1)
+    e_dZ1r = stored_err(dZ1, e_dZ1)
+    e_gW1 = R * U32 * (np.abs(dZ1r).T @ np.abs(A0)) + e_dZ1r.T @ np.abs(A0)
+    e_gb1 = R * U32 * np.abs(dZ1).sum(axis=0) + e_dZ1.sum(axis=0)
+    return eY, [e_gW1, e_gb1, e_gW2, e_gb2, e_gW3, e_gb3]
+
+
+def within(a, b, bound, name):
+    """Element by element: |a - b| <= bound; reports the largest use of it."""
+    d = np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64))
+    worst = float((d / np.maximum(bound, 1e-300)).max())
+    print(f"  {name}: largest |diff| / bound {worst:.2e}")
+    assert np.all(d <= bound), f"{name}: {int((d > bound).sum())} elements beyond their bound"
+
+
 SHAPES = [((518, 256, 256, 512), 300), ((37, 20, 24, 13), 70), ((8, 64, 64, 8), 64), ((518, 256, 256, 512), 1)]
 
 
@@ -85,6 +161,7 @@ def test_forward_matches_oracle(sizes, rows):
     e, e64 = nrel(Y, Yo), nrel(Y, Y64)
     print(f"  |dY|/|Y| vs bf16 oracle {e:.2e}, vs FP64 oracle {e64:.2e}")
     assert e <= 1e-4 and e64 <= 2e-2
+    within(Y, Yo, elementwise_bounds(P64, X), "Y")
     net.close()
 
 
@@ -103,10 +180,12 @@ def test_loss_and_gradient_match_oracle(sizes, rows):
     l64, g64 = om.loss_and_grads(P64, X, T32)
     print(f"  loss {loss:.6e} oracle {lo:.6e}")
     assert abs(loss - lo) <= 1e-5 * lo
+    _, eb = elementwise_bounds(P64, X, T32)
     for k, (a, b, c) in enumerate(zip(g, go, g64)):
         e, e64 = nrel(a, b), nrel(a, c)
         print(f"  grad[{k}] shape {b.shape}: vs bf16 oracle {e:.2e}, vs FP64 oracle {e64:.2e}")
         assert e <= 2e-3 and e64 <= 5e-2
+        within(a, b, eb[k], f"grad[{k}]")
     net.close()
 
 
