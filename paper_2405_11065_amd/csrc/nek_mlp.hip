@@ -19,7 +19,7 @@
 namespace nek {
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int GB = 256;                 // threads of the GEMM workgroup (4 waves)
@@ -50,21 +50,32 @@ struct GemmArgs {
 
 __device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
 
-// Stage a BM x BK (or BN x BK) tile into LDS as [row][k].
+// A BM x BK (or BN x BK) tile, staged into LDS as [row][k]: each thread
+// fetches one 16-byte piece into registers, and stores it once the LDS
+// buffer it goes to is free, so the fetch of the next tile overlaps the
+// products of the current one.
 template <bool KC>
-__device__ __forceinline__ void load_tile(const uint16_t *__restrict__ P, int ld, int rows, int K, int r0, int k0,
-                                          uint16_t *__restrict__ S, int tid)
+__device__ __forceinline__ uint4 fetch_tile(const uint16_t *__restrict__ P, int ld, int rows, int K, int r0, int k0,
+                                            int tid)
+{
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if constexpr (KC) {
+        const int r = tid >> 2, kc = (tid & 3) * 8;
+        if (r0 + r < rows && k0 + kc < ld) v = *reinterpret_cast<const uint4 *>(P + (size_t)(r0 + r) * ld + k0 + kc);
+    } else {
+        const int k = tid >> 3, mc = (tid & 7) * 8;
+        if (k0 + k < K && r0 + mc < ld) v = *reinterpret_cast<const uint4 *>(P + (size_t)(k0 + k) * ld + r0 + mc);
+    }
+    return v;
+}
+
+template <bool KC> __device__ __forceinline__ void store_tile(uint4 v, uint16_t *__restrict__ S, int tid)
 {
     if constexpr (KC) {
         const int r = tid >> 2, kc = (tid & 3) * 8;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (r0 + r < rows && k0 + kc < ld)
-            v = *reinterpret_cast<const uint4 *>(P + (size_t)(r0 + r) * ld + k0 + kc);
         *reinterpret_cast<uint4 *>(S + r * LDT + kc) = v;
     } else {
         const int k = tid >> 3, mc = (tid & 7) * 8;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (k0 + k < K && r0 + mc < ld) v = *reinterpret_cast<const uint4 *>(P + (size_t)(k0 + k) * ld + r0 + mc);
         const uint16_t e[8] = {(uint16_t)(v.x & 0xffff), (uint16_t)(v.x >> 16), (uint16_t)(v.y & 0xffff),
                                (uint16_t)(v.y >> 16),    (uint16_t)(v.z & 0xffff), (uint16_t)(v.z >> 16),
                                (uint16_t)(v.w & 0xffff), (uint16_t)(v.w >> 16)};
@@ -74,47 +85,59 @@ __device__ __forceinline__ void load_tile(const uint16_t *__restrict__ P, int ld
 }
 
 // 64 x 64 output tile per workgroup; wave w owns the 32 x 32 quadrant
-// (w >> 1, w & 1) as 2 x 2 blocks of the 16x16x16 bfloat16 MFMA.  Operand
-// lanes: A row (lane & 15), k = 4 (lane >> 4) + 0..3; B column (lane & 15),
-// same k; result element r of a block is row 4 (lane >> 4) + r, column
-// (lane & 15).
+// (w >> 1, w & 1) as 2 x 2 blocks of gfx950's 16x16x32 bfloat16 MFMA, one
+// instruction per block and K tile.  Operand lanes: A row (lane & 15),
+// k = 8 (lane >> 4) + 0..7; B column (lane & 15), same k; result element r
+// of a block is row 4 (lane >> 4) + r, column (lane & 15).  Two LDS buffers
+// per operand: tile t + 1 is fetched while tile t is multiplied.
 template <bool AKC, bool BKC, int EPI>
 __global__ __launch_bounds__(GB) void k_gemm(GemmArgs a)
 {
-    __shared__ __align__(16) uint16_t As[BM * LDT];
-    __shared__ __align__(16) uint16_t Bs[BN * LDT];
+    __shared__ __align__(16) uint16_t As[2][BM * LDT];
+    __shared__ __align__(16) uint16_t Bs[2][BN * LDT];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int kb = a.kchunk ? blockIdx.z * a.kchunk : 0;
     const int ke = a.kchunk ? min(a.K, kb + a.kchunk) : a.K;
     float *C = a.C + (a.kchunk ? blockIdx.z * a.cstride : 0);
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int lr = lane & 15, lk = 4 * (lane >> 4);
+    const int lr = lane & 15, lk = 4 * (lane >> 4), lk8 = 8 * (lane >> 4);
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    if (kb < ke) {
+        store_tile<AKC>(fetch_tile<AKC>(a.A, a.lda, a.M, ke, m0, kb, tid), As[0], tid);
+        store_tile<BKC>(fetch_tile<BKC>(a.B, a.ldb, a.N, ke, n0, kb, tid), Bs[0], tid);
+    }
+    __syncthreads();
+    int buf = 0;
     for (int k0 = kb; k0 < ke; k0 += BK) {
-        load_tile<AKC>(a.A, a.lda, a.M, ke, m0, k0, As, tid);
-        load_tile<BKC>(a.B, a.ldb, a.N, ke, n0, k0, Bs, tid);
-        __syncthreads();
+        const bool more = k0 + BK < ke;
+        uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+        if (more) {
+            va = fetch_tile<AKC>(a.A, a.lda, a.M, ke, m0, k0 + BK, tid);
+            vb = fetch_tile<BKC>(a.B, a.ldb, a.N, ke, n0, k0 + BK, tid);
+        }
+        bf16x8 af[2], bfv[2];
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 16) {
-            bf16x4 af[2], bfv[2];
+        for (int i = 0; i < 2; ++i) {
+            af[i] = *reinterpret_cast<const bf16x8 *>(As[buf] + (wm + 16 * i + lr) * LDT + lk8);
+            bfv[i] = *reinterpret_cast<const bf16x8 *>(Bs[buf] + (wn + 16 * i + lr) * LDT + lk8);
+        }
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                af[i] = *reinterpret_cast<const bf16x4 *>(As + (wm + 16 * i + lr) * LDT + kk + lk);
-                bfv[i] = *reinterpret_cast<const bf16x4 *>(Bs + (wn + 16 * i + lr) * LDT + kk + lk);
-            }
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfv[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfv[j], acc[i][j], 0, 0, 0);
+        if (more) {
+            store_tile<AKC>(va, As[buf ^ 1], tid);
+            store_tile<BKC>(vb, Bs[buf ^ 1], tid);
         }
         __syncthreads();
+        buf ^= 1;
     }
 
 #pragma unroll
