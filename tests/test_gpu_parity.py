@@ -387,4 +387,17 @@ def test_full_size_32cubed_N9_bf16g():
         rho = P.true_residual(host(xp), f_or)
         print(f"  bf16g {pc}: iters {sp['iters']} outer {sp['outer_iters']} t {sp['t_solve_s']:.3f}s rho* {rho:.2e}")
         assert sp["status"] == 0 and rho <= 1e-8 and sp["iters"] < st["iters"]
+    # Schwarz in the other precisions: FP32-g mixed (vector-ALU window
+    # solves by default) and FP64 (matrix-core window solves by default, then
+    # the vector-ALU ones)
+    for prec, kind in (("fp32", "auto"), ("fp64", "auto"), ("fp64", "valu")):
+        ctx.set_prec(prec)
+        ctx.set_schwarz_kernel(kind)
+        ctx.tune(prec, iters=10)
+        _case(f"cg 32^3 N=9 {prec} schwarz kernel={kind}")
+        xp, sp, _ = ctx.cg_solve(dev(f_gpu), tol=1e-8, maxit=20000)
+        rho = P.true_residual(host(xp), f_or)
+        print(f"  {prec} schwarz ({kind}): iters {sp['iters']} outer {sp['outer_iters']} t {sp['t_solve_s']:.3f}s "
+              f"rho* {rho:.2e}")
+        assert sp["status"] == 0 and rho <= 1e-8 and sp["iters"] < 100
     ctx.close()
