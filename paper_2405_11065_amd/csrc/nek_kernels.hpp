@@ -1477,9 +1477,10 @@ __global__ __launch_bounds__((NP + 2) * (NP + 2)) void k_asm_local(
     const int tid = threadIdx.x;
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int eb = (int)(((long)lb * E) / gridDim.x), ee = (int)(((long)(lb + 1) * E) / gridDim.x);
-    for (int e = eb; e < ee; ++e) {
+    for (int q = eb; q < ee; ++q) {   // column-major: z fastest (the previous window overlaps this one)
     __syncthreads();   // the previous element's LDS reads are done
-    const int ex = e % box.nx, eyz = e / box.nx, ey = eyz % box.ny, ez = eyz / box.ny;
+    const int ez = q % box.nz, col = q / box.nz, ex = col % box.nx, ey = col / box.nx;
+    const int e = ex + box.nx * (ey + box.ny * ez);
     // the modes of each direction's clipping variant, as 16-byte aligned rows
     // in LDS (a thread's pass reads one row per output or input entry)
     const int vx = (ex == 0 ? 1 : 0) + (ex == box.nx - 1 ? 2 : 0);
@@ -1749,9 +1750,10 @@ __global__ __launch_bounds__(256) void k_asm_local_mfma(
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int eb = (int)(((long)lb * E) / gridDim.x), ee = (int)(((long)(lb + 1) * E) / gridDim.x);
     auto ix = [](int a, int b, int c) { return a + PW * (b + NW * c); };
-    for (int e = eb; e < ee; ++e) {
+    for (int q = eb; q < ee; ++q) {   // column-major: z fastest (the previous window overlaps this one)
         __syncthreads();   // the previous element's LDS reads are done
-        const int ex = e % box.nx, eyz = e / box.nx, ey = eyz % box.ny, ez = eyz / box.ny;
+        const int ez = q % box.nz, col = q / box.nz, ex = col % box.nx, ey = col / box.nx;
+        const int e = ex + box.nx * (ey + box.ny * ez);
         const int vx = (ex == 0 ? 1 : 0) + (ex == box.nx - 1 ? 2 : 0);
         const int vy = (ey == 0 ? 1 : 0) + (ey == box.ny - 1 ? 2 : 0);
         const int vz = (ez == 0 ? 1 : 0) + (ez == box.nz - 1 ? 2 : 0);
@@ -1956,10 +1958,12 @@ __device__ __forceinline__ int win_cands(int i, int ed, int nd, int eo[3], int a
 // + the trilinear interpolation of the coarse correction ec (vertex lattice,
 // 0 on the boundary; weights by reference coordinate, so copies agree bit
 // for bit), 0 on Dirichlet nodes; partials of glsc3(r, c, z) to P.  A
-// workgroup of NP^2 threads walks a contiguous range of elements, thread
-// (i, j) its k-column: the x and y subdomains and the coarse weights along x
-// and y are the column's, only the z part changes along it.  With sc set, a
-// CG step of iteration it.
+// workgroup of NP^2 threads walks a contiguous range of elements in
+// column-major order (z fastest), thread (i, j) its k-column: the x and y
+// subdomains and the coarse weights along x and y are the column's, only the
+// z part changes along it, and the window below, read for the lowest layers,
+// is the one the workgroup read for the previous element.  With sc set, a CG
+// step of iteration it.
 template <int NP, typename T>
 __global__ __launch_bounds__(NP *NP) void k_asm_gather(const T *__restrict__ r, T *__restrict__ z,
                                                        const T *__restrict__ u, const double *__restrict__ ec,
@@ -1975,8 +1979,9 @@ __global__ __launch_bounds__(NP *NP) void k_asm_gather(const T *__restrict__ r, 
     const long vx = box.nx + 1, vy = box.ny + 1;
     const double lx0 = ell[i], lx1 = ell[NP + i], ly0 = ell[j], ly1 = ell[NP + j];
     double part = 0.0;
-    for (int e = e0; e < e1; ++e) {
-        const int ex = e % box.nx, eyz = e / box.nx, ey = eyz % box.ny, ez = eyz / box.ny;
+    for (int q = e0; q < e1; ++q) {
+        const int ez = q % box.nz, col = q / box.nz, ex = col % box.nx, ey = col / box.nx;
+        const int e = ex + box.nx * (ey + box.ny * ez);
         const bool dir_xy = (i == 0 && ex == 0) || (i == N && ex == box.nx - 1) || (j == 0 && ey == 0) ||
                             (j == N && ey == box.ny - 1);
         int exo[3] = {ex, ex, ex}, axo[3] = {1, 1, 1}, eyo[3] = {ey, ey, ey}, ayo[3] = {1, 1, 1};
