@@ -324,12 +324,13 @@ def kernel_roofline(ctx, prec):
 def operator_kernels(torch, nek, synth, orders=(7, 9, 11), ne=16, reps=20):
     """The plain operator pass (nek_ax_local) with its D contractions on the
     vector ALUs (the kernel form of every CG iteration) and on the matrix
-    cores, on the ne^3 box at N + 1 = 8, 10, 12, FP32 and FP64: mean time per
-    call and algorithmic bandwidth (u read, w written, six factors read)."""
+    cores, on the ne^3 box at N + 1 = 8, 10, 12, FP32, BF16-stored factors and
+    FP64: mean time per call and algorithmic bandwidth (u read, w written,
+    six factors read)."""
     out = {}
     for N in orders:
         ctx = nek.Context((ne, ne, ne), N, prec="fp64")
-        for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        for prec, dt in (("fp32", torch.float32), ("bf16g", torch.float32), ("fp64", torch.float64)):
             ctx.set_prec(prec)
             ctx.tune(prec, iters=5)
             u = torch.rand(ctx.nl, dtype=dt, device="cuda")
@@ -344,7 +345,7 @@ def operator_kernels(torch, nek, synth, orders=(7, 9, 11), ne=16, reps=20):
                     ctx.ax_local(u, w)
                 torch.cuda.synchronize()
                 t = (time.perf_counter() - t0) / reps
-                gbs = ctx.nl * 8 * u.element_size() / t / 1e9
+                gbs = ctx.nl * (2 * u.element_size() + (12 if prec == "bf16g" else 6 * u.element_size())) / t / 1e9
                 res[kind] = {"us": round(t * 1e6, 1), "GBps": round(gbs, 1)}
             ctx.set_operator_kernel("valu")
             res["mfma_over_valu_time"] = round(res["mfma"]["us"] / res["valu"]["us"], 3)
