@@ -293,6 +293,27 @@ typedef enum {
  */
 int nek_set_schwarz_kernel(nek_ctx *ctx, int kind);
 
+/* Kernel of the CG update step (dssum of w_L, mask, r -= alpha w, glsc3 of r). */
+typedef enum {
+    NEK_UPDATE_AUTO = 0,      /* exchange for FP32 vectors when every workgroup walks
+                                 at least three element groups (problems beyond
+                                 the caches), gather otherwise (the default)     */
+    NEK_UPDATE_GATHER = 1,    /* every copy of a face node read from memory      */
+    NEK_UPDATE_EXCHANGE = 2   /* FP32 vectors: x-face copies of elements walked by
+                                 one workgroup swapped through LDS (FP64 vectors
+                                 always gather)                                   */
+} nek_update_kernel;
+
+/*
+ * nek_set_update_kernel -- choose how the update kernel of the unpreconditioned
+ * and fast-diagonalization / Schwarz CG iterations collects the copies of
+ * each face node for dssum (Table 1).  Both forms add the same copies in the
+ * same fixed order with the same workgroups, so solves are bit-identical
+ * under every choice; only the time differs.  Batched solves always use
+ * NEK_UPDATE_AUTO.  NEK_E_ARG for an unknown kind.
+ */
+int nek_set_update_kernel(nek_ctx *ctx, int kind);
+
 /*
  * nek_precond_apply -- z = M^-1 r with the context's preconditioner (a copy
  * without one); r and z are device vectors of n_local entries of dtype

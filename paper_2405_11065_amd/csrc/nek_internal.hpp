@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdint>
 #include <type_traits>
 #include <vector>
@@ -23,14 +24,6 @@ constexpr int CHUNK_ITERS = 16;   // CG iterations enqueued between flag polls
         if ((expr) != hipSuccess) return NEK_E_HIP;              \
     } while (0)
 
-// Elements per workgroup of the operator kernel for each NP = N+1, chosen so
-// EPW*NP^2 fills whole 64-lane waves where possible and the FP64 LDS
-// footprint 3*EPW*NP^3*8 stays within 160 KB.
-constexpr int epw_for(int NP)
-{
-    return NP == 2 ? 16 : NP == 3 ? 7 : NP == 4 ? 8 : NP == 5 ? 5 : NP == 6 ? 7 : NP == 7 ? 9
-         : NP == 8 ? 4 : NP == 9 ? 4 : NP == 10 ? 3 : NP == 11 ? 2 : NP == 12 ? 2 : 1;
-}
 
 // Slices of geometric factors in flight per thread (register budget:
 // 12 / 6 / 3 VGPRs per slice for FP64 / FP32 / BF16 storage).
@@ -131,6 +124,7 @@ struct nek_ctx {
     int precond = 0;              // 1: diagonal (Jacobi) preconditioner in the CG loop
     int asm_kernel = NEK_SCHWARZ_AUTO;   // Schwarz window solves: matrix cores or vector ALUs
     int op_kernel = NEK_OPERATOR_VALU;   // plain operator pass (nek_ax_local, nek_ax): D contractions
+    int upd_kernel = NEK_UPDATE_AUTO;    // CG update kernel: x-face copies gathered or exchanged in LDS
     double *dg64 = nullptr;       // assembled diagonal, 1 on Dirichlet nodes
     float *dg32 = nullptr;        // its FP32 rounding (mixed inner solves)
     // fast-diagonalization preconditioner: 1-D interior modes S [(N-1)^2],
@@ -195,6 +189,13 @@ inline unsigned red_grid(const nek_ctx *c)
 }
 
 inline int ax_groups(const nek_ctx *c, int epw) { return (int)((c->E + epw - 1) / epw); }
+
+// Fewest element groups per workgroup for which the FP32 update kernel takes
+// the exchange form (nek_set_update_kernel).
+inline int upd_xmin(const nek_ctx *c)
+{
+    return c->upd_kernel == NEK_UPDATE_GATHER ? INT_MAX : c->upd_kernel == NEK_UPDATE_EXCHANGE ? 0 : UPD_X_MIN_GROUPS;
+}
 
 // Workgroups of `kernel` (block threads, static LDS only) resident on one
 // compute unit at once, at least 1.

@@ -35,6 +35,15 @@ namespace nek {
 constexpr int UPD_BS = 256;      // block size of the pointwise kernels
 constexpr int MAXB = 2048;       // cap on workgroups of any reducing kernel (partials per region)
 
+// Elements per workgroup of the operator kernel for each NP = N+1, chosen so
+// EPW*NP^2 fills whole 64-lane waves where possible and the FP64 LDS
+// footprint 3*EPW*NP^3*8 stays within 160 KB.
+constexpr int epw_for(int NP)
+{
+    return NP == 2 ? 16 : NP == 3 ? 7 : NP == 4 ? 8 : NP == 5 ? 5 : NP == 6 ? 7 : NP == 7 ? 9
+         : NP == 8 ? 4 : NP == 9 ? 4 : NP == 10 ? 3 : NP == 11 ? 2 : NP == 12 ? 2 : 1;
+}
+
 // CG state entering iteration it, in slot it & 1.
 struct IterState {
     double rtz;      // glsc3(r, c, z) of the current residual, z = M^-1 r (z = r without preconditioner)
@@ -980,7 +989,10 @@ __device__ __forceinline__ void upd_apply(const UpdCol<NP, T, PC> &c, T *__restr
 // and r stays exactly continuous.
 // With PC (diagonal preconditioner dg, 1 on Dirichlet nodes) r holds z =
 // r / m and the kernel writes the partials of glsc3(r, c, z) to P2cur and
-// of glsc3(r, c, r) to P4cur.
+// of glsc3(r, c, r) to P4cur.  For large FP32 problems the unpreconditioned
+// kernels run upd_body_x (below) instead, which takes the x-face copies
+// shared inside a workgroup from LDS and adds the same values in the same
+// order.
 template <int NP, int EPW, typename T, bool PC = false>
 __device__ __forceinline__ void upd_body(T *__restrict__ r, const T *__restrict__ w, Scal *__restrict__ sc,
                                          const double *__restrict__ P1cur, int nb1, double *__restrict__ P2cur,
@@ -1062,6 +1074,169 @@ __device__ __forceinline__ void upd_body(T *__restrict__ r, const T *__restrict_
     if (writer) sc->k2flag[it & 1] = 0;
 }
 
+// Where a column of the update kernel finds the copies at its x face.  The
+// face columns of two x-adjacent elements (i = N of the left one, i = 0 of
+// the right one, same j) need each other's copies: the partner's own column
+// is this column's x copy, the partner's y-neighbour column its xy copy and
+// the partner's z end nodes (own and y neighbour) its x and xy end nodes.
+//   xin:  the partner is in the same element group; the two swap through LDS.
+//   cin:  the partner is the last element of the group this workgroup
+//         walked just before (left face of the group's first element).
+//   cout: this column is that partner for the next group of the walk.
+// Otherwise (first group of a walk, right face of the last element) the x
+// copies are gathered from memory as in upd_load.
+struct XRole { bool xin, cin, cout; };
+
+template <int NP, int EPW, typename T>
+__device__ __forceinline__ XRole upd_load_x(UpdCol<NP, T, false> &c, const T *__restrict__ r,
+                                            const T *__restrict__ w, int grp, int g0, int g1, int el, int i, int j,
+                                            int ij, Box box, int E)
+{
+    constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = NP - 1;
+    XRole xr{false, false, false};
+    c.e = grp * EPW + el;
+    c.valid = false;
+    if (c.e >= E) return xr;
+    const int ex = c.e % box.nx;
+    const int eyz = c.e / box.nx;
+    const int ey = eyz % box.ny;
+    c.ez = eyz / box.ny;
+    if ((i == 0 && ex == 0) || (i == N && ex == box.nx - 1) || (j == 0 && ey == 0) || (j == N && ey == box.ny - 1))
+        return xr;   // the whole column lies on the Dirichlet boundary
+    c.valid = true;
+    c.hx = (i == 0 && ex > 0) || (i == N && ex < box.nx - 1);
+    c.hy = (j == 0 && ey > 0) || (j == N && ey < box.ny - 1);
+    const bool xneg = i == 0, yneg = j == 0;
+    // x-adjacent elements of one group, or of consecutive groups of one walk,
+    // are consecutive local elements; the partner exists (hx) in the same row
+    xr.xin = c.hx && (xneg ? el > 0 : el < EPW - 1);
+    xr.cin = c.hx && xneg && el == 0 && grp > g0;
+    xr.cout = c.hx && !xneg && el == EPW - 1 && grp + 1 < g1;
+    const int ox = xneg ? -1 : 1, oy = yneg ? -box.nx : box.nx;
+    const int colX = (xneg ? N : 0) + NP * j, colY = i + NP * (yneg ? N : 0);
+    const int colXY = (xneg ? N : 0) + NP * (yneg ? N : 0);
+    c.hzm = c.ez > 0;
+    c.hzp = c.ez < box.nz - 1;
+    const int oz = box.nx * box.ny;   // local indices fit in 32 bits (checked at set-up)
+#pragma unroll
+    for (int k = 0; k < NP; ++k) c.rv[k] = r[c.e * NP3 + k * NP2 + ij];
+    load_copies<NP>(w + c.e * NP3, oz, c.hx && !xr.xin && !xr.cin, c.hy, c.hzm, c.hzp, ij, ox * NP3 + colX,
+                    oy * NP3 + colY, (ox + oy) * NP3 + colXY, c.wo, c.wx, c.wy, c.wxy, c.zm, c.zp);
+    return xr;
+}
+
+// The unpreconditioned update (upd_body without PC) with x-face copies
+// exchanged in LDS between the columns that XRole pairs.  Every copy enters
+// the same fixed-order sums with the same value as when gathered from
+// memory, so the result is bit-identical to the gathering form.  A walk
+// takes consecutive element groups; the exchange buffer is double-buffered
+// and the carry between groups triple-buffered by group, so one barrier per
+// group orders every write before its reads and after the previous reads of
+// the same slot.
+template <int NP, int EPW, typename T>
+__device__ __forceinline__ void upd_body_x(T *__restrict__ r, const T *__restrict__ w, Scal *__restrict__ sc,
+                                           const double *__restrict__ P1cur, int nb1, double *__restrict__ P2cur,
+                                           int it, Box box, int E, int ngroups, unsigned blk, unsigned nblk)
+{
+    constexpr int NP2 = NP * NP, BS = EPW * NP2;
+    constexpr int FV = 2 * NP + 4, FS = FV + 1;   // published values of a face column; odd slot stride
+    __shared__ double sbuf[BS];
+    __shared__ T xf[2][EPW][2][NP][FS];   // [group parity][element][face i = 0 / i = N][j][value]
+    __shared__ T cf[3][NP][FS];           // [group mod 3][j][value]
+    const IterState cur = sc->st[it & 1];
+    if (cur.done) return;
+    const int tid = threadIdx.x;
+    const int el = tid / NP2, ij = tid - el * NP2;
+    const int i = ij % NP, j = ij / NP;
+    const int side = i == 0 ? 0 : 1;
+    const unsigned lb = xcd_block(blk, nblk);
+    const int g0 = (int)(((long)lb * ngroups) / nblk);
+    const int g1 = (int)(((long)(lb + 1) * ngroups) / nblk);
+    // FP32 columns of the first group are loaded before the reduction, FP64
+    // ones after it (held across the reduction they would cost a wave of
+    // occupancy per SIMD)
+    constexpr bool early = sizeof(T) == 4;
+    UpdCol<NP, T, false> c;
+    XRole xr{false, false, false};
+    c.valid = false;
+    if (early && g0 < g1) xr = upd_load_x<NP, EPW, T>(c, r, w, g0, g0, g1, el, i, j, ij, box, E);
+    const double pap = sum_all<BS>(P1cur, nb1, sbuf);
+    const bool writer = blk == 0 && tid == 0;
+    if (!__builtin_isfinite(pap) || !(pap > 0)) {
+        if (writer) sc->k2flag[it & 1] = __builtin_isfinite(pap) ? -5 : -6;
+        return;
+    }
+    const double alpha = cur.rtz / pap;
+    double part = 0.0, part2 = 0.0;
+    int buf = 0, c3 = 0, p3 = 2;   // exchange slot; carry slot written now and by the previous group
+    for (int grp = g0; grp < g1; ++grp) {
+        if (!early || grp > g0) xr = upd_load_x<NP, EPW, T>(c, r, w, grp, g0, g1, el, i, j, ij, box, E);
+        if (c.valid && (xr.xin || xr.cout)) {
+            T *sl = xr.xin ? xf[buf][el][side][j] : cf[c3][j];
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                sl[k] = c.wo[k];
+                sl[NP + k] = c.wy[k];
+            }
+            sl[2 * NP] = c.zm[0];
+            sl[2 * NP + 1] = c.zm[2];
+            sl[2 * NP + 2] = c.zp[0];
+            sl[2 * NP + 3] = c.zp[2];
+        }
+        __syncthreads();
+        if (c.valid) {
+            if (xr.xin || xr.cin) {
+                const T *sl = xr.xin ? xf[buf][el + (i == 0 ? -1 : 1)][side ^ 1][j] : cf[p3][j];
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    c.wx[k] = sl[k];
+                    c.wxy[k] = sl[NP + k];
+                }
+                c.zm[1] = sl[2 * NP];
+                c.zm[3] = sl[2 * NP + 1];
+                c.zp[1] = sl[2 * NP + 2];
+                c.zp[3] = sl[2 * NP + 3];
+            }
+            upd_apply<NP, T, false>(c, r, alpha, ij, box, part, part2);
+        }
+        buf ^= 1;
+        p3 = c3;
+        c3 = c3 == 2 ? 0 : c3 + 1;
+    }
+    const double s = block_sum<BS>(part, sbuf);
+    if (tid == 0) P2cur[blk] = s;
+    if (writer) sc->k2flag[it & 1] = 0;
+}
+
+// The unpreconditioned update of one workgroup.  The exchange form pays one
+// barrier per element group for the copies it does not gather; it is taken
+// for FP32 vectors when the walk has at least three groups per workgroup
+// (problems far larger than the caches, where the strided x-face gathers
+// miss: 32^3 N=9 FP32 123 -> 102 us per launch), the gathering form
+// otherwise (cache-resident problems, where the barrier costs more than the
+// gathers: 16^3 N=9 FP32 17.7 -> 19.8 us with it; and FP64, whose exchange
+// form needs 180 instead of 151 VGPRs at NP = 10, a wave per SIMD fewer).
+// Both forms add the same values in the same order with the same
+// workgroups, so they give bit-identical results and partials.
+// xmin: the fewest element groups per workgroup for the exchange form
+// (UPD_X_MIN_GROUPS by default; 0 always, INT_MAX never).
+constexpr int UPD_X_MIN_GROUPS = 3;
+
+template <int NP, int EPW, typename T>
+__device__ __forceinline__ void upd_body_nopc(T *__restrict__ r, const T *__restrict__ w, Scal *__restrict__ sc,
+                                              const double *__restrict__ P1cur, int nb1, double *__restrict__ P2cur,
+                                              int it, Box box, int E, int ngroups, unsigned blk, unsigned nblk,
+                                              int xmin)
+{
+    if constexpr (sizeof(T) == 4) {
+        if ((long)ngroups >= (long)xmin * nblk) {
+            upd_body_x<NP, EPW, T>(r, w, sc, P1cur, nb1, P2cur, it, box, E, ngroups, blk, nblk);
+            return;
+        }
+    }
+    upd_body<NP, EPW, T>(r, w, sc, P1cur, nb1, P2cur, it, box, E, ngroups, blk, nblk);
+}
+
 // wout = M o dssum(win) out of place, for whole columns: the copies of every
 // node are gathered exactly as in upd_body (same columns, same fixed pairwise
 // order), summed in FP64 and rounded once; Dirichlet nodes get 0.
@@ -1138,9 +1313,9 @@ template <int NP, int EPW, typename T>
 __global__ __launch_bounds__(EPW *NP *NP) void k_cg_update(T *__restrict__ r, const T *__restrict__ w,
                                                            Scal *__restrict__ sc, const double *__restrict__ P1cur,
                                                            int nb1, double *__restrict__ P2cur, int it, Box box,
-                                                           int E, int ngroups)
+                                                           int E, int ngroups, int xmin)
 {
-    upd_body<NP, EPW, T>(r, w, sc, P1cur, nb1, P2cur, it, box, E, ngroups, blockIdx.x, gridDim.x);
+    upd_body_nopc<NP, EPW, T>(r, w, sc, P1cur, nb1, P2cur, it, box, E, ngroups, blockIdx.x, gridDim.x, xmin);
 }
 
 // ------------------------------------------------------------- batched CG
@@ -1197,8 +1372,9 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_cg_update_batch(const BatchProb
     const BatchProb P = tab[o.x];
     if (!P.active) return;
     const int it = batch_it(base, it_local);
-    upd_body<NP, EPW, T>((T *)P.r, (const T *)P.w, P.sc, P.partials + (it & 1) * MAXB, P.nblk,
-                         P.partials + (2 + (it & 1)) * MAXB, it, P.box, P.E, P.ngroups, (unsigned)o.y, P.nblk);
+    upd_body_nopc<NP, EPW, T>((T *)P.r, (const T *)P.w, P.sc, P.partials + (it & 1) * MAXB, P.nblk,
+                              P.partials + (2 + (it & 1)) * MAXB, it, P.box, P.E, P.ngroups, (unsigned)o.y, P.nblk,
+                              UPD_X_MIN_GROUPS);
 }
 
 // out = M o sum over copies of (c o) in: the right-hand side b = M dssum(f)

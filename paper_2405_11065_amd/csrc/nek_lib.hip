@@ -1055,6 +1055,13 @@ int nek_set_schwarz_kernel(nek_ctx *c, int kind)
     return NEK_OK;
 }
 
+int nek_set_update_kernel(nek_ctx *c, int kind)
+{
+    if (!c || kind < NEK_UPDATE_AUTO || kind > NEK_UPDATE_EXCHANGE) return NEK_E_ARG;
+    c->upd_kernel = kind;
+    return NEK_OK;
+}
+
 int nek_precond_apply(nek_ctx *c, const void *r, void *z, int dtype)
 {
     if (!c || !r || !z || r == z || (dtype != NEK_F64 && dtype != NEK_F32)) return NEK_E_ARG;

@@ -65,7 +65,8 @@ template <int NP> struct OpsImpl {
                                    c->P4(it));
             else
                 hipLaunchKernelGGL((k_cg_update<NP, EPW, T>), dim3(grid), dim3(EPW * NP * NP), 0, c->stream, r, w,
-                                   c->sc, c->P1(it), (int)grid, c->P2(it), it, c->box, (int)c->E, ax_groups(c, EPW));
+                                   c->sc, c->P1(it), (int)grid, c->P2(it), it, c->box, (int)c->E, ax_groups(c, EPW),
+                                   upd_xmin(c));
             HIP_TRY(hipGetLastError());
             if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 2], c->stream));
             return NEK_OK;
@@ -177,7 +178,7 @@ template <int NP> struct OpsImpl {
             if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 1], c->stream));
             const unsigned grid = ax_grid(c, EPW, (int)sizeof(T));
             hipLaunchKernelGGL((k_cg_update<NP, EPW, T>), dim3(grid), dim3(EPW * NP * NP), 0, c->stream, r, w, c->sc,
-                               c->P1(it), (int)grid, c->P4(it), it, c->box, (int)c->E, ax_groups(c, EPW));
+                               c->P1(it), (int)grid, c->P4(it), it, c->box, (int)c->E, ax_groups(c, EPW), upd_xmin(c));
             HIP_TRY(hipGetLastError());
             if ((rc = pc_block<T>(c, r, zb, c->P2(it), grid, true, it))) return rc;
             if (slot >= 0) HIP_TRY(hipEventRecord(c->prof_pool[3 * slot + 2], c->stream));

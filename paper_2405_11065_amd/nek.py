@@ -33,7 +33,8 @@ GEOM_NAMES = {"stored": NEK_GSRC_STORED, "trilinear": NEK_GSRC_TRILINEAR}
 
 # every entry point declared in include/nek.h
 EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_set_precond", "nek_set_geometry",
-           "nek_set_max_workgroups", "nek_set_operator_kernel", "nek_set_schwarz_kernel", "nek_precond_apply", "nek_ax_local", "nek_ax", "nek_ax_noalloc",
+           "nek_set_max_workgroups", "nek_set_operator_kernel", "nek_set_schwarz_kernel",
+           "nek_set_update_kernel", "nek_precond_apply", "nek_ax_local", "nek_ax", "nek_ax_noalloc",
            "nek_dssum", "nek_glsc3", "nek_cg_solve", "nek_prof_enable", "nek_prof_read", "nek_num_variants",
            "nek_tune", "nek_set_variant", "nek_get_variant", "nek_setup_batch", "nek_batch_free",
            "nek_batch_size", "nek_batch_ctx", "nek_batch_mesh_of", "nek_batch_orders", "nek_batch_tune", "nek_batch_set_variant",
@@ -44,6 +45,7 @@ EXPORTS = ("nek_setup", "nek_free", "nek_size", "nek_get", "nek_set_prec", "nek_
 
 NEK_MAX_VARIANTS = 6
 SCHWARZ_KERNELS = {"auto": 0, "mfma": 1, "valu": 2}
+UPDATE_KERNELS = {"auto": 0, "gather": 1, "exchange": 2}
 OPERATOR_KERNELS = {"valu": 0, "mfma": 1}
 NEK_BATCH_NO_GRAPH = 1
 
@@ -97,6 +99,7 @@ def load(path: str = LIB_PATH):
     lib.nek_set_geometry.argtypes = [vp, ctypes.c_int]
     lib.nek_set_max_workgroups.argtypes = [vp, ctypes.c_int]
     lib.nek_set_schwarz_kernel.argtypes = [vp, ctypes.c_int]
+    lib.nek_set_update_kernel.argtypes = [vp, ctypes.c_int]
     lib.nek_set_operator_kernel.argtypes = [vp, ctypes.c_int]
     lib.nek_precond_apply.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nek_ax_local.argtypes = [vp, vp, vp, ctypes.c_int]
@@ -310,6 +313,12 @@ class Context:
         """Kernel of the Schwarz window solves: "auto" (default: matrix cores for FP64
         vectors, vector ALUs for FP32), "mfma" or "valu"."""
         _check(self._lib.nek_set_schwarz_kernel(self._h, SCHWARZ_KERNELS[kind]), "nek_set_schwarz_kernel")
+
+    def set_update_kernel(self, kind: str):
+        """How the CG update kernel collects the copies of face nodes: "auto"
+        (default), "gather" (all from memory) or "exchange" (FP32: x-face copies of
+        elements one workgroup walks swapped through LDS).  Bit-identical results."""
+        _check(self._lib.nek_set_update_kernel(self._h, UPDATE_KERNELS[kind]), "nek_set_update_kernel")
 
     def precond_apply(self, r, z=None):
         """z = M^-1 r with the context's preconditioner."""

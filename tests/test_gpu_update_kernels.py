@@ -1,0 +1,102 @@
+"""The two forms of the CG update kernel give bit-identical solves.
+
+The update step of every unpreconditioned (and fast-diagonalization or
+Schwarz) CG iteration sums the copies of each face node of w_L (dssum of
+Table 1), masks, and updates r.  It either gathers every copy from memory,
+or, for FP32 vectors, lets the face columns of x-adjacent elements walked by
+one workgroup swap their copies through LDS (inside an element group, and
+from one group of the walk to the next).  The same copies enter the same
+fixed-order sums in both, so whole solves must agree bit for bit: x, the
+iteration counts and the residual history, for every kernel configuration,
+with the persistent grid capped (each workgroup walks many groups, the carry
+from group to group in use) and uncapped (one group per workgroup, only the
+exchange inside a group), on meshes whose x-rows do not divide into element
+groups (groups that straddle rows).  nek_set_update_kernel selects the form;
+"auto" must match both.  The oracle judges the same kernels elsewhere (the
+capped FP32 runs of the multi-group parity tests take the exchange form).
+"""
+import numpy as np
+import pytest
+
+from paper_2405_11065_amd import nek, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    nek.load()
+
+
+def _solve(ctx, fd, form, tol=1e-8):
+    ctx.set_update_kernel(form)
+    x, st, hist = ctx.cg_solve(fd, tol=tol, maxit=3000, history=True, raise_on_noconv=True)
+    torch.cuda.synchronize()
+    return x.clone(), st, hist.copy()
+
+
+def _same(a, b, what):
+    xa, sa, ha = a
+    xb, sb, hb = b
+    assert torch.equal(xa, xb), f"{what}: x differs (max {float((xa - xb).abs().max()):.3e})"
+    assert sa["iters"] == sb["iters"] and sa["outer_iters"] == sb["outer_iters"], what
+    assert np.array_equal(ha, hb), what
+
+
+@pytest.mark.parametrize("N,nel", [(9, (5, 4, 3)), (7, (6, 3, 4)), (11, (3, 3, 2))])
+@pytest.mark.parametrize("prec", ["fp32", "bf16g"])
+def test_forms_bit_identical(N, nel, prec):
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=11)
+    nl = nel[0] * nel[1] * nel[2] * (N + 1) ** 3
+    fd = torch.from_numpy(synth.uniform_load(nl, 12)).cuda()
+    ctx = nek.Context(nel, N, vtx=vtx, prec=prec)
+    for v in range(ctx.num_variants()):
+        ctx.set_variant(prec, v)
+        for cap in (0, 3):
+            print(f"[case] N={N} nel={nel} {prec} variant {v} cap {cap}", flush=True)
+            ctx.set_max_workgroups(cap)
+            g = _solve(ctx, fd, "gather")
+            x = _solve(ctx, fd, "exchange")
+            a = _solve(ctx, fd, "auto")
+            _same(g, x, f"variant {v} cap {cap}: gather vs exchange")
+            _same(g, a, f"variant {v} cap {cap}: gather vs auto")
+            assert g[1]["true_rel_res"] <= 1e-8
+    ctx.close()
+
+
+@pytest.mark.parametrize("precond", ["fdm", "schwarz"])
+def test_forms_bit_identical_preconditioned(precond):
+    N, nel = 7, (5, 4, 4)
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=13)
+    nl = nel[0] * nel[1] * nel[2] * (N + 1) ** 3
+    fd = torch.from_numpy(synth.uniform_load(nl, 14)).cuda()
+    ctx = nek.Context(nel, N, vtx=vtx, prec="fp32", precond=precond)
+    for cap in (0, 3):
+        print(f"[case] {precond} N={N} nel={nel} cap {cap}", flush=True)
+        ctx.set_max_workgroups(cap)
+        _same(_solve(ctx, fd, "gather"), _solve(ctx, fd, "exchange"), f"{precond} cap {cap}")
+    ctx.close()
+
+
+def test_fp64_ignores_exchange():
+    """FP64 vectors always gather: the choice changes nothing."""
+    N, nel = 9, (4, 3, 3)
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=15)
+    nl = nel[0] * nel[1] * nel[2] * (N + 1) ** 3
+    fd = torch.from_numpy(synth.uniform_load(nl, 16)).cuda()
+    ctx = nek.Context(nel, N, vtx=vtx, prec="fp64")
+    ctx.set_max_workgroups(3)
+    _same(_solve(ctx, fd, "gather"), _solve(ctx, fd, "exchange"), "fp64")
+    ctx.close()
+
+
+def test_unknown_kind_refused():
+    ctx = nek.Context((2, 2, 2), 3)
+    with pytest.raises(KeyError):
+        ctx.set_update_kernel("lds")
+    assert ctx._lib.nek_set_update_kernel(ctx._h, 3) == nek.NEK_E_ARG
+    assert ctx._lib.nek_set_update_kernel(ctx._h, -1) == nek.NEK_E_ARG
+    ctx.close()
