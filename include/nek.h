@@ -305,12 +305,14 @@ typedef enum {
 } nek_update_kernel;
 
 /*
- * nek_set_update_kernel -- choose how the update kernel of the unpreconditioned
- * and fast-diagonalization / Schwarz CG iterations collects the copies of
- * each face node for dssum (Table 1).  Both forms add the same copies in the
- * same fixed order with the same workgroups, so solves are bit-identical
- * under every choice; only the time differs.  Batched solves always use
- * NEK_UPDATE_AUTO.  NEK_E_ARG for an unknown kind.
+ * nek_set_update_kernel -- choose how the kernels that sum the copies of each
+ * face node for dssum (Table 1) collect them: the update kernel of the
+ * unpreconditioned and fast-diagonalization / Schwarz CG iterations, and the
+ * assembly pass of nek_ax and nek_ax_noalloc.  Both forms add the same
+ * copies in the same fixed order (the CG update with the same workgroups and
+ * partials), so solves and nek_ax results are bit-identical under every
+ * choice; only the time differs.  Batched solves always use NEK_UPDATE_AUTO.
+ * NEK_E_ARG for an unknown kind.
  */
 int nek_set_update_kernel(nek_ctx *ctx, int kind);
 

@@ -1085,18 +1085,20 @@ __device__ __forceinline__ void upd_body(T *__restrict__ r, const T *__restrict_
 //   cout: this column is that partner for the next group of the walk.
 // Otherwise (first group of a walk, right face of the last element) the x
 // copies are gathered from memory as in upd_load.
-struct XRole { bool xin, cin, cout; };
+struct XRole { bool xin, cin, cout, in_mesh; };
 
-template <int NP, int EPW, typename T>
+// WITH_R: also the column of r (the update kernel; the assembly reads only w).
+template <int NP, int EPW, typename T, bool WITH_R = true>
 __device__ __forceinline__ XRole upd_load_x(UpdCol<NP, T, false> &c, const T *__restrict__ r,
                                             const T *__restrict__ w, int grp, int g0, int g1, int el, int i, int j,
                                             int ij, Box box, int E)
 {
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = NP - 1;
-    XRole xr{false, false, false};
+    XRole xr{false, false, false, false};
     c.e = grp * EPW + el;
     c.valid = false;
     if (c.e >= E) return xr;
+    xr.in_mesh = true;
     const int ex = c.e % box.nx;
     const int eyz = c.e / box.nx;
     const int ey = eyz % box.ny;
@@ -1118,11 +1120,43 @@ __device__ __forceinline__ XRole upd_load_x(UpdCol<NP, T, false> &c, const T *__
     c.hzm = c.ez > 0;
     c.hzp = c.ez < box.nz - 1;
     const int oz = box.nx * box.ny;   // local indices fit in 32 bits (checked at set-up)
+    if constexpr (WITH_R) {
 #pragma unroll
-    for (int k = 0; k < NP; ++k) c.rv[k] = r[c.e * NP3 + k * NP2 + ij];
+        for (int k = 0; k < NP; ++k) c.rv[k] = r[c.e * NP3 + k * NP2 + ij];
+    }
     load_copies<NP>(w + c.e * NP3, oz, c.hx && !xr.xin && !xr.cin, c.hy, c.hzm, c.hzp, ij, ox * NP3 + colX,
                     oy * NP3 + colY, (ox + oy) * NP3 + colXY, c.wo, c.wx, c.wy, c.wxy, c.zm, c.zp);
     return xr;
+}
+
+// A face column's values for its x partner (2 NP + 4 entries at sl), and the
+// partner's values taken as this column's x and xy copies.
+template <int NP, typename T>
+__device__ __forceinline__ void xf_publish(T *sl, const UpdCol<NP, T, false> &c)
+{
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        sl[k] = c.wo[k];
+        sl[NP + k] = c.wy[k];
+    }
+    sl[2 * NP] = c.zm[0];
+    sl[2 * NP + 1] = c.zm[2];
+    sl[2 * NP + 2] = c.zp[0];
+    sl[2 * NP + 3] = c.zp[2];
+}
+
+template <int NP, typename T>
+__device__ __forceinline__ void xf_take(const T *sl, UpdCol<NP, T, false> &c)
+{
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        c.wx[k] = sl[k];
+        c.wxy[k] = sl[NP + k];
+    }
+    c.zm[1] = sl[2 * NP];
+    c.zm[3] = sl[2 * NP + 1];
+    c.zp[1] = sl[2 * NP + 2];
+    c.zp[3] = sl[2 * NP + 3];
 }
 
 // The unpreconditioned update (upd_body without PC) with x-face copies
@@ -1171,32 +1205,10 @@ __device__ __forceinline__ void upd_body_x(T *__restrict__ r, const T *__restric
     int buf = 0, c3 = 0, p3 = 2;   // exchange slot; carry slot written now and by the previous group
     for (int grp = g0; grp < g1; ++grp) {
         if (!early || grp > g0) xr = upd_load_x<NP, EPW, T>(c, r, w, grp, g0, g1, el, i, j, ij, box, E);
-        if (c.valid && (xr.xin || xr.cout)) {
-            T *sl = xr.xin ? xf[buf][el][side][j] : cf[c3][j];
-#pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                sl[k] = c.wo[k];
-                sl[NP + k] = c.wy[k];
-            }
-            sl[2 * NP] = c.zm[0];
-            sl[2 * NP + 1] = c.zm[2];
-            sl[2 * NP + 2] = c.zp[0];
-            sl[2 * NP + 3] = c.zp[2];
-        }
+        if (c.valid && (xr.xin || xr.cout)) xf_publish<NP, T>(xr.xin ? xf[buf][el][side][j] : cf[c3][j], c);
         __syncthreads();
         if (c.valid) {
-            if (xr.xin || xr.cin) {
-                const T *sl = xr.xin ? xf[buf][el + (i == 0 ? -1 : 1)][side ^ 1][j] : cf[p3][j];
-#pragma unroll
-                for (int k = 0; k < NP; ++k) {
-                    c.wx[k] = sl[k];
-                    c.wxy[k] = sl[NP + k];
-                }
-                c.zm[1] = sl[2 * NP];
-                c.zm[3] = sl[2 * NP + 1];
-                c.zp[1] = sl[2 * NP + 2];
-                c.zp[3] = sl[2 * NP + 3];
-            }
+            if (xr.xin || xr.cin) xf_take<NP, T>(xr.xin ? xf[buf][el + (i == 0 ? -1 : 1)][side ^ 1][j] : cf[p3][j], c);
             upd_apply<NP, T, false>(c, r, alpha, ij, box, part, part2);
         }
         buf ^= 1;
@@ -1285,6 +1297,56 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_assemble(const T *__restrict__ 
             const bool dir = (k == 0 && ez == 0) || (k == N && ez == box.nz - 1);
             oe[k * NP2 + ij] = dir ? (T)0 : (T)S;
         }
+    }
+}
+
+// k_assemble with the x-face copies of elements walked by one workgroup
+// swapped through LDS (see upd_body_x): a capped grid of workgroups, each
+// walking consecutive element groups.  The same values enter the same sums,
+// so the output is bit-identical to k_assemble's.
+template <int NP, int EPW, typename T>
+__global__ __launch_bounds__(EPW *NP *NP) void k_assemble_x(const T *__restrict__ win, T *__restrict__ wout, Box box,
+                                                            int E, int ngroups)
+{
+    constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = NP - 1;
+    constexpr int FS = 2 * NP + 5;
+    __shared__ T xf[2][EPW][2][NP][FS];
+    __shared__ T cf[3][NP][FS];
+    const int tid = threadIdx.x;
+    const int el = tid / NP2, ij = tid - el * NP2;
+    const int i = ij % NP, j = ij / NP;
+    const int side = i == 0 ? 0 : 1;
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int g0 = (int)(((long)lb * ngroups) / gridDim.x);
+    const int g1 = (int)(((long)(lb + 1) * ngroups) / gridDim.x);
+    int buf = 0, c3 = 0, p3 = 2;
+    for (int grp = g0; grp < g1; ++grp) {
+        UpdCol<NP, T, false> c;
+        const XRole xr = upd_load_x<NP, EPW, T, false>(c, nullptr, win, grp, g0, g1, el, i, j, ij, box, E);
+        if (c.valid && (xr.xin || xr.cout)) xf_publish<NP, T>(xr.xin ? xf[buf][el][side][j] : cf[c3][j], c);
+        __syncthreads();
+        if (xr.in_mesh) {
+            T *oe = wout + c.e * NP3;
+            if (!c.valid) {   // a column on the x or y Dirichlet faces
+#pragma unroll
+                for (int k = 0; k < NP; ++k) oe[k * NP2 + ij] = (T)0;
+            } else {
+                if (xr.xin || xr.cin)
+                    xf_take<NP, T>(xr.xin ? xf[buf][el + (i == 0 ? -1 : 1)][side ^ 1][j] : cf[p3][j], c);
+                auto plane = [](double o, double X, double Y, double XY) -> double { return (o + X) + (Y + XY); };
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    double S = plane((double)c.wo[k], (double)c.wx[k], (double)c.wy[k], (double)c.wxy[k]);
+                    if (k == 0 && c.hzm) S = plane((double)c.zm[0], (double)c.zm[1], (double)c.zm[2], (double)c.zm[3]) + S;
+                    if (k == N && c.hzp) S = S + plane((double)c.zp[0], (double)c.zp[1], (double)c.zp[2], (double)c.zp[3]);
+                    const bool dir = (k == 0 && c.ez == 0) || (k == N && c.ez == box.nz - 1);
+                    oe[k * NP2 + ij] = dir ? (T)0 : (T)S;
+                }
+            }
+        }
+        buf ^= 1;
+        p3 = c3;
+        c3 = c3 == 2 ? 0 : c3 + 1;
     }
 }
 

@@ -12,7 +12,9 @@ with the persistent grid capped (each workgroup walks many groups, the carry
 from group to group in use) and uncapped (one group per workgroup, only the
 exchange inside a group), on meshes whose x-rows do not divide into element
 groups (groups that straddle rows).  nek_set_update_kernel selects the form;
-"auto" must match both.  The oracle judges the same kernels elsewhere (the
+"auto" must match both.  nek_ax's assembly pass has the same two forms (the
+exchange on a capped grid of walking workgroups); its output must agree bit
+for bit too.  The oracle judges the same kernels elsewhere (the
 capped FP32 runs of the multi-group parity tests take the exchange form).
 """
 import numpy as np
@@ -78,6 +80,31 @@ def test_forms_bit_identical_preconditioned(precond):
         print(f"[case] {precond} N={N} nel={nel} cap {cap}", flush=True)
         ctx.set_max_workgroups(cap)
         _same(_solve(ctx, fd, "gather"), _solve(ctx, fd, "exchange"), f"{precond} cap {cap}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("N,nel", [(9, (5, 4, 3)), (7, (7, 3, 3))])
+@pytest.mark.parametrize("prec", ["fp32", "bf16g"])
+def test_assembly_forms_bit_identical(N, nel, prec):
+    vtx = synth.box_vertices(nel, perturb=0.1, seed=17)
+    nl = nel[0] * nel[1] * nel[2] * (N + 1) ** 3
+    u = torch.from_numpy(synth.uniform_load(nl, 18)).cuda().float()
+    ctx = nek.Context(nel, N, vtx=vtx, prec=prec)
+    for v in range(ctx.num_variants()):
+        ctx.set_variant(prec, v)
+        for cap in (0, 3):
+            print(f"[case] nek_ax N={N} nel={nel} {prec} variant {v} cap {cap}", flush=True)
+            ctx.set_max_workgroups(cap)
+            out = {}
+            for form in ("gather", "exchange", "auto"):
+                ctx.set_update_kernel(form)
+                out[form] = ctx.ax(u).clone()
+                w2 = torch.empty_like(u)
+                ctx.ax_noalloc(u, w2)
+                assert torch.equal(out[form], w2), f"{form}: nek_ax_noalloc differs from nek_ax"
+            torch.cuda.synchronize()
+            assert torch.equal(out["gather"], out["exchange"]), f"variant {v} cap {cap}"
+            assert torch.equal(out["gather"], out["auto"]), f"variant {v} cap {cap}"
     ctx.close()
 
 
