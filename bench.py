@@ -43,11 +43,11 @@ COUNTER_TRAFFIC = {
     "sources": {
         ("paper_2405_11065_amd/csrc/nek_kernels.hpp", "// --------------------------------------------------"
          "--------- gather-scatter"):
-            "116354477cee01fd79e98d97dc48f9851556400e8daafb1694811523d2e581b7",
+            "e755ca80903cb8ed92ec86b0932793b3385e1fec0fe52efeea909951b882a7e2",
         ("paper_2405_11065_amd/csrc/nek_np.hpp", None):
-            "897375afc226177839ed0784cc6f8fa2a2f3df3ca9b8396d054a7e781b0c6d93",
+            "626b06a649b0effd6ff7419a2ca558c48314f11317023a8c5f2822bd8a2e762e",
         ("paper_2405_11065_amd/csrc/nek_internal.hpp", None):
-            "c928ec840f63d8758b8da6567c51b574efa3d80ce71b25d7a7f8e6d3c31fbbb5",
+            "00c7a956b1aeecbba6133afe0fee3b2c4a3305f86be6e86c24084d683ebea5fd",
     },
     "bytes_per_launch": {4: 226_600_000, 5: 226_300_000},   # FP32 configuration -> bytes
 }
