@@ -127,3 +127,29 @@ def test_unknown_kind_refused():
     assert ctx._lib.nek_set_update_kernel(ctx._h, 3) == nek.NEK_E_ARG
     assert ctx._lib.nek_set_update_kernel(ctx._h, -1) == nek.NEK_E_ARG
     ctx.close()
+
+
+@pytest.mark.parametrize("N", list(range(1, 16)))
+def test_forms_bit_identical_every_order(N):
+    """Every order's exchange form (compiled per order, with its own elements
+    per workgroup): a capped grid puts each workgroup on several groups, so the
+    in-group exchange and the carry both run; solves and nek_ax must equal the
+    gathering form's bit for bit.  FP32 vectors; the default configuration."""
+    nel = (7, 2, 3)
+    vtx = synth.box_vertices(nel, perturb=0.1 if N > 1 else 0.0, seed=19)
+    nl = nel[0] * nel[1] * nel[2] * (N + 1) ** 3
+    f = synth.uniform_load(nl, 20)
+    fd = torch.from_numpy(f).cuda()
+    ctx = nek.Context(nel, N, vtx=vtx, prec="fp32")
+    for cap in (2, 5):
+        print(f"[case] N={N} nel={nel} fp32 cap {cap}", flush=True)
+        ctx.set_max_workgroups(cap)
+        _same(_solve(ctx, fd, "gather"), _solve(ctx, fd, "exchange"), f"N={N} cap {cap}")
+        u = fd.float()
+        ctx.set_update_kernel("gather")
+        wg = ctx.ax(u).clone()
+        ctx.set_update_kernel("exchange")
+        wx = ctx.ax(u).clone()
+        torch.cuda.synchronize()
+        assert torch.equal(wg, wx), f"nek_ax N={N} cap {cap}"
+    ctx.close()
