@@ -37,15 +37,16 @@ PEAK_HBM_GBS = 8000.0
 # holds the runs.  The figure is reported only while the source that the
 # operator kernel compiles from still hashes to the SHA-256 digests below:
 # nek_kernels.hpp up to its gather-scatter section (the operator kernel and
-# every helper it calls), and the launch and context headers in full.
-# Later edits to other kernels in nek_kernels.hpp leave it valid.
+# every helper it calls), nek_np.hpp up to its CG iteration launchers (the
+# operator's launch), and the context header in full.  Later edits to other
+# kernels and launchers leave it valid.
 COUNTER_TRAFFIC = {
     "sources": {
         ("paper_2405_11065_amd/csrc/nek_kernels.hpp", "// --------------------------------------------------"
          "--------- gather-scatter"):
             "e755ca80903cb8ed92ec86b0932793b3385e1fec0fe52efeea909951b882a7e2",
-        ("paper_2405_11065_amd/csrc/nek_np.hpp", None):
-            "626b06a649b0effd6ff7419a2ca558c48314f11317023a8c5f2822bd8a2e762e",
+        ("paper_2405_11065_amd/csrc/nek_np.hpp", "    // CG iteration it (1-based)"):
+            "5370dc438f42553ad0db76050ddf7632b23cda5b1e5852145f73621ea40220f6",
         ("paper_2405_11065_amd/csrc/nek_internal.hpp", None):
             "00c7a956b1aeecbba6133afe0fee3b2c4a3305f86be6e86c24084d683ebea5fd",
     },

@@ -295,13 +295,12 @@ int nek_set_schwarz_kernel(nek_ctx *ctx, int kind);
 
 /* Kernel of the CG update step (dssum of w_L, mask, r -= alpha w, glsc3 of r). */
 typedef enum {
-    NEK_UPDATE_AUTO = 0,      /* exchange for FP32 vectors when every workgroup walks
-                                 at least three element groups (problems beyond
-                                 the caches), gather otherwise (the default)     */
+    NEK_UPDATE_AUTO = 0,      /* exchange when every workgroup walks at least three
+                                 element groups (problems beyond the caches),
+                                 gather otherwise (the default)                   */
     NEK_UPDATE_GATHER = 1,    /* every copy of a face node read from memory      */
-    NEK_UPDATE_EXCHANGE = 2   /* FP32 vectors: x-face copies of elements walked by
-                                 one workgroup swapped through LDS (FP64 vectors
-                                 always gather)                                   */
+    NEK_UPDATE_EXCHANGE = 2   /* x-face copies of elements walked by one workgroup
+                                 swapped through LDS                              */
 } nek_update_kernel;
 
 /*

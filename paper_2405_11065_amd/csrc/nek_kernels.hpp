@@ -989,7 +989,7 @@ __device__ __forceinline__ void upd_apply(const UpdCol<NP, T, PC> &c, T *__restr
 // and r stays exactly continuous.
 // With PC (diagonal preconditioner dg, 1 on Dirichlet nodes) r holds z =
 // r / m and the kernel writes the partials of glsc3(r, c, z) to P2cur and
-// of glsc3(r, c, r) to P4cur.  For large FP32 problems the unpreconditioned
+// of glsc3(r, c, r) to P4cur.  For large problems the unpreconditioned
 // kernels run upd_body_x (below) instead, which takes the x-face copies
 // shared inside a workgroup from LDS and adds the same values in the same
 // order.
@@ -1087,11 +1087,12 @@ __device__ __forceinline__ void upd_body(T *__restrict__ r, const T *__restrict_
 // copies are gathered from memory as in upd_load.
 struct XRole { bool xin, cin, cout, in_mesh; };
 
-// WITH_R: also the column of r (the update kernel; the assembly reads only w).
-template <int NP, int EPW, typename T, bool WITH_R = true>
-__device__ __forceinline__ XRole upd_load_x(UpdCol<NP, T, false> &c, const T *__restrict__ r,
-                                            const T *__restrict__ w, int grp, int g0, int g1, int el, int i, int j,
-                                            int ij, Box box, int E)
+// The copies of one column (of w; the update kernel reads its column of r
+// after the exchange, which keeps fewer registers live across the barrier:
+// 162 instead of 176 VGPRs for FP64 at NP = 10, three waves per SIMD).
+template <int NP, int EPW, typename T>
+__device__ __forceinline__ XRole upd_load_x(UpdCol<NP, T, false> &c, const T *__restrict__ w, int grp, int g0,
+                                            int g1, int el, int i, int j, int ij, Box box, int E)
 {
     constexpr int NP2 = NP * NP, NP3 = NP2 * NP, N = NP - 1;
     XRole xr{false, false, false, false};
@@ -1120,10 +1121,6 @@ __device__ __forceinline__ XRole upd_load_x(UpdCol<NP, T, false> &c, const T *__
     c.hzm = c.ez > 0;
     c.hzp = c.ez < box.nz - 1;
     const int oz = box.nx * box.ny;   // local indices fit in 32 bits (checked at set-up)
-    if constexpr (WITH_R) {
-#pragma unroll
-        for (int k = 0; k < NP; ++k) c.rv[k] = r[c.e * NP3 + k * NP2 + ij];
-    }
     load_copies<NP>(w + c.e * NP3, oz, c.hx && !xr.xin && !xr.cin, c.hy, c.hzm, c.hzp, ij, ox * NP3 + colX,
                     oy * NP3 + colY, (ox + oy) * NP3 + colXY, c.wo, c.wx, c.wy, c.wxy, c.zm, c.zp);
     return xr;
@@ -1186,14 +1183,14 @@ __device__ __forceinline__ void upd_body_x(T *__restrict__ r, const T *__restric
     const unsigned lb = xcd_block(blk, nblk);
     const int g0 = (int)(((long)lb * ngroups) / nblk);
     const int g1 = (int)(((long)(lb + 1) * ngroups) / nblk);
-    // FP32 columns of the first group are loaded before the reduction, FP64
+    // FP32 copies of the first group are loaded before the reduction, FP64
     // ones after it (held across the reduction they would cost a wave of
     // occupancy per SIMD)
     constexpr bool early = sizeof(T) == 4;
     UpdCol<NP, T, false> c;
-    XRole xr{false, false, false};
+    XRole xr{false, false, false, false};
     c.valid = false;
-    if (early && g0 < g1) xr = upd_load_x<NP, EPW, T>(c, r, w, g0, g0, g1, el, i, j, ij, box, E);
+    if (early && g0 < g1) xr = upd_load_x<NP, EPW, T>(c, w, g0, g0, g1, el, i, j, ij, box, E);
     const double pap = sum_all<BS>(P1cur, nb1, sbuf);
     const bool writer = blk == 0 && tid == 0;
     if (!__builtin_isfinite(pap) || !(pap > 0)) {
@@ -1204,10 +1201,12 @@ __device__ __forceinline__ void upd_body_x(T *__restrict__ r, const T *__restric
     double part = 0.0, part2 = 0.0;
     int buf = 0, c3 = 0, p3 = 2;   // exchange slot; carry slot written now and by the previous group
     for (int grp = g0; grp < g1; ++grp) {
-        if (!early || grp > g0) xr = upd_load_x<NP, EPW, T>(c, r, w, grp, g0, g1, el, i, j, ij, box, E);
+        if (!early || grp > g0) xr = upd_load_x<NP, EPW, T>(c, w, grp, g0, g1, el, i, j, ij, box, E);
         if (c.valid && (xr.xin || xr.cout)) xf_publish<NP, T>(xr.xin ? xf[buf][el][side][j] : cf[c3][j], c);
         __syncthreads();
         if (c.valid) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) c.rv[k] = r[c.e * NP2 * NP + k * NP2 + ij];
             if (xr.xin || xr.cin) xf_take<NP, T>(xr.xin ? xf[buf][el + (i == 0 ? -1 : 1)][side ^ 1][j] : cf[p3][j], c);
             upd_apply<NP, T, false>(c, r, alpha, ij, box, part, part2);
         }
@@ -1222,14 +1221,13 @@ __device__ __forceinline__ void upd_body_x(T *__restrict__ r, const T *__restric
 
 // The unpreconditioned update of one workgroup.  The exchange form pays one
 // barrier per element group for the copies it does not gather; it is taken
-// for FP32 vectors when the walk has at least three groups per workgroup
-// (problems far larger than the caches, where the strided x-face gathers
-// miss: 32^3 N=9 FP32 123 -> 102 us per launch), the gathering form
-// otherwise (cache-resident problems, where the barrier costs more than the
-// gathers: 16^3 N=9 FP32 17.7 -> 19.8 us with it; and FP64, whose exchange
-// form needs 180 instead of 151 VGPRs at NP = 10, a wave per SIMD fewer).
-// Both forms add the same values in the same order with the same
-// workgroups, so they give bit-identical results and partials.
+// when the walk has at least three groups per workgroup (problems far
+// larger than the caches, where the strided x-face gathers miss: 32^3 N=9
+// FP32 123 -> 102 us per launch), the gathering form otherwise
+// (cache-resident problems, where the barrier costs more than the gathers:
+// 16^3 N=9 FP32 17.7 -> 19.8 us with it).  Both forms add the same values
+// in the same order with the same workgroups, so they give bit-identical
+// results and partials.
 // xmin: the fewest element groups per workgroup for the exchange form
 // (UPD_X_MIN_GROUPS by default; 0 always, INT_MAX never).
 constexpr int UPD_X_MIN_GROUPS = 3;
@@ -1240,11 +1238,9 @@ __device__ __forceinline__ void upd_body_nopc(T *__restrict__ r, const T *__rest
                                               int it, Box box, int E, int ngroups, unsigned blk, unsigned nblk,
                                               int xmin)
 {
-    if constexpr (sizeof(T) == 4) {
-        if ((long)ngroups >= (long)xmin * nblk) {
-            upd_body_x<NP, EPW, T>(r, w, sc, P1cur, nb1, P2cur, it, box, E, ngroups, blk, nblk);
-            return;
-        }
+    if ((long)ngroups >= (long)xmin * nblk) {
+        upd_body_x<NP, EPW, T>(r, w, sc, P1cur, nb1, P2cur, it, box, E, ngroups, blk, nblk);
+        return;
     }
     upd_body<NP, EPW, T>(r, w, sc, P1cur, nb1, P2cur, it, box, E, ngroups, blk, nblk);
 }
@@ -1322,7 +1318,7 @@ __global__ __launch_bounds__(EPW *NP *NP) void k_assemble_x(const T *__restrict_
     int buf = 0, c3 = 0, p3 = 2;
     for (int grp = g0; grp < g1; ++grp) {
         UpdCol<NP, T, false> c;
-        const XRole xr = upd_load_x<NP, EPW, T, false>(c, nullptr, win, grp, g0, g1, el, i, j, ij, box, E);
+        const XRole xr = upd_load_x<NP, EPW, T>(c, win, grp, g0, g1, el, i, j, ij, box, E);
         if (c.valid && (xr.xin || xr.cout)) xf_publish<NP, T>(xr.xin ? xf[buf][el][side][j] : cf[c3][j], c);
         __syncthreads();
         if (xr.in_mesh) {

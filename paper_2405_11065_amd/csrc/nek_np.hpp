@@ -264,17 +264,15 @@ template <int NP> struct OpsImpl {
             constexpr int EPW = decltype(epw_c)::value, PD = decltype(pd_c)::value;
             int rc = launch_ax<EPW, PD, T, GT, false>(c, u, nullptr, scratch, g, D, 0);
             if (rc) return rc;
-            // FP32: the exchange form on a capped grid when every workgroup
-            // walks enough groups (the choice of the update kernel)
+            // the exchange form on a capped grid when every workgroup walks
+            // enough groups (the choice of the update kernel)
             const int groups = ax_groups(c, EPW);
-            if constexpr (sizeof(T) == 4) {
-                const unsigned cap = ax_grid(c, EPW, (int)sizeof(T));
-                if ((long)groups >= (long)upd_xmin(c) * cap) {
-                    hipLaunchKernelGGL((k_assemble_x<NP, EPW, T>), dim3(cap), dim3(EPW * NP * NP), 0, c->stream,
-                                       scratch, w, c->box, (int)c->E, groups);
-                    HIP_TRY(hipGetLastError());
-                    return NEK_OK;
-                }
+            const unsigned cap = ax_grid(c, EPW, (int)sizeof(T));
+            if ((long)groups >= (long)upd_xmin(c) * cap) {
+                hipLaunchKernelGGL((k_assemble_x<NP, EPW, T>), dim3(cap), dim3(EPW * NP * NP), 0, c->stream, scratch,
+                                   w, c->box, (int)c->E, groups);
+                HIP_TRY(hipGetLastError());
+                return NEK_OK;
             }
             hipLaunchKernelGGL((k_assemble<NP, EPW, T>), dim3(groups), dim3(EPW * NP * NP), 0, c->stream, scratch, w,
                                c->box, (int)c->E, groups);

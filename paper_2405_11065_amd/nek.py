@@ -315,9 +315,9 @@ class Context:
         _check(self._lib.nek_set_schwarz_kernel(self._h, SCHWARZ_KERNELS[kind]), "nek_set_schwarz_kernel")
 
     def set_update_kernel(self, kind: str):
-        """How the CG update kernel collects the copies of face nodes: "auto"
-        (default), "gather" (all from memory) or "exchange" (FP32: x-face copies of
-        elements one workgroup walks swapped through LDS).  Bit-identical results."""
+        """How the CG update kernel and nek_ax's assembly collect the copies of face
+        nodes: "auto" (default), "gather" (all from memory) or "exchange" (x-face copies
+        of elements one workgroup walks swapped through LDS).  Bit-identical results."""
         _check(self._lib.nek_set_update_kernel(self._h, UPDATE_KERNELS[kind]), "nek_set_update_kernel")
 
     def precond_apply(self, r, z=None):

@@ -3,8 +3,8 @@
 The update step of every unpreconditioned (and fast-diagonalization or
 Schwarz) CG iteration sums the copies of each face node of w_L (dssum of
 Table 1), masks, and updates r.  It either gathers every copy from memory,
-or, for FP32 vectors, lets the face columns of x-adjacent elements walked by
-one workgroup swap their copies through LDS (inside an element group, and
+or lets the face columns of x-adjacent elements walked by one workgroup
+swap their copies through LDS (inside an element group, and
 from one group of the walk to the next).  The same copies enter the same
 fixed-order sums in both, so whole solves must agree bit for bit: x, the
 iteration counts and the residual history, for every kernel configuration,
@@ -14,8 +14,8 @@ exchange inside a group), on meshes whose x-rows do not divide into element
 groups (groups that straddle rows).  nek_set_update_kernel selects the form;
 "auto" must match both.  nek_ax's assembly pass has the same two forms (the
 exchange on a capped grid of walking workgroups); its output must agree bit
-for bit too.  The oracle judges the same kernels elsewhere (the
-capped FP32 runs of the multi-group parity tests take the exchange form).
+for bit too.  The oracle judges the same kernels elsewhere (the capped
+FP32 and FP64 runs of the multi-group parity tests take the exchange form).
 """
 import numpy as np
 import pytest
@@ -108,15 +108,25 @@ def test_assembly_forms_bit_identical(N, nel, prec):
     ctx.close()
 
 
-def test_fp64_ignores_exchange():
-    """FP64 vectors always gather: the choice changes nothing."""
-    N, nel = 9, (4, 3, 3)
+@pytest.mark.parametrize("cap", [0, 3])
+def test_fp64_forms_bit_identical(cap):
+    """FP64 vectors: solves and nek_ax, both forms, every configuration."""
+    N, nel = 9, (5, 3, 3)
     vtx = synth.box_vertices(nel, perturb=0.1, seed=15)
     nl = nel[0] * nel[1] * nel[2] * (N + 1) ** 3
     fd = torch.from_numpy(synth.uniform_load(nl, 16)).cuda()
     ctx = nek.Context(nel, N, vtx=vtx, prec="fp64")
-    ctx.set_max_workgroups(3)
-    _same(_solve(ctx, fd, "gather"), _solve(ctx, fd, "exchange"), "fp64")
+    ctx.set_max_workgroups(cap)
+    for v in range(ctx.num_variants()):
+        print(f"[case] fp64 N={N} nel={nel} variant {v} cap {cap}", flush=True)
+        ctx.set_variant("fp64", v)
+        _same(_solve(ctx, fd, "gather"), _solve(ctx, fd, "exchange"), f"fp64 variant {v} cap {cap}")
+        ctx.set_update_kernel("gather")
+        wg = ctx.ax(fd).clone()
+        ctx.set_update_kernel("exchange")
+        wx = ctx.ax(fd).clone()
+        torch.cuda.synchronize()
+        assert torch.equal(wg, wx), f"fp64 nek_ax variant {v} cap {cap}"
     ctx.close()
 
 
@@ -134,22 +144,24 @@ def test_forms_bit_identical_every_order(N):
     """Every order's exchange form (compiled per order, with its own elements
     per workgroup): a capped grid puts each workgroup on several groups, so the
     in-group exchange and the carry both run; solves and nek_ax must equal the
-    gathering form's bit for bit.  FP32 vectors; the default configuration."""
+    gathering form's bit for bit, for FP32 and FP64 vectors in the default
+    configuration."""
     nel = (7, 2, 3)
     vtx = synth.box_vertices(nel, perturb=0.1 if N > 1 else 0.0, seed=19)
     nl = nel[0] * nel[1] * nel[2] * (N + 1) ** 3
     f = synth.uniform_load(nl, 20)
     fd = torch.from_numpy(f).cuda()
-    ctx = nek.Context(nel, N, vtx=vtx, prec="fp32")
-    for cap in (2, 5):
-        print(f"[case] N={N} nel={nel} fp32 cap {cap}", flush=True)
-        ctx.set_max_workgroups(cap)
-        _same(_solve(ctx, fd, "gather"), _solve(ctx, fd, "exchange"), f"N={N} cap {cap}")
-        u = fd.float()
-        ctx.set_update_kernel("gather")
-        wg = ctx.ax(u).clone()
-        ctx.set_update_kernel("exchange")
-        wx = ctx.ax(u).clone()
-        torch.cuda.synchronize()
-        assert torch.equal(wg, wx), f"nek_ax N={N} cap {cap}"
-    ctx.close()
+    for prec in ("fp32", "fp64"):
+        ctx = nek.Context(nel, N, vtx=vtx, prec=prec)
+        u = fd.float() if prec == "fp32" else fd
+        for cap in (2, 5):
+            print(f"[case] N={N} nel={nel} {prec} cap {cap}", flush=True)
+            ctx.set_max_workgroups(cap)
+            _same(_solve(ctx, fd, "gather"), _solve(ctx, fd, "exchange"), f"N={N} {prec} cap {cap}")
+            ctx.set_update_kernel("gather")
+            wg = ctx.ax(u).clone()
+            ctx.set_update_kernel("exchange")
+            wx = ctx.ax(u).clone()
+            torch.cuda.synchronize()
+            assert torch.equal(wg, wx), f"nek_ax N={N} {prec} cap {cap}"
+        ctx.close()
