@@ -1219,18 +1219,24 @@ __device__ __forceinline__ void upd_body_x(T *__restrict__ r, const T *__restric
     if (writer) sc->k2flag[it & 1] = 0;
 }
 
-// The unpreconditioned update of one workgroup.  The exchange form pays one
-// barrier per element group for the copies it does not gather; it is taken
-// when the walk has at least three groups per workgroup (problems far
-// larger than the caches, where the strided x-face gathers miss: 32^3 N=9
-// FP32 123 -> 102 us per launch), the gathering form otherwise
-// (cache-resident problems, where the barrier costs more than the gathers:
-// 16^3 N=9 FP32 17.7 -> 19.8 us with it).  Both forms add the same values
-// in the same order with the same workgroups, so they give bit-identical
-// results and partials.
-// xmin: the fewest element groups per workgroup for the exchange form
-// (UPD_X_MIN_GROUPS by default; 0 always, INT_MAX never).
-constexpr int UPD_X_MIN_GROUPS = 3;
+// The unpreconditioned update of one workgroup: the exchange form when the
+// walk has at least xmin groups per workgroup, the gathering form
+// otherwise.  The exchange form pays one barrier per element group for the
+// copies it does not gather; with its column of r read after the barrier it
+// is the faster one on MI355X both beyond the caches (32^3 N=9: FP32 123 ->
+// 97 us, FP64 222 -> 200 us per launch) and for cache-resident problems
+// (16^3 N=9 solves 0.3-2.5 % faster in every configuration), so the update
+// kernel takes it by default.  Both forms add the same values in the same
+// order with the same workgroups, so they give bit-identical results and
+// partials.
+// Fewest element groups per workgroup for the exchange form (0: always,
+// INT_MAX: never): the update kernel's default, and the assembly pass's,
+// whose exchange form also changes its grid (one group per workgroup when
+// gathering, a capped grid of walking workgroups when exchanging) and is the
+// faster one only beyond the caches (32^3 N=9: 3-6 % faster; 16^3: within
+// -2 / +3.5 %).
+constexpr int UPD_X_MIN_GROUPS = 0;
+constexpr int ASM_X_MIN_GROUPS = 3;
 
 template <int NP, int EPW, typename T>
 __device__ __forceinline__ void upd_body_nopc(T *__restrict__ r, const T *__restrict__ w, Scal *__restrict__ sc,

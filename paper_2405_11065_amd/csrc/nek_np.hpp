@@ -268,7 +268,7 @@ template <int NP> struct OpsImpl {
             // enough groups (the choice of the update kernel)
             const int groups = ax_groups(c, EPW);
             const unsigned cap = ax_grid(c, EPW, (int)sizeof(T));
-            if ((long)groups >= (long)upd_xmin(c) * cap) {
+            if ((long)groups >= (long)upd_xmin(c, true) * cap) {
                 hipLaunchKernelGGL((k_assemble_x<NP, EPW, T>), dim3(cap), dim3(EPW * NP * NP), 0, c->stream, scratch,
                                    w, c->box, (int)c->E, groups);
                 HIP_TRY(hipGetLastError());
