@@ -989,10 +989,10 @@ __device__ __forceinline__ void upd_apply(const UpdCol<NP, T, PC> &c, T *__restr
 // and r stays exactly continuous.
 // With PC (diagonal preconditioner dg, 1 on Dirichlet nodes) r holds z =
 // r / m and the kernel writes the partials of glsc3(r, c, z) to P2cur and
-// of glsc3(r, c, r) to P4cur.  For large problems the unpreconditioned
-// kernels run upd_body_x (below) instead, which takes the x-face copies
-// shared inside a workgroup from LDS and adds the same values in the same
-// order.
+// of glsc3(r, c, r) to P4cur.  The unpreconditioned kernels run this form
+// only when asked to (nek_set_update_kernel); by default they run
+// upd_body_x (below), which takes the x-face copies shared inside a
+// workgroup from LDS and adds the same values in the same order.
 template <int NP, int EPW, typename T, bool PC = false>
 __device__ __forceinline__ void upd_body(T *__restrict__ r, const T *__restrict__ w, Scal *__restrict__ sc,
                                          const double *__restrict__ P1cur, int nb1, double *__restrict__ P2cur,
