@@ -1169,7 +1169,7 @@ __device__ __forceinline__ void upd_body_x(T *__restrict__ r, const T *__restric
                                            const double *__restrict__ P1cur, int nb1, double *__restrict__ P2cur,
                                            int it, Box box, int E, int ngroups, unsigned blk, unsigned nblk)
 {
-    constexpr int NP2 = NP * NP, BS = EPW * NP2;
+    constexpr int NP2 = NP * NP, NP3 = NP2 * NP, BS = EPW * NP2;
     constexpr int FV = 2 * NP + 4, FS = FV + 1;   // published values of a face column; odd slot stride
     __shared__ double sbuf[BS];
     __shared__ T xf[2][EPW][2][NP][FS];   // [group parity][element][face i = 0 / i = N][j][value]
@@ -1206,7 +1206,7 @@ __device__ __forceinline__ void upd_body_x(T *__restrict__ r, const T *__restric
         __syncthreads();
         if (c.valid) {
 #pragma unroll
-            for (int k = 0; k < NP; ++k) c.rv[k] = r[c.e * NP2 * NP + k * NP2 + ij];
+            for (int k = 0; k < NP; ++k) c.rv[k] = r[c.e * NP3 + k * NP2 + ij];
             if (xr.xin || xr.cin) xf_take<NP, T>(xr.xin ? xf[buf][el + (i == 0 ? -1 : 1)][side ^ 1][j] : cf[p3][j], c);
             upd_apply<NP, T, false>(c, r, alpha, ij, box, part, part2);
         }
@@ -1219,6 +1219,15 @@ __device__ __forceinline__ void upd_body_x(T *__restrict__ r, const T *__restric
     if (writer) sc->k2flag[it & 1] = 0;
 }
 
+// Fewest element groups per workgroup for the exchange form (0: always,
+// INT_MAX: never): the update kernel's default, and the assembly pass's,
+// whose exchange form also changes its grid (one group per workgroup when
+// gathering, a capped grid of walking workgroups when exchanging) and is the
+// faster one only beyond the caches (32^3 N=9: 3-6 % faster; 16^3: within
+// -2 / +3.5 %).
+constexpr int UPD_X_MIN_GROUPS = 0;
+constexpr int ASM_X_MIN_GROUPS = 3;
+
 // The unpreconditioned update of one workgroup: the exchange form when the
 // walk has at least xmin groups per workgroup, the gathering form
 // otherwise.  The exchange form pays one barrier per element group for the
@@ -1229,15 +1238,6 @@ __device__ __forceinline__ void upd_body_x(T *__restrict__ r, const T *__restric
 // kernel takes it by default.  Both forms add the same values in the same
 // order with the same workgroups, so they give bit-identical results and
 // partials.
-// Fewest element groups per workgroup for the exchange form (0: always,
-// INT_MAX: never): the update kernel's default, and the assembly pass's,
-// whose exchange form also changes its grid (one group per workgroup when
-// gathering, a capped grid of walking workgroups when exchanging) and is the
-// faster one only beyond the caches (32^3 N=9: 3-6 % faster; 16^3: within
-// -2 / +3.5 %).
-constexpr int UPD_X_MIN_GROUPS = 0;
-constexpr int ASM_X_MIN_GROUPS = 3;
-
 template <int NP, int EPW, typename T>
 __device__ __forceinline__ void upd_body_nopc(T *__restrict__ r, const T *__restrict__ w, Scal *__restrict__ sc,
                                               const double *__restrict__ P1cur, int nb1, double *__restrict__ P2cur,
