@@ -165,3 +165,34 @@ def test_forms_bit_identical_every_order(N):
             torch.cuda.synchronize()
             assert torch.equal(wg, wx), f"nek_ax N={N} {prec} cap {cap}"
         ctx.close()
+
+
+def test_forms_bit_identical_full_size():
+    """The 32^3 N=9 deformed mesh in the configuration the benchmark times
+    (two elements per workgroup, the default persistent grid: eight element
+    groups per walk, so the exchange forms run uncapped with the carry in
+    use): nek_ax and 30 CG iterations, FP32 and FP64, exchange against
+    gather, bit for bit."""
+    nel, N = (32, 32, 32), 9
+    vtx = synth.box_vertices(nel, hi=(1.0, 1.0, 1.0), perturb=0.1, seed=synth.SEED_C3_VERTICES)
+    print("[case] setup 32^3 N=9", flush=True)
+    ctx = nek.Context(nel, N, vtx=vtx, prec="fp32")
+    f = torch.from_numpy(synth.uniform_load(ctx.nl, 21)).cuda()
+    for prec in ("fp32", "fp64"):
+        ctx.set_prec(prec)
+        ctx.set_variant(prec, 2)
+        u = f.float() if prec == "fp32" else f
+        print(f"[case] 32^3 N=9 {prec} nek_ax and 30 iterations, both forms", flush=True)
+        out = {}
+        for form in ("gather", "exchange"):
+            ctx.set_update_kernel(form)
+            w = ctx.ax(u).clone()
+            x, st, hist = ctx.cg_solve(f, tol=1e-30, maxit=30, history=True)
+            torch.cuda.synchronize()
+            out[form] = (w, x.clone(), st, hist.copy())
+        (wg, xg, sg, hg), (wx, xx, sx, hx) = out["gather"], out["exchange"]
+        assert torch.equal(wg, wx), f"{prec} nek_ax"
+        assert sg["iters"] == sx["iters"] and sg["iters"] > 0
+        assert torch.equal(xg, xx), f"{prec} x after {sg['iters']} iterations"
+        assert np.array_equal(hg, hx)
+    ctx.close()
