@@ -190,14 +190,14 @@ inline unsigned red_grid(const nek_ctx *c)
 
 inline int ax_groups(const nek_ctx *c, int epw) { return (int)((c->E + epw - 1) / epw); }
 
-// Fewest element groups per workgroup for which the update kernel (upd) and
-// the assembly pass of nek_ax (asm) take the exchange form
-// (nek_set_update_kernel).
+// When the update kernel (fewest element groups per workgroup) and the
+// assembly pass of nek_ax (fewest elements per workgroup) take the exchange
+// form (nek_set_update_kernel).
 inline int upd_xmin(const nek_ctx *c, bool assembly = false)
 {
     if (c->upd_kernel == NEK_UPDATE_GATHER) return INT_MAX;
     if (c->upd_kernel == NEK_UPDATE_EXCHANGE) return 0;
-    return assembly ? ASM_X_MIN_GROUPS : UPD_X_MIN_GROUPS;
+    return assembly ? ASM_X_MIN_ELEMENTS : UPD_X_MIN_GROUPS;
 }
 
 // Workgroups of `kernel` (block threads, static LDS only) resident on one

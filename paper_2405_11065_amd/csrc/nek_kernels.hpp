@@ -1219,14 +1219,28 @@ __device__ __forceinline__ void upd_body_x(T *__restrict__ r, const T *__restric
     if (writer) sc->k2flag[it & 1] = 0;
 }
 
-// Fewest element groups per workgroup for the exchange form (0: always,
-// INT_MAX: never): the update kernel's default, and the assembly pass's,
-// whose exchange form also changes its grid (one group per workgroup when
-// gathering, a capped grid of walking workgroups when exchanging) and is the
-// faster one only beyond the caches (32^3 N=9: 3-6 % faster; 16^3: within
-// -2 / +3.5 %).
+// When the exchange forms run (0: always, INT_MAX: never): the update
+// kernel by default at every size (fewest element groups per workgroup), the
+// assembly pass of nek_ax when its workgroups walk at least this many
+// elements each.  The assembly's exchange form also changes its grid (one
+// group per workgroup when gathering, a capped grid of walking workgroups
+// when exchanging) and is the faster one only beyond the caches (32^3 N=9:
+// 3-6 % faster; 16^3: within -2 / +3.5 %).
 constexpr int UPD_X_MIN_GROUPS = 0;
-constexpr int ASM_X_MIN_GROUPS = 3;
+constexpr int ASM_X_MIN_ELEMENTS = 6;
+
+// Elements per workgroup of the assembly pass, per order and independent of
+// the operator's configuration (the pass reduces nothing, so any grouping
+// gives the same output): the count, within 512 threads and 48 KB of FP64
+// exchange buffers, whose EPW * NP^2 threads fill 64-lane waves best.  At
+// NP = 10 that is 5 (500 threads in 8 waves): the 32^3 N=9 exchange form
+// takes 72-74 us (FP32) and 139-145 us (FP64) against 78 and 173 us with
+// two elements per workgroup.
+constexpr int asm_epw(int NP)
+{
+    return NP == 2 ? 80 : NP == 3 ? 42 : NP == 4 ? 28 : NP == 5 ? 15 : NP == 6 ? 14 : NP == 7 ? 9 : NP == 8 ? 8
+         : NP == 9 ? 6 : NP == 10 ? 5 : NP == 11 ? 4 : NP <= 13 ? 3 : NP <= 15 ? 2 : 1;
+}
 
 // The unpreconditioned update of one workgroup: the exchange form when the
 // walk has at least xmin groups per workgroup, the gathering form

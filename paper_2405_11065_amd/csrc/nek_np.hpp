@@ -264,17 +264,19 @@ template <int NP> struct OpsImpl {
             constexpr int EPW = decltype(epw_c)::value, PD = decltype(pd_c)::value;
             int rc = launch_ax<EPW, PD, T, GT, false>(c, u, nullptr, scratch, g, D, 0);
             if (rc) return rc;
-            // the exchange form on a capped grid when every workgroup walks
-            // enough groups (the choice of the update kernel)
-            const int groups = ax_groups(c, EPW);
-            const unsigned cap = ax_grid(c, EPW, (int)sizeof(T));
-            if ((long)groups >= (long)upd_xmin(c, true) * cap) {
-                hipLaunchKernelGGL((k_assemble_x<NP, EPW, T>), dim3(cap), dim3(EPW * NP * NP), 0, c->stream, scratch,
+            // the assembly in its own element groups; the exchange form on a
+            // capped grid when every workgroup walks enough elements (the
+            // choice of nek_set_update_kernel)
+            constexpr int EA = asm_epw(NP);
+            const int groups = ax_groups(c, EA);
+            const unsigned cap = ax_grid(c, EA, (int)sizeof(T));
+            if ((long)c->E >= (long)upd_xmin(c, true) * cap) {
+                hipLaunchKernelGGL((k_assemble_x<NP, EA, T>), dim3(cap), dim3(EA * NP * NP), 0, c->stream, scratch,
                                    w, c->box, (int)c->E, groups);
                 HIP_TRY(hipGetLastError());
                 return NEK_OK;
             }
-            hipLaunchKernelGGL((k_assemble<NP, EPW, T>), dim3(groups), dim3(EPW * NP * NP), 0, c->stream, scratch, w,
+            hipLaunchKernelGGL((k_assemble<NP, EA, T>), dim3(groups), dim3(EA * NP * NP), 0, c->stream, scratch, w,
                                c->box, (int)c->E, groups);
             HIP_TRY(hipGetLastError());
             return NEK_OK;
