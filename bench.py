@@ -48,7 +48,7 @@ COUNTER_TRAFFIC = {
         ("paper_2405_11065_amd/csrc/nek_np.hpp", "    // CG iteration it (1-based)"):
             "5370dc438f42553ad0db76050ddf7632b23cda5b1e5852145f73621ea40220f6",
         ("paper_2405_11065_amd/csrc/nek_internal.hpp", None):
-            "42f4f23a545b5041d9cba9d82ca2575b74ba5d4b71a899c020d5b3bbab9d1da9",
+            "ec60c54ea130004c265a803ff81ae11e50b530fd65d6ae95fb149f14f7b5d5c8",
     },
     "bytes_per_launch": {4: 226_600_000, 5: 226_300_000},   # FP32 configuration -> bytes
 }
