@@ -296,9 +296,10 @@ int nek_set_schwarz_kernel(nek_ctx *ctx, int kind);
 /* Kernel of the CG update step (dssum of w_L, mask, r -= alpha w, glsc3 of r). */
 typedef enum {
     NEK_UPDATE_AUTO = 0,      /* the default: exchange in the CG update kernel; in
-                                 nek_ax's assembly, exchange when every workgroup
-                                 walks at least three element groups (problems
-                                 beyond the caches), gather otherwise             */
+                                 nek_ax's assembly, exchange when the mesh has at
+                                 least six elements per workgroup of the capped
+                                 grid (problems beyond the caches), gather
+                                 otherwise                                        */
     NEK_UPDATE_GATHER = 1,    /* every copy of a face node read from memory      */
     NEK_UPDATE_EXCHANGE = 2   /* x-face copies of elements walked by one workgroup
                                  swapped through LDS                              */
